@@ -1,0 +1,44 @@
+"""Checks of the seeded input recipes (geometry, source mask of Section 2.1)."""
+import numpy as np
+
+import scenarios
+
+
+def test_tanh_factor_shape():
+    h = 0.4
+    r = np.array([0.0, 1e-9, h, 10 * h])
+    f = scenarios.tanh_factor(r, h, 5.0)
+    assert f[0] == 1.0 and f[1] == 1.0
+    assert abs(f[2] - 0.5) < 1e-15             # bracket vanishes at r = W/2
+    assert f[3] < 1e-20
+    rr = np.linspace(0, 3 * h, 200)
+    ff = scenarios.tanh_factor(rr, h, 5.0)
+    assert np.all(np.diff(ff) <= 0) and ff.min() >= 0 and ff.max() <= 1
+
+
+def test_room_geometry():
+    sc = scenarios.room(64, 48, 40, dx=0.05, n_boxes=3, seed=1)
+    b = sc.beta
+    assert b.dtype == np.uint8 and set(np.unique(b)) <= {0, 1}
+    nd = sc.meta["duct_cells"]
+    # slabs closed except for the duct cut through the x walls
+    assert b[:2].max() == 0 and b[:, :2].max() == 0
+    assert b[:, :, :2].sum() == 2 * nd * nd
+    # forced cells are fluid, sorted, unique, S in (0, 1]
+    idx = sc.forced_idx
+    assert np.all(np.diff(idx) > 0)
+    assert np.all(b.ravel()[idx] == 1)
+    assert sc.forced_S.min() > 1e-6 and sc.forced_S.max() <= 1.0
+    assert np.all(sc.forced_uset[:, 0] == 1.0) and np.all(sc.forced_cset == 400.0)
+    assert np.all(sc.c[b == 1] == 1000.0) and np.all(sc.c[b == 0] == 0.0)
+    # same seed, same scenario
+    sc2 = scenarios.room(64, 48, 40, dx=0.05, n_boxes=3, seed=1)
+    assert np.array_equal(sc.beta, sc2.beta) and np.array_equal(sc.forced_S, sc2.forced_S)
+
+
+def test_serving_stream_is_seeded():
+    a = scenarios.serving_requests(8)
+    b = scenarios.serving_requests(8)
+    assert a == b
+    assert all(r["grid"] in [(64, 64, 64), (128, 64, 64), (192, 96, 64), (256, 128, 96)] for r in a)
+    assert all(0 <= r["n_boxes"] <= 12 for r in a)
