@@ -373,3 +373,26 @@ def test_step_diagnostics_definitions():
     assert dg["dt"] == 0.02 and dg["step"] == 1 and dg["t"] == 0.02
     rate = np.max(np.abs(v0)) / (L[1] / 6)
     assert dg["cfl_max"] == pytest.approx(0.02 * rate, rel=1e-14)
+
+
+def test_momentum_shear_mode_advected_by_uniform_flow():
+    """u = (U, A cos(k x), 0): C_y = U D_x v and C_x = 0 exactly, the field is
+    divergence-free, so v is advected and diffused with the exact complex RK4
+    factor z = dt(-i U sin(th)/dx - 4 nu sin^2(th/2)/dx^2).  Pins the sign and
+    weight of the momentum convection."""
+    shape = (2, 3, 12)
+    L = (3.0, 1.0, 1.0)
+    nu, dt = 0.02, 0.03
+    O = make(shape, L, nu=nu, dt_fixed=dt)
+    dx = L[0] / shape[2]
+    x = np.arange(shape[2]) * dx
+    th = 2 * np.pi * 2 / shape[2]
+    kx = th / dx
+    U = 0.8
+    v0 = np.broadcast_to(np.cos(kx * x), shape).copy()
+    s = OracleState(np.full(shape, U), v0.copy(), zeros(shape), zeros(shape), zeros(shape))
+    nst = 5
+    s, _ = O.run(s, nst)
+    z = dt * (-1j * U * np.sin(th) / dx - nu * 4 * np.sin(th / 2) ** 2 / dx ** 2)
+    np.testing.assert_allclose(s.v[0, 0], np.real(np.exp(1j * kx * x) * R4(z) ** nst), atol=1e-14)
+    np.testing.assert_allclose(s.u, U, rtol=1e-15)
