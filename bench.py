@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Throughput of the full projection time step on one MI355X.
+
+Workload: the ventilated room, 256 x 128 x 96 cells (10 x 5 x 3.75 m, dx = 3.9 cm),
+2-cell solid walls, a 0.3 m duct blowing 1 m/s through the periodic seam, 8
+seeded obstacles, CO2 1000 ppm inside and 400 ppm supply, FP64, CFL 0.3,
+sixth-order filter on, four immersed-boundary FFT pressure iterations per step.
+A step is the whole hot path: dt, momentum RK4, divergence, 4 x (IB right-hand
+side + 3D real FFT + spectral solve + inverse FFT), correction, scalar RK4,
+filter, FP64 diagnostics.
+
+Prints one JSON line.  ``value`` is Gcell-steps/s with all inputs resident in
+HBM.  ``roofline`` prices the dominant kernel's algorithmic bytes per launch
+against its average launch time, measured with HIP events recorded by the
+library on its own stream.  ``cpu_baseline`` times the FP64 CPU oracle on a
+bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+
+
+def kernel_bytes(sc, esz=8):
+    """Algorithmic (compulsory) HBM bytes per launch of each kernel, for the
+    step sequence of the library (stage-averaged where a kernel has modes)."""
+    n = sc.ncells
+    m = sc.nx // 2
+    spec = 2 * esz * (m + 1) * sc.ny * sc.nz          # complex half spectrum
+    return {
+        # RK4 momentum: fields touched per stage 9, 15, 15, 9 (x esz) + mask byte
+        "mom_stage": n * ((9 + 15 + 15 + 9) / 4 * esz + 1),
+        # RK4 scalar: 6, 8, 8, 6 fields + mask byte
+        "scalar_stage": n * ((6 + 8 + 8 + 6) / 4 * esz + 1),
+        "fft_x_fwd": n * (esz + 1) + spec,            # r0 + mask in, spectrum out
+        "fft_y": 2 * spec,
+        "fft_z": 2 * spec,
+        "fft_x_inv": spec + n * esz,
+        "filter": n * (8 * esz + 1),
+        "correct": n * (7 * esz + 1),
+        "div": n * 4 * esz,
+    }
+
+
+def step_bytes(sc, esz=8):
+    """Pass-model bytes of one whole step (launch counts of the step sequence)."""
+    kb = kernel_bytes(sc, esz)
+    it = sc.n_piter if (sc.beta == 0).any() else min(sc.n_piter, 1)
+    y_passes = 2 if sc.ny > 1 else 0
+    poisson = kb["fft_x_fwd"] + y_passes * kb["fft_y"] + kb["fft_z"] + kb["fft_x_inv"]
+    return (4 * kb["mom_stage"] + kb["div"] + it * poisson + kb["correct"]
+            + 4 * kb["scalar_stage"] + (kb["filter"] if sc.filter else 0))
+
+
+def workload():
+    import scenarios
+    return scenarios.room()
+
+
+def cpu_baseline(sc, budget_s=20.0):
+    """Time the oracle (plain numpy FP64, single thread) on whole steps of the
+    same workload until about budget_s seconds have passed."""
+    from oracle.step import Oracle
+    O = Oracle.from_scenario(sc)
+    st = Oracle.state_from_scenario(sc)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        st, _ = O.step(st)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or steps >= 10:
+            break
+    return {
+        "value": sc.ncells * steps / el / 1e9,
+        "unit": "Gcell-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} full steps of the same 256x128x96 room from its initial state, "
+                  f"{el:.1f} s wall on 1 of {os.cpu_count()} host cores (numpy elementwise and "
+                  f"pocketfft run single-threaded)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-steps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the step runs on a single MI355X and this build has "
+              "no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2204_02107_amd as m
+
+    sc = workload()
+    dev = torch.device("cuda:0")
+    S = m.Solver(sc, precision=m.FP64, device=dev)
+    stream = S.stream
+    print(f"[bench] workload {sc.name} cells={sc.ncells} warmup={args.warmup}", file=sys.stderr, flush=True)
+    S.step(args.warmup, diag=False)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps, bracketed by synchronisation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(args.steps, diag=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hist = S.read_diags(1)[0]
+    value = sc.ncells * args.steps / el / 1e9
+    print(f"[bench] {args.steps} steps in {el:.3f} s -> {value:.3f} Gcell-steps/s; "
+          f"t={hist['t']:.3f} ke={hist['ke']:.4e} co2_mean={hist['co2_room_mean']:.3f}",
+          file=sys.stderr, flush=True)
+
+    # per-kernel launch times from HIP events on the library's stream
+    kb = kernel_bytes(sc)
+    per = {}
+    for name in kb:
+        S.profile(name)
+        S.step(args.profile_steps, diag=False)
+        ms, nl = S.profile_read()
+        S.profile(None)
+        if nl:
+            per[name] = {"avg_us": 1e3 * ms / nl, "launches_per_step": nl / args.profile_steps,
+                         "ms_per_step": ms / args.profile_steps,
+                         "GBs": kb[name] / (1e-3 * ms / nl) / 1e9}
+    dom = max(per, key=lambda k: per[k]["ms_per_step"])
+    pk = per[dom]
+    achieved = pk["GBs"]
+    print("[bench] per-kernel: " + json.dumps({k: {kk: round(vv, 3) for kk, vv in v.items()}
+                                               for k, v in per.items()}), file=sys.stderr, flush=True)
+
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            with open(tfile) as f:
+                tr = json.load(f)
+            traffic = tr.get(dom)
+        except (OSError, ValueError):
+            traffic = None
+
+    sbytes = step_bytes(sc)
+    out = {
+        "metric": "Gcell-steps/s (full step incl. FFT Poisson)",
+        "value": value,
+        "unit": "Gcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "ventilated room 256x128x96 (10x5x3.75 m), 8 seeded boxes, 1 m/s duct, "
+                        "FP64, CFL 0.3, filter on, 4 IB pressure iterations",
+            "cells": sc.ncells,
+            "forced_cells": int(len(sc.forced_idx)),
+        },
+        "step_bytes_per_cell": sbytes / sc.ncells,
+        "hbm_frac_end_to_end": sbytes * (value * 1e9 / sc.ncells) / (HBM_PEAK_GBS * 1e9),
+        "roofline": {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["GBs"], 1),
+                        "launches_per_step": v["launches_per_step"]} for k, v in per.items()},
+    }
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sc)
+    S.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * dnslab.h - C ABI of an MI355X (gfx950) library for one explicit projection
+ * time step of the incompressible Navier-Stokes equations with a passive
+ * scalar and a binary immersed-boundary mask, after Korhonen et al.,
+ * arXiv 2204.02107 (Sections 2.1, 2.2 and 2.4).
+ *
+ * What one step computes (Section 2.1 unless noted):
+ *   1. dt from a maximum Courant number (Section 2.4), or a fixed dt;
+ *   2. classical RK4 of the momentum equation without the pressure gradient,
+ *      second-order central differences, skew-symmetric convection, viscous
+ *      term, relaxation forcing S (u_set - u)/tau_f and body force b, all
+ *      multiplied by the mask beta;
+ *   3. the immersed-boundary pressure iteration of Section 2.2: n_piter FFT
+ *      solves of  Lap p^{k+1} = div u* + div((1 - beta) grad p^k), warm-started
+ *      from the previous step's pressure, with the central-difference symbol
+ *      lambda(m) = -sum_a sin^2(2 pi m_a / N_a) / dx_a^2 (zero on the modes
+ *      whose every m_a is 0 or N_a/2);
+ *   4. the correction u = beta (u* - grad p);
+ *   5. classical RK4 of the passive scalar (flux-form convection with the
+ *      projected velocity frozen, masked diffusion alpha_c div(beta grad c),
+ *      relaxation forcing), then c = beta c;
+ *   6. optionally the sixth-order explicit filter f + pi^-6 sum_a delta6_a f on
+ *      u, v, w and c, followed by the mask;
+ *   7. FP64 diagnostics (kinetic energy, divergence norm, CO2 mass, room-mean
+ *      CO2, Courant number).
+ *
+ * Conventions for every entry point:
+ *   - Device pointers are caller-owned, contiguous, structure-of-arrays, x
+ *     fastest: cell (i, j, k) is element i + nx*(j + ny*k).
+ *   - Field element type ("field type" below): double for DNSLAB_FP64, float
+ *     for DNSLAB_FP32_REFINE, for all of u, v, w, p and c.
+ *   - All work is enqueued on params.stream (a hipStream_t; NULL = the null
+ *     stream) and is asynchronous, except where an entry point says it
+ *     synchronises.
+ *   - Return value 0 on success, a negative DNSLAB_E* code otherwise.  On an
+ *     argument or state error nothing is enqueued.  No C++ exception crosses
+ *     this interface.  dnslab_last_error() gives a message.
+ *   - One context per stream; a context is not thread-safe.  The context owns
+ *     its workspace (device memory it allocates with hipMalloc); the bound
+ *     state buffers stay owned by the caller and must outlive the context.
+ *   - Units are SI; the scalar is a plain number (ppm in the room cases).
+ */
+#ifndef DNSLAB_H
+#define DNSLAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DNSLAB_OK            0
+#define DNSLAB_EINVAL       -1   /* bad argument (NULL pointer, bad size, bad parameter) */
+#define DNSLAB_ENOMEM       -2   /* device allocation failed */
+#define DNSLAB_EUNSUPPORTED -3   /* grid size not of the form 2^a 3^b, or too large */
+#define DNSLAB_EHIP         -4   /* a HIP runtime call failed */
+#define DNSLAB_ESTATE       -5   /* call not valid in the current state */
+#define DNSLAB_EAGAIN       -6   /* pool: not enough HBM budget left right now */
+#define DNSLAB_ENONFINITE   -7   /* a diagnostic came out NaN or Inf */
+
+typedef enum { DNSLAB_FP64 = 0, DNSLAB_FP32_REFINE = 1 } dnslab_precision;
+
+typedef struct dnslab_ctx dnslab_ctx;     /* opaque */
+typedef struct dnslab_pool dnslab_pool;   /* opaque */
+
+/* Case parameters (the paper's case-setup script, Section 2.4). */
+typedef struct {
+    int32_t nx, ny, nz;     /* cells; nx = 2^a 3^b with a >= 1 and nx >= 4; ny, nz = 1 or
+                               2^a 3^b >= 2; each at most 4096 (nx) / 2048 (ny, nz) */
+    double lx, ly, lz;      /* periodic box lengths [m]; dx = lx/nx etc. */
+    double nu;              /* kinematic viscosity [m^2/s] */
+    double alpha_c;         /* scalar diffusivity [m^2/s] */
+    double tau_f;           /* forcing relaxation time [s] (> 0) */
+    double body[3];         /* body-force acceleration b [m/s^2] */
+    double cfl;             /* maximum Courant number sum_a |u_a| dt / dx_a */
+    double dt_fixed;        /* > 0: fixed time step; otherwise dt from cfl */
+    double u_ref;           /* Courant denominator floor u_ref / min(dx) (> 0 if adaptive) */
+    int32_t n_piter;        /* immersed-boundary pressure iterations per step (paper: 4) */
+    int32_t filter;         /* 1: sixth-order filter at the end of each step */
+    int32_t precision;      /* dnslab_precision */
+    void* stream;           /* hipStream_t for all work of this context */
+} dnslab_params;
+
+/* Per-step diagnostics, all FP64. */
+typedef struct {
+    double t;               /* simulated time after the step */
+    double dt;              /* time step taken */
+    double ke;              /* 1/2 sum beta |u|^2 dV after the step */
+    double div_l2;          /* sqrt(sum (div u)^2 dV) of the projected velocity */
+    double co2_mass;        /* sum beta c dV after the step */
+    double co2_room_mean;   /* sum_R beta c / sum_R beta (R = room mask, or all cells) */
+    double cfl_max;         /* dt * max sum_a |u_a|/dx_a over the start-of-step velocity */
+    int64_t step;           /* steps taken since init / set_state */
+} dnslab_diag;
+
+/* Bytes of device workspace a context with these parameters allocates (for
+ * HBM-budget admission).  Host-only; enqueues nothing. */
+int dnslab_workspace_bytes(const dnslab_params* params, size_t* out_bytes);
+
+/* Create a context bound to caller-owned state buffers u, v, w, p, c (device,
+ * nx*ny*nz elements each, types per precision).  beta_dev: uint8 mask, 1 fluid,
+ * 0 solid (Section 2.1).  The forcing region S (Section 2.1, eq. tanh) is given
+ * sparse: n_forced sorted unique flat indices, S in (0, 1], u_set [3*n] as
+ * (x,y,z) triples and c_set [n], all device arrays (may be NULL if n_forced is
+ * 0).  room_mask_dev: uint8 region of the room-mean diagnostic, NULL = all
+ * cells.  The mask and forcing arrays are copied; the state buffers are kept.
+ * Synchronises the stream (computes the first time step). */
+int dnslab_init(const dnslab_params* params, const uint8_t* beta_dev,
+                int64_t n_forced, const int64_t* forced_idx_dev, const double* forced_S_dev,
+                const double* forced_uset_dev, const double* forced_cset_dev,
+                const uint8_t* room_mask_dev,
+                void* u, void* v, void* w, void* p, void* c,
+                dnslab_ctx** out);
+
+/* Advance the bound state by nsteps full steps (items 1-7 above).  If diag is
+ * non-NULL the call synchronises and fills it with the last step's values;
+ * then it returns DNSLAB_ENONFINITE if any diagnostic of the steps is not
+ * finite. */
+int dnslab_step(dnslab_ctx* ctx, int32_t nsteps, dnslab_diag* diag);
+
+/* Copy the diagnostics of the last n steps (n <= 4096, oldest first) into
+ * out[0..n-1].  Synchronises. */
+int dnslab_read_diags(dnslab_ctx* ctx, int32_t n, dnslab_diag* out);
+
+/* One FFT solve of the pressure equation of Section 2.2 without the mask
+ * term: p = Lap^-1 rhs with the central-difference symbol, null modes set to
+ * zero.  rhs_dev and p_dev: device, nx*ny*nz elements of the field type; they
+ * may alias. */
+int dnslab_poisson(dnslab_ctx* ctx, const void* rhs_dev, void* p_dev);
+
+/* The projection of Section 2.2 applied in place to the velocity u*, v*, w*
+ * (device, field type): n_piter immersed-boundary iterations warm-started from
+ * the bound pressure p (which is updated), then u = beta (u* - grad p). */
+int dnslab_project(dnslab_ctx* ctx, void* u, void* v, void* w);
+
+/* One RK4 step of the scalar (item 5) of length dt with the bound velocity
+ * frozen; updates the bound c in place. */
+int dnslab_scalar_step(dnslab_ctx* ctx, double dt);
+
+/* Momentum right-hand side F(u) of item 2 (without pressure), written to
+ * fu, fv, fw (device, field type).  Inputs are not modified. */
+int dnslab_momentum_rhs(dnslab_ctx* ctx, const void* u, const void* v, const void* w,
+                        void* fu, void* fv, void* fw);
+
+/* Scalar right-hand side G(c; u) of item 5 written to out (device, field type). */
+int dnslab_scalar_rhs(dnslab_ctx* ctx, const void* c, const void* u, const void* v,
+                      const void* w, void* out);
+
+/* Masked sixth-order filter (item 6) of one field: out = beta (f + pi^-6 sum_a
+ * delta6_a f).  f and out must not alias. */
+int dnslab_filter(dnslab_ctx* ctx, const void* f, void* out);
+
+/* Re-read the bound state after the caller changed it (recomputes the Courant
+ * time step; resets t and the step counter to the given values).  Synchronises. */
+int dnslab_set_time(dnslab_ctx* ctx, double t, int64_t step);
+
+/* Release the workspace.  Synchronises the stream first.  NULL is a no-op. */
+void dnslab_destroy(dnslab_ctx* ctx);
+
+/* Message of the last error on ctx; with ctx = NULL the last error of this
+ * thread (for failed dnslab_init calls).  Never NULL. */
+const char* dnslab_last_error(const dnslab_ctx* ctx);
+
+/* Kernel timing for roofline measurements: when enabled, every launch of the
+ * named kernel ("mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
+ * "fft_x_inv", "filter", "correct", "div") is bracketed by HIP events on the
+ * context's stream, and the total and count accumulate.  Read synchronises. */
+int dnslab_profile_enable(dnslab_ctx* ctx, const char* kernel_name);
+int dnslab_profile_read(dnslab_ctx* ctx, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DNSLAB_H */

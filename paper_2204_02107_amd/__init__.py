@@ -1,0 +1,180 @@
+"""MI355X (gfx950) library for one explicit projection time step of the
+incompressible Navier-Stokes equations with a passive CO2 scalar and a binary
+immersed-boundary mask (Korhonen et al., arXiv 2204.02107, Sections 2.1-2.4).
+
+The compute path is the HIP library ``libdnslab.so`` (C ABI in
+``include/dnslab.h``).  This module only marshals arguments: PyTorch provides
+device memory and the stream.  There is no CPU fallback; without the built
+library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+from . import _lib
+from ._lib import Diag, DnslabError, Params, FP64, FP32_REFINE
+
+__all__ = ["Solver", "Diag", "DnslabError", "Params", "FP64", "FP32_REFINE", "workspace_bytes", "load"]
+
+load = _lib.load
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def make_params(case, precision=FP64, stream=None) -> Params:
+    P = Params()
+    P.nx, P.ny, P.nz = int(case.nx), int(case.ny), int(case.nz)
+    P.lx, P.ly, P.lz = float(case.lx), float(case.ly), float(case.lz)
+    P.nu, P.alpha_c, P.tau_f = float(case.nu), float(case.alpha_c), float(case.tau_f)
+    for i in range(3):
+        P.body[i] = float(case.body[i])
+    P.cfl, P.dt_fixed, P.u_ref = float(case.cfl), float(case.dt_fixed), float(case.u_ref)
+    P.n_piter, P.filter, P.precision = int(case.n_piter), int(bool(case.filter)), int(precision)
+    P.stream = stream
+    return P
+
+
+def workspace_bytes(case, precision=FP64) -> int:
+    out = ctypes.c_size_t()
+    lib = load()
+    _lib.check(lib.dnslab_workspace_bytes(ctypes.byref(make_params(case, precision)), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Solver:
+    """One context of the library bound to resident torch state tensors.
+
+    ``case`` is any object with the attributes of a scenario: grid and
+    parameters, ``beta`` (uint8, shape (nz, ny, nx)), the sparse forcing list
+    (``forced_idx``, ``forced_S``, ``forced_uset``, ``forced_cset``),
+    ``room_mask`` and the initial fields ``u, v, w, p, c``.
+    """
+
+    def __init__(self, case, precision=FP64, device="cuda:0", stream=None):
+        torch = _torch()
+        self.lib = load()
+        self.device = torch.device(device)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        self.shape = (int(case.nz), int(case.ny), int(case.nx))
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        dev = self.device
+
+        def field(a):
+            return torch.as_tensor(a, dtype=self.dtype).reshape(self.shape).to(dev).contiguous()
+
+        self.u, self.v, self.w = field(case.u), field(case.v), field(case.w)
+        self.p, self.c = field(case.p), field(case.c)
+        beta = torch.as_tensor(case.beta, dtype=torch.uint8).reshape(self.shape).to(dev).contiguous()
+        n = int(len(case.forced_idx))
+        fidx = torch.as_tensor(case.forced_idx, dtype=torch.int64).to(dev).contiguous()
+        fS = torch.as_tensor(case.forced_S, dtype=torch.float64).to(dev).contiguous()
+        fus = torch.as_tensor(case.forced_uset, dtype=torch.float64).reshape(-1).to(dev).contiguous()
+        fcs = torch.as_tensor(case.forced_cset, dtype=torch.float64).to(dev).contiguous()
+        room = None
+        if getattr(case, "room_mask", None) is not None:
+            room = torch.as_tensor(case.room_mask, dtype=torch.uint8).reshape(self.shape).to(dev).contiguous()
+        self.params = make_params(case, precision, ctypes.c_void_p(stream.cuda_stream))
+        ctx = ctypes.c_void_p()
+        rc = self.lib.dnslab_init(
+            ctypes.byref(self.params), _ptr(beta), n,
+            _ptr(fidx) if n else None, _ptr(fS) if n else None,
+            _ptr(fus) if n else None, _ptr(fcs) if n else None,
+            _ptr(room) if room is not None else None,
+            _ptr(self.u), _ptr(self.v), _ptr(self.w), _ptr(self.p), _ptr(self.c),
+            ctypes.byref(ctx))
+        _lib.check(rc, None)
+        self.ctx = ctx
+
+    # -- life cycle ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.dnslab_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        return _lib.check(rc, self.ctx)
+
+    # -- the step ------------------------------------------------------------
+    def step(self, nsteps: int = 1, diag: bool = True) -> Optional[dict]:
+        d = Diag() if diag else None
+        self._check(self.lib.dnslab_step(self.ctx, int(nsteps), ctypes.byref(d) if diag else None))
+        return d.as_dict() if diag else None
+
+    def read_diags(self, n: int):
+        arr = (Diag * n)()
+        self._check(self.lib.dnslab_read_diags(self.ctx, int(n), arr))
+        return [a.as_dict() for a in arr]
+
+    def set_time(self, t: float = 0.0, step: int = 0):
+        self._check(self.lib.dnslab_set_time(self.ctx, float(t), int(step)))
+
+    # -- pieces of the step --------------------------------------------------
+    def poisson(self, rhs, out=None):
+        out = self._empty() if out is None else out
+        self._check(self.lib.dnslab_poisson(self.ctx, _ptr(self._dev(rhs)), _ptr(out)))
+        return out
+
+    def project(self, u, v, w):
+        self._check(self.lib.dnslab_project(self.ctx, _ptr(u), _ptr(v), _ptr(w)))
+
+    def scalar_step(self, dt: float):
+        self._check(self.lib.dnslab_scalar_step(self.ctx, float(dt)))
+
+    def momentum_rhs(self, u, v, w):
+        u, v, w = self._dev(u), self._dev(v), self._dev(w)
+        out = [self._empty() for _ in range(3)]
+        self._check(self.lib.dnslab_momentum_rhs(self.ctx, _ptr(u), _ptr(v), _ptr(w), *map(_ptr, out)))
+        return out
+
+    def scalar_rhs(self, c, u, v, w):
+        c, u, v, w = map(self._dev, (c, u, v, w))
+        out = self._empty()
+        self._check(self.lib.dnslab_scalar_rhs(self.ctx, _ptr(c), _ptr(u), _ptr(v), _ptr(w), _ptr(out)))
+        return out
+
+    def filter(self, f):
+        f = self._dev(f)
+        out = self._empty()
+        self._check(self.lib.dnslab_filter(self.ctx, _ptr(f), _ptr(out)))
+        return out
+
+    # -- kernel timing -------------------------------------------------------
+    def profile(self, kernel: Optional[str]):
+        self._check(self.lib.dnslab_profile_enable(self.ctx, kernel.encode() if kernel else None))
+
+    def profile_read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.dnslab_profile_read(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    # -- helpers -------------------------------------------------------------
+    def _empty(self):
+        return _torch().empty(self.shape, dtype=self.dtype, device=self.device)
+
+    def _dev(self, a):
+        torch = _torch()
+        t = torch.as_tensor(a, dtype=self.dtype, device=self.device).reshape(self.shape)
+        return t.contiguous()
+
+    def state(self):
+        """Host copies (numpy) of the bound fields (synchronises)."""
+        self.stream.synchronize()
+        return {k: getattr(self, k).double().cpu().numpy() for k in ("u", "v", "w", "p", "c")}

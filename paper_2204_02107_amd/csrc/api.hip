@@ -1,0 +1,825 @@
+// C ABI of libdnslab: context management and the sequencing of one
+// projection time step (Sections 2.1, 2.2 and 2.4 of arXiv 2204.02107).
+// Host code only; every arithmetic step runs in the kernels of stencil.hip
+// and fft.hip, enqueued on the caller's stream.
+#include "dnslab.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "fft.h"
+#include "stencil.h"
+
+using namespace dnslab;
+
+namespace {
+
+thread_local std::string g_thread_err;
+constexpr int RING_CAP = 4096;
+constexpr int PROF_POOL = 32768;
+
+enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_CORR, K_DIV, K_COUNT };
+const char* const kKernelNames[K_COUNT] = {"mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
+                                            "fft_x_inv", "filter", "correct", "div"};
+
+bool is_2a3b(int n) {
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+int pow2_floor(long long v) {
+    int p = 1;
+    while ((long long)p * 2 <= v) p *= 2;
+    return p;
+}
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v) ++l;
+    return l;
+}
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t esz;           // field element size
+    long long n;
+    int m, sx;            // fft
+    int nl_x, ls_x, lg_tx_y, lg_tx_z;
+    AxisPlan px, py, pz;
+    StencilLaunch L;
+    // byte offsets inside the workspace
+    size_t off_flags, off_fields, off_spec, off_tw, off_s2, off_forced, off_part, off_pdiv, off_sc, off_ring;
+    size_t total;
+    int nforced_cap;
+};
+
+int validate(const dnslab_params* P, std::string& why) {
+    if (!P) { why = "params is NULL"; return DNSLAB_EINVAL; }
+    if (P->precision != DNSLAB_FP64 && P->precision != DNSLAB_FP32_REFINE) { why = "bad precision"; return DNSLAB_EINVAL; }
+    if (P->nx < 4 || P->nx % 2 != 0 || !is_2a3b(P->nx) || P->nx > 4096) {
+        why = "nx must be even, 2^a 3^b, 4 <= nx <= 4096";
+        return DNSLAB_EUNSUPPORTED;
+    }
+    for (int n : {P->ny, P->nz})
+        if (!is_2a3b(n) || n > 2048) { why = "ny, nz must be 1 or 2^a 3^b <= 2048"; return DNSLAB_EUNSUPPORTED; }
+    const long long n = (long long)P->nx * P->ny * P->nz;
+    if (n >= (1LL << 31)) { why = "grid too large (>= 2^31 cells)"; return DNSLAB_EUNSUPPORTED; }
+    if (!(P->lx > 0 && P->ly > 0 && P->lz > 0)) { why = "box lengths must be positive"; return DNSLAB_EINVAL; }
+    if (!(P->tau_f > 0)) { why = "tau_f must be positive"; return DNSLAB_EINVAL; }
+    if (P->n_piter < 0 || P->n_piter > 64) { why = "n_piter out of range"; return DNSLAB_EINVAL; }
+    if (!(P->dt_fixed > 0)) {
+        if (!(P->cfl > 0) || !(P->u_ref > 0)) { why = "adaptive dt needs cfl > 0 and u_ref > 0"; return DNSLAB_EINVAL; }
+    }
+    if (!std::isfinite(P->nu) || !std::isfinite(P->alpha_c) || !std::isfinite(P->body[0]) ||
+        !std::isfinite(P->body[1]) || !std::isfinite(P->body[2])) {
+        why = "non-finite parameter";
+        return DNSLAB_EINVAL;
+    }
+    return DNSLAB_OK;
+}
+
+Grid make_grid(const dnslab_params* P) {
+    Grid g;
+    g.nx = P->nx; g.ny = P->ny; g.nz = P->nz;
+    g.nxy = (long long)P->nx * P->ny;
+    g.n = g.nxy * P->nz;
+    g.d[0] = P->lx / P->nx; g.d[1] = P->ly / P->ny; g.d[2] = P->lz / P->nz;
+    for (int a = 0; a < 3; ++a) {
+        g.inv2d[a] = 1.0 / (2.0 * g.d[a]);
+        g.inv4d[a] = 1.0 / (4.0 * g.d[a]);
+        g.invd2[a] = 1.0 / (g.d[a] * g.d[a]);
+    }
+    g.dv = g.d[0] * g.d[1] * g.d[2];
+    return g;
+}
+
+int stencil_kc(const Grid& g) {
+    const StencilLaunch one = stencil_launch(g, g.nz);
+    const long long cols = (long long)one.grid.x * one.grid.y;
+    // aim for at least ~4096 blocks, each walking at least 4 planes
+    long long kc = (long long)g.nz * cols / 4096;
+    kc = std::max(4LL, std::min(32LL, kc));
+    return (int)std::min<long long>(kc, g.nz);
+}
+
+Layout make_layout(const dnslab_params* P, int n_forced) {
+    Layout Lo = {};
+    const Grid g = make_grid(P);
+    Lo.esz = P->precision == DNSLAB_FP64 ? 8 : 4;
+    const size_t csz = 2 * Lo.esz;
+    Lo.n = g.n;
+    Lo.m = P->nx / 2;
+    Lo.sx = (int)align_up(Lo.m + 1, 16);
+    Lo.px = make_axis_plan(Lo.m);
+    Lo.py = make_axis_plan(P->ny);
+    Lo.pz = make_axis_plan(P->nz);
+    Lo.ls_x = ((Lo.m + 1) % 2 == 1) ? Lo.m + 1 : Lo.m + 2;
+    const long long nlines = (long long)P->ny * P->nz;
+    {
+        int nl = 1;
+        while (nl * 2 * Lo.px.tpl <= 256 && (size_t)nl * 2 * Lo.ls_x * csz <= 48 * 1024 && nl < nlines) nl *= 2;
+        Lo.nl_x = ilog2(nl);
+    }
+    auto pick_tx = [&](int n, const AxisPlan& ap) {
+        int tx = 1;
+        const int cap = std::min(64, pow2_floor(2LL * (Lo.m + 1) - 1));
+        while (tx * 2 <= cap && (size_t)tx * 2 * n * csz <= 32 * 1024 && tx * 2 * ap.tpl <= 1024) tx *= 2;
+        return ilog2(tx);
+    };
+    Lo.lg_tx_y = pick_tx(P->ny, Lo.py);
+    Lo.lg_tx_z = pick_tx(P->nz, Lo.pz);
+    Lo.L = stencil_launch(g, stencil_kc(g));
+    // workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    Lo.off_flags = take((size_t)g.n);
+    Lo.off_fields = take((size_t)13 * g.n * Lo.esz);
+    Lo.off_spec = take((size_t)Lo.sx * nlines * csz);
+    Lo.off_tw = take((size_t)(Lo.m + P->ny + P->nz + Lo.m + 1) * csz);
+    Lo.off_s2 = take((size_t)(Lo.m + 1 + P->ny + P->nz) * sizeof(double));
+    Lo.nforced_cap = std::max(1, n_forced);
+    Lo.off_forced = take((size_t)Lo.nforced_cap * (sizeof(long long) + 5 * sizeof(double)));
+    Lo.off_part = take((size_t)Lo.L.nblocks * sizeof(Partial));
+    Lo.off_pdiv = take((size_t)Lo.L.nblocks * sizeof(Partial));
+    Lo.off_sc = take(sizeof(StepScalars));
+    Lo.off_ring = take((size_t)RING_CAP * sizeof(DiagRec));
+    Lo.total = off;
+    return Lo;
+}
+
+// exp(-2 pi i j / n) in long double, rounded once.
+void twiddles(int n, std::vector<long double>& re, std::vector<long double>& im, int count) {
+    re.resize(count);
+    im.resize(count);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int j = 0; j < count; ++j) {
+        const long double ang = -2.0L * pi * (long double)j / (long double)n;
+        re[j] = cosl(ang);
+        im[j] = sinl(ang);
+    }
+}
+
+// sin^2(2 pi m / n) / h^2 with exact zeros where 2m is a multiple of n.
+void sin2_table(int n, int count, double h, double* out) {
+    for (int m = 0; m < count; ++m) {
+        if ((2LL * m) % n == 0) { out[m] = 0.0; continue; }
+        const double s = std::sin(2.0 * M_PI * m / n);
+        out[m] = s * s / (h * h);
+    }
+}
+
+}  // namespace
+
+struct dnslab_ctx {
+    dnslab_params P;
+    hipStream_t stream;
+    Grid g;
+    Layout Lo;
+    void* ws;
+    void *u, *v, *w, *p, *c;
+    uint8_t* flags;
+    void* f[13];           // A0..2, B0..2, Cb0..2, R0, CA, CS1, CS2
+    void* spec;
+    void *wx, *wy, *wz, *tw;
+    double *sx2, *sy2, *sz2;
+    long long* fidx;
+    double *fS, *fuset, *fcset;
+    int nforced;
+    Partial *part, *pdiv;
+    StepScalars* sc;
+    DiagRec* ring;
+    bool any_solid;
+    bool rate_valid;
+    long long host_step;
+    DiagRec* pinned;       // host staging for diagnostics
+    StepScalars* pinned_sc;
+    std::string err;
+    // profiling
+    int prof_kid;
+    std::vector<hipEvent_t> ev;
+    int ev_used;
+    double prof_ms;
+    long long prof_n;
+};
+
+namespace {
+
+int fail(dnslab_ctx* ctx, int code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    else g_thread_err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, DNSLAB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int prof_flush(dnslab_ctx* x) {
+    if (x->ev_used == 0) return DNSLAB_OK;
+    HIPCHK(x, hipStreamSynchronize(x->stream));
+    for (int i = 0; i + 1 < x->ev_used; i += 2) {
+        float ms = 0;
+        HIPCHK(x, hipEventElapsedTime(&ms, x->ev[i], x->ev[i + 1]));
+        x->prof_ms += ms;
+        x->prof_n += 1;
+    }
+    x->ev_used = 0;
+    return DNSLAB_OK;
+}
+
+// Bracket a launch with events when that kernel is being profiled.
+struct Prof {
+    dnslab_ctx* x;
+    bool on;
+    Prof(dnslab_ctx* x_, int kid) : x(x_), on(x_->prof_kid == kid) {
+        if (on) {
+            if (x->ev_used + 2 > (int)x->ev.size()) prof_flush(x);
+            (void)hipEventRecord(x->ev[x->ev_used], x->stream);
+        }
+    }
+    ~Prof() {
+        if (on) {
+            (void)hipEventRecord(x->ev[x->ev_used + 1], x->stream);
+            x->ev_used += 2;
+        }
+    }
+};
+
+#define LAUNCH(ctx, kid, expr)                                                             \
+    do {                                                                                   \
+        hipError_t e_;                                                                     \
+        {                                                                                  \
+            Prof pr_(ctx, kid);                                                            \
+            e_ = (expr);                                                                   \
+        }                                                                                  \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ctx, DNSLAB_EHIP, std::string("launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+Forcing forcing_of(dnslab_ctx* x) {
+    Forcing f;
+    f.idx = x->fidx;
+    f.S = x->fS;
+    f.uset = x->fuset;
+    f.cset = x->fcset;
+    f.n = x->nforced;
+    f.inv_tau = 1.0 / x->P.tau_f;
+    return f;
+}
+
+template <typename T>
+FFTArgs<T> fft_args(dnslab_ctx* x) {
+    FFTArgs<T> a;
+    a.g = x->g;
+    a.m = x->Lo.m;
+    a.sx = x->Lo.sx;
+    a.spec = (C2<T>*)x->spec;
+    a.px = x->Lo.px;
+    a.py = x->Lo.py;
+    a.pz = x->Lo.pz;
+    a.wx = (const C2<T>*)x->wx;
+    a.wy = (const C2<T>*)x->wy;
+    a.wz = (const C2<T>*)x->wz;
+    a.tw = (const C2<T>*)x->tw;
+    a.sx2 = x->sx2;
+    a.sy2 = x->sy2;
+    a.sz2 = x->sz2;
+    a.inv_ntot = 1.0 / (double)x->g.n;
+    a.nl_x = x->Lo.nl_x;
+    a.ls_x = x->Lo.ls_x;
+    a.lg_tx_y = x->Lo.lg_tx_y;
+    a.lg_tx_z = x->Lo.lg_tx_z;
+    return a;
+}
+
+// One FFT solve: spectrum of r0 (+ IB term from p when flags != NULL), divide, back into pout.
+template <typename T>
+int poisson_solve(dnslab_ctx* x, const T* r0, const T* pin, const uint8_t* flags, T* pout) {
+    const FFTArgs<T> a = fft_args<T>(x);
+    LAUNCH(x, K_FXF, launch_fft_x_fwd<T>(a, r0, pin, flags, x->stream));
+    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, false, x->stream));
+    LAUNCH(x, K_FZ, launch_fft_z_solve<T>(a, x->stream));
+    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, true, x->stream));
+    LAUNCH(x, K_FXI, launch_fft_x_inv<T>(a, pout, x->stream));
+    return DNSLAB_OK;
+}
+
+// Projection of Section 2.2: r0 = div u*, n IB iterations on the bound p, correction.
+template <typename T>
+int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
+    T* r0 = (T*)x->f[9];
+    T* p = (T*)x->p;
+    DivArgs<T> d;
+    for (int a = 0; a < 3; ++a) d.u[a] = us[a];
+    d.out = r0;
+    d.g = x->g;
+    LAUNCH(x, K_DIV, launch_div<T>(d, x->Lo.L, x->stream));
+    const int nit = x->any_solid ? x->P.n_piter : std::min(x->P.n_piter, 1);
+    for (int it = 0; it < nit; ++it) {
+        int rc = poisson_solve<T>(x, r0, p, x->any_solid ? x->flags : nullptr, p);
+        if (rc) return rc;
+    }
+    CorrArgs<T> ca;
+    for (int a = 0; a < 3; ++a) { ca.us[a] = us[a]; ca.out[a] = out[a]; }
+    ca.p = p;
+    ca.flags = x->flags;
+    ca.g = x->g;
+    LAUNCH(x, K_CORR, launch_correct<T>(ca, x->Lo.L, x->stream));
+    return DNSLAB_OK;
+}
+
+template <typename T>
+int scalar_rk4(dnslab_ctx* x, const T* const uvel[3], const double* dtp, double dt, T* cout, Partial* pdiv,
+               Partial* pdiag) {
+    T* C = (T*)x->c;
+    T* CA = (T*)x->f[10];
+    T* CS1 = (T*)x->f[11];
+    T* CS2 = (T*)x->f[12];
+    ScaArgs<T> s = {};
+    for (int a = 0; a < 3; ++a) s.u[a] = uvel[a];
+    s.flags = x->flags;
+    s.dtp = dtp;
+    s.dt = dt;
+    s.frc = forcing_of<T>(x);
+    s.alpha = x->P.alpha_c;
+    s.g = x->g;
+    s.acc = CA;
+    const StencilLaunch& L = x->Lo.L;
+    s.cs = C; s.out = CS1; s.part = pdiv;
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FIRST, s, L, x->stream));
+    s.cs = CS1; s.cn = C; s.out = CS2; s.part = nullptr;
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_HALF, s, L, x->stream));
+    s.cs = CS2; s.cn = C; s.out = CS1;
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FULL, s, L, x->stream));
+    s.cs = CS1; s.cn = nullptr; s.out = cout; s.part = pdiag;
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_LAST, s, L, x->stream));
+    return DNSLAB_OK;
+}
+
+template <typename T>
+int ensure_rate(dnslab_ctx* x) {
+    if (x->rate_valid) return DNSLAB_OK;
+    HIPCHK(x, launch_rate<T>((const T*)x->u, (const T*)x->v, (const T*)x->w, x->g, x->part, x->Lo.L, x->stream));
+    HIPCHK(x, launch_set_rate(x->part, x->Lo.L.nblocks, x->sc, x->stream));
+    x->rate_valid = true;
+    return DNSLAB_OK;
+}
+
+template <typename T>
+int one_step(dnslab_ctx* x) {
+    int rc = ensure_rate<T>(x);
+    if (rc) return rc;
+    T* U[3] = {(T*)x->u, (T*)x->v, (T*)x->w};
+    T* A[3] = {(T*)x->f[0], (T*)x->f[1], (T*)x->f[2]};
+    T* B[3] = {(T*)x->f[3], (T*)x->f[4], (T*)x->f[5]};
+    T* Cb[3] = {(T*)x->f[6], (T*)x->f[7], (T*)x->f[8]};
+    const StencilLaunch& L = x->Lo.L;
+    MomArgs<T> m = {};
+    m.flags = x->flags;
+    m.dtp = &x->sc->dt;
+    m.frc = forcing_of<T>(x);
+    m.nu = x->P.nu;
+    for (int a = 0; a < 3; ++a) m.body[a] = x->P.body[a];
+    m.g = x->g;
+    // RK4 stages (Section 2.1), no pressure gradient
+    for (int a = 0; a < 3; ++a) { m.us[a] = U[a]; m.acc[a] = A[a]; m.out[a] = B[a]; m.un[a] = nullptr; }
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FIRST, m, L, x->stream));
+    for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = U[a]; m.out[a] = Cb[a]; }
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_HALF, m, L, x->stream));
+    for (int a = 0; a < 3; ++a) { m.us[a] = Cb[a]; m.out[a] = B[a]; }
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FULL, m, L, x->stream));
+    for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = nullptr; m.out[a] = Cb[a]; }
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_LAST, m, L, x->stream));
+    // projection: u* in Cb -> corrected velocity (into A when the filter follows)
+    const bool filt = x->P.filter != 0;
+    T* const* V = filt ? A : U;
+    rc = project<T>(x, Cb, V);
+    if (rc) return rc;
+    // scalar RK4 with the projected velocity frozen
+    T* C = (T*)x->c;
+    T* CS2 = (T*)x->f[12];
+    rc = scalar_rk4<T>(x, V, &x->sc->dt, 0.0, filt ? CS2 : C, x->pdiv, filt ? nullptr : x->part);
+    if (rc) return rc;
+    if (filt) {
+        FiltArgs<T> fa = {};
+        for (int a = 0; a < 3; ++a) { fa.in[a] = A[a]; fa.out[a] = U[a]; }
+        fa.in[3] = CS2;
+        fa.out[3] = C;
+        fa.nf = 4;
+        fa.flags = x->flags;
+        fa.g = x->g;
+        fa.part = x->part;
+        LAUNCH(x, K_FILT, launch_filter<T>(fa, L, x->stream));
+    }
+    HIPCHK(x, launch_finish(x->part, L.nblocks, x->pdiv, L.nblocks, x->sc, x->ring, RING_CAP, x->g.dv, x->stream));
+    x->host_step += 1;
+    return DNSLAB_OK;
+}
+
+void diag_copy(const DiagRec& r, dnslab_diag* d) {
+    d->t = r.t;
+    d->dt = r.dt;
+    d->ke = r.ke;
+    d->div_l2 = r.div_l2;
+    d->co2_mass = r.co2_mass;
+    d->co2_room_mean = r.co2_room_mean;
+    d->cfl_max = r.cfl_max;
+    d->step = r.step;
+}
+
+int build_flags(dnslab_ctx* x, const uint8_t* beta_dev, const long long* fidx_host, int64_t nf,
+                const uint8_t* room_dev) {
+    const Grid& g = x->g;
+    std::vector<uint8_t> beta((size_t)g.n), room;
+    HIPCHK(x, hipMemcpy(beta.data(), beta_dev, (size_t)g.n, hipMemcpyDeviceToHost));
+    if (room_dev) {
+        room.resize((size_t)g.n);
+        HIPCHK(x, hipMemcpy(room.data(), room_dev, (size_t)g.n, hipMemcpyDeviceToHost));
+    }
+    std::vector<uint8_t> fl((size_t)g.n, 0);
+    bool any_solid = false;
+    for (long long i = 0; i < g.n; ++i) {
+        if (beta[i] > 1) return fail(x, DNSLAB_EINVAL, "beta must hold 0 or 1");
+        if (!beta[i]) any_solid = true;
+    }
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const long long id = i + (long long)nx * (j + (long long)ny * k);
+                uint8_t f = beta[id] ? F_FLUID : 0;
+                if (room_dev ? room[id] != 0 : true) f |= F_ROOM;
+                const int ip = (i + 1) % nx, im = (i + nx - 1) % nx;
+                const int jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
+                const int kp = (k + 1) % nz, km = (k + nz - 1) % nz;
+                const long long nb[6] = {ip + (long long)nx * (j + (long long)ny * k),
+                                         im + (long long)nx * (j + (long long)ny * k),
+                                         i + (long long)nx * (jp + (long long)ny * k),
+                                         i + (long long)nx * (jm + (long long)ny * k),
+                                         i + (long long)nx * (j + (long long)ny * kp),
+                                         i + (long long)nx * (j + (long long)ny * km)};
+                for (int q = 0; q < 6; ++q)
+                    if (!beta[nb[q]]) f |= F_NEAR_SOLID;
+                fl[id] = f;
+            }
+    for (int64_t e = 0; e < nf; ++e) {
+        const long long id = fidx_host[e];
+        if (id < 0 || id >= g.n) return fail(x, DNSLAB_EINVAL, "forced index out of range");
+        if (e > 0 && fidx_host[e - 1] >= id) return fail(x, DNSLAB_EINVAL, "forced indices must be sorted and unique");
+        fl[id] |= F_FORCED;
+    }
+    HIPCHK(x, hipMemcpy(x->flags, fl.data(), (size_t)g.n, hipMemcpyHostToDevice));
+    x->any_solid = any_solid;
+    return DNSLAB_OK;
+}
+
+template <typename T>
+int upload_tables(dnslab_ctx* x) {
+    const Grid& g = x->g;
+    const int m = x->Lo.m;
+    std::vector<C2<T>> h;
+    std::vector<long double> re, im;
+    auto push = [&](int n, int count) {
+        twiddles(n, re, im, count);
+        for (int j = 0; j < count; ++j) h.push_back(C2<T>{(T)re[j], (T)im[j]});
+    };
+    push(m, m);
+    push(g.ny, g.ny);
+    push(g.nz, g.nz);
+    push(g.nx, m + 1);
+    HIPCHK(x, hipMemcpy(x->wx, h.data(), h.size() * sizeof(C2<T>), hipMemcpyHostToDevice));
+    std::vector<double> s2((size_t)(m + 1 + g.ny + g.nz));
+    sin2_table(g.nx, m + 1, g.d[0], s2.data());
+    sin2_table(g.ny, g.ny, g.d[1], s2.data() + m + 1);
+    sin2_table(g.nz, g.nz, g.d[2], s2.data() + m + 1 + g.ny);
+    HIPCHK(x, hipMemcpy(x->sx2, s2.data(), s2.size() * sizeof(double), hipMemcpyHostToDevice));
+    return DNSLAB_OK;
+}
+
+template <typename T>
+int run_steps(dnslab_ctx* x, int nsteps) {
+    for (int s = 0; s < nsteps; ++s) {
+        int rc = one_step<T>(x);
+        if (rc) return rc;
+    }
+    return DNSLAB_OK;
+}
+
+int check_ctx(dnslab_ctx* x) {
+    if (!x) return fail(nullptr, DNSLAB_EINVAL, "ctx is NULL");
+    return DNSLAB_OK;
+}
+
+}  // namespace
+
+namespace {
+template <typename T>
+int mom_rhs(dnslab_ctx* x, const void* u, const void* v, const void* w, void* fu, void* fv, void* fw) {
+    MomArgs<T> m = {};
+    m.us[0] = (const T*)u; m.us[1] = (const T*)v; m.us[2] = (const T*)w;
+    m.out[0] = (T*)fu; m.out[1] = (T*)fv; m.out[2] = (T*)fw;
+    m.flags = x->flags;
+    m.frc = forcing_of<T>(x);
+    m.nu = x->P.nu;
+    for (int a = 0; a < 3; ++a) m.body[a] = x->P.body[a];
+    m.g = x->g;
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_RHS, m, x->Lo.L, x->stream));
+    return DNSLAB_OK;
+}
+template <typename T>
+int sca_rhs(dnslab_ctx* x, const void* c, const void* u, const void* v, const void* w, void* out) {
+    ScaArgs<T> s = {};
+    s.cs = (const T*)c;
+    s.u[0] = (const T*)u; s.u[1] = (const T*)v; s.u[2] = (const T*)w;
+    s.out = (T*)out;
+    s.flags = x->flags;
+    s.frc = forcing_of<T>(x);
+    s.alpha = x->P.alpha_c;
+    s.g = x->g;
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_RHS, s, x->Lo.L, x->stream));
+    return DNSLAB_OK;
+}
+template <typename T>
+int filt1(dnslab_ctx* x, const void* f, void* out) {
+    FiltArgs<T> a = {};
+    a.in[0] = (const T*)f;
+    a.out[0] = (T*)out;
+    a.nf = 1;
+    a.flags = x->flags;
+    a.g = x->g;
+    LAUNCH(x, K_FILT, launch_filter<T>(a, x->Lo.L, x->stream));
+    return DNSLAB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dnslab_workspace_bytes(const dnslab_params* params, size_t* out_bytes) {
+    try {
+        std::string why;
+        int rc = validate(params, why);
+        if (rc) return fail(nullptr, rc, why);
+        if (!out_bytes) return fail(nullptr, DNSLAB_EINVAL, "out_bytes is NULL");
+        *out_bytes = make_layout(params, 0).total;
+        return DNSLAB_OK;
+    } catch (...) {
+        return fail(nullptr, DNSLAB_ENOMEM, "host allocation failed");
+    }
+}
+
+int dnslab_init(const dnslab_params* params, const uint8_t* beta_dev, int64_t n_forced,
+                const int64_t* forced_idx_dev, const double* forced_S_dev, const double* forced_uset_dev,
+                const double* forced_cset_dev, const uint8_t* room_mask_dev, void* u, void* v, void* w, void* p,
+                void* c, dnslab_ctx** out) {
+    dnslab_ctx* x = nullptr;
+    try {
+        std::string why;
+        int rc = validate(params, why);
+        if (rc) return fail(nullptr, rc, why);
+        if (!out || !beta_dev || !u || !v || !w || !p || !c) return fail(nullptr, DNSLAB_EINVAL, "NULL pointer argument");
+        if (n_forced < 0 || n_forced > (1 << 30)) return fail(nullptr, DNSLAB_EINVAL, "bad n_forced");
+        if (n_forced > 0 && (!forced_idx_dev || !forced_S_dev || !forced_uset_dev || !forced_cset_dev))
+            return fail(nullptr, DNSLAB_EINVAL, "NULL forcing array");
+        *out = nullptr;
+        x = new dnslab_ctx();
+        x->P = *params;
+        x->stream = (hipStream_t)params->stream;
+        x->g = make_grid(params);
+        x->Lo = make_layout(params, (int)n_forced);
+        x->u = u; x->v = v; x->w = w; x->p = p; x->c = c;
+        x->prof_kid = K_NONE;
+        x->nforced = (int)n_forced;
+        if (hipMalloc(&x->ws, x->Lo.total) != hipSuccess) {
+            (void)hipGetLastError();
+            delete x;
+            return fail(nullptr, DNSLAB_ENOMEM, "hipMalloc of the workspace failed");
+        }
+        char* base = (char*)x->ws;
+        const Layout& Lo = x->Lo;
+        x->flags = (uint8_t*)(base + Lo.off_flags);
+        for (int i = 0; i < 13; ++i) x->f[i] = base + Lo.off_fields + (size_t)i * Lo.n * Lo.esz;
+        x->spec = base + Lo.off_spec;
+        const size_t csz = 2 * Lo.esz;
+        x->wx = base + Lo.off_tw;
+        x->wy = (char*)x->wx + (size_t)Lo.m * csz;
+        x->wz = (char*)x->wy + (size_t)params->ny * csz;
+        x->tw = (char*)x->wz + (size_t)params->nz * csz;
+        x->sx2 = (double*)(base + Lo.off_s2);
+        x->sy2 = x->sx2 + Lo.m + 1;
+        x->sz2 = x->sy2 + params->ny;
+        x->fidx = (long long*)(base + Lo.off_forced);
+        x->fS = (double*)(x->fidx + Lo.nforced_cap);
+        x->fuset = x->fS + Lo.nforced_cap;
+        x->fcset = x->fuset + 3 * (size_t)Lo.nforced_cap;
+        x->part = (Partial*)(base + Lo.off_part);
+        x->pdiv = (Partial*)(base + Lo.off_pdiv);
+        x->sc = (StepScalars*)(base + Lo.off_sc);
+        x->ring = (DiagRec*)(base + Lo.off_ring);
+        if (hipHostMalloc((void**)&x->pinned, RING_CAP * sizeof(DiagRec), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&x->pinned_sc, sizeof(StepScalars), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            dnslab_destroy(x);
+            return fail(nullptr, DNSLAB_ENOMEM, "hipHostMalloc failed");
+        }
+        std::vector<long long> fidx_h((size_t)n_forced);
+        if (n_forced > 0) {
+            if (hipMemcpy(fidx_h.data(), forced_idx_dev, n_forced * sizeof(long long), hipMemcpyDeviceToHost) != hipSuccess) {
+                dnslab_destroy(x);
+                return fail(nullptr, DNSLAB_EHIP, "reading forced indices failed");
+            }
+        }
+        rc = build_flags(x, beta_dev, fidx_h.data(), n_forced, room_mask_dev);
+        if (rc == DNSLAB_OK && n_forced > 0) {
+            if (hipMemcpy(x->fidx, forced_idx_dev, n_forced * sizeof(long long), hipMemcpyDeviceToDevice) != hipSuccess ||
+                hipMemcpy(x->fS, forced_S_dev, n_forced * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
+                hipMemcpy(x->fuset, forced_uset_dev, 3 * n_forced * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
+                hipMemcpy(x->fcset, forced_cset_dev, n_forced * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess)
+                rc = fail(x, DNSLAB_EHIP, "copying forcing arrays failed");
+        }
+        if (rc == DNSLAB_OK) rc = Lo.esz == 8 ? upload_tables<double>(x) : upload_tables<float>(x);
+        if (rc == DNSLAB_OK) {
+            StepScalars s = {};
+            s.dt_fixed = params->dt_fixed > 0 ? params->dt_fixed : 0.0;
+            s.cfl = params->cfl;
+            const double dmin = std::min(x->g.d[0], std::min(x->g.d[1], x->g.d[2]));
+            s.rate_floor = params->dt_fixed > 0 ? 0.0 : params->u_ref / dmin;
+            s.dt = s.dt_fixed;
+            if (hipMemcpy(x->sc, &s, sizeof(s), hipMemcpyHostToDevice) != hipSuccess)
+                rc = fail(x, DNSLAB_EHIP, "uploading step scalars failed");
+        }
+        if (rc == DNSLAB_OK) rc = Lo.esz == 8 ? ensure_rate<double>(x) : ensure_rate<float>(x);
+        if (rc == DNSLAB_OK && hipStreamSynchronize(x->stream) != hipSuccess) rc = fail(x, DNSLAB_EHIP, "sync failed");
+        if (rc != DNSLAB_OK) {
+            g_thread_err = x->err.empty() ? g_thread_err : x->err;
+            dnslab_destroy(x);
+            return rc;
+        }
+        *out = x;
+        return DNSLAB_OK;
+    } catch (...) {
+        if (x) dnslab_destroy(x);
+        return fail(nullptr, DNSLAB_ENOMEM, "host allocation failed");
+    }
+}
+
+int dnslab_step(dnslab_ctx* x, int32_t nsteps, dnslab_diag* diag) {
+    if (int rc = check_ctx(x)) return rc;
+    try {
+        if (nsteps < 0) return fail(x, DNSLAB_EINVAL, "nsteps < 0");
+        int rc = x->Lo.esz == 8 ? run_steps<double>(x, nsteps) : run_steps<float>(x, nsteps);
+        if (rc) return rc;
+        if (diag) {
+            if (x->host_step == 0) return fail(x, DNSLAB_ESTATE, "no step taken yet");
+            const long long slot = (x->host_step - 1) % RING_CAP;
+            HIPCHK(x, hipMemcpyAsync(x->pinned, x->ring + slot, sizeof(DiagRec), hipMemcpyDeviceToHost, x->stream));
+            HIPCHK(x, hipMemcpyAsync(x->pinned_sc, x->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, x->stream));
+            HIPCHK(x, hipStreamSynchronize(x->stream));
+            diag_copy(x->pinned[0], diag);
+            if (x->pinned_sc->nonfinite) return fail(x, DNSLAB_ENONFINITE, "non-finite diagnostics");
+        }
+        return DNSLAB_OK;
+    } catch (...) {
+        return fail(x, DNSLAB_ENOMEM, "host allocation failed");
+    }
+}
+
+int dnslab_read_diags(dnslab_ctx* x, int32_t n, dnslab_diag* out) {
+    if (int rc = check_ctx(x)) return rc;
+    if (n < 0 || n > RING_CAP || (n > 0 && !out)) return fail(x, DNSLAB_EINVAL, "bad n or out");
+    if (n > x->host_step) return fail(x, DNSLAB_ESTATE, "fewer steps taken than requested");
+    HIPCHK(x, hipMemcpyAsync(x->pinned, x->ring, RING_CAP * sizeof(DiagRec), hipMemcpyDeviceToHost, x->stream));
+    HIPCHK(x, hipStreamSynchronize(x->stream));
+    for (int i = 0; i < n; ++i) {
+        const long long st = x->host_step - n + i;   // 0-based step index
+        diag_copy(x->pinned[st % RING_CAP], out + i);
+    }
+    return DNSLAB_OK;
+}
+
+int dnslab_poisson(dnslab_ctx* x, const void* rhs, void* p) {
+    if (int rc = check_ctx(x)) return rc;
+    if (!rhs || !p) return fail(x, DNSLAB_EINVAL, "NULL pointer");
+    if (x->Lo.esz == 8) return poisson_solve<double>(x, (const double*)rhs, nullptr, nullptr, (double*)p);
+    return poisson_solve<float>(x, (const float*)rhs, nullptr, nullptr, (float*)p);
+}
+
+int dnslab_project(dnslab_ctx* x, void* u, void* v, void* w) {
+    if (int rc = check_ctx(x)) return rc;
+    if (!u || !v || !w) return fail(x, DNSLAB_EINVAL, "NULL pointer");
+    x->rate_valid = false;
+    if (x->Lo.esz == 8) {
+        double* U[3] = {(double*)u, (double*)v, (double*)w};
+        return project<double>(x, U, U);
+    }
+    float* U[3] = {(float*)u, (float*)v, (float*)w};
+    return project<float>(x, U, U);
+}
+
+int dnslab_scalar_step(dnslab_ctx* x, double dt) {
+    if (int rc = check_ctx(x)) return rc;
+    if (!std::isfinite(dt)) return fail(x, DNSLAB_EINVAL, "dt not finite");
+    if (x->Lo.esz == 8) {
+        const double* U[3] = {(double*)x->u, (double*)x->v, (double*)x->w};
+        return scalar_rk4<double>(x, U, nullptr, dt, (double*)x->c, nullptr, nullptr);
+    }
+    const float* U[3] = {(float*)x->u, (float*)x->v, (float*)x->w};
+    return scalar_rk4<float>(x, U, nullptr, dt, (float*)x->c, nullptr, nullptr);
+}
+
+
+int dnslab_momentum_rhs(dnslab_ctx* x, const void* u, const void* v, const void* w, void* fu, void* fv, void* fw) {
+    if (int rc = check_ctx(x)) return rc;
+    if (!u || !v || !w || !fu || !fv || !fw) return fail(x, DNSLAB_EINVAL, "NULL pointer");
+    return x->Lo.esz == 8 ? mom_rhs<double>(x, u, v, w, fu, fv, fw) : mom_rhs<float>(x, u, v, w, fu, fv, fw);
+}
+
+int dnslab_scalar_rhs(dnslab_ctx* x, const void* c, const void* u, const void* v, const void* w, void* out) {
+    if (int rc = check_ctx(x)) return rc;
+    if (!c || !u || !v || !w || !out) return fail(x, DNSLAB_EINVAL, "NULL pointer");
+    return x->Lo.esz == 8 ? sca_rhs<double>(x, c, u, v, w, out) : sca_rhs<float>(x, c, u, v, w, out);
+}
+
+int dnslab_filter(dnslab_ctx* x, const void* f, void* out) {
+    if (int rc = check_ctx(x)) return rc;
+    if (!f || !out || f == out) return fail(x, DNSLAB_EINVAL, "NULL or aliased pointer");
+    return x->Lo.esz == 8 ? filt1<double>(x, f, out) : filt1<float>(x, f, out);
+}
+
+int dnslab_set_time(dnslab_ctx* x, double t, int64_t step) {
+    if (int rc = check_ctx(x)) return rc;
+    if (!std::isfinite(t) || step < 0) return fail(x, DNSLAB_EINVAL, "bad t or step");
+    HIPCHK(x, hipMemcpyAsync(x->pinned_sc, x->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, x->stream));
+    HIPCHK(x, hipStreamSynchronize(x->stream));
+    StepScalars s = *x->pinned_sc;
+    s.t = t;
+    s.step = step;
+    s.nonfinite = 0;
+    *x->pinned_sc = s;
+    HIPCHK(x, hipMemcpyAsync(x->sc, x->pinned_sc, sizeof(StepScalars), hipMemcpyHostToDevice, x->stream));
+    x->host_step = step;
+    x->rate_valid = false;
+    int rc = x->Lo.esz == 8 ? ensure_rate<double>(x) : ensure_rate<float>(x);
+    if (rc) return rc;
+    HIPCHK(x, hipStreamSynchronize(x->stream));
+    return DNSLAB_OK;
+}
+
+void dnslab_destroy(dnslab_ctx* x) {
+    if (!x) return;
+    (void)hipStreamSynchronize(x->stream);
+    for (hipEvent_t e : x->ev) (void)hipEventDestroy(e);
+    if (x->ws) (void)hipFree(x->ws);
+    if (x->pinned) (void)hipHostFree(x->pinned);
+    if (x->pinned_sc) (void)hipHostFree(x->pinned_sc);
+    delete x;
+}
+
+const char* dnslab_last_error(const dnslab_ctx* x) {
+    if (x) return x->err.c_str();
+    return g_thread_err.c_str();
+}
+
+int dnslab_profile_enable(dnslab_ctx* x, const char* name) {
+    if (int rc = check_ctx(x)) return rc;
+    int kid = K_NONE;
+    if (name)
+        for (int k = 0; k < K_COUNT; ++k)
+            if (std::strcmp(name, kKernelNames[k]) == 0) kid = k;
+    if (name && kid == K_NONE) return fail(x, DNSLAB_EINVAL, "unknown kernel name");
+    int rc = prof_flush(x);
+    if (rc) return rc;
+    if (x->ev.empty() && kid != K_NONE) {
+        try {
+            x->ev.resize(PROF_POOL);
+        } catch (...) {
+            return fail(x, DNSLAB_ENOMEM, "host allocation failed");
+        }
+        for (auto& e : x->ev) HIPCHK(x, hipEventCreate(&e));
+    }
+    x->prof_kid = kid;
+    x->prof_ms = 0;
+    x->prof_n = 0;
+    return DNSLAB_OK;
+}
+
+int dnslab_profile_read(dnslab_ctx* x, double* total_ms, int64_t* launches) {
+    if (int rc = check_ctx(x)) return rc;
+    int rc = prof_flush(x);
+    if (rc) return rc;
+    if (total_ms) *total_ms = x->prof_ms;
+    if (launches) *launches = x->prof_n;
+    return DNSLAB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Internal definitions shared by the HIP translation units of libdnslab.
+// gfx950 only: 64-wide wavefronts, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace dnslab {
+
+// Per-cell flag byte (the library's own copy of the mask beta, Section 2.1).
+enum : uint8_t {
+    F_FLUID = 1,       // beta = 1
+    F_FORCED = 2,      // cell is in the sparse forcing list (S > 0)
+    F_NEAR_SOLID = 4,  // some face neighbour is solid: div((1-beta) grad p) may be nonzero here
+    F_ROOM = 8,        // inside the region of the room-mean diagnostic
+};
+
+template <typename T>
+struct alignas(2 * sizeof(T)) C2 {
+    T x, y;
+};
+
+// Grid geometry passed by value to every stencil kernel.
+struct Grid {
+    int nx, ny, nz;
+    long long nxy, n;
+    double d[3];       // spacing
+    double inv2d[3];   // 1 / (2 dx_a)
+    double inv4d[3];   // 1 / (4 dx_a)
+    double invd2[3];   // 1 / dx_a^2
+    double dv;         // cell volume
+};
+
+// Scalars of the running step, resident in device memory so that an adaptive
+// dt never needs a host round trip.
+struct StepScalars {
+    double dt;        // time step of the next step
+    double rate;      // max_cells sum_a |u_a|/dx_a of the current velocity
+    double t;         // simulated time
+    long long step;   // steps taken
+    double dt_fixed, cfl, rate_floor;
+    int nonfinite;    // sticky flag: a diagnostic was NaN/Inf
+    int pad;
+};
+
+// One diagnostics record, same layout as dnslab_diag.
+struct DiagRec {
+    double t, dt, ke, div_l2, co2_mass, co2_room_mean, cfl_max;
+    long long step;
+};
+
+// Per-block partial results of the fused reductions.
+struct Partial {
+    double ke, mass, room_num, room_den, rate;   // rate: max
+    double div2;
+    double pad[2];
+};
+
+// Sparse forcing list (Section 2.1 source term), sorted by cell index.
+struct Forcing {
+    const long long* idx;
+    const double* S;
+    const double* uset;   // 3 per entry
+    const double* cset;
+    int n;
+    double inv_tau;
+};
+
+__device__ __forceinline__ int wrap(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Index of cell `cell` in the sorted forcing list (only called for flagged cells).
+__device__ __forceinline__ int forced_entry(const Forcing& f, long long cell) {
+    int lo = 0, hi = f.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (f.idx[mid] < cell) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Wavefront (64 lanes) sum and max with a fixed reduction tree.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide deterministic reduction of a Partial (blockDim.x*y*z <= 1024).
+__device__ inline void block_reduce_partial(Partial p, Partial* out) {
+    __shared__ Partial sh[16];
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthr = blockDim.x * blockDim.y * blockDim.z;
+    const int lane = tid & 63, wid = tid >> 6;
+    p.ke = wave_sum(p.ke);
+    p.mass = wave_sum(p.mass);
+    p.room_num = wave_sum(p.room_num);
+    p.room_den = wave_sum(p.room_den);
+    p.rate = wave_max(p.rate);
+    p.div2 = wave_sum(p.div2);
+    if (lane == 0) sh[wid] = p;
+    __syncthreads();
+    if (tid == 0) {
+        Partial r = sh[0];
+        const int nw = (nthr + 63) >> 6;
+        for (int w = 1; w < nw; ++w) {
+            r.ke += sh[w].ke;
+            r.mass += sh[w].mass;
+            r.room_num += sh[w].room_num;
+            r.room_den += sh[w].room_den;
+            r.rate = fmax(r.rate, sh[w].rate);
+            r.div2 += sh[w].div2;
+        }
+        *out = r;
+    }
+}
+
+}  // namespace dnslab

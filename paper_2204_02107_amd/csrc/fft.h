@@ -1,0 +1,57 @@
+// Launch interface of the FFT Poisson kernels (fft.hip).
+#pragma once
+#include "common.h"
+
+namespace dnslab {
+
+constexpr int FFT_MAX_PASSES = 16;
+
+// Stockham plan of one complex transform length n = prod(rad): passes of
+// radix 8, 4, 2 (largest first) then 3.
+struct AxisPlan {
+    int n;
+    int npass;
+    int rad[FFT_MAX_PASSES];
+    int tpl;        // threads per line = n / rad[0] (1 if n == 1)
+};
+
+// Spectrum layout: complex, row (kx = 0..nx/2) stride sx elements, rows
+// ordered (ky, kz) with ky fastest: element (kx, ky, kz) at kx + sx*(ky + ny*kz).
+template <typename T>
+struct FFTArgs {
+    Grid g;
+    int m;              // nx/2 (complex length along x)
+    int sx;             // padded row stride of the spectrum
+    C2<T>* spec;
+    AxisPlan px, py, pz;
+    const C2<T>* wx;    // W_m^j, j < m
+    const C2<T>* wy;    // W_ny^j
+    const C2<T>* wz;    // W_nz^j
+    const C2<T>* tw;    // e^{-2 pi i k / nx}, k <= m
+    const double* sx2;  // sin^2(2 pi m / N)/dx^2 tables, exact zeros at m = 0, N/2
+    const double* sy2;
+    const double* sz2;
+    double inv_ntot;
+    // x pass
+    int nl_x;           // lines per block (power of two)
+    int ls_x;           // LDS line stride (odd, >= m + 1)
+    // y / z passes
+    int lg_tx_y, lg_tx_z;
+};
+
+// Forward x pass: r = r0 (+ div((1-beta) grad p) where flagged), R2C along x.
+// p and flags may be NULL (then r = r0).
+template <typename T>
+hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r0, const T* p, const uint8_t* flags, hipStream_t s);
+template <typename T>
+hipError_t launch_fft_y(const FFTArgs<T>& a, bool inverse, hipStream_t s);
+// z pass: forward, divide by lambda * ntot (zero on the null modes), inverse.
+template <typename T>
+hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s);
+// Inverse x pass: C2R along x into p.
+template <typename T>
+hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s);
+
+AxisPlan make_axis_plan(int n);
+
+}  // namespace dnslab

@@ -1,0 +1,101 @@
+// Launch interface of the stencil kernels (stencil.hip).
+#pragma once
+#include "common.h"
+
+namespace dnslab {
+
+// Stage modes of the classical RK4 (Section 2.1), with acc the running sum
+// u^n + dt/6 k1 + dt/3 k2 + dt/3 k3.
+enum StageMode {
+    ST_FIRST = 0,   // k1 = F(u^n); acc = u^n + dt/6 k1; out = u^n + dt/2 k1
+    ST_HALF = 1,    // k2 = F(u1);  acc += dt/3 k2;      out = u^n + dt/2 k2
+    ST_FULL = 2,    // k3 = F(u2);  acc += dt/3 k3;      out = u^n + dt k3
+    ST_LAST = 3,    // k4 = F(u3);  out = acc + dt/6 k4 (scalar: times beta)
+    ST_RHS = 4,     // out = F(in)
+};
+
+template <typename T>
+struct MomArgs {
+    const T* us[3];   // stage input (read with neighbours)
+    const T* un[3];   // u^n (ST_HALF, ST_FULL)
+    T* acc[3];
+    T* out[3];
+    const uint8_t* flags;
+    const double* dtp;   // device dt (NULL: use dt)
+    double dt;
+    Forcing frc;
+    double nu;
+    double body[3];
+    Grid g;
+    int kc;              // cells per thread along z
+};
+
+template <typename T>
+struct ScaArgs {
+    const T* cs;      // stage input (read with neighbours)
+    const T* cn;      // c^n (ST_HALF, ST_FULL)
+    T* acc;
+    T* out;
+    const T* u[3];    // frozen velocity
+    const uint8_t* flags;
+    const double* dtp;
+    double dt;
+    Forcing frc;
+    double alpha;
+    Grid g;
+    int kc;
+    Partial* part;    // ST_FIRST: div^2 partials; ST_LAST: step diagnostics partials
+};
+
+template <typename T>
+struct FiltArgs {
+    const T* in[4];
+    T* out[4];
+    int nf;
+    const uint8_t* flags;
+    Grid g;
+    int kc;
+    Partial* part;    // step diagnostics of the outputs (nf == 4), or NULL
+};
+
+template <typename T>
+struct CorrArgs {
+    const T* us[3];   // u* (pointwise; may alias out)
+    T* out[3];
+    const T* p;
+    const uint8_t* flags;
+    Grid g;
+    int kc;
+};
+
+template <typename T>
+struct DivArgs {
+    const T* u[3];
+    T* out;
+    Grid g;
+    int kc;
+};
+
+// Launch geometry shared by all z-marching stencil kernels.
+struct StencilLaunch {
+    dim3 grid, block;
+    int kc;
+    int nblocks;
+};
+StencilLaunch stencil_launch(const Grid& g, int kc);
+
+template <typename T> hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s);
+template <typename T> hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s);
+template <typename T> hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream_t s);
+template <typename T> hipError_t launch_correct(const CorrArgs<T>& a, const StencilLaunch& L, hipStream_t s);
+template <typename T> hipError_t launch_div(const DivArgs<T>& a, const StencilLaunch& L, hipStream_t s);
+template <typename T> hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g,
+                                             Partial* part, const StencilLaunch& L, hipStream_t s);
+
+// Reduce the partials of a step and advance the device step scalars.
+hipError_t launch_finish(const Partial* part, int np, const Partial* pdiv, int nd, StepScalars* sc,
+                         DiagRec* ring, int ring_cap, double dv, hipStream_t s);
+// Reduce Courant partials only: sets sc->rate and the next dt.
+hipError_t launch_set_rate(const Partial* part, int np, StepScalars* sc, hipStream_t s);
+
+}  // namespace dnslab

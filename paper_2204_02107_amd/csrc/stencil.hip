@@ -1,0 +1,523 @@
+// Stencil kernels of the projection step (Sections 2.1-2.2), z-marching.
+//
+// Every kernel maps a thread to one (i, j) column of a block tile and walks a
+// chunk of kc cells along z, keeping the z-neighbours of its column in
+// registers (a rolling window) so that each z-plane of a field is fetched from
+// memory once per chunk.  x- and y-neighbours are loaded directly; within a
+// 64-wide wavefront they are the same cache lines as the centre loads, and the
+// rows above and below are shared through L1/L2 by the block's other rows.
+// All loads and stores are coalesced along x (64 consecutive elements per
+// wavefront).
+#include "stencil.h"
+
+namespace dnslab {
+
+namespace {
+
+constexpr double INV_PI6 = 1.0 / (3.14159265358979323846 * 3.14159265358979323846 *
+                                  3.14159265358979323846 * 3.14159265358979323846 *
+                                  3.14159265358979323846 * 3.14159265358979323846);
+
+struct Col {
+    int i, j, im, ip, jm, jp;
+    unsigned row, rowm, rowp;   // j*nx, jm*nx, jp*nx
+    bool active;
+};
+
+__device__ __forceinline__ Col column(const Grid& g) {
+    Col c;
+    c.i = blockIdx.x * blockDim.x + threadIdx.x;
+    c.j = blockIdx.y * blockDim.y + threadIdx.y;
+    c.active = c.i < g.nx && c.j < g.ny;
+    if (!c.active) { c.i = 0; c.j = 0; }
+    c.im = c.i == 0 ? g.nx - 1 : c.i - 1;
+    c.ip = c.i + 1 == g.nx ? 0 : c.i + 1;
+    c.jm = c.j == 0 ? g.ny - 1 : c.j - 1;
+    c.jp = c.j + 1 == g.ny ? 0 : c.j + 1;
+    c.row = (unsigned)c.j * g.nx;
+    c.rowm = (unsigned)c.jm * g.nx;
+    c.rowp = (unsigned)c.jp * g.nx;
+    return c;
+}
+
+__device__ __forceinline__ int block_linear() {
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+// Courant rate |u|/dx + |v|/dy + |w|/dz in FP64, summed left to right without
+// contraction so that it rounds like a plain sequential evaluation.
+__device__ __forceinline__ double courant_rate(double u, double v, double w, const Grid& g) {
+#pragma clang fp contract(off)
+    double r = fabs(u) / g.d[0];
+    r = r + fabs(v) / g.d[1];
+    r = r + fabs(w) / g.d[2];
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Momentum RK4 stage.  k = beta [ -C(u) + nu L u + S (u_set - u)/tau_f + b ]
+// with the skew-symmetric convection written per axis as
+//   1/2 [D_a(u_a u_i) + u_a D_a u_i] = [(u_a+ + u_a0) u_i+ - (u_a- + u_a0) u_i-] / (4 dx_a).
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_mom_stage(const MomArgs<T> a) {
+    const Grid& g = a.g;
+    const Col col = column(g);
+    if (!col.active) return;
+    const int k0 = blockIdx.z * a.kc;
+    const int k1 = min(k0 + a.kc, g.nz);
+    const unsigned nxy = (unsigned)g.nxy;
+    const T dt = (MODE == ST_RHS) ? T(0) : T(a.dtp ? *a.dtp : a.dt);
+    const T q4x = T(g.inv4d[0]), q4y = T(g.inv4d[1]), q4z = T(g.inv4d[2]);
+    const T ix2 = T(g.invd2[0]), iy2 = T(g.invd2[1]), iz2 = T(g.invd2[2]);
+    const T nu = T(a.nu);
+    const T bx = T(a.body[0]), by = T(a.body[1]), bz = T(a.body[2]);
+    const T* __restrict__ u0p = a.us[0];
+    const T* __restrict__ u1p = a.us[1];
+    const T* __restrict__ u2p = a.us[2];
+
+    T zm[3], z0[3], zp[3];
+    {
+        const int km = k0 == 0 ? g.nz - 1 : k0 - 1;
+        const unsigned im_ = (unsigned)km * nxy + col.row + col.i;
+        const unsigned i0_ = (unsigned)k0 * nxy + col.row + col.i;
+        zm[0] = u0p[im_]; zm[1] = u1p[im_]; zm[2] = u2p[im_];
+        z0[0] = u0p[i0_]; z0[1] = u1p[i0_]; z0[2] = u2p[i0_];
+    }
+    for (int k = k0; k < k1; ++k) {
+        const int kp = k + 1 == g.nz ? 0 : k + 1;
+        const unsigned base = (unsigned)k * nxy;
+        const unsigned idx = base + col.row + col.i;
+        const unsigned ipz = (unsigned)kp * nxy + col.row + col.i;
+        zp[0] = u0p[ipz]; zp[1] = u1p[ipz]; zp[2] = u2p[ipz];
+        T xm[3], xp[3], ym[3], yp[3];
+        const unsigned ixm = base + col.row + col.im, ixp = base + col.row + col.ip;
+        const unsigned iym = base + col.rowm + col.i, iyp = base + col.rowp + col.i;
+        xm[0] = u0p[ixm]; xm[1] = u1p[ixm]; xm[2] = u2p[ixm];
+        xp[0] = u0p[ixp]; xp[1] = u1p[ixp]; xp[2] = u2p[ixp];
+        ym[0] = u0p[iym]; ym[1] = u1p[iym]; ym[2] = u2p[iym];
+        yp[0] = u0p[iyp]; yp[1] = u1p[iyp]; yp[2] = u2p[iyp];
+        const uint8_t fl = a.flags[idx];
+
+        T kv[3];
+        const T ax_p = xp[0] + z0[0], ax_m = xm[0] + z0[0];
+        const T ay_p = yp[1] + z0[1], ay_m = ym[1] + z0[1];
+        const T az_p = zp[2] + z0[2], az_m = zm[2] + z0[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T C = (ax_p * xp[c] - ax_m * xm[c]) * q4x + (ay_p * yp[c] - ay_m * ym[c]) * q4y +
+                        (az_p * zp[c] - az_m * zm[c]) * q4z;
+            const T L = (xp[c] - T(2) * z0[c] + xm[c]) * ix2 + (yp[c] - T(2) * z0[c] + ym[c]) * iy2 +
+                        (zp[c] - T(2) * z0[c] + zm[c]) * iz2;
+            const T b = c == 0 ? bx : (c == 1 ? by : bz);
+            kv[c] = -C + nu * L + b;
+        }
+        if (fl & F_FORCED) {
+            const int e = forced_entry(a.frc, (long long)idx);
+            const T S = T(a.frc.S[e]) * T(a.frc.inv_tau);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) kv[c] += S * (T(a.frc.uset[3 * e + c]) - z0[c]);
+        }
+        if (!(fl & F_FLUID)) { kv[0] = T(0); kv[1] = T(0); kv[2] = T(0); }
+
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (MODE == ST_FIRST) {
+                a.acc[c][idx] = z0[c] + (dt / T(6)) * kv[c];
+                a.out[c][idx] = z0[c] + (dt / T(2)) * kv[c];
+            } else if (MODE == ST_HALF || MODE == ST_FULL) {
+                const T un = a.un[c][idx];
+                a.acc[c][idx] = a.acc[c][idx] + (dt / T(3)) * kv[c];
+                a.out[c][idx] = un + (MODE == ST_HALF ? dt / T(2) : dt) * kv[c];
+            } else if (MODE == ST_LAST) {
+                a.out[c][idx] = a.acc[c][idx] + (dt / T(6)) * kv[c];
+            } else {
+                a.out[c][idx] = kv[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { zm[c] = z0[c]; z0[c] = zp[c]; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scalar RK4 stage.  G = beta [ -sum_a D_a(u_a c) + alpha div(beta grad c)
+//                              + S (c_set - c)/tau_f ],
+// the masked diffusion conducting only across fluid-fluid faces.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_sca_stage(const ScaArgs<T> a) {
+    const Grid& g = a.g;
+    const Col col = column(g);
+    const int k0 = blockIdx.z * a.kc;
+    const int k1 = min(k0 + a.kc, g.nz);
+    const unsigned nxy = (unsigned)g.nxy;
+    const T dt = (MODE == ST_RHS) ? T(0) : T(a.dtp ? *a.dtp : a.dt);
+    const T h2x = T(g.inv2d[0]), h2y = T(g.inv2d[1]), h2z = T(g.inv2d[2]);
+    const T ix2 = T(g.invd2[0]), iy2 = T(g.invd2[1]), iz2 = T(g.invd2[2]);
+    const T alpha = T(a.alpha);
+    const T* __restrict__ cs = a.cs;
+    const T* __restrict__ ux = a.u[0];
+    const T* __restrict__ uy = a.u[1];
+    const T* __restrict__ uz = a.u[2];
+    Partial part = {0, 0, 0, 0, 0, 0, {0, 0}};
+
+    if (col.active) {
+        T cm, c0, cp, wm, w0, wp;
+        uint8_t fm, f0, fp;
+        {
+            const int km = k0 == 0 ? g.nz - 1 : k0 - 1;
+            const unsigned im_ = (unsigned)km * nxy + col.row + col.i;
+            const unsigned i0_ = (unsigned)k0 * nxy + col.row + col.i;
+            cm = cs[im_]; c0 = cs[i0_];
+            wm = uz[im_]; w0 = uz[i0_];
+            fm = a.flags[im_]; f0 = a.flags[i0_];
+        }
+        for (int k = k0; k < k1; ++k) {
+            const int kp = k + 1 == g.nz ? 0 : k + 1;
+            const unsigned base = (unsigned)k * nxy;
+            const unsigned idx = base + col.row + col.i;
+            const unsigned ipz = (unsigned)kp * nxy + col.row + col.i;
+            cp = cs[ipz]; wp = uz[ipz]; fp = a.flags[ipz];
+            const unsigned ixm = base + col.row + col.im, ixp = base + col.row + col.ip;
+            const unsigned iym = base + col.rowm + col.i, iyp = base + col.rowp + col.i;
+            const T cxm = cs[ixm], cxp = cs[ixp], cym = cs[iym], cyp = cs[iyp];
+            const T uxm = ux[ixm], uxp = ux[ixp], vym = uy[iym], vyp = uy[iyp];
+            const uint8_t fxm = a.flags[ixm], fxp = a.flags[ixp], fym = a.flags[iym], fyp = a.flags[iyp];
+
+            T G = T(0);
+            if (f0 & F_FLUID) {
+                const T conv = (uxp * cxp - uxm * cxm) * h2x + (vyp * cyp - vym * cym) * h2y +
+                               (wp * cp - wm * cm) * h2z;
+                const T lx = ((fxp & F_FLUID) ? cxp - c0 : T(0)) - ((fxm & F_FLUID) ? c0 - cxm : T(0));
+                const T ly = ((fyp & F_FLUID) ? cyp - c0 : T(0)) - ((fym & F_FLUID) ? c0 - cym : T(0));
+                const T lz = ((fp & F_FLUID) ? cp - c0 : T(0)) - ((fm & F_FLUID) ? c0 - cm : T(0));
+                G = -conv + alpha * (lx * ix2 + ly * iy2 + lz * iz2);
+                if (f0 & F_FORCED) {
+                    const int e = forced_entry(a.frc, (long long)idx);
+                    G += T(a.frc.S[e]) * T(a.frc.inv_tau) * (T(a.frc.cset[e]) - c0);
+                }
+            }
+            if (MODE == ST_FIRST) {
+                a.acc[idx] = c0 + (dt / T(6)) * G;
+                a.out[idx] = c0 + (dt / T(2)) * G;
+                if (a.part) {
+                    const double dv = (double)((uxp - uxm) * h2x + (vyp - vym) * h2y + (wp - wm) * h2z);
+                    part.div2 += dv * dv;
+                }
+            } else if (MODE == ST_HALF || MODE == ST_FULL) {
+                const T cn = a.cn[idx];
+                a.acc[idx] = a.acc[idx] + (dt / T(3)) * G;
+                a.out[idx] = cn + (MODE == ST_HALF ? dt / T(2) : dt) * G;
+            } else if (MODE == ST_LAST) {
+                const T cnew = (f0 & F_FLUID) ? a.acc[idx] + (dt / T(6)) * G : T(0);
+                a.out[idx] = cnew;
+                if (a.part) {
+                    const double u = (double)ux[idx], v = (double)uy[idx], w = (double)w0;
+                    const double b = (f0 & F_FLUID) ? 1.0 : 0.0;
+                    part.ke += b * (u * u + v * v + w * w);
+                    part.mass += b * (double)cnew;
+                    if (f0 & F_ROOM) { part.room_num += b * (double)cnew; part.room_den += b; }
+                    part.rate = fmax(part.rate, courant_rate(u, v, w, g));
+                }
+            } else {
+                a.out[idx] = G;
+            }
+            cm = c0; c0 = cp; wm = w0; w0 = wp; fm = f0; f0 = fp;
+        }
+    }
+    if ((MODE == ST_FIRST || MODE == ST_LAST) && a.part) block_reduce_partial(part, a.part + block_linear());
+}
+
+// ---------------------------------------------------------------------------
+// Sixth-order filter of Section 2.1 with the undivided seven-point difference:
+// out = beta (f + pi^-6 sum_a delta6_a f).
+// ---------------------------------------------------------------------------
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void k_filter(const FiltArgs<T> a) {
+    const Grid& g = a.g;
+    const Col col = column(g);
+    const int k0 = blockIdx.z * a.kc;
+    const int k1 = min(k0 + a.kc, g.nz);
+    const unsigned nxy = (unsigned)g.nxy;
+    const T c6 = T(INV_PI6);
+    Partial part = {0, 0, 0, 0, 0, 0, {0, 0}};
+    if (col.active) {
+        int ix[7], jy[7];
+#pragma unroll
+        for (int m = -3; m <= 3; ++m) {
+            ix[m + 3] = wrap(col.i + m, g.nx);
+            jy[m + 3] = wrap(col.j + m, g.ny) * g.nx;
+        }
+        T win[NF][7];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                const int kk = wrap(k0 - 3 + m, g.nz);
+                win[f][m] = a.in[f][(unsigned)kk * nxy + col.row + col.i];
+            }
+        for (int k = k0; k < k1; ++k) {
+            const unsigned base = (unsigned)k * nxy;
+            const unsigned idx = base + col.row + col.i;
+            const int kk = wrap(k + 3, g.nz);
+            const uint8_t fl = a.flags[idx];
+            T res[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const T* __restrict__ src = a.in[f];
+                win[f][6] = src[(unsigned)kk * nxy + col.row + col.i];
+                const T f0 = win[f][3];
+                const T* rowp = src + base + col.row;
+                const T dx6 = (rowp[ix[0]] + rowp[ix[6]]) - T(6) * (rowp[ix[1]] + rowp[ix[5]]) +
+                              T(15) * (rowp[ix[2]] + rowp[ix[4]]) - T(20) * f0;
+                const T* colp = src + base + col.i;
+                const T dy6 = (colp[jy[0]] + colp[jy[6]]) - T(6) * (colp[jy[1]] + colp[jy[5]]) +
+                              T(15) * (colp[jy[2]] + colp[jy[4]]) - T(20) * f0;
+                const T dz6 = (win[f][0] + win[f][6]) - T(6) * (win[f][1] + win[f][5]) +
+                              T(15) * (win[f][2] + win[f][4]) - T(20) * f0;
+                res[f] = (fl & F_FLUID) ? f0 + c6 * (dx6 + dy6 + dz6) : T(0);
+                a.out[f][idx] = res[f];
+#pragma unroll
+                for (int m = 0; m < 6; ++m) win[f][m] = win[f][m + 1];
+            }
+            if (NF == 4 && a.part) {
+                const double u = (double)res[0], v = (double)res[1], w = (double)res[2];
+                const double c = (double)res[NF - 1];
+                const double b = (fl & F_FLUID) ? 1.0 : 0.0;
+                part.ke += b * (u * u + v * v + w * w);
+                part.mass += b * c;
+                if (fl & F_ROOM) { part.room_num += b * c; part.room_den += b; }
+                part.rate = fmax(part.rate, courant_rate(u, v, w, g));
+            }
+        }
+    }
+    if (NF == 4 && a.part) block_reduce_partial(part, a.part + block_linear());
+}
+
+// ---------------------------------------------------------------------------
+// Velocity correction of Section 2.2 with the mask: out = beta (u* - grad p).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_correct(const CorrArgs<T> a) {
+    const Grid& g = a.g;
+    const Col col = column(g);
+    if (!col.active) return;
+    const int k0 = blockIdx.z * a.kc;
+    const int k1 = min(k0 + a.kc, g.nz);
+    const unsigned nxy = (unsigned)g.nxy;
+    const T hx = T(g.inv2d[0]), hy = T(g.inv2d[1]), hz = T(g.inv2d[2]);
+    const T* __restrict__ p = a.p;
+    T pm = p[(unsigned)(k0 == 0 ? g.nz - 1 : k0 - 1) * nxy + col.row + col.i];
+    T p0 = p[(unsigned)k0 * nxy + col.row + col.i];
+    for (int k = k0; k < k1; ++k) {
+        const int kp = k + 1 == g.nz ? 0 : k + 1;
+        const unsigned base = (unsigned)k * nxy;
+        const unsigned idx = base + col.row + col.i;
+        const T pp = p[(unsigned)kp * nxy + col.row + col.i];
+        const T gx = (p[base + col.row + col.ip] - p[base + col.row + col.im]) * hx;
+        const T gy = (p[base + col.rowp + col.i] - p[base + col.rowm + col.i]) * hy;
+        const T gz = (pp - pm) * hz;
+        const bool fluid = a.flags[idx] & F_FLUID;
+        const T u = a.us[0][idx], v = a.us[1][idx], w = a.us[2][idx];
+        a.out[0][idx] = fluid ? u - gx : T(0);
+        a.out[1][idx] = fluid ? v - gy : T(0);
+        a.out[2][idx] = fluid ? w - gz : T(0);
+        pm = p0; p0 = pp;
+    }
+}
+
+// Divergence with central differences: out = sum_a D_a u_a (Section 2.2).
+template <typename T>
+__global__ __launch_bounds__(256) void k_div(const DivArgs<T> a) {
+    const Grid& g = a.g;
+    const Col col = column(g);
+    if (!col.active) return;
+    const int k0 = blockIdx.z * a.kc;
+    const int k1 = min(k0 + a.kc, g.nz);
+    const unsigned nxy = (unsigned)g.nxy;
+    const T hx = T(g.inv2d[0]), hy = T(g.inv2d[1]), hz = T(g.inv2d[2]);
+    const T* __restrict__ w = a.u[2];
+    T wm = w[(unsigned)(k0 == 0 ? g.nz - 1 : k0 - 1) * nxy + col.row + col.i];
+    T w0 = w[(unsigned)k0 * nxy + col.row + col.i];
+    for (int k = k0; k < k1; ++k) {
+        const int kp = k + 1 == g.nz ? 0 : k + 1;
+        const unsigned base = (unsigned)k * nxy;
+        const unsigned idx = base + col.row + col.i;
+        const T wp = w[(unsigned)kp * nxy + col.row + col.i];
+        const T dx = (a.u[0][base + col.row + col.ip] - a.u[0][base + col.row + col.im]) * hx;
+        const T dy = (a.u[1][base + col.rowp + col.i] - a.u[1][base + col.rowm + col.i]) * hy;
+        a.out[idx] = dx + dy + (wp - wm) * hz;
+        wm = w0; w0 = wp;
+    }
+}
+
+// Courant rate partials (max over cells), for the first step after (re)binding.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rate(const T* u, const T* v, const T* w, const Grid g, int kc,
+                                              Partial* part) {
+    const Col col = column(g);
+    const int k0 = blockIdx.z * kc;
+    const int k1 = min(k0 + kc, g.nz);
+    Partial pp = {0, 0, 0, 0, 0, 0, {0, 0}};
+    if (col.active) {
+        for (int k = k0; k < k1; ++k) {
+            const unsigned idx = (unsigned)k * (unsigned)g.nxy + col.row + col.i;
+            pp.rate = fmax(pp.rate, courant_rate((double)u[idx], (double)v[idx], (double)w[idx], g));
+        }
+    }
+    block_reduce_partial(pp, part + block_linear());
+}
+
+__device__ inline double next_dt(const StepScalars& s, double rate) {
+    return s.dt_fixed > 0 ? s.dt_fixed : s.cfl / fmax(rate, s.rate_floor);
+}
+
+// One block: reduce the partials in a fixed order, write the diagnostics of
+// the step just taken, and advance t, the step count and dt.
+__global__ __launch_bounds__(256) void k_finish(const Partial* part, int np, const Partial* pdiv, int nd,
+                                                StepScalars* sc, DiagRec* ring, int ring_cap, double dv) {
+    Partial acc = {0, 0, 0, 0, 0, 0, {0, 0}};
+    for (int b = threadIdx.x; b < np; b += blockDim.x) {
+        const Partial q = part[b];
+        acc.ke += q.ke; acc.mass += q.mass; acc.room_num += q.room_num; acc.room_den += q.room_den;
+        acc.rate = fmax(acc.rate, q.rate);
+    }
+    for (int b = threadIdx.x; b < nd; b += blockDim.x) acc.div2 += pdiv[b].div2;
+    __shared__ Partial res;
+    block_reduce_partial(acc, &res);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        StepScalars s = *sc;
+        DiagRec d;
+        d.dt = s.dt;
+        d.t = s.t + s.dt;
+        d.ke = 0.5 * res.ke * dv;
+        d.div_l2 = sqrt(res.div2 * dv);
+        d.co2_mass = res.mass * dv;
+        d.co2_room_mean = res.room_den > 0 ? res.room_num / res.room_den : 0.0;
+        d.cfl_max = s.dt * s.rate;
+        d.step = s.step + 1;
+        const bool bad = !isfinite(d.ke) || !isfinite(d.co2_mass) || !isfinite(d.div_l2) || !isfinite(res.rate);
+        s.nonfinite = s.nonfinite | (bad ? 1 : 0);
+        s.t = d.t;
+        s.step = d.step;
+        s.rate = res.rate;
+        s.dt = next_dt(s, res.rate);
+        *sc = s;
+        ring[(d.step - 1) % ring_cap] = d;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_set_rate(const Partial* part, int np, StepScalars* sc) {
+    Partial acc = {0, 0, 0, 0, 0, 0, {0, 0}};
+    for (int b = threadIdx.x; b < np; b += blockDim.x) acc.rate = fmax(acc.rate, part[b].rate);
+    __shared__ Partial res;
+    block_reduce_partial(acc, &res);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        StepScalars s = *sc;
+        s.rate = res.rate;
+        s.dt = next_dt(s, res.rate);
+        if (!isfinite(res.rate)) s.nonfinite = 1;
+        *sc = s;
+    }
+}
+
+}  // namespace
+
+StencilLaunch stencil_launch(const Grid& g, int kc) {
+    StencilLaunch L;
+    int bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
+    int by = 256 / bx;
+    L.block = dim3(bx, by, 1);
+    L.kc = kc < 1 ? 1 : kc;
+    L.grid = dim3((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, (g.nz + L.kc - 1) / L.kc);
+    L.nblocks = (int)(L.grid.x * L.grid.y * L.grid.z);
+    return L;
+}
+
+template <typename T>
+hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+    MomArgs<T> b = a;
+    b.kc = L.kc;
+    switch (mode) {
+        case ST_FIRST: hipLaunchKernelGGL((k_mom_stage<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
+        case ST_HALF: hipLaunchKernelGGL((k_mom_stage<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
+        case ST_FULL: hipLaunchKernelGGL((k_mom_stage<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
+        case ST_LAST: hipLaunchKernelGGL((k_mom_stage<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
+        default: hipLaunchKernelGGL((k_mom_stage<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+    ScaArgs<T> b = a;
+    b.kc = L.kc;
+    switch (mode) {
+        case ST_FIRST: hipLaunchKernelGGL((k_sca_stage<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
+        case ST_HALF: hipLaunchKernelGGL((k_sca_stage<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
+        case ST_FULL: hipLaunchKernelGGL((k_sca_stage<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
+        case ST_LAST: hipLaunchKernelGGL((k_sca_stage<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
+        default: hipLaunchKernelGGL((k_sca_stage<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+    FiltArgs<T> b = a;
+    b.kc = L.kc;
+    if (a.nf == 4) hipLaunchKernelGGL((k_filter<T, 4>), L.grid, L.block, 0, s, b);
+    else hipLaunchKernelGGL((k_filter<T, 1>), L.grid, L.block, 0, s, b);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_correct(const CorrArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+    CorrArgs<T> b = a;
+    b.kc = L.kc;
+    hipLaunchKernelGGL((k_correct<T>), L.grid, L.block, 0, s, b);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_div(const DivArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+    DivArgs<T> b = a;
+    b.kc = L.kc;
+    hipLaunchKernelGGL((k_div<T>), L.grid, L.block, 0, s, b);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g, Partial* part,
+                       const StencilLaunch& L, hipStream_t s) {
+    hipLaunchKernelGGL((k_rate<T>), L.grid, L.block, 0, s, u, v, w, g, L.kc, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const Partial* part, int np, const Partial* pdiv, int nd, StepScalars* sc,
+                         DiagRec* ring, int ring_cap, double dv, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, part, np, pdiv, nd, sc, ring, ring_cap, dv);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_rate(const Partial* part, int np, StepScalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_rate, dim3(1), dim3(256), 0, s, part, np, sc);
+    return hipGetLastError();
+}
+
+#define DNSLAB_INST(T)                                                                                  \
+    template hipError_t launch_mom_stage<T>(int, const MomArgs<T>&, const StencilLaunch&, hipStream_t); \
+    template hipError_t launch_sca_stage<T>(int, const ScaArgs<T>&, const StencilLaunch&, hipStream_t); \
+    template hipError_t launch_filter<T>(const FiltArgs<T>&, const StencilLaunch&, hipStream_t);        \
+    template hipError_t launch_correct<T>(const CorrArgs<T>&, const StencilLaunch&, hipStream_t);       \
+    template hipError_t launch_div<T>(const DivArgs<T>&, const StencilLaunch&, hipStream_t);            \
+    template hipError_t launch_rate<T>(const T*, const T*, const T*, const Grid&, Partial*,             \
+                                       const StencilLaunch&, hipStream_t);
+DNSLAB_INST(double)
+DNSLAB_INST(float)
+#undef DNSLAB_INST
+
+}  // namespace dnslab

@@ -1,0 +1,77 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared
+symbol, and validates parameters on the host without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import scenarios
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2204_02107_amd", "libdnslab.so")
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "dnslab.h")).read()
+    return sorted(set(re.findall(r"\b(dnslab_[a-z_]+)\s*\(", text)))
+
+
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libdnslab.so not built")
+
+
+@needs_lib
+def test_every_header_symbol_is_exported():
+    import paper_2204_02107_amd as m
+    from paper_2204_02107_amd._lib import EXPORTS
+    lib = m.load()
+    syms = header_symbols()
+    assert syms == sorted(EXPORTS)
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+@needs_lib
+def test_workspace_bytes_and_validation():
+    import paper_2204_02107_amd as m
+    from paper_2204_02107_amd._lib import DnslabError
+    sc = scenarios.room(64, 32, 24, dx=0.05, n_boxes=1)
+    b64 = m.workspace_bytes(sc, m.FP64)
+    b32 = m.workspace_bytes(sc, m.FP32_REFINE)
+    n = sc.ncells
+    assert b64 > 13 * 8 * n and b32 > 13 * 4 * n and b32 < b64
+    bad = sc.copy()
+    bad.nx = 40          # 40 = 2^3 * 5 is not a supported FFT length
+    with pytest.raises(DnslabError) as e:
+        m.workspace_bytes(bad)
+    assert e.value.code == -3
+    bad = sc.copy()
+    bad.tau_f = 0.0
+    with pytest.raises(DnslabError) as e:
+        m.workspace_bytes(bad)
+    assert e.value.code == -1
+    bad = sc.copy()
+    bad.nx = 6
+    bad.ny = 1
+    bad.nz = 1
+    assert m.workspace_bytes(bad) > 0
+
+
+@needs_lib
+def test_null_context_is_rejected_without_gpu():
+    import paper_2204_02107_amd as m
+    lib = m.load()
+    assert lib.dnslab_step(None, 1, None) == -1
+    assert lib.dnslab_poisson(None, None, None) == -1
+    assert b"NULL" in lib.dnslab_last_error(None)
+    lib.dnslab_destroy(None)
+
+
+def test_header_documents_every_entry_point():
+    text = open(os.path.join(ROOT, "include", "dnslab.h")).read()
+    for s in header_symbols():
+        m = re.search(r"\n(int|void|const char\*)\s+" + s + r"\(", text)
+        assert m, s
+        before = text[:m.start()].rstrip()
+        # each declaration follows a comment, or shares one with the entry point above it
+        assert before.endswith("*/") or before.endswith(");"), s
