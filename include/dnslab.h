@@ -67,7 +67,8 @@ typedef struct dnslab_pool dnslab_pool;   /* opaque */
 /* Case parameters (the paper's case-setup script, Section 2.4). */
 typedef struct {
     int32_t nx, ny, nz;     /* cells; nx = 2^a 3^b with a >= 1 and nx >= 4; ny, nz = 1 or
-                               2^a 3^b >= 2; each at most 4096 (nx) / 2048 (ny, nz) */
+                               2^a 3^b >= 2; nx <= 2048 and ny, nz <= 1024 in FP64
+                               (4096 and 2048 in FP32); fewer than 2^31 cells */
     double lx, ly, lz;      /* periodic box lengths [m]; dx = lx/nx etc. */
     double nu;              /* kinematic viscosity [m^2/s] */
     double alpha_c;         /* scalar diffusivity [m^2/s] */
@@ -95,7 +96,9 @@ typedef struct {
 } dnslab_diag;
 
 /* Bytes of device workspace a context with these parameters allocates (for
- * HBM-budget admission).  Host-only; enqueues nothing. */
+ * HBM-budget admission), not counting the list of cells next to a solid that
+ * dnslab_init builds from the mask (at most 13 bytes per such cell).
+ * Host-only; enqueues nothing. */
 int dnslab_workspace_bytes(const dnslab_params* params, size_t* out_bytes);
 
 /* Create a context bound to caller-owned state buffers u, v, w, p, c (device,
@@ -164,7 +167,7 @@ const char* dnslab_last_error(const dnslab_ctx* ctx);
 
 /* Kernel timing for roofline measurements: when enabled, every launch of the
  * named kernel ("mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
- * "fft_x_inv", "filter", "correct", "div") is bracketed by HIP events on the
+ * "fft_x_inv", "filter", "correct", "div", "ib_rhs", "finish") is bracketed by HIP events on the
  * context's stream, and the total and count accumulate.  Read synchronises. */
 int dnslab_profile_enable(dnslab_ctx* ctx, const char* kernel_name);
 int dnslab_profile_read(dnslab_ctx* ctx, double* total_ms, int64_t* launches);

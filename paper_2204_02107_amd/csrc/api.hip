@@ -25,9 +25,9 @@ thread_local std::string g_thread_err;
 constexpr int RING_CAP = 4096;
 constexpr int PROF_POOL = 32768;
 
-enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_CORR, K_DIV, K_COUNT };
+enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_CORR, K_DIV, K_IB, K_FIN, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {"mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
-                                            "fft_x_inv", "filter", "correct", "div"};
+                                            "fft_x_inv", "filter", "correct", "div", "ib_rhs", "finish"};
 
 bool is_2a3b(int n) {
     if (n < 1) return false;
@@ -53,7 +53,10 @@ struct Layout {
     int m, sx;            // fft
     int nl_x, ls_x, lg_tx_y, lg_tx_z;
     AxisPlan px, py, pz;
-    StencilLaunch L;
+    StencilLaunch L;       // momentum and scalar stage kernels
+    StencilLaunch L1;      // one-cell-per-thread kernels (correct, div, rate)
+    StencilLaunch LF;      // filter
+    int nparts;            // partial-result slots (max block count of the reducing kernels)
     // byte offsets inside the workspace
     size_t off_flags, off_fields, off_spec, off_tw, off_s2, off_forced, off_part, off_pdiv, off_sc, off_ring;
     size_t total;
@@ -63,12 +66,16 @@ struct Layout {
 int validate(const dnslab_params* P, std::string& why) {
     if (!P) { why = "params is NULL"; return DNSLAB_EINVAL; }
     if (P->precision != DNSLAB_FP64 && P->precision != DNSLAB_FP32_REFINE) { why = "bad precision"; return DNSLAB_EINVAL; }
-    if (P->nx < 4 || P->nx % 2 != 0 || !is_2a3b(P->nx) || P->nx > 4096) {
-        why = "nx must be even, 2^a 3^b, 4 <= nx <= 4096";
+    // FFT lines are staged whole in LDS: lengths up to 2048 (FP64) / 4096 (FP32)
+    // along x and 1024 / 2048 along y and z.
+    const int fp64 = P->precision == DNSLAB_FP64;
+    const int maxx = fp64 ? 2048 : 4096, maxyz = fp64 ? 1024 : 2048;
+    if (P->nx < 4 || P->nx % 2 != 0 || !is_2a3b(P->nx) || P->nx > maxx) {
+        why = "nx must be even, 2^a 3^b, 4 <= nx <= 2048 (FP64) / 4096 (FP32)";
         return DNSLAB_EUNSUPPORTED;
     }
     for (int n : {P->ny, P->nz})
-        if (!is_2a3b(n) || n > 2048) { why = "ny, nz must be 1 or 2^a 3^b <= 2048"; return DNSLAB_EUNSUPPORTED; }
+        if (!is_2a3b(n) || n > maxyz) { why = "ny, nz must be 1 or 2^a 3^b <= 1024 (FP64) / 2048 (FP32)"; return DNSLAB_EUNSUPPORTED; }
     const long long n = (long long)P->nx * P->ny * P->nz;
     if (n >= (1LL << 31)) { why = "grid too large (>= 2^31 cells)"; return DNSLAB_EUNSUPPORTED; }
     if (!(P->lx > 0 && P->ly > 0 && P->lz > 0)) { why = "box lengths must be positive"; return DNSLAB_EINVAL; }
@@ -100,10 +107,24 @@ Grid make_grid(const dnslab_params* P) {
     return g;
 }
 
-int stencil_kc(const Grid& g) {
-    const StencilLaunch one = stencil_launch(g, g.nz);
+#ifndef DNSLAB_ROWS
+#define DNSLAB_ROWS 4          // block height of the radius-1 stencil kernels
+#endif
+#ifndef DNSLAB_KC
+#define DNSLAB_KC 0            // z cells per thread (0: from the grid size)
+#endif
+#ifndef DNSLAB_FROWS
+#define DNSLAB_FROWS 4         // block height of the radius-3 filter
+#endif
+#ifndef DNSLAB_FKC
+#define DNSLAB_FKC 0
+#endif
+
+// z chunk: enough blocks to fill the chip, each walking at least 4 planes.
+int stencil_kc(const Grid& g, int rows, int forced) {
+    if (forced > 0) return std::min(forced, g.nz);
+    const StencilLaunch one = stencil_launch(g, rows, g.nz, 1);
     const long long cols = (long long)one.grid.x * one.grid.y;
-    // aim for at least ~4096 blocks, each walking at least 4 planes
     long long kc = (long long)g.nz * cols / 4096;
     kc = std::max(4LL, std::min(32LL, kc));
     return (int)std::min<long long>(kc, g.nz);
@@ -124,7 +145,9 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     const long long nlines = (long long)P->ny * P->nz;
     {
         int nl = 1;
-        while (nl * 2 * Lo.px.tpl <= 256 && (size_t)nl * 2 * Lo.ls_x * csz <= 48 * 1024 && nl < nlines) nl *= 2;
+        while (nl * 2 * Lo.px.tpl <= 256 && ((size_t)nl * 2 * Lo.ls_x + 2 * Lo.m + 1) * csz <= 48 * 1024 &&
+               nl < nlines)
+            nl *= 2;
         Lo.nl_x = ilog2(nl);
     }
     auto pick_tx = [&](int n, const AxisPlan& ap) {
@@ -135,7 +158,10 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     };
     Lo.lg_tx_y = pick_tx(P->ny, Lo.py);
     Lo.lg_tx_z = pick_tx(P->nz, Lo.pz);
-    Lo.L = stencil_launch(g, stencil_kc(g));
+    Lo.L = stencil_launch(g, DNSLAB_ROWS, stencil_kc(g, DNSLAB_ROWS, DNSLAB_KC), 1);
+    Lo.L1 = Lo.L;
+    Lo.LF = stencil_launch(g, DNSLAB_FROWS, stencil_kc(g, DNSLAB_FROWS, DNSLAB_FKC), 1);
+    Lo.nparts = std::max(std::max(Lo.L.nblocks, Lo.L1.nblocks), Lo.LF.nblocks);
     // workspace layout
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
@@ -146,8 +172,8 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     Lo.off_s2 = take((size_t)(Lo.m + 1 + P->ny + P->nz) * sizeof(double));
     Lo.nforced_cap = std::max(1, n_forced);
     Lo.off_forced = take((size_t)Lo.nforced_cap * (sizeof(long long) + 5 * sizeof(double)));
-    Lo.off_part = take((size_t)Lo.L.nblocks * sizeof(Partial));
-    Lo.off_pdiv = take((size_t)Lo.L.nblocks * sizeof(Partial));
+    Lo.off_part = take((size_t)Lo.nparts * sizeof(Partial));
+    Lo.off_pdiv = take((size_t)Lo.nparts * sizeof(Partial));
     Lo.off_sc = take(sizeof(StepScalars));
     Lo.off_ring = take((size_t)RING_CAP * sizeof(DiagRec));
     Lo.total = off;
@@ -196,6 +222,9 @@ struct dnslab_ctx {
     StepScalars* sc;
     DiagRec* ring;
     bool any_solid;
+    void* ib_buf;          // near-solid list: idx (int), mask (uint8), saved r0 (field type)
+    IBList ib;
+    void* ib_r0;
     bool rate_valid;
     long long host_step;
     DiagRec* pinned;       // host staging for diagnostics
@@ -303,11 +332,11 @@ FFTArgs<T> fft_args(dnslab_ctx* x) {
     return a;
 }
 
-// One FFT solve: spectrum of r0 (+ IB term from p when flags != NULL), divide, back into pout.
+// One FFT solve of Lap p = r (central-difference symbol, null modes zero).
 template <typename T>
-int poisson_solve(dnslab_ctx* x, const T* r0, const T* pin, const uint8_t* flags, T* pout) {
+int poisson_solve(dnslab_ctx* x, const T* r, T* pout) {
     const FFTArgs<T> a = fft_args<T>(x);
-    LAUNCH(x, K_FXF, launch_fft_x_fwd<T>(a, r0, pin, flags, x->stream));
+    LAUNCH(x, K_FXF, launch_fft_x_fwd<T>(a, r, x->stream));
     if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, false, x->stream));
     LAUNCH(x, K_FZ, launch_fft_z_solve<T>(a, x->stream));
     if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, true, x->stream));
@@ -324,10 +353,12 @@ int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
     for (int a = 0; a < 3; ++a) d.u[a] = us[a];
     d.out = r0;
     d.g = x->g;
-    LAUNCH(x, K_DIV, launch_div<T>(d, x->Lo.L, x->stream));
+    LAUNCH(x, K_DIV, launch_div<T>(d, x->Lo.L1, x->stream));
+    // With no solid cell the iterates are identical: one solve gives them all.
     const int nit = x->any_solid ? x->P.n_piter : std::min(x->P.n_piter, 1);
     for (int it = 0; it < nit; ++it) {
-        int rc = poisson_solve<T>(x, r0, p, x->any_solid ? x->flags : nullptr, p);
+        if (x->any_solid) LAUNCH(x, K_IB, launch_ib_rhs<T>(x->ib, x->g, p, r0, (T*)x->ib_r0, it == 0, x->stream));
+        int rc = poisson_solve<T>(x, r0, p);
         if (rc) return rc;
     }
     CorrArgs<T> ca;
@@ -335,7 +366,7 @@ int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
     ca.p = p;
     ca.flags = x->flags;
     ca.g = x->g;
-    LAUNCH(x, K_CORR, launch_correct<T>(ca, x->Lo.L, x->stream));
+    LAUNCH(x, K_CORR, launch_correct<T>(ca, x->Lo.L1, x->stream));
     return DNSLAB_OK;
 }
 
@@ -370,8 +401,8 @@ int scalar_rk4(dnslab_ctx* x, const T* const uvel[3], const double* dtp, double 
 template <typename T>
 int ensure_rate(dnslab_ctx* x) {
     if (x->rate_valid) return DNSLAB_OK;
-    HIPCHK(x, launch_rate<T>((const T*)x->u, (const T*)x->v, (const T*)x->w, x->g, x->part, x->Lo.L, x->stream));
-    HIPCHK(x, launch_set_rate(x->part, x->Lo.L.nblocks, x->sc, x->stream));
+    HIPCHK(x, launch_rate<T>((const T*)x->u, (const T*)x->v, (const T*)x->w, x->g, x->part, x->Lo.L1, x->stream));
+    HIPCHK(x, launch_set_rate(x->part, x->Lo.L1.nblocks, x->sc, x->stream));
     x->rate_valid = true;
     return DNSLAB_OK;
 }
@@ -420,9 +451,10 @@ int one_step(dnslab_ctx* x) {
         fa.flags = x->flags;
         fa.g = x->g;
         fa.part = x->part;
-        LAUNCH(x, K_FILT, launch_filter<T>(fa, L, x->stream));
+        LAUNCH(x, K_FILT, launch_filter<T>(fa, x->Lo.LF, x->stream));
     }
-    HIPCHK(x, launch_finish(x->part, L.nblocks, x->pdiv, L.nblocks, x->sc, x->ring, RING_CAP, x->g.dv, x->stream));
+    const int np = filt ? x->Lo.LF.nblocks : L.nblocks;
+    LAUNCH(x, K_FIN, launch_finish(x->part, np, x->pdiv, L.nblocks, x->sc, x->ring, RING_CAP, x->g.dv, x->stream));
     x->host_step += 1;
     return DNSLAB_OK;
 }
@@ -448,6 +480,8 @@ int build_flags(dnslab_ctx* x, const uint8_t* beta_dev, const long long* fidx_ho
         HIPCHK(x, hipMemcpy(room.data(), room_dev, (size_t)g.n, hipMemcpyDeviceToHost));
     }
     std::vector<uint8_t> fl((size_t)g.n, 0);
+    std::vector<int> ibidx;
+    std::vector<uint8_t> ibmask;
     bool any_solid = false;
     for (long long i = 0; i < g.n; ++i) {
         if (beta[i] > 1) return fail(x, DNSLAB_EINVAL, "beta must hold 0 or 1");
@@ -469,8 +503,14 @@ int build_flags(dnslab_ctx* x, const uint8_t* beta_dev, const long long* fidx_ho
                                          i + (long long)nx * (jm + (long long)ny * k),
                                          i + (long long)nx * (j + (long long)ny * kp),
                                          i + (long long)nx * (j + (long long)ny * km)};
+                uint8_t solid_nb = 0;
                 for (int q = 0; q < 6; ++q)
-                    if (!beta[nb[q]]) f |= F_NEAR_SOLID;
+                    if (!beta[nb[q]]) solid_nb |= (uint8_t)(1u << q);
+                if (solid_nb) {
+                    f |= F_NEAR_SOLID;
+                    ibidx.push_back((int)id);
+                    ibmask.push_back(solid_nb);
+                }
                 fl[id] = f;
             }
     for (int64_t e = 0; e < nf; ++e) {
@@ -481,6 +521,21 @@ int build_flags(dnslab_ctx* x, const uint8_t* beta_dev, const long long* fidx_ho
     }
     HIPCHK(x, hipMemcpy(x->flags, fl.data(), (size_t)g.n, hipMemcpyHostToDevice));
     x->any_solid = any_solid;
+    const size_t nib = ibidx.size();
+    if (nib > 0) {
+        const size_t b_idx = align_up(nib * sizeof(int), 256), b_mask = align_up(nib, 256);
+        if (hipMalloc(&x->ib_buf, b_idx + b_mask + nib * x->Lo.esz) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(x, DNSLAB_ENOMEM, "hipMalloc of the immersed-boundary list failed");
+        }
+        char* b = (char*)x->ib_buf;
+        HIPCHK(x, hipMemcpy(b, ibidx.data(), nib * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(x, hipMemcpy(b + b_idx, ibmask.data(), nib, hipMemcpyHostToDevice));
+        x->ib.idx = (const int*)b;
+        x->ib.mask = (const uint8_t*)(b + b_idx);
+        x->ib_r0 = b + b_idx + b_mask;
+    }
+    x->ib.n = (int)nib;
     return DNSLAB_OK;
 }
 
@@ -558,7 +613,7 @@ int filt1(dnslab_ctx* x, const void* f, void* out) {
     a.nf = 1;
     a.flags = x->flags;
     a.g = x->g;
-    LAUNCH(x, K_FILT, launch_filter<T>(a, x->Lo.L, x->stream));
+    LAUNCH(x, K_FILT, launch_filter<T>(a, x->Lo.LF, x->stream));
     return DNSLAB_OK;
 }
 }  // namespace
@@ -710,8 +765,8 @@ int dnslab_read_diags(dnslab_ctx* x, int32_t n, dnslab_diag* out) {
 int dnslab_poisson(dnslab_ctx* x, const void* rhs, void* p) {
     if (int rc = check_ctx(x)) return rc;
     if (!rhs || !p) return fail(x, DNSLAB_EINVAL, "NULL pointer");
-    if (x->Lo.esz == 8) return poisson_solve<double>(x, (const double*)rhs, nullptr, nullptr, (double*)p);
-    return poisson_solve<float>(x, (const float*)rhs, nullptr, nullptr, (float*)p);
+    if (x->Lo.esz == 8) return poisson_solve<double>(x, (const double*)rhs, (double*)p);
+    return poisson_solve<float>(x, (const float*)rhs, (float*)p);
 }
 
 int dnslab_project(dnslab_ctx* x, void* u, void* v, void* w) {
@@ -780,6 +835,7 @@ void dnslab_destroy(dnslab_ctx* x) {
     (void)hipStreamSynchronize(x->stream);
     for (hipEvent_t e : x->ev) (void)hipEventDestroy(e);
     if (x->ws) (void)hipFree(x->ws);
+    if (x->ib_buf) (void)hipFree(x->ib_buf);
     if (x->pinned) (void)hipHostFree(x->pinned);
     if (x->pinned_sc) (void)hipHostFree(x->pinned_sc);
     delete x;

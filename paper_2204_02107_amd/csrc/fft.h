@@ -39,10 +39,24 @@ struct FFTArgs {
     int lg_tx_y, lg_tx_z;
 };
 
-// Forward x pass: r = r0 (+ div((1-beta) grad p) where flagged), R2C along x.
-// p and flags may be NULL (then r = r0).
+// Cells next to a solid, where the immersed-boundary term div((1-beta) grad p)
+// can be nonzero (Section 2.2), with the solid face neighbours as bits
+// (+x, -x, +y, -y, +z, -z) = (1, 2, 4, 8, 16, 32).
+struct IBList {
+    const int* idx;
+    const uint8_t* mask;
+    int n;
+};
+
+// r = r0 + div((1-beta) grad p) at the listed cells, in place in r.  On the
+// first iteration (first != 0) r holds r0 and r0 is saved into r0s[e];
+// later iterations read r0 from r0s.
 template <typename T>
-hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r0, const T* p, const uint8_t* flags, hipStream_t s);
+hipError_t launch_ib_rhs(const IBList& ib, const Grid& g, const T* p, T* r, T* r0s, int first, hipStream_t s);
+
+// Forward x pass: real-to-complex along x of r into the spectrum.
+template <typename T>
+hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r, hipStream_t s);
 template <typename T>
 hipError_t launch_fft_y(const FFTArgs<T>& a, bool inverse, hipStream_t s);
 // z pass: forward, divide by lambda * ntot (zero on the null modes), inverse.

@@ -111,7 +111,7 @@ struct DFT<T, 3, INV> {
 // consecutive threads work on consecutive lines.  In place: every thread
 // reads its inputs, the block synchronises, then writes the outputs.
 template <typename T, int R, int MAXB, bool INV>
-__device__ __forceinline__ void stockham_pass(C2<T>* s, int n, int ns, const C2<T>* __restrict__ W, int es,
+__device__ __forceinline__ void stockham_pass(C2<T>* s, int n, int ns, const C2<T>* W, int es,
                                               int ls, int lg_nl, int tid, int nthr) {
     const int nbl = n / R;
     const int nb = nbl << lg_nl;
@@ -153,7 +153,7 @@ __device__ __forceinline__ void stockham_pass(C2<T>* s, int n, int ns, const C2<
 }
 
 template <typename T, bool INV>
-__device__ void fft_lds(C2<T>* s, const AxisPlan& ap, const C2<T>* __restrict__ W, int es, int ls, int lg_nl,
+__device__ void fft_lds(C2<T>* s, const AxisPlan& ap, const C2<T>* W, int es, int ls, int lg_nl,
                         int tid, int nthr) {
     int ns = 1;
     for (int p = 0; p < ap.npass; ++p) {
@@ -166,28 +166,41 @@ __device__ void fft_lds(C2<T>* s, const AxisPlan& ap, const C2<T>* __restrict__ 
     }
 }
 
-// div((1 - beta) grad p) at cell (i, j, k) with central differences and the
-// mask taken at the face neighbours (only called for flagged cells).
+// Immersed-boundary right-hand side at the listed cells (Section 2.2):
+// r = r0 + sum_a [ (1-beta)(x+e_a) D_a p(x+e_a) - (1-beta)(x-e_a) D_a p(x-e_a) ] / (2 dx_a)
+// with central D_a; (1-beta) is 1 exactly where the mask bit says "solid".
 template <typename T>
-__device__ T ib_term(const Grid& g, const T* __restrict__ p, const uint8_t* __restrict__ fl, int i, int j, int k) {
-    T acc = T(0);
-    const int nn[3] = {g.nx, g.ny, g.nz};
-    const int c0[3] = {i, j, k};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        int cc[3] = {c0[0], c0[1], c0[2]};
-        auto at = [&](int off) -> unsigned {
-            cc[a] = wrap(c0[a] + off, nn[a]);
-            const unsigned r = (unsigned)cc[0] + (unsigned)g.nx * ((unsigned)cc[1] + (unsigned)g.ny * cc[2]);
-            cc[a] = c0[a];
-            return r;
-        };
-        const T h = T(g.inv2d[a]);
-        const unsigned ip = at(1), im = at(-1);
-        if (!(fl[ip] & F_FLUID)) acc += ((p[at(2)] - p[at(0)]) * h) * h;
-        if (!(fl[im] & F_FLUID)) acc -= ((p[at(0)] - p[at(-2)]) * h) * h;
+__global__ __launch_bounds__(256) void k_ib_rhs(const IBList ib, const Grid g, const T* __restrict__ p,
+                                                T* __restrict__ r, T* __restrict__ r0s, int first) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ib.n) return;
+    const unsigned idx = (unsigned)ib.idx[e];
+    const unsigned mask = ib.mask[e];
+    const unsigned nx = g.nx, ny = g.ny, nz = g.nz;
+    const unsigned i = idx % nx, jk = idx / nx;
+    const unsigned j = jk % ny, k = jk / ny;
+    const unsigned nxy = nx * ny;
+    T r0;
+    if (first) {
+        r0 = r[idx];
+        r0s[e] = r0;
+    } else {
+        r0 = r0s[e];
     }
-    return acc;
+    const T p0 = p[idx];
+    T acc = T(0);
+    // +-2 neighbours along each axis with periodic wrap
+    const unsigned ip2 = idx - i + (i + 2) % nx, im2 = idx - i + (i + 2 * nx - 2) % nx;
+    const unsigned jp2 = idx + (((j + 2) % ny) - j) * nx, jm2 = idx + (((j + 2 * ny - 2) % ny) - j) * nx;
+    const unsigned kp2 = idx + (((k + 2) % nz) - k) * nxy, km2 = idx + (((k + 2 * nz - 2) % nz) - k) * nxy;
+    const T hx = T(g.inv2d[0]), hy = T(g.inv2d[1]), hz = T(g.inv2d[2]);
+    if (mask & 1u) acc += ((p[ip2] - p0) * hx) * hx;
+    if (mask & 2u) acc -= ((p0 - p[im2]) * hx) * hx;
+    if (mask & 4u) acc += ((p[jp2] - p0) * hy) * hy;
+    if (mask & 8u) acc -= ((p0 - p[jm2]) * hy) * hy;
+    if (mask & 16u) acc += ((p[kp2] - p0) * hz) * hz;
+    if (mask & 32u) acc -= ((p0 - p[km2]) * hz) * hz;
+    r[idx] = r0 + acc;
 }
 
 // X[k] of the real transform from Z = FFT(x_even + i x_odd):
@@ -209,37 +222,60 @@ __device__ __forceinline__ C2<T> c2r_pre(C2<T> xa, C2<T> xb, C2<T> w) {
     return cadd(e, rot<T, true>(o));
 }
 
+// Batched global -> register -> LDS staging: every thread issues all of its
+// loads before the first LDS store, so that a block keeps many independent
+// memory requests in flight (the passes are otherwise latency bound).
+constexpr int STAGE_MAX = 9;   // elements per thread: at most rad[0] (+1 for the x inverse)
+
+// Split e into (line, element) for line length m (power of two: shifts).
+struct LineSplit {
+    int m, lgm;
+    __device__ __forceinline__ void split(int e, int& l, int& n) const {
+        if (lgm >= 0) { l = e >> lgm; n = e & (m - 1); }
+        else { l = e / m; n = e - l * m; }
+    }
+};
+__device__ __forceinline__ LineSplit line_split(int m) {
+    LineSplit ls;
+    ls.m = m;
+    ls.lgm = (m & (m - 1)) == 0 ? __ffs(m) - 1 : -1;
+    return ls;
+}
+
 template <typename T>
-__global__ __launch_bounds__(1024) void k_fft_x_fwd(const FFTArgs<T> a, const T* __restrict__ r0,
-                                                    const T* __restrict__ p, const uint8_t* __restrict__ flags) {
+__global__ __launch_bounds__(1024) void k_fft_x_fwd(const FFTArgs<T> a, const T* __restrict__ r) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* s = reinterpret_cast<C2<T>*>(smem_raw);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lg = a.nl_x, m = a.m, ls = a.ls_x;
     const int line0 = blockIdx.x << lg;
     const int nlines = a.g.ny * a.g.nz;
-    const int nx = a.g.nx;
-    for (int e = tid; e < (m << lg); e += nthr) {
-        const int l = e / m;
-        const int n = e - l * m;
-        const int L = line0 + l;
-        C2<T> z = {T(0), T(0)};
-        if (L < nlines) {
-            const unsigned idx = (unsigned)L * (unsigned)nx + 2u * (unsigned)n;
-            z = *reinterpret_cast<const C2<T>*>(r0 + idx);
-            if (flags) {
-                const uint8_t f0 = flags[idx], f1 = flags[idx + 1];
-                if ((f0 | f1) & F_NEAR_SOLID) {
-                    const int j = L % a.g.ny, k = L / a.g.ny;
-                    if (f0 & F_NEAR_SOLID) z.x += ib_term(a.g, p, flags, 2 * n, j, k);
-                    if (f1 & F_NEAR_SOLID) z.y += ib_term(a.g, p, flags, 2 * n + 1, j, k);
-                }
-            }
-        }
-        s[l * ls + n] = z;
+    const unsigned nx = a.g.nx;
+    const LineSplit sp = line_split(m);
+    const int tot = m << lg;
+    C2<T>* wl = s + (ls << lg);      // W_m table, then the real-transform twist
+    C2<T>* tl = wl + m;
+    for (int j = tid; j < m; j += nthr) wl[j] = a.wx[j];
+    for (int j = tid; j <= m; j += nthr) tl[j] = a.tw[j];
+    C2<T> buf[STAGE_MAX];
+#pragma unroll
+    for (int q = 0; q < STAGE_MAX; ++q) {
+        const int e = tid + q * nthr;
+        int l, n;
+        sp.split(e, l, n);
+        buf[q] = C2<T>{T(0), T(0)};
+        if (e < tot && line0 + l < nlines)
+            buf[q] = *reinterpret_cast<const C2<T>*>(r + (unsigned)(line0 + l) * nx + 2u * (unsigned)n);
+    }
+#pragma unroll
+    for (int q = 0; q < STAGE_MAX; ++q) {
+        const int e = tid + q * nthr;
+        int l, n;
+        sp.split(e, l, n);
+        if (e < tot) s[l * ls + n] = buf[q];
     }
     __syncthreads();
-    fft_lds<T, false>(s, a.px, a.wx, 1, ls, lg, tid, nthr);
+    fft_lds<T, false>(s, a.px, wl, 1, ls, lg, tid, nthr);
     const int half = m / 2 + 1;
     for (int e = tid; e < (half << lg); e += nthr) {
         const int l = e / half;
@@ -250,8 +286,8 @@ __global__ __launch_bounds__(1024) void k_fft_x_fwd(const FFTArgs<T> a, const T*
         C2<T>* out = a.spec + (size_t)L * a.sx;
         const C2<T> za = zl[k];
         const C2<T> zb = zl[k == 0 ? 0 : m - k];
-        out[k] = r2c_post(za, zb, a.tw[k]);
-        if (m - k != k) out[m - k] = r2c_post(zb, za, a.tw[m - k]);
+        out[k] = r2c_post(za, zb, tl[k]);
+        if (m - k != k) out[m - k] = r2c_post(zb, za, tl[m - k]);
     }
 }
 
@@ -263,13 +299,33 @@ __global__ __launch_bounds__(1024) void k_fft_x_inv(const FFTArgs<T> a, T* __res
     const int lg = a.nl_x, m = a.m, ls = a.ls_x;
     const int line0 = blockIdx.x << lg;
     const int nlines = a.g.ny * a.g.nz;
-    const int nx = a.g.nx;
+    const unsigned nx = a.g.nx;
     const int m1 = m + 1;
-    for (int e = tid; e < (m1 << lg); e += nthr) {
-        const int l = e / m1;
-        const int k = e - l * m1;
-        const int L = line0 + l;
-        s[l * ls + k] = L < nlines ? a.spec[(size_t)L * a.sx + k] : C2<T>{T(0), T(0)};
+    C2<T>* wl = s + (ls << lg);
+    C2<T>* tl = wl + m;
+    for (int j = tid; j < m; j += nthr) wl[j] = a.wx[j];
+    for (int j = tid; j <= m; j += nthr) tl[j] = a.tw[j];
+    {
+        const int tot = m1 << lg;
+        C2<T> buf[STAGE_MAX];
+#pragma unroll
+        for (int q = 0; q < STAGE_MAX; ++q) {
+            const int e = tid + q * nthr;
+            const int l = e / m1, k = e - l * m1;
+            buf[q] = C2<T>{T(0), T(0)};
+            if (e < tot && line0 + l < nlines) buf[q] = a.spec[(size_t)(line0 + l) * a.sx + k];
+        }
+#pragma unroll
+        for (int q = 0; q < STAGE_MAX; ++q) {
+            const int e = tid + q * nthr;
+            const int l = e / m1, k = e - l * m1;
+            if (e < tot) s[l * ls + k] = buf[q];
+        }
+        // elements beyond STAGE_MAX per thread (only when nthr * STAGE_MAX < tot)
+        for (int e = tid + STAGE_MAX * nthr; e < tot; e += nthr) {
+            const int l = e / m1, k = e - l * m1;
+            s[l * ls + k] = line0 + l < nlines ? a.spec[(size_t)(line0 + l) * a.sx + k] : C2<T>{T(0), T(0)};
+        }
     }
     __syncthreads();
     const int half = m / 2 + 1;
@@ -279,77 +335,115 @@ __global__ __launch_bounds__(1024) void k_fft_x_inv(const FFTArgs<T> a, T* __res
         C2<T>* zl = s + l * ls;
         C2<T> xa = zl[k], xb = zl[m - k];
         if (k == 0) { xa.y = T(0); xb.y = T(0); }   // the real transform ignores Im X[0], Im X[m]
-        const C2<T> za = c2r_pre(xa, xb, a.tw[k]);
-        if (k != 0 && m - k != k) zl[m - k] = c2r_pre(xb, xa, a.tw[m - k]);
+        const C2<T> za = c2r_pre(xa, xb, tl[k]);
+        if (k != 0 && m - k != k) zl[m - k] = c2r_pre(xb, xa, tl[m - k]);
         zl[k] = za;
     }
     __syncthreads();
-    fft_lds<T, true>(s, a.px, a.wx, 1, ls, lg, tid, nthr);
+    fft_lds<T, true>(s, a.px, wl, 1, ls, lg, tid, nthr);
+    const LineSplit sp = line_split(m);
     for (int e = tid; e < (m << lg); e += nthr) {
-        const int l = e / m;
-        const int n = e - l * m;
+        int l, n;
+        sp.split(e, l, n);
         const int L = line0 + l;
-        if (L < nlines)
-            *reinterpret_cast<C2<T>*>(p + (unsigned)L * (unsigned)nx + 2u * (unsigned)n) = s[l * ls + n];
+        if (L < nlines) *reinterpret_cast<C2<T>*>(p + (unsigned)L * nx + 2u * (unsigned)n) = s[l * ls + n];
     }
 }
 
-template <typename T, bool INV>
-__global__ __launch_bounds__(1024) void k_fft_y(const FFTArgs<T> a) {
-    extern __shared__ unsigned char smem_raw[];
-    C2<T>* s = reinterpret_cast<C2<T>*>(smem_raw);
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lg = a.lg_tx_y, tx = 1 << lg;
-    const int c0 = blockIdx.x << lg;
-    const int kz = blockIdx.y;
-    const int ny = a.g.ny, ncols = a.m + 1;
-    C2<T>* base = a.spec + (size_t)kz * ny * a.sx + c0;
-    const int tot = ny << lg;
-    for (int e = tid; e < tot; e += nthr) {
-        const int row = e >> lg, c = e & (tx - 1);
-        s[e] = (c0 + c < ncols) ? base[(size_t)row * a.sx + c] : C2<T>{T(0), T(0)};
-    }
-    __syncthreads();
-    fft_lds<T, INV>(s, a.py, a.wy, tx, 1, lg, tid, nthr);
-    for (int e = tid; e < tot; e += nthr) {
-        const int row = e >> lg, c = e & (tx - 1);
-        if (c0 + c < ncols) base[(size_t)row * a.sx + c] = s[e];
-    }
+// 1/x to about one ulp: hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_fft_z_solve(const FFTArgs<T> a) {
+// Column passes along y (MODE 0 forward, 1 inverse) or z (MODE 2: forward,
+// divide by lambda N with the null modes zeroed, inverse).  A block holds TX
+// lines of the spectrum in LDS as [row][line].  Main blocks take TX
+// consecutive kx columns 0..m-1 of one plane (TX complex values contiguous
+// per row); the Nyquist column kx = m, which would otherwise leave a nearly
+// empty tile in every plane, is handled by a few extra blocks that take TX
+// different planes of that column each.
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_fft_cols(const FFTArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* s = reinterpret_cast<C2<T>*>(smem_raw);
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lg = a.lg_tx_z, tx = 1 << lg;
-    const int c0 = blockIdx.x << lg;
-    const int ky = blockIdx.y;
-    const int ny = a.g.ny, nz = a.g.nz, ncols = a.m + 1;
-    C2<T>* base = a.spec + (size_t)ky * a.sx + c0;
-    const size_t rs = (size_t)ny * a.sx;
-    const int tot = nz << lg;
-    for (int e = tid; e < tot; e += nthr) {
-        const int row = e >> lg, c = e & (tx - 1);
-        s[e] = (c0 + c < ncols) ? base[row * rs + c] : C2<T>{T(0), T(0)};
+    const bool zp = MODE == 2;
+    const int lg = zp ? a.lg_tx_z : a.lg_tx_y, tx = 1 << lg;
+    const int ny = a.g.ny, nz = a.g.nz, m = a.m;
+    const int nrow = zp ? nz : ny;                 // transform length
+    const int nplane = zp ? ny : nz;               // other spectral index
+    const size_t rs = zp ? (size_t)ny * a.sx : (size_t)a.sx;   // row (transform) stride
+    const size_t ps = zp ? (size_t)a.sx : (size_t)ny * a.sx;   // plane stride
+    const int ntile = (m + tx - 1) >> lg;
+    const int nmain = ntile * nplane;
+    const int b = blockIdx.x;
+    C2<T>* base;
+    size_t cs;
+    int ncol, kx0, plane0;
+    bool nyq;
+    if (b < nmain) {
+        const int tile = b % ntile;
+        plane0 = b / ntile;
+        kx0 = tile << lg;
+        base = a.spec + (size_t)plane0 * ps + kx0;
+        cs = 1;
+        ncol = min(tx, m - kx0);
+        nyq = false;
+    } else {
+        plane0 = (b - nmain) << lg;
+        kx0 = m;
+        base = a.spec + (size_t)plane0 * ps + m;
+        cs = ps;
+        ncol = min(tx, nplane - plane0);
+        nyq = true;
     }
-    __syncthreads();
-    fft_lds<T, false>(s, a.pz, a.wz, tx, 1, lg, tid, nthr);
-    const double syk = a.sy2[ky];
-    for (int e = tid; e < tot; e += nthr) {
-        const int kz = e >> lg, c = e & (tx - 1);
-        const int kx = c0 + c;
-        if (kx < ncols) {
-            const double lam = (a.sz2[kz] + syk) + a.sx2[kx];   // -lambda
-            const T f = lam == 0.0 ? T(0) : T(-a.inv_ntot / lam);
-            s[e] = cscale(s[e], f);
+    const int tot = nrow << lg;
+    C2<T>* wl = s + tot;               // W_nrow table
+    {
+        const C2<T>* W = zp ? a.wz : a.wy;
+        for (int j = tid; j < nrow; j += nthr) wl[j] = W[j];
+    }
+    {
+        C2<T> buf[STAGE_MAX];
+#pragma unroll
+        for (int q = 0; q < STAGE_MAX; ++q) {
+            const int e = tid + q * nthr;
+            const int row = e >> lg, c = e & (tx - 1);
+            buf[q] = C2<T>{T(0), T(0)};
+            if (e < tot && c < ncol) buf[q] = base[row * rs + c * cs];
+        }
+#pragma unroll
+        for (int q = 0; q < STAGE_MAX; ++q) {
+            const int e = tid + q * nthr;
+            if (e < tot) s[e] = buf[q];
         }
     }
     __syncthreads();
-    fft_lds<T, true>(s, a.pz, a.wz, tx, 1, lg, tid, nthr);
-    for (int e = tid; e < tot; e += nthr) {
+    if (MODE == 2) {
+        fft_lds<T, false>(s, a.pz, wl, tx, 1, lg, tid, nthr);
+        for (int e = tid; e < tot; e += nthr) {
+            const int kz = e >> lg, c = e & (tx - 1);
+            if (c < ncol) {
+                const int kx = nyq ? m : kx0 + c;
+                const int ky = nyq ? plane0 + c : plane0;
+                const double lam = (a.sz2[kz] + a.sy2[ky]) + a.sx2[kx];   // -lambda
+                const T f = lam == 0.0 ? T(0) : T(-a.inv_ntot * recip(lam));
+                s[e] = cscale(s[e], f);
+            }
+        }
+        __syncthreads();
+        fft_lds<T, true>(s, a.pz, wl, tx, 1, lg, tid, nthr);
+    } else {
+        fft_lds<T, MODE == 1>(s, a.py, wl, tx, 1, lg, tid, nthr);
+    }
+#pragma unroll
+    for (int q = 0; q < STAGE_MAX; ++q) {
+        const int e = tid + q * nthr;
         const int row = e >> lg, c = e & (tx - 1);
-        if (c0 + c < ncols) base[row * rs + c] = s[e];
+        if (e < tot && c < ncol) base[row * rs + c * cs] = s[e];
     }
 }
 
@@ -382,13 +476,20 @@ AxisPlan make_axis_plan(int n) {
 }
 
 template <typename T>
-hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r0, const T* p, const uint8_t* flags, hipStream_t s) {
+hipError_t launch_ib_rhs(const IBList& ib, const Grid& g, const T* p, T* r, T* r0s, int first, hipStream_t s) {
+    if (ib.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_ib_rhs<T>), dim3((ib.n + 255) / 256), dim3(256), 0, s, ib, g, p, r, r0s, first);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r, hipStream_t s) {
     const int nl = 1 << a.nl_x;
     const int nlines = a.g.ny * a.g.nz;
     dim3 grid((nlines + nl - 1) / nl);
     dim3 block(round64(nl * a.px.tpl));
-    size_t lds = (size_t)nl * a.ls_x * sizeof(C2<T>);
-    hipLaunchKernelGGL((k_fft_x_fwd<T>), grid, block, lds, s, a, r0, p, flags);
+    size_t lds = ((size_t)nl * a.ls_x + 2 * a.m + 1) * sizeof(C2<T>);
+    hipLaunchKernelGGL((k_fft_x_fwd<T>), grid, block, lds, s, a, r);
     return hipGetLastError();
 }
 
@@ -398,34 +499,40 @@ hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s) {
     const int nlines = a.g.ny * a.g.nz;
     dim3 grid((nlines + nl - 1) / nl);
     dim3 block(round64(nl * a.px.tpl));
-    size_t lds = (size_t)nl * a.ls_x * sizeof(C2<T>);
+    size_t lds = ((size_t)nl * a.ls_x + 2 * a.m + 1) * sizeof(C2<T>);
     hipLaunchKernelGGL((k_fft_x_inv<T>), grid, block, lds, s, a, p);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fft_y(const FFTArgs<T>& a, bool inverse, hipStream_t s) {
-    const int tx = 1 << a.lg_tx_y;
-    dim3 grid((a.m + 1 + tx - 1) / tx, a.g.nz);
-    dim3 block(round64(tx * a.py.tpl));
-    size_t lds = (size_t)tx * a.g.ny * sizeof(C2<T>);
-    if (inverse) hipLaunchKernelGGL((k_fft_y<T, true>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_fft_y<T, false>), grid, block, lds, s, a);
+static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s) {
+    const bool zp = mode == 2;
+    const int lg = zp ? a.lg_tx_z : a.lg_tx_y, tx = 1 << lg;
+    const int nrow = zp ? a.g.nz : a.g.ny, nplane = zp ? a.g.ny : a.g.nz;
+    const int ntile = (a.m + tx - 1) / tx;
+    const int nblocks = ntile * nplane + (nplane + tx - 1) / tx;
+    const AxisPlan& ap = zp ? a.pz : a.py;
+    dim3 block(round64(tx * ap.tpl));
+    size_t lds = ((size_t)tx * nrow + nrow) * sizeof(C2<T>);
+    if (mode == 0) hipLaunchKernelGGL((k_fft_cols<T, 0>), dim3(nblocks), block, lds, s, a);
+    else if (mode == 1) hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3(nblocks), block, lds, s, a);
+    else hipLaunchKernelGGL((k_fft_cols<T, 2>), dim3(nblocks), block, lds, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
+hipError_t launch_fft_y(const FFTArgs<T>& a, bool inverse, hipStream_t s) {
+    return launch_cols<T>(a, inverse ? 1 : 0, s);
+}
+
+template <typename T>
 hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s) {
-    const int tx = 1 << a.lg_tx_z;
-    dim3 grid((a.m + 1 + tx - 1) / tx, a.g.ny);
-    dim3 block(round64(tx * a.pz.tpl));
-    size_t lds = (size_t)tx * a.g.nz * sizeof(C2<T>);
-    hipLaunchKernelGGL((k_fft_z_solve<T>), grid, block, lds, s, a);
-    return hipGetLastError();
+    return launch_cols<T>(a, 2, s);
 }
 
 #define DNSLAB_INST(T)                                                                                      \
-    template hipError_t launch_fft_x_fwd<T>(const FFTArgs<T>&, const T*, const T*, const uint8_t*, hipStream_t); \
+    template hipError_t launch_fft_x_fwd<T>(const FFTArgs<T>&, const T*, hipStream_t);                      \
+    template hipError_t launch_ib_rhs<T>(const IBList&, const Grid&, const T*, T*, T*, int, hipStream_t);   \
     template hipError_t launch_fft_x_inv<T>(const FFTArgs<T>&, T*, hipStream_t);                            \
     template hipError_t launch_fft_y<T>(const FFTArgs<T>&, bool, hipStream_t);                              \
     template hipError_t launch_fft_z_solve<T>(const FFTArgs<T>&, hipStream_t);

@@ -82,7 +82,9 @@ struct StencilLaunch {
     int kc;
     int nblocks;
 };
-StencilLaunch stencil_launch(const Grid& g, int kc);
+// rows: block height for a 64-wide block (the block has 64 * rows threads);
+// cells_x: cells per thread along x (1, or 2 for the pair kernels).
+StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x);
 
 template <typename T> hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s);
 template <typename T> hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s);

@@ -10,9 +10,15 @@
 // wavefront).
 #include "stencil.h"
 
+#include <algorithm>
+
 namespace dnslab {
 
 namespace {
+
+#ifndef DNSLAB_ZFAST
+#define DNSLAB_ZFAST 0
+#endif
 
 constexpr double INV_PI6 = 1.0 / (3.14159265358979323846 * 3.14159265358979323846 *
                                   3.14159265358979323846 * 3.14159265358979323846 *
@@ -20,14 +26,41 @@ constexpr double INV_PI6 = 1.0 / (3.14159265358979323846 * 3.1415926535897932384
 
 struct Col {
     int i, j, im, ip, jm, jp;
+    int k0, k1;
     unsigned row, rowm, rowp;   // j*nx, jm*nx, jp*nx
     bool active;
 };
 
-__device__ __forceinline__ Col column(const Grid& g) {
+// XCD-aware block order.  Workgroups are dealt to the 8 XCDs round-robin by
+// hardware id; remapping hardware id -> logical tile so that each XCD owns a
+// contiguous range of tiles keeps the y- and z-neighbour rows of a tile in the
+// L2 of the XCD that reads them.
+__device__ __forceinline__ void logical_block(int& bx, int& by, int& bz) {
+    const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    const unsigned nb = gx * gy * gz;
+    const unsigned hw = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned x = hw & 7u, q = hw >> 3;
+    const unsigned per = nb >> 3, rem = nb & 7u;
+    const unsigned L = x * per + min(x, rem) + q;
+#if DNSLAB_ZFAST
+    bz = (int)(L % gz);
+    bx = (int)((L / gz) % gx);
+    by = (int)(L / (gz * gx));
+#else
+    bx = (int)(L % gx);
+    by = (int)((L / gx) % gy);
+    bz = (int)(L / (gx * gy));
+#endif
+}
+
+__device__ __forceinline__ Col column(const Grid& g, int kc) {
     Col c;
-    c.i = blockIdx.x * blockDim.x + threadIdx.x;
-    c.j = blockIdx.y * blockDim.y + threadIdx.y;
+    int bx, by, bz;
+    logical_block(bx, by, bz);
+    c.i = bx * blockDim.x + threadIdx.x;
+    c.j = by * blockDim.y + threadIdx.y;
+    c.k0 = bz * kc;
+    c.k1 = min(c.k0 + kc, g.nz);
     c.active = c.i < g.nx && c.j < g.ny;
     if (!c.active) { c.i = 0; c.j = 0; }
     c.im = c.i == 0 ? g.nx - 1 : c.i - 1;
@@ -40,6 +73,7 @@ __device__ __forceinline__ Col column(const Grid& g) {
     return c;
 }
 
+// Slot of this block in a partial-result array (hardware id: any bijection).
 __device__ __forceinline__ int block_linear() {
     return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
@@ -60,12 +94,11 @@ __device__ __forceinline__ double courant_rate(double u, double v, double w, con
 //   1/2 [D_a(u_a u_i) + u_a D_a u_i] = [(u_a+ + u_a0) u_i+ - (u_a- + u_a0) u_i-] / (4 dx_a).
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_mom_stage(const MomArgs<T> a) {
+__global__ __launch_bounds__(1024) void k_mom_stage(const MomArgs<T> a) {
     const Grid& g = a.g;
-    const Col col = column(g);
+    const Col col = column(g, a.kc);
     if (!col.active) return;
-    const int k0 = blockIdx.z * a.kc;
-    const int k1 = min(k0 + a.kc, g.nz);
+    const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T dt = (MODE == ST_RHS) ? T(0) : T(a.dtp ? *a.dtp : a.dt);
     const T q4x = T(g.inv4d[0]), q4y = T(g.inv4d[1]), q4z = T(g.inv4d[2]);
@@ -146,11 +179,10 @@ __global__ __launch_bounds__(256) void k_mom_stage(const MomArgs<T> a) {
 // the masked diffusion conducting only across fluid-fluid faces.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_sca_stage(const ScaArgs<T> a) {
+__global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) {
     const Grid& g = a.g;
-    const Col col = column(g);
-    const int k0 = blockIdx.z * a.kc;
-    const int k1 = min(k0 + a.kc, g.nz);
+    const Col col = column(g, a.kc);
+    const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T dt = (MODE == ST_RHS) ? T(0) : T(a.dtp ? *a.dtp : a.dt);
     const T h2x = T(g.inv2d[0]), h2y = T(g.inv2d[1]), h2z = T(g.inv2d[2]);
@@ -234,11 +266,10 @@ __global__ __launch_bounds__(256) void k_sca_stage(const ScaArgs<T> a) {
 // out = beta (f + pi^-6 sum_a delta6_a f).
 // ---------------------------------------------------------------------------
 template <typename T, int NF>
-__global__ __launch_bounds__(256) void k_filter(const FiltArgs<T> a) {
+__global__ __launch_bounds__(1024) void k_filter(const FiltArgs<T> a) {
     const Grid& g = a.g;
-    const Col col = column(g);
-    const int k0 = blockIdx.z * a.kc;
-    const int k1 = min(k0 + a.kc, g.nz);
+    const Col col = column(g, a.kc);
+    const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T c6 = T(INV_PI6);
     Partial part = {0, 0, 0, 0, 0, 0, {0, 0}};
@@ -299,12 +330,11 @@ __global__ __launch_bounds__(256) void k_filter(const FiltArgs<T> a) {
 // Velocity correction of Section 2.2 with the mask: out = beta (u* - grad p).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_correct(const CorrArgs<T> a) {
+__global__ __launch_bounds__(1024) void k_correct(const CorrArgs<T> a) {
     const Grid& g = a.g;
-    const Col col = column(g);
+    const Col col = column(g, a.kc);
     if (!col.active) return;
-    const int k0 = blockIdx.z * a.kc;
-    const int k1 = min(k0 + a.kc, g.nz);
+    const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T hx = T(g.inv2d[0]), hy = T(g.inv2d[1]), hz = T(g.inv2d[2]);
     const T* __restrict__ p = a.p;
@@ -329,12 +359,11 @@ __global__ __launch_bounds__(256) void k_correct(const CorrArgs<T> a) {
 
 // Divergence with central differences: out = sum_a D_a u_a (Section 2.2).
 template <typename T>
-__global__ __launch_bounds__(256) void k_div(const DivArgs<T> a) {
+__global__ __launch_bounds__(1024) void k_div(const DivArgs<T> a) {
     const Grid& g = a.g;
-    const Col col = column(g);
+    const Col col = column(g, a.kc);
     if (!col.active) return;
-    const int k0 = blockIdx.z * a.kc;
-    const int k1 = min(k0 + a.kc, g.nz);
+    const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T hx = T(g.inv2d[0]), hy = T(g.inv2d[1]), hz = T(g.inv2d[2]);
     const T* __restrict__ w = a.u[2];
@@ -354,11 +383,10 @@ __global__ __launch_bounds__(256) void k_div(const DivArgs<T> a) {
 
 // Courant rate partials (max over cells), for the first step after (re)binding.
 template <typename T>
-__global__ __launch_bounds__(256) void k_rate(const T* u, const T* v, const T* w, const Grid g, int kc,
+__global__ __launch_bounds__(1024) void k_rate(const T* u, const T* v, const T* w, const Grid g, int kc,
                                               Partial* part) {
-    const Col col = column(g);
-    const int k0 = blockIdx.z * kc;
-    const int k1 = min(k0 + kc, g.nz);
+    const Col col = column(g, kc);
+    const int k0 = col.k0, k1 = col.k1;
     Partial pp = {0, 0, 0, 0, 0, 0, {0, 0}};
     if (col.active) {
         for (int k = k0; k < k1; ++k) {
@@ -375,7 +403,7 @@ __device__ inline double next_dt(const StepScalars& s, double rate) {
 
 // One block: reduce the partials in a fixed order, write the diagnostics of
 // the step just taken, and advance t, the step count and dt.
-__global__ __launch_bounds__(256) void k_finish(const Partial* part, int np, const Partial* pdiv, int nd,
+__global__ __launch_bounds__(1024) void k_finish(const Partial* part, int np, const Partial* pdiv, int nd,
                                                 StepScalars* sc, DiagRec* ring, int ring_cap, double dv) {
     Partial acc = {0, 0, 0, 0, 0, 0, {0, 0}};
     for (int b = threadIdx.x; b < np; b += blockDim.x) {
@@ -409,7 +437,7 @@ __global__ __launch_bounds__(256) void k_finish(const Partial* part, int np, con
     }
 }
 
-__global__ __launch_bounds__(256) void k_set_rate(const Partial* part, int np, StepScalars* sc) {
+__global__ __launch_bounds__(1024) void k_set_rate(const Partial* part, int np, StepScalars* sc) {
     Partial acc = {0, 0, 0, 0, 0, 0, {0, 0}};
     for (int b = threadIdx.x; b < np; b += blockDim.x) acc.rate = fmax(acc.rate, part[b].rate);
     __shared__ Partial res;
@@ -426,27 +454,31 @@ __global__ __launch_bounds__(256) void k_set_rate(const Partial* part, int np, S
 
 }  // namespace
 
-StencilLaunch stencil_launch(const Grid& g, int kc) {
+StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x) {
     StencilLaunch L;
-    int bx = g.nx >= 64 ? 64 : (g.nx >= 32 ? 32 : 16);
-    int by = 256 / bx;
+    const int nxt = g.nx / cells_x;          // threads needed along x
+    int bx = nxt >= 64 ? 64 : (nxt >= 32 ? 32 : 16);
+    int by = std::max(1, std::min(rows * 64 / bx, 1024 / bx));
     L.block = dim3(bx, by, 1);
     L.kc = kc < 1 ? 1 : kc;
-    L.grid = dim3((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, (g.nz + L.kc - 1) / L.kc);
+    L.grid = dim3((nxt + bx - 1) / bx, (g.ny + by - 1) / by, (g.nz + L.kc - 1) / L.kc);
     L.nblocks = (int)(L.grid.x * L.grid.y * L.grid.z);
     return L;
 }
+
+#define MOM_KERNEL k_mom_stage
+#define SCA_KERNEL k_sca_stage
 
 template <typename T>
 hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
     MomArgs<T> b = a;
     b.kc = L.kc;
     switch (mode) {
-        case ST_FIRST: hipLaunchKernelGGL((k_mom_stage<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
-        case ST_HALF: hipLaunchKernelGGL((k_mom_stage<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
-        case ST_FULL: hipLaunchKernelGGL((k_mom_stage<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
-        case ST_LAST: hipLaunchKernelGGL((k_mom_stage<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
-        default: hipLaunchKernelGGL((k_mom_stage<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
+        case ST_FIRST: hipLaunchKernelGGL((MOM_KERNEL<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
+        case ST_HALF: hipLaunchKernelGGL((MOM_KERNEL<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
+        case ST_FULL: hipLaunchKernelGGL((MOM_KERNEL<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
+        case ST_LAST: hipLaunchKernelGGL((MOM_KERNEL<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
+        default: hipLaunchKernelGGL((MOM_KERNEL<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
     }
     return hipGetLastError();
 }
@@ -456,11 +488,11 @@ hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& 
     ScaArgs<T> b = a;
     b.kc = L.kc;
     switch (mode) {
-        case ST_FIRST: hipLaunchKernelGGL((k_sca_stage<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
-        case ST_HALF: hipLaunchKernelGGL((k_sca_stage<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
-        case ST_FULL: hipLaunchKernelGGL((k_sca_stage<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
-        case ST_LAST: hipLaunchKernelGGL((k_sca_stage<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
-        default: hipLaunchKernelGGL((k_sca_stage<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
+        case ST_FIRST: hipLaunchKernelGGL((SCA_KERNEL<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
+        case ST_HALF: hipLaunchKernelGGL((SCA_KERNEL<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
+        case ST_FULL: hipLaunchKernelGGL((SCA_KERNEL<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
+        case ST_LAST: hipLaunchKernelGGL((SCA_KERNEL<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
+        default: hipLaunchKernelGGL((SCA_KERNEL<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
     }
     return hipGetLastError();
 }
@@ -499,12 +531,12 @@ hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g, Partia
 
 hipError_t launch_finish(const Partial* part, int np, const Partial* pdiv, int nd, StepScalars* sc,
                          DiagRec* ring, int ring_cap, double dv, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, part, np, pdiv, nd, sc, ring, ring_cap, dv);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, part, np, pdiv, nd, sc, ring, ring_cap, dv);
     return hipGetLastError();
 }
 
 hipError_t launch_set_rate(const Partial* part, int np, StepScalars* sc, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_rate, dim3(1), dim3(256), 0, s, part, np, sc);
+    hipLaunchKernelGGL(k_set_rate, dim3(1), dim3(1024), 0, s, part, np, sc);
     return hipGetLastError();
 }
 
