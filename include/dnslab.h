@@ -134,7 +134,10 @@ int dnslab_poisson(dnslab_ctx* ctx, const void* rhs_dev, void* p_dev);
 
 /* The projection of Section 2.2 applied in place to the velocity u*, v*, w*
  * (device, field type): n_piter immersed-boundary iterations warm-started from
- * the bound pressure p (which is updated), then u = beta (u* - grad p). */
+ * the bound pressure p (which is updated), then u = beta (u* - grad p).  In
+ * DNSLAB_FP32_REFINE the last pressure solve is refined once in FP64: its
+ * residual is formed in FP64 from the FP32 fields, a correction is solved for,
+ * and the velocity correction is applied in FP64 arithmetic. */
 int dnslab_project(dnslab_ctx* ctx, void* u, void* v, void* w);
 
 /* One RK4 step of the scalar (item 5) of length dt with the bound velocity
@@ -167,7 +170,8 @@ const char* dnslab_last_error(const dnslab_ctx* ctx);
 
 /* Kernel timing for roofline measurements: when enabled, every launch of the
  * named kernel ("mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
- * "fft_x_inv", "filter", "correct", "div", "ib_rhs", "finish") is bracketed by HIP events on the
+ * "fft_x_inv", "filter", "correct", "div", "ib_rhs", "finish", "refine_res") is bracketed
+ * by HIP events on the
  * context's stream, and the total and count accumulate.  Read synchronises. */
 int dnslab_profile_enable(dnslab_ctx* ctx, const char* kernel_name);
 int dnslab_profile_read(dnslab_ctx* ctx, double* total_ms, int64_t* launches);

@@ -25,9 +25,10 @@ thread_local std::string g_thread_err;
 constexpr int RING_CAP = 4096;
 constexpr int PROF_POOL = 32768;
 
-enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_CORR, K_DIV, K_IB, K_FIN, K_COUNT };
-const char* const kKernelNames[K_COUNT] = {"mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
-                                            "fft_x_inv", "filter", "correct", "div", "ib_rhs", "finish"};
+enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_CORR, K_DIV, K_IB, K_FIN, K_REF,
+                K_COUNT };
+const char* const kKernelNames[K_COUNT] = {"mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z", "fft_x_inv",
+                                            "filter", "correct", "div", "ib_rhs", "finish", "refine_res"};
 
 bool is_2a3b(int n) {
     if (n < 1) return false;
@@ -345,6 +346,10 @@ int poisson_solve(dnslab_ctx* x, const T* r, T* pout) {
 }
 
 // Projection of Section 2.2: r0 = div u*, n IB iterations on the bound p, correction.
+// In the FP32 form the last solve is refined once in FP64 (iterative
+// refinement): its residual r_n - Lap_h p_n is formed in FP64 from the FP32
+// fields, solved for a correction dp, and the velocity correction
+// u = beta (u* - grad(p_n + dp)) is applied in FP64 arithmetic.
 template <typename T>
 int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
     T* r0 = (T*)x->f[9];
@@ -356,10 +361,38 @@ int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
     LAUNCH(x, K_DIV, launch_div<T>(d, x->Lo.L1, x->stream));
     // With no solid cell the iterates are identical: one solve gives them all.
     const int nit = x->any_solid ? x->P.n_piter : std::min(x->P.n_piter, 1);
+    constexpr bool fp32 = sizeof(T) == 4;
+    const bool refine = fp32 && x->P.precision == DNSLAB_FP32_REFINE && nit > 0;
+    T* p_last = refine ? (T*)x->f[3] : p;    // the last iterate goes to a scratch field when refining
     for (int it = 0; it < nit; ++it) {
         if (x->any_solid) LAUNCH(x, K_IB, launch_ib_rhs<T>(x->ib, x->g, p, r0, (T*)x->ib_r0, it == 0, x->stream));
-        int rc = poisson_solve<T>(x, r0, p);
+        int rc = poisson_solve<T>(x, r0, it == nit - 1 ? p_last : p);
         if (rc) return rc;
+    }
+    if constexpr (fp32) {
+        if (refine) {
+            float* res = (float*)x->f[4];
+            float* dp = (float*)x->f[5];
+            RefineResArgs ra;
+            for (int a = 0; a < 3; ++a) ra.us[a] = (const float*)us[a];
+            ra.p3 = (const float*)p;
+            ra.p4 = (const float*)p_last;
+            ra.flags = x->flags;
+            ra.res = res;
+            ra.g = x->g;
+            LAUNCH(x, K_REF, launch_refine_res(ra, x->Lo.L1, x->stream));
+            int rc = poisson_solve<float>(x, res, dp);
+            if (rc) return rc;
+            RefineCorrArgs rc2;
+            for (int a = 0; a < 3; ++a) { rc2.us[a] = (const float*)us[a]; rc2.out[a] = (float*)out[a]; }
+            rc2.p4 = (const float*)p_last;
+            rc2.dp = dp;
+            rc2.p = (float*)p;
+            rc2.flags = x->flags;
+            rc2.g = x->g;
+            LAUNCH(x, K_CORR, launch_refine_correct(rc2, x->Lo.L1, x->stream));
+            return DNSLAB_OK;
+        }
     }
     CorrArgs<T> ca;
     for (int a = 0; a < 3; ++a) { ca.us[a] = us[a]; ca.out[a] = out[a]; }

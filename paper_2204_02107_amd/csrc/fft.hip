@@ -16,6 +16,7 @@
 // coalesced.
 #include "fft.h"
 
+
 namespace dnslab {
 
 namespace {

@@ -76,6 +76,32 @@ struct DivArgs {
     int kc;
 };
 
+// FP64 refinement of the last pressure solve of the FP32 form.
+// res = div u* + div((1-beta) grad p3) - Lap_h p4, evaluated in FP64 from the
+// FP32 fields (Lap_h = div grad with central differences), stored as FP32.
+struct RefineResArgs {
+    const float* us[3];
+    const float* p3;       // pressure iterate entering the last solve
+    const float* p4;       // result of the last FP32 solve
+    const uint8_t* flags;
+    float* res;
+    Grid g;
+    int kc;
+};
+// u = beta (u* - grad(p4 + dp)) and p = p4 + dp, in FP64 arithmetic.
+struct RefineCorrArgs {
+    const float* us[3];    // may alias out
+    float* out[3];
+    const float* p4;
+    const float* dp;
+    float* p;
+    const uint8_t* flags;
+    Grid g;
+    int kc;
+};
+hipError_t launch_refine_res(const RefineResArgs& a, const struct StencilLaunch& L, hipStream_t s);
+hipError_t launch_refine_correct(const RefineCorrArgs& a, const struct StencilLaunch& L, hipStream_t s);
+
 // Launch geometry shared by all z-marching stencil kernels.
 struct StencilLaunch {
     dim3 grid, block;

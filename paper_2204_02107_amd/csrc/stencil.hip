@@ -234,7 +234,8 @@ __global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) {
                 a.acc[idx] = c0 + (dt / T(6)) * G;
                 a.out[idx] = c0 + (dt / T(2)) * G;
                 if (a.part) {
-                    const double dv = (double)((uxp - uxm) * h2x + (vyp - vym) * h2y + (wp - wm) * h2z);
+                    const double dv = ((double)uxp - (double)uxm) * g.inv2d[0] + ((double)vyp - (double)vym) * g.inv2d[1] +
+                                      ((double)wp - (double)wm) * g.inv2d[2];
                     part.div2 += dv * dv;
                 }
             } else if (MODE == ST_HALF || MODE == ST_FULL) {
@@ -354,6 +355,92 @@ __global__ __launch_bounds__(1024) void k_correct(const CorrArgs<T> a) {
         a.out[1][idx] = fluid ? v - gy : T(0);
         a.out[2][idx] = fluid ? w - gz : T(0);
         pm = p0; p0 = pp;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual of the last FP32 pressure solve (iterative refinement):
+// res = div u* + div((1-beta) grad p3) - div grad p4, all in FP64.  The
+// radius-2 operator div grad p4 = sum_a (p4(x+2e) - 2 p4 + p4(x-2e)) / (4 dx_a^2).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_refine_res(const RefineResArgs a) {
+    const Grid& g = a.g;
+    const Col col = column(g, a.kc);
+    if (!col.active) return;
+    const int k0 = col.k0, k1 = col.k1;
+    const unsigned nxy = (unsigned)g.nxy;
+    const int ixm2 = wrap(col.i - 2, g.nx), ixp2 = wrap(col.i + 2, g.nx);
+    const unsigned rowm2 = (unsigned)wrap(col.j - 2, g.ny) * g.nx, rowp2 = (unsigned)wrap(col.j + 2, g.ny) * g.nx;
+    const double h2[3] = {g.inv2d[0], g.inv2d[1], g.inv2d[2]};
+    // z windows: w at k-1..k+1, p4 at k-2..k+2
+    double wz[3], pz[5];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) wz[m] = (double)a.us[2][(unsigned)wrap(k0 - 1 + m, g.nz) * nxy + col.row + col.i];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) pz[m] = (double)a.p4[(unsigned)wrap(k0 - 2 + m, g.nz) * nxy + col.row + col.i];
+    for (int k = k0; k < k1; ++k) {
+        const unsigned base = (unsigned)k * nxy;
+        const unsigned idx = base + col.row + col.i;
+        wz[2] = (double)a.us[2][(unsigned)wrap(k + 1, g.nz) * nxy + col.row + col.i];
+        pz[4] = (double)a.p4[(unsigned)wrap(k + 2, g.nz) * nxy + col.row + col.i];
+        const double div = ((double)a.us[0][base + col.row + col.ip] - (double)a.us[0][base + col.row + col.im]) * h2[0] +
+                           ((double)a.us[1][base + col.rowp + col.i] - (double)a.us[1][base + col.rowm + col.i]) * h2[1] +
+                           (wz[2] - wz[0]) * h2[2];
+        const double p0 = pz[2];
+        const double lap =
+            ((double)a.p4[base + col.row + ixp2] - 2.0 * p0 + (double)a.p4[base + col.row + ixm2]) * (h2[0] * h2[0]) +
+            ((double)a.p4[base + rowp2 + col.i] - 2.0 * p0 + (double)a.p4[base + rowm2 + col.i]) * (h2[1] * h2[1]) +
+            (pz[4] - 2.0 * p0 + pz[0]) * (h2[2] * h2[2]);
+        double ib = 0.0;
+        if (a.flags[idx] & F_NEAR_SOLID) {
+            // div((1-beta) grad p3) from the face neighbours that are solid
+            const int c0[3] = {col.i, col.j, k};
+            const int nn[3] = {g.nx, g.ny, g.nz};
+            const double q0 = (double)a.p3[idx];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                int c[3] = {c0[0], c0[1], c0[2]};
+                auto at = [&](int off) -> unsigned {
+                    c[ax] = wrap(c0[ax] + off, nn[ax]);
+                    const unsigned r = (unsigned)c[0] + (unsigned)g.nx * ((unsigned)c[1] + (unsigned)g.ny * c[2]);
+                    c[ax] = c0[ax];
+                    return r;
+                };
+                if (!(a.flags[at(1)] & F_FLUID)) ib += (((double)a.p3[at(2)] - q0) * h2[ax]) * h2[ax];
+                if (!(a.flags[at(-1)] & F_FLUID)) ib -= ((q0 - (double)a.p3[at(-2)]) * h2[ax]) * h2[ax];
+            }
+        }
+        a.res[idx] = (float)(div + ib - lap);
+        wz[0] = wz[1]; wz[1] = wz[2];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) pz[m] = pz[m + 1];
+    }
+}
+
+// u = beta (u* - grad(p4 + dp)), p = p4 + dp, FP64 arithmetic, FP32 storage.
+__global__ __launch_bounds__(1024) void k_refine_correct(const RefineCorrArgs a) {
+    const Grid& g = a.g;
+    const Col col = column(g, a.kc);
+    if (!col.active) return;
+    const int k0 = col.k0, k1 = col.k1;
+    const unsigned nxy = (unsigned)g.nxy;
+    auto P = [&](unsigned i) -> double { return (double)a.p4[i] + (double)a.dp[i]; };
+    double qm = P((unsigned)wrap(k0 - 1, g.nz) * nxy + col.row + col.i);
+    double q0 = P((unsigned)k0 * nxy + col.row + col.i);
+    for (int k = k0; k < k1; ++k) {
+        const unsigned base = (unsigned)k * nxy;
+        const unsigned idx = base + col.row + col.i;
+        const double qp = P((unsigned)wrap(k + 1, g.nz) * nxy + col.row + col.i);
+        const double gx = (P(base + col.row + col.ip) - P(base + col.row + col.im)) * g.inv2d[0];
+        const double gy = (P(base + col.rowp + col.i) - P(base + col.rowm + col.i)) * g.inv2d[1];
+        const double gz = (qp - qm) * g.inv2d[2];
+        const bool fluid = a.flags[idx] & F_FLUID;
+        const double u = a.us[0][idx], v = a.us[1][idx], w = a.us[2][idx];
+        a.out[0][idx] = fluid ? (float)(u - gx) : 0.0f;
+        a.out[1][idx] = fluid ? (float)(v - gy) : 0.0f;
+        a.out[2][idx] = fluid ? (float)(w - gz) : 0.0f;
+        a.p[idx] = (float)q0;
+        qm = q0; q0 = qp;
     }
 }
 
@@ -526,6 +613,20 @@ template <typename T>
 hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g, Partial* part,
                        const StencilLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL((k_rate<T>), L.grid, L.block, 0, s, u, v, w, g, L.kc, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_res(const RefineResArgs& a, const StencilLaunch& L, hipStream_t s) {
+    RefineResArgs b = a;
+    b.kc = L.kc;
+    hipLaunchKernelGGL(k_refine_res, L.grid, L.block, 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_correct(const RefineCorrArgs& a, const StencilLaunch& L, hipStream_t s) {
+    RefineCorrArgs b = a;
+    b.kc = L.kc;
+    hipLaunchKernelGGL(k_refine_correct, L.grid, L.block, 0, s, b);
     return hipGetLastError();
 }
 
