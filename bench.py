@@ -92,6 +92,25 @@ def cpu_baseline(sc, budget_s=20.0):
     }
 
 
+def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7):
+    """The serving stream: Poisson arrivals of room scenarios of four grid
+    sizes, served (a) with continuous batching in the pool (FP32 with FP64
+    refinement, HBM budget deliberately small so admission binds) and (b) FIFO
+    with the plain per-scenario FP64 loop.  Returns both summaries."""
+    import scenarios
+    from paper_2204_02107_amd import serving, FP32_REFINE, FP64
+    reqs = scenarios.serving_requests(n_req, seed=seed, mean_gap=mean_gap, n_steps=n_steps)
+    cases = {r["id"]: scenarios.serving_scenario(r) for r in reqs}
+    pooled = serving.serve(reqs, cases, int(budget_gib * (1 << 30)), FP32_REFINE)
+    base = serving.fifo(reqs, cases, FP64)
+    out = {
+        "requests": n_req, "steps_each": n_steps, "mean_gap_s": mean_gap, "hbm_budget_GiB": budget_gib,
+        "pool_fp32_refine": serving.summarize(pooled),
+        "fifo_fp64": serving.summarize(base),
+    }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +118,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--serving", default="short", choices=["none", "short", "full"],
+                    help="serving stream: short = 16 requests x 300 steps, full = 64 x 2000")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step runs on a single MI355X and this build has "
@@ -190,10 +211,15 @@ def main():
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["GBs"], 1),
                         "launches_per_step": v["launches_per_step"]} for k, v in per.items()},
     }
+    S.close()
+    if args.serving != "none":
+        n_req, n_steps = (16, 300) if args.serving == "short" else (64, 2000)
+        print(f"[bench] serving stream {n_req} x {n_steps} ...", file=sys.stderr, flush=True)
+        out["serving"] = serving_bench(n_req, n_steps, budget_gib=1.0)
+        print("[bench] serving: " + json.dumps(out["serving"]), file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc)
-    S.close()
     print(json.dumps(out), flush=True)
 
 

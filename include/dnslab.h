@@ -176,6 +176,59 @@ const char* dnslab_last_error(const dnslab_ctx* ctx);
 int dnslab_profile_enable(dnslab_ctx* ctx, const char* kernel_name);
 int dnslab_profile_read(dnslab_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* ------------------------------------------------------------------------
+ * Serving pool: many scenarios of different grid sizes resident at once,
+ * admitted against an HBM budget and advanced together.  Each step of the
+ * pool issues, for every kernel of the step sequence, one batched launch over
+ * all active scenarios (scenarios with identical launch sequences share a
+ * launch); every scenario computes exactly what dnslab_step would compute for
+ * it alone, so its result is independent of the mix.  The pool owns the
+ * scenarios' device memory.  All pool calls use the pool's stream; a pool is
+ * not thread-safe.
+ * ------------------------------------------------------------------------ */
+
+/* Create an empty pool with hbm_budget bytes of device memory for scenarios
+ * (state + workspace), all of the given precision, working on stream. */
+int dnslab_pool_create(size_t hbm_budget, int32_t precision, void* stream, dnslab_pool** out);
+
+/* Admit a scenario that will run target_steps steps.  All arrays are HOST
+ * memory with the layouts of dnslab_init (initial fields in FP64, converted to
+ * the pool precision); params->precision must equal the pool's and
+ * params->stream is ignored.  Returns DNSLAB_EAGAIN, with nothing allocated,
+ * when the scenario's memory does not fit in what is left of the budget.
+ * Synchronises the pool's stream.  *slot_out receives the slot id. */
+int dnslab_pool_admit(dnslab_pool* pool, const dnslab_params* params, int64_t target_steps,
+                      const uint8_t* beta_host, int64_t n_forced, const int64_t* forced_idx_host,
+                      const double* forced_S_host, const double* forced_uset_host,
+                      const double* forced_cset_host, const uint8_t* room_mask_host,
+                      const double* u0_host, const double* v0_host, const double* w0_host,
+                      const double* p0_host, const double* c0_host, int32_t* slot_out);
+
+/* Advance every admitted scenario that has not reached its target by up to
+ * nsteps steps (asynchronous; scenarios stop at their own target). */
+int dnslab_pool_step(dnslab_pool* pool, int32_t nsteps);
+
+/* Progress of a slot: the last step's diagnostics (zeros before the first
+ * step), steps taken and whether the target is reached.  Synchronises. */
+int dnslab_pool_query(dnslab_pool* pool, int32_t slot, dnslab_diag* last, int64_t* steps_done,
+                      int32_t* done);
+
+/* Copy field 0..4 (u, v, w, p, c) of a slot to host memory as FP64
+ * (nx*ny*nz values).  Synchronises. */
+int dnslab_pool_read_field(dnslab_pool* pool, int32_t slot, int32_t field, double* host_out);
+
+/* Free a slot's memory and return it to the budget.  Synchronises. */
+int dnslab_pool_release(dnslab_pool* pool, int32_t slot);
+
+/* Bytes of the budget in use, scenarios still running, scenarios resident. */
+int dnslab_pool_usage(dnslab_pool* pool, size_t* bytes_in_use, int32_t* active, int32_t* resident);
+
+/* Message of the last error on pool (NULL: this thread's last error).  Never NULL. */
+const char* dnslab_pool_last_error(const dnslab_pool* pool);
+
+/* Release every slot and the pool.  NULL is a no-op. */
+void dnslab_pool_destroy(dnslab_pool* pool);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,9 @@ EXPORTS = [
     "dnslab_project", "dnslab_scalar_step", "dnslab_momentum_rhs", "dnslab_scalar_rhs",
     "dnslab_filter", "dnslab_set_time", "dnslab_destroy", "dnslab_last_error",
     "dnslab_profile_enable", "dnslab_profile_read",
+    "dnslab_pool_create", "dnslab_pool_admit", "dnslab_pool_step", "dnslab_pool_query",
+    "dnslab_pool_read_field", "dnslab_pool_release", "dnslab_pool_usage", "dnslab_pool_last_error",
+    "dnslab_pool_destroy",
 ]
 
 
@@ -81,6 +84,16 @@ def load():
         "dnslab_last_error": (c_char_p, [V]),
         "dnslab_profile_enable": (c_int, [V, c_char_p]),
         "dnslab_profile_read": (c_int, [V, P(c_double), P(c_int64)]),
+        "dnslab_pool_create": (c_int, [c_size_t, c_int32, V, P(V)]),
+        "dnslab_pool_admit": (c_int, [V, P(Params), c_int64, V, c_int64, V, V, V, V, V, V, V, V, V, V,
+                                      P(c_int32)]),
+        "dnslab_pool_step": (c_int, [V, c_int32]),
+        "dnslab_pool_query": (c_int, [V, c_int32, P(Diag), P(c_int64), P(c_int32)]),
+        "dnslab_pool_read_field": (c_int, [V, c_int32, c_int32, V]),
+        "dnslab_pool_release": (c_int, [V, c_int32]),
+        "dnslab_pool_usage": (c_int, [V, P(c_size_t), P(c_int32), P(c_int32)]),
+        "dnslab_pool_last_error": (c_char_p, [V]),
+        "dnslab_pool_destroy": (None, [V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -93,5 +106,12 @@ def load():
 def check(rc, ctx=None):
     if rc != DNSLAB_OK:
         msg = load().dnslab_last_error(ctx)
+        raise DnslabError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def check_pool(rc, pool=None):
+    if rc != DNSLAB_OK:
+        msg = load().dnslab_pool_last_error(pool)
         raise DnslabError(rc, msg.decode() if msg else "")
     return rc

@@ -231,6 +231,7 @@ struct dnslab_ctx {
     DiagRec* pinned;       // host staging for diagnostics
     StepScalars* pinned_sc;
     std::string err;
+    Recorder* rec;         // non-NULL: launches are recorded for batched replay, not issued
     // profiling
     int prof_kid;
     std::vector<hipEvent_t> ev;
@@ -271,7 +272,7 @@ int prof_flush(dnslab_ctx* x) {
 struct Prof {
     dnslab_ctx* x;
     bool on;
-    Prof(dnslab_ctx* x_, int kid) : x(x_), on(x_->prof_kid == kid) {
+    Prof(dnslab_ctx* x_, int kid) : x(x_), on(x_->prof_kid == kid && !x_->rec) {
         if (on) {
             if (x->ev_used + 2 > (int)x->ev.size()) prof_flush(x);
             (void)hipEventRecord(x->ev[x->ev_used], x->stream);
@@ -337,11 +338,11 @@ FFTArgs<T> fft_args(dnslab_ctx* x) {
 template <typename T>
 int poisson_solve(dnslab_ctx* x, const T* r, T* pout) {
     const FFTArgs<T> a = fft_args<T>(x);
-    LAUNCH(x, K_FXF, launch_fft_x_fwd<T>(a, r, x->stream));
-    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, false, x->stream));
-    LAUNCH(x, K_FZ, launch_fft_z_solve<T>(a, x->stream));
-    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, true, x->stream));
-    LAUNCH(x, K_FXI, launch_fft_x_inv<T>(a, pout, x->stream));
+    LAUNCH(x, K_FXF, launch_fft_x_fwd<T>(a, r, x->stream, x->rec));
+    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, false, x->stream, x->rec));
+    LAUNCH(x, K_FZ, launch_fft_z_solve<T>(a, x->stream, x->rec));
+    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, true, x->stream, x->rec));
+    LAUNCH(x, K_FXI, launch_fft_x_inv<T>(a, pout, x->stream, x->rec));
     return DNSLAB_OK;
 }
 
@@ -358,14 +359,14 @@ int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
     for (int a = 0; a < 3; ++a) d.u[a] = us[a];
     d.out = r0;
     d.g = x->g;
-    LAUNCH(x, K_DIV, launch_div<T>(d, x->Lo.L1, x->stream));
+    LAUNCH(x, K_DIV, launch_div<T>(d, x->Lo.L1, x->stream, x->rec));
     // With no solid cell the iterates are identical: one solve gives them all.
     const int nit = x->any_solid ? x->P.n_piter : std::min(x->P.n_piter, 1);
     constexpr bool fp32 = sizeof(T) == 4;
     const bool refine = fp32 && x->P.precision == DNSLAB_FP32_REFINE && nit > 0;
     T* p_last = refine ? (T*)x->f[3] : p;    // the last iterate goes to a scratch field when refining
     for (int it = 0; it < nit; ++it) {
-        if (x->any_solid) LAUNCH(x, K_IB, launch_ib_rhs<T>(x->ib, x->g, p, r0, (T*)x->ib_r0, it == 0, x->stream));
+        if (x->any_solid) LAUNCH(x, K_IB, launch_ib_rhs<T>(x->ib, x->g, p, r0, (T*)x->ib_r0, it == 0, x->stream, x->rec));
         int rc = poisson_solve<T>(x, r0, it == nit - 1 ? p_last : p);
         if (rc) return rc;
     }
@@ -380,7 +381,7 @@ int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
             ra.flags = x->flags;
             ra.res = res;
             ra.g = x->g;
-            LAUNCH(x, K_REF, launch_refine_res(ra, x->Lo.L1, x->stream));
+            LAUNCH(x, K_REF, launch_refine_res(ra, x->Lo.L1, x->stream, x->rec));
             int rc = poisson_solve<float>(x, res, dp);
             if (rc) return rc;
             RefineCorrArgs rc2;
@@ -390,7 +391,7 @@ int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
             rc2.p = (float*)p;
             rc2.flags = x->flags;
             rc2.g = x->g;
-            LAUNCH(x, K_CORR, launch_refine_correct(rc2, x->Lo.L1, x->stream));
+            LAUNCH(x, K_CORR, launch_refine_correct(rc2, x->Lo.L1, x->stream, x->rec));
             return DNSLAB_OK;
         }
     }
@@ -399,7 +400,7 @@ int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
     ca.p = p;
     ca.flags = x->flags;
     ca.g = x->g;
-    LAUNCH(x, K_CORR, launch_correct<T>(ca, x->Lo.L1, x->stream));
+    LAUNCH(x, K_CORR, launch_correct<T>(ca, x->Lo.L1, x->stream, x->rec));
     return DNSLAB_OK;
 }
 
@@ -421,19 +422,19 @@ int scalar_rk4(dnslab_ctx* x, const T* const uvel[3], const double* dtp, double 
     s.acc = CA;
     const StencilLaunch& L = x->Lo.L;
     s.cs = C; s.out = CS1; s.part = pdiv;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FIRST, s, L, x->stream));
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FIRST, s, L, x->stream, x->rec));
     s.cs = CS1; s.cn = C; s.out = CS2; s.part = nullptr;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_HALF, s, L, x->stream));
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_HALF, s, L, x->stream, x->rec));
     s.cs = CS2; s.cn = C; s.out = CS1;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FULL, s, L, x->stream));
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FULL, s, L, x->stream, x->rec));
     s.cs = CS1; s.cn = nullptr; s.out = cout; s.part = pdiag;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_LAST, s, L, x->stream));
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_LAST, s, L, x->stream, x->rec));
     return DNSLAB_OK;
 }
 
 template <typename T>
 int ensure_rate(dnslab_ctx* x) {
-    if (x->rate_valid) return DNSLAB_OK;
+    if (x->rate_valid || x->rec) return DNSLAB_OK;
     HIPCHK(x, launch_rate<T>((const T*)x->u, (const T*)x->v, (const T*)x->w, x->g, x->part, x->Lo.L1, x->stream));
     HIPCHK(x, launch_set_rate(x->part, x->Lo.L1.nblocks, x->sc, x->stream));
     x->rate_valid = true;
@@ -458,13 +459,13 @@ int one_step(dnslab_ctx* x) {
     m.g = x->g;
     // RK4 stages (Section 2.1), no pressure gradient
     for (int a = 0; a < 3; ++a) { m.us[a] = U[a]; m.acc[a] = A[a]; m.out[a] = B[a]; m.un[a] = nullptr; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FIRST, m, L, x->stream));
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FIRST, m, L, x->stream, x->rec));
     for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = U[a]; m.out[a] = Cb[a]; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_HALF, m, L, x->stream));
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_HALF, m, L, x->stream, x->rec));
     for (int a = 0; a < 3; ++a) { m.us[a] = Cb[a]; m.out[a] = B[a]; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FULL, m, L, x->stream));
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FULL, m, L, x->stream, x->rec));
     for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = nullptr; m.out[a] = Cb[a]; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_LAST, m, L, x->stream));
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_LAST, m, L, x->stream, x->rec));
     // projection: u* in Cb -> corrected velocity (into A when the filter follows)
     const bool filt = x->P.filter != 0;
     T* const* V = filt ? A : U;
@@ -484,11 +485,20 @@ int one_step(dnslab_ctx* x) {
         fa.flags = x->flags;
         fa.g = x->g;
         fa.part = x->part;
-        LAUNCH(x, K_FILT, launch_filter<T>(fa, x->Lo.LF, x->stream));
+        LAUNCH(x, K_FILT, launch_filter<T>(fa, x->Lo.LF, x->stream, x->rec));
     }
     const int np = filt ? x->Lo.LF.nblocks : L.nblocks;
-    LAUNCH(x, K_FIN, launch_finish(x->part, np, x->pdiv, L.nblocks, x->sc, x->ring, RING_CAP, x->g.dv, x->stream));
-    x->host_step += 1;
+    FinishArgs fa2;
+    fa2.part = x->part;
+    fa2.np = np;
+    fa2.pdiv = x->pdiv;
+    fa2.nd = L.nblocks;
+    fa2.sc = x->sc;
+    fa2.ring = x->ring;
+    fa2.ring_cap = RING_CAP;
+    fa2.dv = x->g.dv;
+    LAUNCH(x, K_FIN, launch_finish(fa2, x->stream, x->rec));
+    if (!x->rec) x->host_step += 1;
     return DNSLAB_OK;
 }
 
@@ -501,6 +511,30 @@ void diag_copy(const DiagRec& r, dnslab_diag* d) {
     d->co2_room_mean = r.co2_room_mean;
     d->cfl_max = r.cfl_max;
     d->step = r.step;
+}
+
+// Visit every cell with the bit set of its solid face neighbours
+// (+x, -x, +y, -y, +z, -z) = (1, 2, 4, 8, 16, 32), periodic.
+template <class F>
+void for_each_cell_solid_neighbours(const uint8_t* beta, int nx, int ny, int nz, F&& visit) {
+    for (int k = 0; k < nz; ++k) {
+        const int kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
+        for (int j = 0; j < ny; ++j) {
+            const int jp = j + 1 == ny ? 0 : j + 1, jm = j == 0 ? ny - 1 : j - 1;
+            const size_t row = ((size_t)k * ny + j) * nx;
+            const uint8_t* r0 = beta + row;
+            const uint8_t* ryp = beta + ((size_t)k * ny + jp) * nx;
+            const uint8_t* rym = beta + ((size_t)k * ny + jm) * nx;
+            const uint8_t* rzp = beta + ((size_t)kp * ny + j) * nx;
+            const uint8_t* rzm = beta + ((size_t)km * ny + j) * nx;
+            for (int i = 0; i < nx; ++i) {
+                const int ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
+                const unsigned m = (unsigned)(!r0[ip]) | (unsigned)(!r0[im]) << 1 | (unsigned)(!ryp[i]) << 2 |
+                                   (unsigned)(!rym[i]) << 3 | (unsigned)(!rzp[i]) << 4 | (unsigned)(!rzm[i]) << 5;
+                visit(row + i, m);
+            }
+        }
+    }
 }
 
 int build_flags(dnslab_ctx* x, const uint8_t* beta_dev, const long long* fidx_host, int64_t nf,
@@ -520,32 +554,16 @@ int build_flags(dnslab_ctx* x, const uint8_t* beta_dev, const long long* fidx_ho
         if (beta[i] > 1) return fail(x, DNSLAB_EINVAL, "beta must hold 0 or 1");
         if (!beta[i]) any_solid = true;
     }
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    for (int k = 0; k < nz; ++k)
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                const long long id = i + (long long)nx * (j + (long long)ny * k);
-                uint8_t f = beta[id] ? F_FLUID : 0;
-                if (room_dev ? room[id] != 0 : true) f |= F_ROOM;
-                const int ip = (i + 1) % nx, im = (i + nx - 1) % nx;
-                const int jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
-                const int kp = (k + 1) % nz, km = (k + nz - 1) % nz;
-                const long long nb[6] = {ip + (long long)nx * (j + (long long)ny * k),
-                                         im + (long long)nx * (j + (long long)ny * k),
-                                         i + (long long)nx * (jp + (long long)ny * k),
-                                         i + (long long)nx * (jm + (long long)ny * k),
-                                         i + (long long)nx * (j + (long long)ny * kp),
-                                         i + (long long)nx * (j + (long long)ny * km)};
-                uint8_t solid_nb = 0;
-                for (int q = 0; q < 6; ++q)
-                    if (!beta[nb[q]]) solid_nb |= (uint8_t)(1u << q);
-                if (solid_nb) {
-                    f |= F_NEAR_SOLID;
-                    ibidx.push_back((int)id);
-                    ibmask.push_back(solid_nb);
-                }
-                fl[id] = f;
-            }
+    for_each_cell_solid_neighbours(beta.data(), g.nx, g.ny, g.nz, [&](size_t id, unsigned solid_nb) {
+        uint8_t f = beta[id] ? F_FLUID : 0;
+        if (room_dev ? room[id] != 0 : true) f |= F_ROOM;
+        if (solid_nb) {
+            f |= F_NEAR_SOLID;
+            ibidx.push_back((int)id);
+            ibmask.push_back((uint8_t)solid_nb);
+        }
+        fl[id] = f;
+    });
     for (int64_t e = 0; e < nf; ++e) {
         const long long id = fidx_host[e];
         if (id < 0 || id >= g.n) return fail(x, DNSLAB_EINVAL, "forced index out of range");
@@ -622,7 +640,7 @@ int mom_rhs(dnslab_ctx* x, const void* u, const void* v, const void* w, void* fu
     m.nu = x->P.nu;
     for (int a = 0; a < 3; ++a) m.body[a] = x->P.body[a];
     m.g = x->g;
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_RHS, m, x->Lo.L, x->stream));
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_RHS, m, x->Lo.L, x->stream, x->rec));
     return DNSLAB_OK;
 }
 template <typename T>
@@ -635,7 +653,7 @@ int sca_rhs(dnslab_ctx* x, const void* c, const void* u, const void* v, const vo
     s.frc = forcing_of<T>(x);
     s.alpha = x->P.alpha_c;
     s.g = x->g;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_RHS, s, x->Lo.L, x->stream));
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_RHS, s, x->Lo.L, x->stream, x->rec));
     return DNSLAB_OK;
 }
 template <typename T>
@@ -646,7 +664,7 @@ int filt1(dnslab_ctx* x, const void* f, void* out) {
     a.nf = 1;
     a.flags = x->flags;
     a.g = x->g;
-    LAUNCH(x, K_FILT, launch_filter<T>(a, x->Lo.LF, x->stream));
+    LAUNCH(x, K_FILT, launch_filter<T>(a, x->Lo.LF, x->stream, x->rec));
     return DNSLAB_OK;
 }
 }  // namespace
@@ -729,10 +747,11 @@ int dnslab_init(const dnslab_params* params, const uint8_t* beta_dev, int64_t n_
         }
         rc = build_flags(x, beta_dev, fidx_h.data(), n_forced, room_mask_dev);
         if (rc == DNSLAB_OK && n_forced > 0) {
-            if (hipMemcpy(x->fidx, forced_idx_dev, n_forced * sizeof(long long), hipMemcpyDeviceToDevice) != hipSuccess ||
-                hipMemcpy(x->fS, forced_S_dev, n_forced * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
-                hipMemcpy(x->fuset, forced_uset_dev, 3 * n_forced * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
-                hipMemcpy(x->fcset, forced_cset_dev, n_forced * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess)
+            const hipStream_t st = x->stream;
+            if (hipMemcpyAsync(x->fidx, forced_idx_dev, n_forced * sizeof(long long), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(x->fS, forced_S_dev, n_forced * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(x->fuset, forced_uset_dev, 3 * n_forced * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(x->fcset, forced_cset_dev, n_forced * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
                 rc = fail(x, DNSLAB_EHIP, "copying forcing arrays failed");
         }
         if (rc == DNSLAB_OK) rc = Lo.esz == 8 ? upload_tables<double>(x) : upload_tables<float>(x);
@@ -909,6 +928,415 @@ int dnslab_profile_read(dnslab_ctx* x, double* total_ms, int64_t* launches) {
     if (total_ms) *total_ms = x->prof_ms;
     if (launches) *launches = x->prof_n;
     return DNSLAB_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving pool: many resident scenarios advanced together.  Each scenario is
+// an ordinary context with its own state and workspace.  The pool records the
+// launch sequence of one step of every active scenario once (nothing is
+// issued while recording), groups scenarios whose sequences match, and
+// replays each position of a group's sequence as one batched launch over all
+// its scenarios.  A scenario's blocks compute exactly what its own launches
+// would, so its result is the same alone and in any mix.
+// ===========================================================================
+namespace {
+
+struct PoolSlot {
+    dnslab_ctx* ctx = nullptr;
+    void* state = nullptr;
+    size_t bytes = 0;
+    long long target = 0, done = 0;
+    bool used = false;
+};
+
+struct BatchPos {
+    int kind;
+    dim3 block;
+    size_t lds;
+    unsigned total;
+    int ns;
+    size_t tab_off, st_off;
+};
+
+struct BatchGroup {
+    std::vector<int> slots;
+    std::vector<BatchPos> seq;
+};
+
+}  // namespace
+
+struct dnslab_pool {
+    size_t budget = 0, used = 0;
+    int precision = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t admit_stream = nullptr;   // init work of new scenarios, off the stepping stream
+    void* stage = nullptr;                // device staging for admission inputs (kept: hipFree synchronises)
+    size_t stage_cap = 0;
+    std::vector<PoolSlot> slots;
+    std::vector<BatchGroup> groups;
+    std::vector<int> active_ids;
+    bool dirty = true;
+    void* tab_dev = nullptr;
+    size_t tab_cap = 0;
+    std::string err;
+};
+
+namespace {
+
+int pfail(dnslab_pool* p, int code, const std::string& msg) {
+    if (p) p->err = msg;
+    else g_thread_err = msg;
+    return code;
+}
+
+#define PHIP(pool, call)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return pfail(pool, DNSLAB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_stencil_kind(int kind) { return (kind >> 8) < KK_IB; }
+
+// Record one step of every active slot and build the batched tables.
+int pool_rebuild(dnslab_pool* P, const std::vector<int>& active) {
+    PHIP(P, hipStreamSynchronize(P->stream));   // old tables may still be in use
+    std::vector<std::vector<LaunchRecord>> recs(active.size());
+    for (size_t q = 0; q < active.size(); ++q) {
+        dnslab_ctx* x = P->slots[active[q]].ctx;
+        Recorder r;
+        x->rec = &r;
+        const int rc = x->Lo.esz == 8 ? one_step<double>(x) : one_step<float>(x);
+        x->rec = nullptr;
+        if (rc) return pfail(P, rc, "recording a step failed: " + x->err);
+        recs[q] = std::move(r.recs);
+    }
+    // group slots by sequence signature
+    auto sig = [&](size_t q) {
+        std::vector<long long> v;
+        for (const LaunchRecord& l : recs[q]) {
+            long long key = (long long)l.kind << 32;
+            if (is_stencil_kind(l.kind)) key |= (long long)(l.block.x << 16 | l.block.y);
+            v.push_back(key);
+            v.push_back((long long)l.rec.size());
+        }
+        return v;
+    };
+    std::vector<std::vector<long long>> sigs;
+    P->groups.clear();
+    for (size_t q = 0; q < active.size(); ++q) {
+        const std::vector<long long> s = sig(q);
+        size_t g = 0;
+        for (; g < sigs.size(); ++g)
+            if (sigs[g] == s) break;
+        if (g == sigs.size()) {
+            sigs.push_back(s);
+            P->groups.emplace_back();
+        }
+        P->groups[g].slots.push_back((int)q);   // index into active/recs for now
+    }
+    // lay out the tables
+    std::vector<unsigned char> host;
+    auto put = [&](const void* src, size_t n) {
+        const size_t off = align_up(host.size(), 256);
+        host.resize(off + n);
+        std::memcpy(host.data() + off, src, n);
+        return off;
+    };
+    for (BatchGroup& G : P->groups) {
+        const size_t nseq = recs[G.slots[0]].size();
+        G.seq.resize(nseq);
+        for (size_t i = 0; i < nseq; ++i) {
+            BatchPos& bp = G.seq[i];
+            const LaunchRecord& l0 = recs[G.slots[0]][i];
+            bp.kind = l0.kind;
+            bp.block = l0.block;
+            bp.lds = 0;
+            bp.ns = (int)G.slots.size();
+            std::vector<unsigned char> tab;
+            std::vector<unsigned> starts;
+            unsigned total = 0;
+            for (int q : G.slots) {
+                const LaunchRecord& l = recs[q][i];
+                starts.push_back(total);
+                total += l.grid.x * l.grid.y * l.grid.z;
+                bp.block.x = std::max(bp.block.x, l.block.x);
+                bp.lds = std::max(bp.lds, l.lds);
+                tab.insert(tab.end(), l.rec.begin(), l.rec.end());
+            }
+            starts.push_back(total);
+            bp.total = total;
+            bp.tab_off = put(tab.data(), tab.size());
+            bp.st_off = put(starts.data(), starts.size() * sizeof(unsigned));
+        }
+        for (int& q : G.slots) q = active[q];   // back to slot ids
+    }
+    if (host.size() > P->tab_cap) {
+        if (P->tab_dev) (void)hipFree(P->tab_dev);
+        P->tab_dev = nullptr;
+        P->tab_cap = 0;
+        PHIP(P, hipMalloc(&P->tab_dev, host.size()));
+        P->tab_cap = host.size();
+    }
+    if (!host.empty()) PHIP(P, hipMemcpy(P->tab_dev, host.data(), host.size(), hipMemcpyHostToDevice));
+    P->active_ids = active;
+    P->dirty = false;
+    return DNSLAB_OK;
+}
+
+int pool_replay(dnslab_pool* P) {
+    char* base = (char*)P->tab_dev;
+    for (const BatchGroup& G : P->groups) {
+        for (const BatchPos& bp : G.seq) {
+            const void* tab = base + bp.tab_off;
+            const unsigned* st = (const unsigned*)(base + bp.st_off);
+            hipError_t e = is_stencil_kind(bp.kind)
+                               ? launch_batched_stencil(bp.kind, tab, st, bp.ns, bp.total, bp.block, bp.lds, P->stream)
+                               : launch_batched_fft(bp.kind, tab, st, bp.ns, bp.total, bp.block, bp.lds, P->stream);
+            if (e != hipSuccess) return pfail(P, DNSLAB_EHIP, std::string("batched launch: ") + hipGetErrorString(e));
+        }
+    }
+    return DNSLAB_OK;
+}
+
+size_t count_near_solid(const uint8_t* beta, int nx, int ny, int nz) {
+    size_t cnt = 0;
+    for_each_cell_solid_neighbours(beta, nx, ny, nz, [&](size_t, unsigned m) { cnt += m != 0; });
+    return cnt;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dnslab_pool_create(size_t hbm_budget, int32_t precision, void* stream, dnslab_pool** out) {
+    if (!out) return pfail(nullptr, DNSLAB_EINVAL, "out is NULL");
+    if (precision != DNSLAB_FP64 && precision != DNSLAB_FP32_REFINE) return pfail(nullptr, DNSLAB_EINVAL, "bad precision");
+    try {
+        dnslab_pool* P = new dnslab_pool();
+        P->budget = hbm_budget;
+        P->precision = precision;
+        P->stream = (hipStream_t)stream;
+        if (hipStreamCreateWithFlags(&P->admit_stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            delete P;
+            return pfail(nullptr, DNSLAB_EHIP, "creating the admission stream failed");
+        }
+        *out = P;
+        return DNSLAB_OK;
+    } catch (...) {
+        return pfail(nullptr, DNSLAB_ENOMEM, "host allocation failed");
+    }
+}
+
+int dnslab_pool_admit(dnslab_pool* P, const dnslab_params* params, int64_t target_steps, const uint8_t* beta_host,
+                      int64_t n_forced, const int64_t* fidx_host, const double* fS_host, const double* fuset_host,
+                      const double* fcset_host, const uint8_t* room_host, const double* u0, const double* v0,
+                      const double* w0, const double* p0, const double* c0, int32_t* slot_out) {
+    if (!P) return pfail(nullptr, DNSLAB_EINVAL, "pool is NULL");
+    try {
+        std::string why;
+        int rc = validate(params, why);
+        if (rc) return pfail(P, rc, why);
+        if (params->precision != P->precision) return pfail(P, DNSLAB_EINVAL, "precision differs from the pool's");
+        if (!beta_host || !u0 || !v0 || !w0 || !p0 || !c0 || !slot_out || target_steps < 0)
+            return pfail(P, DNSLAB_EINVAL, "bad argument");
+        if (n_forced < 0 || (n_forced > 0 && (!fidx_host || !fS_host || !fuset_host || !fcset_host)))
+            return pfail(P, DNSLAB_EINVAL, "bad forcing arguments");
+        dnslab_params prm = *params;
+        prm.stream = P->admit_stream;
+        const Layout Lo = make_layout(&prm, (int)n_forced);
+        const size_t n = (size_t)Lo.n, esz = Lo.esz;
+        const size_t field = align_up(n * esz, 256);
+        const size_t nib = count_near_solid(beta_host, prm.nx, prm.ny, prm.nz);
+        const size_t bytes = 5 * field + Lo.total + align_up(nib * 4, 256) + align_up(nib, 256) + nib * esz;
+        if (P->used + bytes > P->budget) return pfail(P, DNSLAB_EAGAIN, "HBM budget exhausted");
+        PoolSlot S;
+        S.bytes = bytes;
+        S.target = target_steps;
+        PHIP(P, hipMalloc(&S.state, 5 * field));
+        // upload the initial fields in the field type
+        std::vector<unsigned char> tmp(n * esz);
+        const double* src[5] = {u0, v0, w0, p0, c0};
+        void* dst[5];
+        for (int f = 0; f < 5; ++f) {
+            dst[f] = (char*)S.state + f * field;
+            if (esz == 8) std::memcpy(tmp.data(), src[f], n * 8);
+            else
+                for (size_t i = 0; i < n; ++i) ((float*)tmp.data())[i] = (float)src[f][i];
+            if (hipMemcpy(dst[f], tmp.data(), n * esz, hipMemcpyHostToDevice) != hipSuccess) {
+                (void)hipFree(S.state);
+                return pfail(P, DNSLAB_EHIP, "uploading initial fields failed");
+            }
+        }
+        // static inputs through temporary device buffers (dnslab_init copies them)
+        const size_t nf = (size_t)n_forced;
+        const size_t tb = align_up(n, 256) + (room_host ? align_up(n, 256) : 0) + nf * (8 + 8 + 24 + 8) + 1024;
+        if (tb > P->stage_cap) {
+            if (P->stage) (void)hipFree(P->stage);
+            P->stage = nullptr;
+            P->stage_cap = 0;
+            if (hipMalloc(&P->stage, tb) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipFree(S.state);
+                return pfail(P, DNSLAB_ENOMEM, "staging allocation failed");
+            }
+            P->stage_cap = tb;
+        }
+        char* t = (char*)P->stage;
+        uint8_t* beta_d = (uint8_t*)t;
+        t += align_up(n, 256);
+        uint8_t* room_d = nullptr;
+        if (room_host) { room_d = (uint8_t*)t; t += align_up(n, 256); }
+        int64_t* fidx_d = (int64_t*)t; t += nf * 8;
+        double* fS_d = (double*)t; t += nf * 8;
+        double* fus_d = (double*)t; t += nf * 24;
+        double* fcs_d = (double*)t;
+        bool ok = hipMemcpy(beta_d, beta_host, n, hipMemcpyHostToDevice) == hipSuccess;
+        if (room_host) ok = ok && hipMemcpy(room_d, room_host, n, hipMemcpyHostToDevice) == hipSuccess;
+        if (nf) {
+            ok = ok && hipMemcpy(fidx_d, fidx_host, nf * 8, hipMemcpyHostToDevice) == hipSuccess;
+            ok = ok && hipMemcpy(fS_d, fS_host, nf * 8, hipMemcpyHostToDevice) == hipSuccess;
+            ok = ok && hipMemcpy(fus_d, fuset_host, nf * 24, hipMemcpyHostToDevice) == hipSuccess;
+            ok = ok && hipMemcpy(fcs_d, fcset_host, nf * 8, hipMemcpyHostToDevice) == hipSuccess;
+        }
+        if (!ok) {
+            (void)hipFree(S.state);
+            return pfail(P, DNSLAB_EHIP, "uploading inputs failed");
+        }
+        rc = dnslab_init(&prm, beta_d, n_forced, nf ? fidx_d : nullptr, nf ? fS_d : nullptr, nf ? fus_d : nullptr,
+                         nf ? fcs_d : nullptr, room_d, dst[0], dst[1], dst[2], dst[3], dst[4], &S.ctx);
+        if (rc) {
+            (void)hipFree(S.state);
+            return pfail(P, rc, std::string("init: ") + dnslab_last_error(nullptr));
+        }
+        // dnslab_init has completed its work on the admission stream; from now on
+        // the scenario is advanced on the pool's stream.
+        S.ctx->stream = P->stream;
+        S.ctx->P.stream = P->stream;
+        S.used = true;
+        int slot = -1;
+        for (size_t i = 0; i < P->slots.size(); ++i)
+            if (!P->slots[i].used) { slot = (int)i; break; }
+        if (slot < 0) {
+            slot = (int)P->slots.size();
+            P->slots.push_back(S);
+        } else {
+            P->slots[slot] = S;
+        }
+        P->used += bytes;
+        P->dirty = true;
+        *slot_out = slot;
+        return DNSLAB_OK;
+    } catch (...) {
+        return pfail(P, DNSLAB_ENOMEM, "host allocation failed");
+    }
+}
+
+int dnslab_pool_step(dnslab_pool* P, int32_t nsteps) {
+    if (!P) return pfail(nullptr, DNSLAB_EINVAL, "pool is NULL");
+    if (nsteps < 0) return pfail(P, DNSLAB_EINVAL, "nsteps < 0");
+    try {
+        for (int it = 0; it < nsteps; ++it) {
+            std::vector<int> active;
+            for (size_t i = 0; i < P->slots.size(); ++i)
+                if (P->slots[i].used && P->slots[i].done < P->slots[i].target) active.push_back((int)i);
+            if (active.empty()) break;
+            if (P->dirty || active != P->active_ids) {
+                int rc = pool_rebuild(P, active);
+                if (rc) return rc;
+            }
+            int rc = pool_replay(P);
+            if (rc) return rc;
+            for (int i : active) {
+                P->slots[i].done += 1;
+                P->slots[i].ctx->host_step += 1;
+            }
+        }
+        return DNSLAB_OK;
+    } catch (...) {
+        return pfail(P, DNSLAB_ENOMEM, "host allocation failed");
+    }
+}
+
+int dnslab_pool_query(dnslab_pool* P, int32_t slot, dnslab_diag* last, int64_t* steps_done, int32_t* done) {
+    if (!P) return pfail(nullptr, DNSLAB_EINVAL, "pool is NULL");
+    if (slot < 0 || slot >= (int)P->slots.size() || !P->slots[slot].used) return pfail(P, DNSLAB_EINVAL, "bad slot");
+    PoolSlot& S = P->slots[slot];
+    if (steps_done) *steps_done = S.done;
+    if (done) *done = S.done >= S.target ? 1 : 0;
+    if (last) {
+        if (S.done == 0) {
+            std::memset(last, 0, sizeof(*last));
+        } else {
+            const int rc = dnslab_read_diags(S.ctx, 1, last);
+            if (rc) return pfail(P, rc, S.ctx->err);
+        }
+    }
+    return DNSLAB_OK;
+}
+
+int dnslab_pool_read_field(dnslab_pool* P, int32_t slot, int32_t field, double* host_out) {
+    if (!P) return pfail(nullptr, DNSLAB_EINVAL, "pool is NULL");
+    if (slot < 0 || slot >= (int)P->slots.size() || !P->slots[slot].used || field < 0 || field > 4 || !host_out)
+        return pfail(P, DNSLAB_EINVAL, "bad argument");
+    dnslab_ctx* x = P->slots[slot].ctx;
+    const size_t n = (size_t)x->g.n, esz = x->Lo.esz;
+    void* f[5] = {x->u, x->v, x->w, x->p, x->c};
+    PHIP(P, hipStreamSynchronize(P->stream));
+    if (esz == 8) {
+        PHIP(P, hipMemcpy(host_out, f[field], n * 8, hipMemcpyDeviceToHost));
+    } else {
+        try {
+            std::vector<float> tmp(n);
+            PHIP(P, hipMemcpy(tmp.data(), f[field], n * 4, hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < n; ++i) host_out[i] = tmp[i];
+        } catch (...) {
+            return pfail(P, DNSLAB_ENOMEM, "host allocation failed");
+        }
+    }
+    return DNSLAB_OK;
+}
+
+int dnslab_pool_release(dnslab_pool* P, int32_t slot) {
+    if (!P) return pfail(nullptr, DNSLAB_EINVAL, "pool is NULL");
+    if (slot < 0 || slot >= (int)P->slots.size() || !P->slots[slot].used) return pfail(P, DNSLAB_EINVAL, "bad slot");
+    PoolSlot& S = P->slots[slot];
+    dnslab_destroy(S.ctx);      // synchronises the stream
+    (void)hipFree(S.state);
+    P->used -= S.bytes;
+    S = PoolSlot();
+    P->dirty = true;
+    return DNSLAB_OK;
+}
+
+int dnslab_pool_usage(dnslab_pool* P, size_t* bytes_in_use, int32_t* active, int32_t* resident) {
+    if (!P) return pfail(nullptr, DNSLAB_EINVAL, "pool is NULL");
+    int a = 0, r = 0;
+    for (const PoolSlot& S : P->slots)
+        if (S.used) {
+            ++r;
+            if (S.done < S.target) ++a;
+        }
+    if (bytes_in_use) *bytes_in_use = P->used;
+    if (active) *active = a;
+    if (resident) *resident = r;
+    return DNSLAB_OK;
+}
+
+const char* dnslab_pool_last_error(const dnslab_pool* P) { return P ? P->err.c_str() : g_thread_err.c_str(); }
+
+void dnslab_pool_destroy(dnslab_pool* P) {
+    if (!P) return;
+    (void)hipStreamSynchronize(P->stream);
+    for (size_t i = 0; i < P->slots.size(); ++i)
+        if (P->slots[i].used) dnslab_pool_release(P, (int)i);
+    if (P->tab_dev) (void)hipFree(P->tab_dev);
+    if (P->admit_stream) (void)hipStreamDestroy(P->admit_stream);
+    if (P->stage) (void)hipFree(P->stage);
+    delete P;
 }
 
 }  // extern "C"

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
+#include <vector>
 
 namespace dnslab {
 
@@ -66,6 +68,79 @@ struct Forcing {
     int n;
     double inv_tau;
 };
+
+// Block coordinates of a launch: the block's index in its own (per-scenario)
+// grid and that grid's dimensions.  A plain launch takes them from blockIdx and
+// gridDim; a batched launch over several scenarios derives them from a table.
+struct BlockIdx3 {
+    unsigned hw;          // linear block index within the scenario's grid
+    unsigned gx, gy, gz;  // the scenario's grid dimensions
+};
+
+__device__ __forceinline__ BlockIdx3 hw_block() {
+    BlockIdx3 b;
+    b.gx = gridDim.x;
+    b.gy = gridDim.y;
+    b.gz = gridDim.z;
+    b.hw = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    return b;
+}
+
+// One entry of a batched launch table: a kernel's arguments for one scenario
+// and that scenario's grid dimensions.
+template <class A>
+struct BRec {
+    A a;
+    unsigned g[3];
+};
+
+// Scenario of this block in a batched launch: starts[s] <= blockIdx.x < starts[s+1].
+__device__ __forceinline__ int batch_slot(const unsigned* __restrict__ starts, int ns) {
+    int lo = 0, hi = ns - 1;
+    const unsigned b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Kernel kinds of the step sequence (for recording and batched replay).
+enum KernelKind : int {
+    KK_MOM = 1, KK_SCA, KK_FILT, KK_CORR, KK_DIV, KK_REFRES, KK_REFCORR, KK_FINISH,   // stencil.hip
+    KK_IB = 32, KK_FXF, KK_FXI, KK_COLS,                                              // fft.hip
+};
+__host__ __device__ constexpr int kind_code(int base, int mode, int fp32) { return (base << 8) | (mode << 1) | fp32; }
+
+// A launch captured instead of issued: the pool records each scenario's step
+// once and replays every position of the sequence as one batched launch.
+struct LaunchRecord {
+    int kind;             // kind_code(...)
+    dim3 grid, block;
+    size_t lds;
+    std::vector<unsigned char> rec;   // bytes of one BRec<Args>
+};
+struct Recorder {
+    std::vector<LaunchRecord> recs;
+};
+
+template <class A>
+inline void record_launch(Recorder* r, int kind, dim3 grid, dim3 block, size_t lds, const A& a) {
+    BRec<A> b;
+    std::memset(&b, 0, sizeof(b));
+    b.a = a;
+    b.g[0] = grid.x;
+    b.g[1] = grid.y;
+    b.g[2] = grid.z;
+    LaunchRecord lr;
+    lr.kind = kind;
+    lr.grid = grid;
+    lr.block = block;
+    lr.lds = lds;
+    lr.rec.resize(sizeof(b));
+    std::memcpy(lr.rec.data(), &b, sizeof(b));
+    r->recs.push_back(std::move(lr));
+}
 
 __device__ __forceinline__ int wrap(int i, int n) {
     i %= n;

@@ -48,23 +48,52 @@ struct IBList {
     int n;
 };
 
+// Arguments of the kernels that take more than the FFT description.
+template <typename T>
+struct IbArgs {
+    IBList ib;
+    Grid g;
+    const T* p;
+    T* r;
+    T* r0s;
+    int first;
+};
+template <typename T>
+struct FxfArgs {
+    FFTArgs<T> f;
+    const T* r;
+};
+template <typename T>
+struct FxiArgs {
+    FFTArgs<T> f;
+    T* p;
+};
+
+// Every launch_* issues one kernel on stream s, or, when rec is non-NULL,
+// records it for batched replay without issuing it.
+
 // r = r0 + div((1-beta) grad p) at the listed cells, in place in r.  On the
 // first iteration (first != 0) r holds r0 and r0 is saved into r0s[e];
 // later iterations read r0 from r0s.
 template <typename T>
-hipError_t launch_ib_rhs(const IBList& ib, const Grid& g, const T* p, T* r, T* r0s, int first, hipStream_t s);
+hipError_t launch_ib_rhs(const IBList& ib, const Grid& g, const T* p, T* r, T* r0s, int first, hipStream_t s,
+                         Recorder* rec = nullptr);
 
 // Forward x pass: real-to-complex along x of r into the spectrum.
 template <typename T>
-hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r, hipStream_t s);
+hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r, hipStream_t s, Recorder* rec = nullptr);
 template <typename T>
-hipError_t launch_fft_y(const FFTArgs<T>& a, bool inverse, hipStream_t s);
+hipError_t launch_fft_y(const FFTArgs<T>& a, bool inverse, hipStream_t s, Recorder* rec = nullptr);
 // z pass: forward, divide by lambda * ntot (zero on the null modes), inverse.
 template <typename T>
-hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s);
+hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec = nullptr);
 // Inverse x pass: C2R along x into p.
 template <typename T>
-hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s);
+hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s, Recorder* rec = nullptr);
+
+// Batched replay of one recorded FFT-kernel position (see launch_batched_stencil).
+hipError_t launch_batched_fft(int kind, const void* tab, const unsigned* starts, int ns, unsigned total_blocks,
+                              dim3 block, size_t lds, hipStream_t s);
 
 AxisPlan make_axis_plan(int n);
 

@@ -171,9 +171,14 @@ __device__ void fft_lds(C2<T>* s, const AxisPlan& ap, const C2<T>* W, int es, in
 // r = r0 + sum_a [ (1-beta)(x+e_a) D_a p(x+e_a) - (1-beta)(x-e_a) D_a p(x-e_a) ] / (2 dx_a)
 // with central D_a; (1-beta) is 1 exactly where the mask bit says "solid".
 template <typename T>
-__global__ __launch_bounds__(256) void k_ib_rhs(const IBList ib, const Grid g, const T* __restrict__ p,
-                                                T* __restrict__ r, T* __restrict__ r0s, int first) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void ib_rhs_body(const IbArgs<T>& A, unsigned blk) {
+    const IBList& ib = A.ib;
+    const Grid& g = A.g;
+    const T* __restrict__ p = A.p;
+    T* __restrict__ r = A.r;
+    T* __restrict__ r0s = A.r0s;
+    const int first = A.first;
+    const int e = blk * blockDim.x + threadIdx.x;
     if (e >= ib.n) return;
     const unsigned idx = (unsigned)ib.idx[e];
     const unsigned mask = ib.mask[e];
@@ -244,12 +249,14 @@ __device__ __forceinline__ LineSplit line_split(int m) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_fft_x_fwd(const FFTArgs<T> a, const T* __restrict__ r) {
+__device__ __forceinline__ void fft_x_fwd_body(const FxfArgs<T>& A, unsigned blk) {
+    const FFTArgs<T>& a = A.f;
+    const T* __restrict__ r = A.r;
     extern __shared__ unsigned char smem_raw[];
     C2<T>* s = reinterpret_cast<C2<T>*>(smem_raw);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lg = a.nl_x, m = a.m, ls = a.ls_x;
-    const int line0 = blockIdx.x << lg;
+    const int line0 = (int)blk << lg;
     const int nlines = a.g.ny * a.g.nz;
     const unsigned nx = a.g.nx;
     const LineSplit sp = line_split(m);
@@ -293,12 +300,14 @@ __global__ __launch_bounds__(1024) void k_fft_x_fwd(const FFTArgs<T> a, const T*
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_fft_x_inv(const FFTArgs<T> a, T* __restrict__ p) {
+__device__ __forceinline__ void fft_x_inv_body(const FxiArgs<T>& A, unsigned blk) {
+    const FFTArgs<T>& a = A.f;
+    T* __restrict__ p = A.p;
     extern __shared__ unsigned char smem_raw[];
     C2<T>* s = reinterpret_cast<C2<T>*>(smem_raw);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lg = a.nl_x, m = a.m, ls = a.ls_x;
-    const int line0 = blockIdx.x << lg;
+    const int line0 = (int)blk << lg;
     const int nlines = a.g.ny * a.g.nz;
     const unsigned nx = a.g.nx;
     const int m1 = m + 1;
@@ -367,7 +376,7 @@ __device__ __forceinline__ double recip(double x) {
 // empty tile in every plane, is handled by a few extra blocks that take TX
 // different planes of that column each.
 template <typename T, int MODE>
-__global__ __launch_bounds__(1024) void k_fft_cols(const FFTArgs<T> a) {
+__device__ __forceinline__ void fft_cols_body(const FFTArgs<T>& a, unsigned blk) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* s = reinterpret_cast<C2<T>*>(smem_raw);
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -380,7 +389,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(const FFTArgs<T> a) {
     const size_t ps = zp ? (size_t)a.sx : (size_t)ny * a.sx;   // plane stride
     const int ntile = (m + tx - 1) >> lg;
     const int nmain = ntile * nplane;
-    const int b = blockIdx.x;
+    const int b = (int)blk;
     C2<T>* base;
     size_t cs;
     int ncol, kx0, plane0;
@@ -448,6 +457,49 @@ __global__ __launch_bounds__(1024) void k_fft_cols(const FFTArgs<T> a) {
     }
 }
 
+
+// Plain and batched launch wrappers (see stencil.hip).
+#define DNSLAB_BATCH_BLOCK(st, ns)         \
+    const int s_ = batch_slot(st, ns);     \
+    const unsigned blk_ = blockIdx.x - st[s_];
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ib_rhs(const IbArgs<T> a) { ib_rhs_body<T>(a, blockIdx.x); }
+template <typename T>
+__global__ __launch_bounds__(256) void k_ib_rhs_b(const BRec<IbArgs<T>>* __restrict__ tab,
+                                                  const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_BLOCK(st, ns)
+    const IbArgs<T> a = tab[s_].a;
+    ib_rhs_body<T>(a, blk_);
+}
+template <typename T>
+__global__ __launch_bounds__(1024) void k_fft_x_fwd(const FxfArgs<T> a) { fft_x_fwd_body<T>(a, blockIdx.x); }
+template <typename T>
+__global__ __launch_bounds__(1024) void k_fft_x_fwd_b(const BRec<FxfArgs<T>>* __restrict__ tab,
+                                                      const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_BLOCK(st, ns)
+    const FxfArgs<T> a = tab[s_].a;
+    fft_x_fwd_body<T>(a, blk_);
+}
+template <typename T>
+__global__ __launch_bounds__(1024) void k_fft_x_inv(const FxiArgs<T> a) { fft_x_inv_body<T>(a, blockIdx.x); }
+template <typename T>
+__global__ __launch_bounds__(1024) void k_fft_x_inv_b(const BRec<FxiArgs<T>>* __restrict__ tab,
+                                                      const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_BLOCK(st, ns)
+    const FxiArgs<T> a = tab[s_].a;
+    fft_x_inv_body<T>(a, blk_);
+}
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_fft_cols(const FFTArgs<T> a) { fft_cols_body<T, MODE>(a, blockIdx.x); }
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_fft_cols_b(const BRec<FFTArgs<T>>* __restrict__ tab,
+                                                     const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_BLOCK(st, ns)
+    const FFTArgs<T> a = tab[s_].a;
+    fft_cols_body<T, MODE>(a, blk_);
+}
+
 inline int round64(int t) { return ((t + 63) / 64) * 64; }
 
 }  // namespace
@@ -477,36 +529,63 @@ AxisPlan make_axis_plan(int n) {
 }
 
 template <typename T>
-hipError_t launch_ib_rhs(const IBList& ib, const Grid& g, const T* p, T* r, T* r0s, int first, hipStream_t s) {
+hipError_t launch_ib_rhs(const IBList& ib, const Grid& g, const T* p, T* r, T* r0s, int first, hipStream_t s,
+                         Recorder* rec) {
     if (ib.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_ib_rhs<T>), dim3((ib.n + 255) / 256), dim3(256), 0, s, ib, g, p, r, r0s, first);
+    IbArgs<T> a;
+    a.ib = ib;
+    a.g = g;
+    a.p = p;
+    a.r = r;
+    a.r0s = r0s;
+    a.first = first;
+    const dim3 grid((ib.n + 255) / 256), block(256);
+    if (rec) {
+        record_launch(rec, kind_code(KK_IB, 0, sizeof(T) == 4), grid, block, 0, a);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL((k_ib_rhs<T>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r, hipStream_t s) {
+hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r, hipStream_t s, Recorder* rec) {
     const int nl = 1 << a.nl_x;
     const int nlines = a.g.ny * a.g.nz;
     dim3 grid((nlines + nl - 1) / nl);
     dim3 block(round64(nl * a.px.tpl));
     size_t lds = ((size_t)nl * a.ls_x + 2 * a.m + 1) * sizeof(C2<T>);
-    hipLaunchKernelGGL((k_fft_x_fwd<T>), grid, block, lds, s, a, r);
+    FxfArgs<T> b;
+    b.f = a;
+    b.r = r;
+    if (rec) {
+        record_launch(rec, kind_code(KK_FXF, 0, sizeof(T) == 4), grid, block, lds, b);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL((k_fft_x_fwd<T>), grid, block, lds, s, b);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s) {
+hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s, Recorder* rec) {
     const int nl = 1 << a.nl_x;
     const int nlines = a.g.ny * a.g.nz;
     dim3 grid((nlines + nl - 1) / nl);
     dim3 block(round64(nl * a.px.tpl));
     size_t lds = ((size_t)nl * a.ls_x + 2 * a.m + 1) * sizeof(C2<T>);
-    hipLaunchKernelGGL((k_fft_x_inv<T>), grid, block, lds, s, a, p);
+    FxiArgs<T> b;
+    b.f = a;
+    b.p = p;
+    if (rec) {
+        record_launch(rec, kind_code(KK_FXI, 0, sizeof(T) == 4), grid, block, lds, b);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL((k_fft_x_inv<T>), grid, block, lds, s, b);
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s) {
+static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s, Recorder* rec) {
     const bool zp = mode == 2;
     const int lg = zp ? a.lg_tx_z : a.lg_tx_y, tx = 1 << lg;
     const int nrow = zp ? a.g.nz : a.g.ny, nplane = zp ? a.g.ny : a.g.nz;
@@ -515,6 +594,10 @@ static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s) {
     const AxisPlan& ap = zp ? a.pz : a.py;
     dim3 block(round64(tx * ap.tpl));
     size_t lds = ((size_t)tx * nrow + nrow) * sizeof(C2<T>);
+    if (rec) {
+        record_launch(rec, kind_code(KK_COLS, mode, sizeof(T) == 4), dim3(nblocks), block, lds, a);
+        return hipSuccess;
+    }
     if (mode == 0) hipLaunchKernelGGL((k_fft_cols<T, 0>), dim3(nblocks), block, lds, s, a);
     else if (mode == 1) hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3(nblocks), block, lds, s, a);
     else hipLaunchKernelGGL((k_fft_cols<T, 2>), dim3(nblocks), block, lds, s, a);
@@ -522,21 +605,58 @@ static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_fft_y(const FFTArgs<T>& a, bool inverse, hipStream_t s) {
-    return launch_cols<T>(a, inverse ? 1 : 0, s);
+hipError_t launch_fft_y(const FFTArgs<T>& a, bool inverse, hipStream_t s, Recorder* rec) {
+    return launch_cols<T>(a, inverse ? 1 : 0, s, rec);
 }
 
 template <typename T>
-hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s) {
-    return launch_cols<T>(a, 2, s);
+hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec) {
+    return launch_cols<T>(a, 2, s, rec);
 }
 
-#define DNSLAB_INST(T)                                                                                      \
-    template hipError_t launch_fft_x_fwd<T>(const FFTArgs<T>&, const T*, hipStream_t);                      \
-    template hipError_t launch_ib_rhs<T>(const IBList&, const Grid&, const T*, T*, T*, int, hipStream_t);   \
-    template hipError_t launch_fft_x_inv<T>(const FFTArgs<T>&, T*, hipStream_t);                            \
-    template hipError_t launch_fft_y<T>(const FFTArgs<T>&, bool, hipStream_t);                              \
-    template hipError_t launch_fft_z_solve<T>(const FFTArgs<T>&, hipStream_t);
+namespace {
+template <typename T>
+hipError_t fft_batched_typed(int base, int mode, const void* tab, const unsigned* st, int ns, unsigned nb, dim3 blk,
+                             size_t lds, hipStream_t s) {
+    const dim3 grid(nb);
+    switch (base) {
+        case KK_IB:
+            hipLaunchKernelGGL((k_ib_rhs_b<T>), grid, blk, 0, s, (const BRec<IbArgs<T>>*)tab, st, ns);
+            break;
+        case KK_FXF:
+            hipLaunchKernelGGL((k_fft_x_fwd_b<T>), grid, blk, lds, s, (const BRec<FxfArgs<T>>*)tab, st, ns);
+            break;
+        case KK_FXI:
+            hipLaunchKernelGGL((k_fft_x_inv_b<T>), grid, blk, lds, s, (const BRec<FxiArgs<T>>*)tab, st, ns);
+            break;
+        case KK_COLS: {
+            auto t = (const BRec<FFTArgs<T>>*)tab;
+            if (mode == 0) hipLaunchKernelGGL((k_fft_cols_b<T, 0>), grid, blk, lds, s, t, st, ns);
+            else if (mode == 1) hipLaunchKernelGGL((k_fft_cols_b<T, 1>), grid, blk, lds, s, t, st, ns);
+            else hipLaunchKernelGGL((k_fft_cols_b<T, 2>), grid, blk, lds, s, t, st, ns);
+            break;
+        }
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_batched_fft(int kind, const void* tab, const unsigned* st, int ns, unsigned nb, dim3 blk,
+                              size_t lds, hipStream_t s) {
+    const int base = kind >> 8, mode = (kind >> 1) & 127, fp32 = kind & 1;
+    return fp32 ? fft_batched_typed<float>(base, mode, tab, st, ns, nb, blk, lds, s)
+                : fft_batched_typed<double>(base, mode, tab, st, ns, nb, blk, lds, s);
+}
+
+#define DNSLAB_INST(T)                                                                                  \
+    template hipError_t launch_fft_x_fwd<T>(const FFTArgs<T>&, const T*, hipStream_t, Recorder*);       \
+    template hipError_t launch_ib_rhs<T>(const IBList&, const Grid&, const T*, T*, T*, int, hipStream_t,  \
+                                         Recorder*);                                                    \
+    template hipError_t launch_fft_x_inv<T>(const FFTArgs<T>&, T*, hipStream_t, Recorder*);              \
+    template hipError_t launch_fft_y<T>(const FFTArgs<T>&, bool, hipStream_t, Recorder*);                \
+    template hipError_t launch_fft_z_solve<T>(const FFTArgs<T>&, hipStream_t, Recorder*);
 DNSLAB_INST(double)
 DNSLAB_INST(float)
 #undef DNSLAB_INST

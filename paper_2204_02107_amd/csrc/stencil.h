@@ -99,8 +99,10 @@ struct RefineCorrArgs {
     Grid g;
     int kc;
 };
-hipError_t launch_refine_res(const RefineResArgs& a, const struct StencilLaunch& L, hipStream_t s);
-hipError_t launch_refine_correct(const RefineCorrArgs& a, const struct StencilLaunch& L, hipStream_t s);
+hipError_t launch_refine_res(const RefineResArgs& a, const struct StencilLaunch& L, hipStream_t s,
+                             Recorder* rec = nullptr);
+hipError_t launch_refine_correct(const RefineCorrArgs& a, const struct StencilLaunch& L, hipStream_t s,
+                                 Recorder* rec = nullptr);
 
 // Launch geometry shared by all z-marching stencil kernels.
 struct StencilLaunch {
@@ -112,17 +114,38 @@ struct StencilLaunch {
 // cells_x: cells per thread along x (1, or 2 for the pair kernels).
 StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x);
 
-template <typename T> hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s);
-template <typename T> hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s);
-template <typename T> hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream_t s);
-template <typename T> hipError_t launch_correct(const CorrArgs<T>& a, const StencilLaunch& L, hipStream_t s);
-template <typename T> hipError_t launch_div(const DivArgs<T>& a, const StencilLaunch& L, hipStream_t s);
+// Every launch_* issues one kernel on stream s, or, when rec is non-NULL,
+// records the launch (for batched replay by the pool) without issuing it.
+template <typename T> hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s,
+                                                  Recorder* rec = nullptr);
+template <typename T> hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s,
+                                                  Recorder* rec = nullptr);
+template <typename T> hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream_t s,
+                                               Recorder* rec = nullptr);
+template <typename T> hipError_t launch_correct(const CorrArgs<T>& a, const StencilLaunch& L, hipStream_t s,
+                                                Recorder* rec = nullptr);
+template <typename T> hipError_t launch_div(const DivArgs<T>& a, const StencilLaunch& L, hipStream_t s,
+                                            Recorder* rec = nullptr);
 template <typename T> hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g,
                                              Partial* part, const StencilLaunch& L, hipStream_t s);
 
 // Reduce the partials of a step and advance the device step scalars.
-hipError_t launch_finish(const Partial* part, int np, const Partial* pdiv, int nd, StepScalars* sc,
-                         DiagRec* ring, int ring_cap, double dv, hipStream_t s);
+struct FinishArgs {
+    const Partial* part;
+    int np;
+    const Partial* pdiv;
+    int nd;
+    StepScalars* sc;
+    DiagRec* ring;
+    int ring_cap;
+    double dv;
+};
+hipError_t launch_finish(const FinishArgs& f, hipStream_t s, Recorder* rec = nullptr);
+
+// Batched replay of one recorded position over ns scenarios: tab holds ns
+// BRec<Args> entries (device), starts the ns+1 block offsets (device).
+hipError_t launch_batched_stencil(int kind, const void* tab, const unsigned* starts, int ns, unsigned total_blocks,
+                                  dim3 block, size_t lds, hipStream_t s);
 // Reduce Courant partials only: sets sc->rate and the next dt.
 hipError_t launch_set_rate(const Partial* part, int np, StepScalars* sc, hipStream_t s);
 

@@ -35,10 +35,10 @@ struct Col {
 // hardware id; remapping hardware id -> logical tile so that each XCD owns a
 // contiguous range of tiles keeps the y- and z-neighbour rows of a tile in the
 // L2 of the XCD that reads them.
-__device__ __forceinline__ void logical_block(int& bx, int& by, int& bz) {
-    const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+__device__ __forceinline__ void logical_block(const BlockIdx3& bi, int& bx, int& by, int& bz) {
+    const unsigned gx = bi.gx, gy = bi.gy, gz = bi.gz;
     const unsigned nb = gx * gy * gz;
-    const unsigned hw = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned hw = bi.hw;
     const unsigned x = hw & 7u, q = hw >> 3;
     const unsigned per = nb >> 3, rem = nb & 7u;
     const unsigned L = x * per + min(x, rem) + q;
@@ -53,10 +53,10 @@ __device__ __forceinline__ void logical_block(int& bx, int& by, int& bz) {
 #endif
 }
 
-__device__ __forceinline__ Col column(const Grid& g, int kc) {
+__device__ __forceinline__ Col column(const Grid& g, int kc, const BlockIdx3& bi) {
     Col c;
     int bx, by, bz;
-    logical_block(bx, by, bz);
+    logical_block(bi, bx, by, bz);
     c.i = bx * blockDim.x + threadIdx.x;
     c.j = by * blockDim.y + threadIdx.y;
     c.k0 = bz * kc;
@@ -73,10 +73,6 @@ __device__ __forceinline__ Col column(const Grid& g, int kc) {
     return c;
 }
 
-// Slot of this block in a partial-result array (hardware id: any bijection).
-__device__ __forceinline__ int block_linear() {
-    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-}
 
 // Courant rate |u|/dx + |v|/dy + |w|/dz in FP64, summed left to right without
 // contraction so that it rounds like a plain sequential evaluation.
@@ -94,9 +90,9 @@ __device__ __forceinline__ double courant_rate(double u, double v, double w, con
 //   1/2 [D_a(u_a u_i) + u_a D_a u_i] = [(u_a+ + u_a0) u_i+ - (u_a- + u_a0) u_i-] / (4 dx_a).
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ __launch_bounds__(1024) void k_mom_stage(const MomArgs<T> a) {
+__device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
-    const Col col = column(g, a.kc);
+    const Col col = column(g, a.kc, bi);
     if (!col.active) return;
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
@@ -179,9 +175,9 @@ __global__ __launch_bounds__(1024) void k_mom_stage(const MomArgs<T> a) {
 // the masked diffusion conducting only across fluid-fluid faces.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) {
+__device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
-    const Col col = column(g, a.kc);
+    const Col col = column(g, a.kc, bi);
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T dt = (MODE == ST_RHS) ? T(0) : T(a.dtp ? *a.dtp : a.dt);
@@ -259,7 +255,7 @@ __global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) {
             cm = c0; c0 = cp; wm = w0; w0 = wp; fm = f0; f0 = fp;
         }
     }
-    if ((MODE == ST_FIRST || MODE == ST_LAST) && a.part) block_reduce_partial(part, a.part + block_linear());
+    if ((MODE == ST_FIRST || MODE == ST_LAST) && a.part) block_reduce_partial(part, a.part + (int)bi.hw);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,9 +263,9 @@ __global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) {
 // out = beta (f + pi^-6 sum_a delta6_a f).
 // ---------------------------------------------------------------------------
 template <typename T, int NF>
-__global__ __launch_bounds__(1024) void k_filter(const FiltArgs<T> a) {
+__device__ __forceinline__ void filter_body(const FiltArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
-    const Col col = column(g, a.kc);
+    const Col col = column(g, a.kc, bi);
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T c6 = T(INV_PI6);
@@ -324,16 +320,16 @@ __global__ __launch_bounds__(1024) void k_filter(const FiltArgs<T> a) {
             }
         }
     }
-    if (NF == 4 && a.part) block_reduce_partial(part, a.part + block_linear());
+    if (NF == 4 && a.part) block_reduce_partial(part, a.part + (int)bi.hw);
 }
 
 // ---------------------------------------------------------------------------
 // Velocity correction of Section 2.2 with the mask: out = beta (u* - grad p).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(1024) void k_correct(const CorrArgs<T> a) {
+__device__ __forceinline__ void correct_body(const CorrArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
-    const Col col = column(g, a.kc);
+    const Col col = column(g, a.kc, bi);
     if (!col.active) return;
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
@@ -363,9 +359,9 @@ __global__ __launch_bounds__(1024) void k_correct(const CorrArgs<T> a) {
 // res = div u* + div((1-beta) grad p3) - div grad p4, all in FP64.  The
 // radius-2 operator div grad p4 = sum_a (p4(x+2e) - 2 p4 + p4(x-2e)) / (4 dx_a^2).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_refine_res(const RefineResArgs a) {
+__device__ __forceinline__ void refine_res_body(const RefineResArgs& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
-    const Col col = column(g, a.kc);
+    const Col col = column(g, a.kc, bi);
     if (!col.active) return;
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
@@ -418,9 +414,9 @@ __global__ __launch_bounds__(1024) void k_refine_res(const RefineResArgs a) {
 }
 
 // u = beta (u* - grad(p4 + dp)), p = p4 + dp, FP64 arithmetic, FP32 storage.
-__global__ __launch_bounds__(1024) void k_refine_correct(const RefineCorrArgs a) {
+__device__ __forceinline__ void refine_correct_body(const RefineCorrArgs& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
-    const Col col = column(g, a.kc);
+    const Col col = column(g, a.kc, bi);
     if (!col.active) return;
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
@@ -446,9 +442,9 @@ __global__ __launch_bounds__(1024) void k_refine_correct(const RefineCorrArgs a)
 
 // Divergence with central differences: out = sum_a D_a u_a (Section 2.2).
 template <typename T>
-__global__ __launch_bounds__(1024) void k_div(const DivArgs<T> a) {
+__device__ __forceinline__ void div_body(const DivArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
-    const Col col = column(g, a.kc);
+    const Col col = column(g, a.kc, bi);
     if (!col.active) return;
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
@@ -472,7 +468,8 @@ __global__ __launch_bounds__(1024) void k_div(const DivArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(1024) void k_rate(const T* u, const T* v, const T* w, const Grid g, int kc,
                                               Partial* part) {
-    const Col col = column(g, kc);
+    const BlockIdx3 bi = hw_block();
+    const Col col = column(g, kc, bi);
     const int k0 = col.k0, k1 = col.k1;
     Partial pp = {0, 0, 0, 0, 0, 0, {0, 0}};
     if (col.active) {
@@ -481,7 +478,7 @@ __global__ __launch_bounds__(1024) void k_rate(const T* u, const T* v, const T* 
             pp.rate = fmax(pp.rate, courant_rate((double)u[idx], (double)v[idx], (double)w[idx], g));
         }
     }
-    block_reduce_partial(pp, part + block_linear());
+    block_reduce_partial(pp, part + (int)bi.hw);
 }
 
 __device__ inline double next_dt(const StepScalars& s, double rate) {
@@ -490,8 +487,13 @@ __device__ inline double next_dt(const StepScalars& s, double rate) {
 
 // One block: reduce the partials in a fixed order, write the diagnostics of
 // the step just taken, and advance t, the step count and dt.
-__global__ __launch_bounds__(1024) void k_finish(const Partial* part, int np, const Partial* pdiv, int nd,
-                                                StepScalars* sc, DiagRec* ring, int ring_cap, double dv) {
+__device__ __forceinline__ void finish_body(const FinishArgs& f) {
+    const Partial* part = f.part;
+    const int np = f.np, nd = f.nd, ring_cap = f.ring_cap;
+    const Partial* pdiv = f.pdiv;
+    StepScalars* sc = f.sc;
+    DiagRec* ring = f.ring;
+    const double dv = f.dv;
     Partial acc = {0, 0, 0, 0, 0, 0, {0, 0}};
     for (int b = threadIdx.x; b < np; b += blockDim.x) {
         const Partial q = part[b];
@@ -539,6 +541,89 @@ __global__ __launch_bounds__(1024) void k_set_rate(const Partial* part, int np, 
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Launch wrappers: a plain launch (block coordinates from the hardware) and a
+// batched launch over several scenarios (coordinates from a table; each
+// scenario's blocks compute exactly what its plain launch would).
+// ---------------------------------------------------------------------------
+#define DNSLAB_BATCH_COORD(tab, st, ns)                 \
+    const int s_ = batch_slot(st, ns);                  \
+    BlockIdx3 bi_;                                      \
+    bi_.hw = blockIdx.x - st[s_];                       \
+    bi_.gx = tab[s_].g[0];                              \
+    bi_.gy = tab[s_].g[1];                              \
+    bi_.gz = tab[s_].g[2];
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_mom_stage(const MomArgs<T> a) { mom_stage_body<T, MODE>(a, hw_block()); }
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_mom_stage_b(const BRec<MomArgs<T>>* __restrict__ tab,
+                                                      const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const MomArgs<T> a = tab[s_].a;
+    mom_stage_body<T, MODE>(a, bi_);
+}
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) { sca_stage_body<T, MODE>(a, hw_block()); }
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_sca_stage_b(const BRec<ScaArgs<T>>* __restrict__ tab,
+                                                      const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const ScaArgs<T> a = tab[s_].a;
+    sca_stage_body<T, MODE>(a, bi_);
+}
+template <typename T, int NF>
+__global__ __launch_bounds__(1024) void k_filter(const FiltArgs<T> a) { filter_body<T, NF>(a, hw_block()); }
+template <typename T, int NF>
+__global__ __launch_bounds__(1024) void k_filter_b(const BRec<FiltArgs<T>>* __restrict__ tab,
+                                                   const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const FiltArgs<T> a = tab[s_].a;
+    filter_body<T, NF>(a, bi_);
+}
+template <typename T>
+__global__ __launch_bounds__(1024) void k_correct(const CorrArgs<T> a) { correct_body<T>(a, hw_block()); }
+template <typename T>
+__global__ __launch_bounds__(1024) void k_correct_b(const BRec<CorrArgs<T>>* __restrict__ tab,
+                                                    const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const CorrArgs<T> a = tab[s_].a;
+    correct_body<T>(a, bi_);
+}
+template <typename T>
+__global__ __launch_bounds__(1024) void k_div(const DivArgs<T> a) { div_body<T>(a, hw_block()); }
+template <typename T>
+__global__ __launch_bounds__(1024) void k_div_b(const BRec<DivArgs<T>>* __restrict__ tab,
+                                                const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const DivArgs<T> a = tab[s_].a;
+    div_body<T>(a, bi_);
+}
+__global__ __launch_bounds__(1024) void k_refine_res(const RefineResArgs a) { refine_res_body(a, hw_block()); }
+__global__ __launch_bounds__(1024) void k_refine_res_b(const BRec<RefineResArgs>* __restrict__ tab,
+                                                       const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const RefineResArgs a = tab[s_].a;
+    refine_res_body(a, bi_);
+}
+__global__ __launch_bounds__(1024) void k_refine_correct(const RefineCorrArgs a) {
+    refine_correct_body(a, hw_block());
+}
+__global__ __launch_bounds__(1024) void k_refine_correct_b(const BRec<RefineCorrArgs>* __restrict__ tab,
+                                                           const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const RefineCorrArgs a = tab[s_].a;
+    refine_correct_body(a, bi_);
+}
+__global__ __launch_bounds__(1024) void k_finish(const FinishArgs f) { finish_body(f); }
+__global__ __launch_bounds__(1024) void k_finish_b(const BRec<FinishArgs>* __restrict__ tab,
+                                                   const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const FinishArgs f = tab[s_].a;
+    finish_body(f);
+}
+
 }  // namespace
 
 StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x) {
@@ -557,54 +642,74 @@ StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x) {
 #define SCA_KERNEL k_sca_stage
 
 template <typename T>
-hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     MomArgs<T> b = a;
     b.kc = L.kc;
+    if (rec) {
+        record_launch(rec, kind_code(KK_MOM, mode, sizeof(T) == 4), L.grid, L.block, 0, b);
+        return hipSuccess;
+    }
     switch (mode) {
-        case ST_FIRST: hipLaunchKernelGGL((MOM_KERNEL<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
-        case ST_HALF: hipLaunchKernelGGL((MOM_KERNEL<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
-        case ST_FULL: hipLaunchKernelGGL((MOM_KERNEL<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
-        case ST_LAST: hipLaunchKernelGGL((MOM_KERNEL<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
-        default: hipLaunchKernelGGL((MOM_KERNEL<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
+        case ST_FIRST: hipLaunchKernelGGL((k_mom_stage<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
+        case ST_HALF: hipLaunchKernelGGL((k_mom_stage<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
+        case ST_FULL: hipLaunchKernelGGL((k_mom_stage<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
+        case ST_LAST: hipLaunchKernelGGL((k_mom_stage<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
+        default: hipLaunchKernelGGL((k_mom_stage<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     ScaArgs<T> b = a;
     b.kc = L.kc;
+    if (rec) {
+        record_launch(rec, kind_code(KK_SCA, mode, sizeof(T) == 4), L.grid, L.block, 0, b);
+        return hipSuccess;
+    }
     switch (mode) {
-        case ST_FIRST: hipLaunchKernelGGL((SCA_KERNEL<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
-        case ST_HALF: hipLaunchKernelGGL((SCA_KERNEL<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
-        case ST_FULL: hipLaunchKernelGGL((SCA_KERNEL<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
-        case ST_LAST: hipLaunchKernelGGL((SCA_KERNEL<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
-        default: hipLaunchKernelGGL((SCA_KERNEL<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
+        case ST_FIRST: hipLaunchKernelGGL((k_sca_stage<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
+        case ST_HALF: hipLaunchKernelGGL((k_sca_stage<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
+        case ST_FULL: hipLaunchKernelGGL((k_sca_stage<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
+        case ST_LAST: hipLaunchKernelGGL((k_sca_stage<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
+        default: hipLaunchKernelGGL((k_sca_stage<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     FiltArgs<T> b = a;
     b.kc = L.kc;
+    if (rec) {
+        record_launch(rec, kind_code(KK_FILT, a.nf == 4 ? 4 : 1, sizeof(T) == 4), L.grid, L.block, 0, b);
+        return hipSuccess;
+    }
     if (a.nf == 4) hipLaunchKernelGGL((k_filter<T, 4>), L.grid, L.block, 0, s, b);
     else hipLaunchKernelGGL((k_filter<T, 1>), L.grid, L.block, 0, s, b);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_correct(const CorrArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+hipError_t launch_correct(const CorrArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     CorrArgs<T> b = a;
     b.kc = L.kc;
+    if (rec) {
+        record_launch(rec, kind_code(KK_CORR, 0, sizeof(T) == 4), L.grid, L.block, 0, b);
+        return hipSuccess;
+    }
     hipLaunchKernelGGL((k_correct<T>), L.grid, L.block, 0, s, b);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_div(const DivArgs<T>& a, const StencilLaunch& L, hipStream_t s) {
+hipError_t launch_div(const DivArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     DivArgs<T> b = a;
     b.kc = L.kc;
+    if (rec) {
+        record_launch(rec, kind_code(KK_DIV, 0, sizeof(T) == 4), L.grid, L.block, 0, b);
+        return hipSuccess;
+    }
     hipLaunchKernelGGL((k_div<T>), L.grid, L.block, 0, s, b);
     return hipGetLastError();
 }
@@ -616,24 +721,102 @@ hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g, Partia
     return hipGetLastError();
 }
 
-hipError_t launch_refine_res(const RefineResArgs& a, const StencilLaunch& L, hipStream_t s) {
+hipError_t launch_refine_res(const RefineResArgs& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     RefineResArgs b = a;
     b.kc = L.kc;
+    if (rec) {
+        record_launch(rec, kind_code(KK_REFRES, 0, 1), L.grid, L.block, 0, b);
+        return hipSuccess;
+    }
     hipLaunchKernelGGL(k_refine_res, L.grid, L.block, 0, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_refine_correct(const RefineCorrArgs& a, const StencilLaunch& L, hipStream_t s) {
+hipError_t launch_refine_correct(const RefineCorrArgs& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     RefineCorrArgs b = a;
     b.kc = L.kc;
+    if (rec) {
+        record_launch(rec, kind_code(KK_REFCORR, 0, 1), L.grid, L.block, 0, b);
+        return hipSuccess;
+    }
     hipLaunchKernelGGL(k_refine_correct, L.grid, L.block, 0, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const Partial* part, int np, const Partial* pdiv, int nd, StepScalars* sc,
-                         DiagRec* ring, int ring_cap, double dv, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, part, np, pdiv, nd, sc, ring, ring_cap, dv);
+hipError_t launch_finish(const FinishArgs& f, hipStream_t s, Recorder* rec) {
+    if (rec) {
+        record_launch(rec, kind_code(KK_FINISH, 0, 0), dim3(1), dim3(1024), 0, f);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, f);
     return hipGetLastError();
+}
+
+namespace {
+template <typename T>
+hipError_t batched_typed(int base, int mode, const void* tab, const unsigned* st, int ns, unsigned nb, dim3 blk,
+                         hipStream_t s) {
+    const dim3 grid(nb);
+    switch (base) {
+        case KK_MOM: {
+            auto t = (const BRec<MomArgs<T>>*)tab;
+            switch (mode) {
+                case ST_FIRST: hipLaunchKernelGGL((k_mom_stage_b<T, ST_FIRST>), grid, blk, 0, s, t, st, ns); break;
+                case ST_HALF: hipLaunchKernelGGL((k_mom_stage_b<T, ST_HALF>), grid, blk, 0, s, t, st, ns); break;
+                case ST_FULL: hipLaunchKernelGGL((k_mom_stage_b<T, ST_FULL>), grid, blk, 0, s, t, st, ns); break;
+                case ST_LAST: hipLaunchKernelGGL((k_mom_stage_b<T, ST_LAST>), grid, blk, 0, s, t, st, ns); break;
+                default: hipLaunchKernelGGL((k_mom_stage_b<T, ST_RHS>), grid, blk, 0, s, t, st, ns); break;
+            }
+            break;
+        }
+        case KK_SCA: {
+            auto t = (const BRec<ScaArgs<T>>*)tab;
+            switch (mode) {
+                case ST_FIRST: hipLaunchKernelGGL((k_sca_stage_b<T, ST_FIRST>), grid, blk, 0, s, t, st, ns); break;
+                case ST_HALF: hipLaunchKernelGGL((k_sca_stage_b<T, ST_HALF>), grid, blk, 0, s, t, st, ns); break;
+                case ST_FULL: hipLaunchKernelGGL((k_sca_stage_b<T, ST_FULL>), grid, blk, 0, s, t, st, ns); break;
+                case ST_LAST: hipLaunchKernelGGL((k_sca_stage_b<T, ST_LAST>), grid, blk, 0, s, t, st, ns); break;
+                default: hipLaunchKernelGGL((k_sca_stage_b<T, ST_RHS>), grid, blk, 0, s, t, st, ns); break;
+            }
+            break;
+        }
+        case KK_FILT: {
+            auto t = (const BRec<FiltArgs<T>>*)tab;
+            if (mode == 4) hipLaunchKernelGGL((k_filter_b<T, 4>), grid, blk, 0, s, t, st, ns);
+            else hipLaunchKernelGGL((k_filter_b<T, 1>), grid, blk, 0, s, t, st, ns);
+            break;
+        }
+        case KK_CORR:
+            hipLaunchKernelGGL((k_correct_b<T>), grid, blk, 0, s, (const BRec<CorrArgs<T>>*)tab, st, ns);
+            break;
+        case KK_DIV:
+            hipLaunchKernelGGL((k_div_b<T>), grid, blk, 0, s, (const BRec<DivArgs<T>>*)tab, st, ns);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_batched_stencil(int kind, const void* tab, const unsigned* st, int ns, unsigned nb, dim3 blk,
+                                  size_t lds, hipStream_t s) {
+    (void)lds;
+    const int base = kind >> 8, mode = (kind >> 1) & 127, fp32 = kind & 1;
+    if (base == KK_REFRES) {
+        hipLaunchKernelGGL(k_refine_res_b, dim3(nb), blk, 0, s, (const BRec<RefineResArgs>*)tab, st, ns);
+        return hipGetLastError();
+    }
+    if (base == KK_REFCORR) {
+        hipLaunchKernelGGL(k_refine_correct_b, dim3(nb), blk, 0, s, (const BRec<RefineCorrArgs>*)tab, st, ns);
+        return hipGetLastError();
+    }
+    if (base == KK_FINISH) {
+        hipLaunchKernelGGL(k_finish_b, dim3(nb), blk, 0, s, (const BRec<FinishArgs>*)tab, st, ns);
+        return hipGetLastError();
+    }
+    return fp32 ? batched_typed<float>(base, mode, tab, st, ns, nb, blk, s)
+                : batched_typed<double>(base, mode, tab, st, ns, nb, blk, s);
 }
 
 hipError_t launch_set_rate(const Partial* part, int np, StepScalars* sc, hipStream_t s) {
@@ -641,13 +824,13 @@ hipError_t launch_set_rate(const Partial* part, int np, StepScalars* sc, hipStre
     return hipGetLastError();
 }
 
-#define DNSLAB_INST(T)                                                                                  \
-    template hipError_t launch_mom_stage<T>(int, const MomArgs<T>&, const StencilLaunch&, hipStream_t); \
-    template hipError_t launch_sca_stage<T>(int, const ScaArgs<T>&, const StencilLaunch&, hipStream_t); \
-    template hipError_t launch_filter<T>(const FiltArgs<T>&, const StencilLaunch&, hipStream_t);        \
-    template hipError_t launch_correct<T>(const CorrArgs<T>&, const StencilLaunch&, hipStream_t);       \
-    template hipError_t launch_div<T>(const DivArgs<T>&, const StencilLaunch&, hipStream_t);            \
-    template hipError_t launch_rate<T>(const T*, const T*, const T*, const Grid&, Partial*,             \
+#define DNSLAB_INST(T)                                                                                              \
+    template hipError_t launch_mom_stage<T>(int, const MomArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*); \
+    template hipError_t launch_sca_stage<T>(int, const ScaArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*); \
+    template hipError_t launch_filter<T>(const FiltArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);        \
+    template hipError_t launch_correct<T>(const CorrArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);       \
+    template hipError_t launch_div<T>(const DivArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);            \
+    template hipError_t launch_rate<T>(const T*, const T*, const T*, const Grid&, Partial*,                        \
                                        const StencilLaunch&, hipStream_t);
 DNSLAB_INST(double)
 DNSLAB_INST(float)

@@ -1,0 +1,134 @@
+"""Serving pool: admission by HBM budget, continuous batching, and results that
+are the same alone and in the mix.
+
+Scenarios of different grid sizes are admitted at different times into one
+pool and advanced by batched launches; each must end bitwise equal to the same
+scenario run alone (plain dnslab_step in FP64, a pool of one in FP32), and a
+pooled FP64 scenario must match the oracle like a plain one.
+"""
+import numpy as np
+import pytest
+
+from oracle.step import Oracle
+import scenarios
+from gpu_util import announce, need_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DX = 0.0390625
+
+
+def cases():
+    return [
+        scenarios.room(64, 64, 64, dx=DX, u_in=1.0, n_boxes=3, seed=11, box_max_frac=0.4),
+        scenarios.room(128, 64, 64, dx=DX, u_in=0.1, n_boxes=5, seed=12, box_max_frac=0.4),
+        scenarios.room(96, 48, 32, dx=DX, u_in=1.0, n_boxes=0, seed=13, box_max_frac=0.4),
+    ]
+
+
+def run_mixed(pool, cs, steps, stagger=(0, 3, 7)):
+    """Admit scenario q after stagger[q] pool steps; every scenario runs `steps`."""
+    slots = [None] * len(cs)
+    t = 0
+    while True:
+        for q, c in enumerate(cs):
+            if slots[q] is None and t >= stagger[q]:
+                slots[q] = pool.admit(c, steps)
+                assert slots[q] is not None
+        if all(s is not None for s in slots):
+            _, active, _ = pool.usage()
+            if active == 0:
+                break
+        pool.step(1)
+        t += 1
+    return slots
+
+
+def test_pool_fp64_mix_equals_plain_step():
+    torch, m = need_gpu()
+    from paper_2204_02107_amd.serving import Pool
+    cs = cases()
+    steps = 12
+    announce("pool fp64 mix vs plain")
+    alone = []
+    for c in cs:
+        S = m.Solver(c)
+        S.step(steps, diag=False)
+        alone.append(S.state())
+        S.close()
+    pool = Pool(8 << 30, m.FP64)
+    slots = run_mixed(pool, cs, steps)
+    for q, c in enumerate(cs):
+        got = pool.state(slots[q], c.shape)
+        d, nst, done = pool.query(slots[q])
+        assert done and nst == steps and d["step"] == steps
+        for k in ("u", "v", "w", "p", "c"):
+            assert np.array_equal(got[k], alone[q][k]), (q, k)
+    pool.close()
+
+
+def test_pool_fp32_mix_equals_alone():
+    torch, m = need_gpu()
+    from paper_2204_02107_amd.serving import Pool
+    cs = cases()
+    steps = 10
+    announce("pool fp32 mix vs alone")
+    alone = []
+    for c in cs:
+        pool = Pool(8 << 30, m.FP32_REFINE)
+        s = pool.admit(c, steps)
+        pool.step(steps)
+        alone.append(pool.state(s, c.shape))
+        pool.close()
+    pool = Pool(8 << 30, m.FP32_REFINE)
+    slots = run_mixed(pool, cs, steps, stagger=(5, 0, 2))
+    for q, c in enumerate(cs):
+        got = pool.state(slots[q], c.shape)
+        for k in ("u", "v", "w", "p", "c"):
+            assert np.array_equal(got[k], alone[q][k]), (q, k)
+    pool.close()
+
+
+def test_pool_budget_admission_and_release():
+    torch, m = need_gpu()
+    from paper_2204_02107_amd.serving import Pool
+    c0, c1, _ = cases()
+    announce("pool budget")
+    probe = Pool(1 << 40, m.FP32_REFINE)
+    s = probe.admit(c1, 1)
+    need1, _, _ = probe.usage()
+    probe.close()
+    pool = Pool(int(need1 * 1.5), m.FP32_REFINE)
+    a = pool.admit(c1, 3)
+    assert a is not None
+    assert pool.admit(c1, 3) is None          # no room for a second one
+    used, active, resident = pool.usage()
+    assert used == need1 and active == 1 and resident == 1
+    pool.step(3)
+    _, _, done = pool.query(a)
+    assert done
+    pool.release(a)
+    assert pool.usage()[0] == 0
+    b = pool.admit(c1, 2)                     # memory returned to the budget
+    assert b is not None
+    pool.close()
+
+
+def test_pooled_scenario_matches_oracle():
+    torch, m = need_gpu()
+    from paper_2204_02107_amd.serving import Pool
+    cs = cases()
+    target = scenarios.room(64, 48, 36, dx=DX, n_boxes=3, seed=2204)
+    announce("pool vs oracle")
+    pool = Pool(8 << 30, m.FP64)
+    other = pool.admit(cs[1], 6)
+    slot = pool.admit(target, 6)
+    pool.step(6)
+    got = pool.state(slot, target.shape)
+    O = Oracle.from_scenario(target)
+    st, diags = O.run(Oracle.state_from_scenario(target), 6)
+    for k in ("u", "v", "w", "p", "c"):
+        assert rel_err(got[k], getattr(st, k)) < 1e-10, k
+    d, _, _ = pool.query(slot)
+    assert abs(d["co2_room_mean"] - diags[-1]["co2_room_mean"]) < 1e-10 * diags[-1]["co2_room_mean"]
+    pool.close()
