@@ -31,24 +31,37 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
 
 
+def near_solid_cells(sc):
+    """Cells with a solid face neighbour (where the IB term can be nonzero)."""
+    b = sc.beta == 0
+    near = np.zeros_like(b)
+    for ax in range(3):
+        near |= np.roll(b, 1, axis=ax) | np.roll(b, -1, axis=ax)
+    return int(near.sum())
+
+
 def kernel_bytes(sc, esz=8):
     """Algorithmic (compulsory) HBM bytes per launch of each kernel, for the
     step sequence of the library (stage-averaged where a kernel has modes)."""
     n = sc.ncells
     m = sc.nx // 2
     spec = 2 * esz * (m + 1) * sc.ny * sc.nz          # complex half spectrum
+    nib = near_solid_cells(sc)
     return {
         # RK4 momentum: fields touched per stage 9, 15, 15, 9 (x esz) + mask byte
         "mom_stage": n * ((9 + 15 + 15 + 9) / 4 * esz + 1),
         # RK4 scalar: 6, 8, 8, 6 fields + mask byte
         "scalar_stage": n * ((6 + 8 + 8 + 6) / 4 * esz + 1),
-        "fft_x_fwd": n * (esz + 1) + spec,            # r0 + mask in, spectrum out
+        "ib_rhs": nib * (4 + 1 + 3 * esz),             # list entry, saved r0, r, p centre
+        "fft_x_fwd": n * esz + spec,                  # r in, spectrum out
         "fft_y": 2 * spec,
         "fft_z": 2 * spec,
         "fft_x_inv": spec + n * esz,
         "filter": n * (8 * esz + 1),
-        "correct": n * (7 * esz + 1),
+        # FP64: u* and p in, u out; FP32 form: u*, p_n, dp in, u and p out (FP64 arithmetic)
+        "correct": n * (7 * esz + 1) if esz == 8 else n * (9 * esz + 1),
         "div": n * 4 * esz,
+        "refine_res": n * (5 * esz + 1),              # u*, p_n in (p_{n-1} only next to solids), res out
     }
 
 
@@ -58,13 +71,33 @@ def step_bytes(sc, esz=8):
     it = sc.n_piter if (sc.beta == 0).any() else min(sc.n_piter, 1)
     y_passes = 2 if sc.ny > 1 else 0
     poisson = kb["fft_x_fwd"] + y_passes * kb["fft_y"] + kb["fft_z"] + kb["fft_x_inv"]
-    return (4 * kb["mom_stage"] + kb["div"] + it * poisson + kb["correct"]
-            + 4 * kb["scalar_stage"] + (kb["filter"] if sc.filter else 0))
+    ib = kb["ib_rhs"] if (sc.beta == 0).any() else 0
+    total = (4 * kb["mom_stage"] + kb["div"] + it * (poisson + ib) + kb["correct"]
+             + 4 * kb["scalar_stage"] + (kb["filter"] if sc.filter else 0))
+    if esz == 4 and it > 0:
+        total += kb["refine_res"] + poisson           # FP64 residual and one correction solve
+    return total
 
 
-def workload():
+WORKLOADS = {
+    "room": "ventilated room 256x128x96 (10x5x3.75 m), 8 seeded boxes, 1 m/s duct, CFL 0.3, filter on, "
+            "4 IB pressure iterations",
+    "large": "large room 512x256x192 (10x5x3.75 m), 8 seeded boxes, 1 m/s duct, CFL 0.3, filter on, "
+             "4 IB pressure iterations",
+    "hall": "hall 1024x512x256 (40x20x10 m), ceiling plenum, 4 forced inlets, 2 outlets, 64 seeded boxes, "
+            "1 m/s, CFL 0.3, filter on, 4 IB pressure iterations",
+}
+
+
+def workload(name="room"):
     import scenarios
-    return scenarios.room()
+    if name == "room":
+        return scenarios.room()
+    if name == "large":
+        return scenarios.room(512, 256, 192, dx=10.0 / 512)
+    if name == "hall":
+        return scenarios.hall()
+    raise ValueError(name)
 
 
 def cpu_baseline(sc, budget_s=20.0):
@@ -118,6 +151,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--workload", default="room", choices=list(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--serving", default="short", choices=["none", "short", "full"],
                     help="serving stream: short = 16 requests x 300 steps, full = 64 x 2000")
     args = ap.parse_args()
@@ -129,9 +164,11 @@ def main():
     import torch
     import paper_2204_02107_amd as m
 
-    sc = workload()
+    sc = workload(args.workload)
+    prec = m.FP64 if args.precision == "fp64" else m.FP32_REFINE
+    esz = 8 if prec == m.FP64 else 4
     dev = torch.device("cuda:0")
-    S = m.Solver(sc, precision=m.FP64, device=dev)
+    S = m.Solver(sc, precision=prec, device=dev)
     stream = S.stream
     print(f"[bench] workload {sc.name} cells={sc.ncells} warmup={args.warmup}", file=sys.stderr, flush=True)
     S.step(args.warmup, diag=False)
@@ -150,9 +187,11 @@ def main():
           file=sys.stderr, flush=True)
 
     # per-kernel launch times from HIP events on the library's stream
-    kb = kernel_bytes(sc)
+    kb = kernel_bytes(sc, esz)
     per = {}
     for name in kb:
+        if name == "refine_res" and prec == m.FP64:
+            continue
         S.profile(name)
         S.step(args.profile_steps, diag=False)
         ms, nl = S.profile_read()
@@ -173,11 +212,11 @@ def main():
         try:
             with open(tfile) as f:
                 tr = json.load(f)
-            traffic = tr.get(dom)
+            traffic = tr.get(f"{args.workload}/{args.precision}", {}).get(dom)
         except (OSError, ValueError):
             traffic = None
 
-    sbytes = step_bytes(sc)
+    sbytes = step_bytes(sc, esz)
     out = {
         "metric": "Gcell-steps/s (full step incl. FFT Poisson)",
         "value": value,
@@ -189,11 +228,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == m.FP64 else "f32 (FP64 refinement and reductions)",
         "data": "synthetic",
         "config": {
-            "workload": "ventilated room 256x128x96 (10x5x3.75 m), 8 seeded boxes, 1 m/s duct, "
-                        "FP64, CFL 0.3, filter on, 4 IB pressure iterations",
+            "workload": WORKLOADS[args.workload] + (", FP64" if prec == m.FP64 else ", FP32 + FP64 refinement"),
             "cells": sc.ncells,
             "forced_cells": int(len(sc.forced_idx)),
         },
@@ -212,12 +250,12 @@ def main():
                         "launches_per_step": v["launches_per_step"]} for k, v in per.items()},
     }
     S.close()
-    if args.serving != "none":
+    if args.serving != "none" and args.workload == "room" and prec == m.FP64:
         n_req, n_steps = (16, 300) if args.serving == "short" else (64, 2000)
         print(f"[bench] serving stream {n_req} x {n_steps} ...", file=sys.stderr, flush=True)
         out["serving"] = serving_bench(n_req, n_steps, budget_gib=1.0)
         print("[bench] serving: " + json.dumps(out["serving"]), file=sys.stderr, flush=True)
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "room":
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(out), flush=True)
