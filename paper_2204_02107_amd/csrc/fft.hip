@@ -154,8 +154,8 @@ __device__ __forceinline__ void stockham_pass(C2<T>* s, int n, int ns, const C2<
 }
 
 template <typename T, bool INV>
-__device__ void fft_lds(C2<T>* s, const AxisPlan& ap, const C2<T>* W, int es, int ls, int lg_nl,
-                        int tid, int nthr) {
+__device__ void fft_lds_runtime(C2<T>* s, const AxisPlan& ap, const C2<T>* W, int es, int ls, int lg_nl, int tid,
+                                int nthr) {
     int ns = 1;
     for (int p = 0; p < ap.npass; ++p) {
         const int R = ap.rad[p];
@@ -164,6 +164,114 @@ __device__ void fft_lds(C2<T>* s, const AxisPlan& ap, const C2<T>* W, int es, in
         else if (R == 2) stockham_pass<T, 2, 4, INV>(s, ap.n, ns, W, es, ls, lg_nl, tid, nthr);
         else stockham_pass<T, 3, 3, INV>(s, ap.n, ns, W, es, ls, lg_nl, tid, nthr);
         ns *= R;
+    }
+}
+
+// Compile-time plan: the same radix sequence as make_axis_plan (8s first,
+// then 4/2, then 3s), so that the threads per line match the launch.
+struct CPlan {
+    int np;
+    int r[FFT_MAX_PASSES];
+};
+constexpr CPlan cplan(int n) {
+    CPlan p{0, {}};
+    int a = 0, b = 0, m = n;
+    while (m > 1 && m % 2 == 0) { m /= 2; ++a; }
+    while (m > 1 && m % 3 == 0) { m /= 3; ++b; }
+    const int eights = a / 3, rest = a % 3;
+    if (rest == 1 && eights >= 1) {
+        for (int i = 0; i < eights - 1; ++i) p.r[p.np++] = 8;
+        p.r[p.np++] = 4;
+        p.r[p.np++] = 4;
+    } else {
+        for (int i = 0; i < eights; ++i) p.r[p.np++] = 8;
+        if (rest == 2) p.r[p.np++] = 4;
+        if (rest == 1) p.r[p.np++] = 2;
+    }
+    for (int i = 0; i < b; ++i) p.r[p.np++] = 3;
+    return p;
+}
+constexpr int cns(int n, int pass) {
+    const CPlan p = cplan(n);
+    int ns = 1;
+    for (int i = 0; i < pass; ++i) ns *= p.r[i];
+    return ns;
+}
+
+// One Stockham pass with the transform length, radix and span known at
+// compile time (the index arithmetic becomes shifts and constant multiplies).
+template <typename T, int R, int MAXB, bool INV, int N, int NS>
+__device__ __forceinline__ void stockham_pass_c(C2<T>* s, const C2<T>* W, int es, int ls, int lg_nl, int tid,
+                                                int nthr) {
+    constexpr int nbl = N / R;
+    constexpr int step = N / (NS * R);
+    const int nb = nbl << lg_nl;
+    const int mask = (1 << lg_nl) - 1;
+    C2<T> v[MAXB][R];
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int b = tid + q * nthr;
+        if (b < nb) {
+            const int j = b >> lg_nl;
+            const C2<T>* base = s + (b & mask) * ls;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = base[(j + r * nbl) * es];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int b = tid + q * nthr;
+        if (b < nb) {
+            const int j = b >> lg_nl;
+            const int k = j % NS;
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const C2<T> w = W[r * k * step];
+                    v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
+                }
+            }
+            DFT<T, R, INV>::run(v[q]);
+            C2<T>* base = s + (b & mask) * ls;
+            const int d = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) base[(d + r * NS) * es] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, bool INV, int N, int P>
+__device__ __forceinline__ void fft_chain(C2<T>* s, const C2<T>* W, int es, int ls, int lg_nl, int tid, int nthr) {
+    constexpr CPlan pl = cplan(N);
+    if constexpr (P < pl.np) {
+        constexpr int R = pl.r[P];
+        constexpr int MAXB = (pl.r[0] + R - 1) / R;
+        stockham_pass_c<T, R, MAXB, INV, N, cns(N, P)>(s, W, es, ls, lg_nl, tid, nthr);
+        fft_chain<T, INV, N, P + 1>(s, W, es, ls, lg_nl, tid, nthr);
+    }
+}
+
+// In-place transform of all lines held in LDS; specialised chains for the
+// common lengths, the runtime plan otherwise.
+template <typename T, bool INV>
+__device__ void fft_lds(C2<T>* s, const AxisPlan& ap, const C2<T>* W, int es, int ls, int lg_nl, int tid, int nthr) {
+    switch (ap.n) {
+        case 1: return;
+        case 16: fft_chain<T, INV, 16, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 32: fft_chain<T, INV, 32, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 48: fft_chain<T, INV, 48, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 64: fft_chain<T, INV, 64, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 96: fft_chain<T, INV, 96, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 128: fft_chain<T, INV, 128, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 192: fft_chain<T, INV, 192, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 256: fft_chain<T, INV, 256, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 384: fft_chain<T, INV, 384, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 512: fft_chain<T, INV, 512, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 768: fft_chain<T, INV, 768, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 1024: fft_chain<T, INV, 1024, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        default: fft_lds_runtime<T, INV>(s, ap, W, es, ls, lg_nl, tid, nthr); return;
     }
 }
 
