@@ -16,6 +16,12 @@
 // coalesced.
 #include "fft.h"
 
+#include <algorithm>
+
+#ifndef DNSLAB_FFT_TPL_MUL
+#define DNSLAB_FFT_TPL_MUL 1   // threads per line = MUL * n / rad[0] (extra threads only stage memory)
+#endif
+
 
 namespace dnslab {
 
@@ -661,7 +667,7 @@ hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r, hipStream_t s, Reco
     const int nl = 1 << a.nl_x;
     const int nlines = a.g.ny * a.g.nz;
     dim3 grid((nlines + nl - 1) / nl);
-    dim3 block(round64(nl * a.px.tpl));
+    dim3 block(round64(std::min(1024, nl * a.px.tpl * DNSLAB_FFT_TPL_MUL)));
     size_t lds = ((size_t)nl * a.ls_x + 2 * a.m + 1) * sizeof(C2<T>);
     FxfArgs<T> b;
     b.f = a;
@@ -679,7 +685,7 @@ hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s, Recorder* 
     const int nl = 1 << a.nl_x;
     const int nlines = a.g.ny * a.g.nz;
     dim3 grid((nlines + nl - 1) / nl);
-    dim3 block(round64(nl * a.px.tpl));
+    dim3 block(round64(std::min(1024, nl * a.px.tpl * DNSLAB_FFT_TPL_MUL)));
     size_t lds = ((size_t)nl * a.ls_x + 2 * a.m + 1) * sizeof(C2<T>);
     FxiArgs<T> b;
     b.f = a;
@@ -700,7 +706,7 @@ static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s, Reco
     const int ntile = (a.m + tx - 1) / tx;
     const int nblocks = ntile * nplane + (nplane + tx - 1) / tx;
     const AxisPlan& ap = zp ? a.pz : a.py;
-    dim3 block(round64(tx * ap.tpl));
+    dim3 block(round64(std::min(1024, tx * ap.tpl * DNSLAB_FFT_TPL_MUL)));
     size_t lds = ((size_t)tx * nrow + nrow) * sizeof(C2<T>);
     if (rec) {
         record_launch(rec, kind_code(KK_COLS, mode, sizeof(T) == 4), dim3(nblocks), block, lds, a);

@@ -495,12 +495,27 @@ __device__ __forceinline__ void finish_body(const FinishArgs& f) {
     DiagRec* ring = f.ring;
     const double dv = f.dv;
     Partial acc = {0, 0, 0, 0, 0, 0, {0, 0}};
-    for (int b = threadIdx.x; b < np; b += blockDim.x) {
-        const Partial q = part[b];
-        acc.ke += q.ke; acc.mass += q.mass; acc.room_num += q.room_num; acc.room_den += q.room_den;
-        acc.rate = fmax(acc.rate, q.rate);
+    // Four partials per thread in flight before any is summed: the block is
+    // alone on the chip, so the loads' latency, not their bytes, is the cost.
+    constexpr int U = 4;
+    const int nthr = blockDim.x;
+    for (int b0 = threadIdx.x; b0 < np || b0 < nd; b0 += U * nthr) {
+        Partial q[U];
+        double dq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * nthr;
+            q[u] = b < np ? part[b] : Partial{0, 0, 0, 0, 0, 0, {0, 0}};
+            dq[u] = b < nd ? pdiv[b].div2 : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc.ke += q[u].ke; acc.mass += q[u].mass; acc.room_num += q[u].room_num;
+            acc.room_den += q[u].room_den;
+            acc.rate = fmax(acc.rate, q[u].rate);
+            acc.div2 += dq[u];
+        }
     }
-    for (int b = threadIdx.x; b < nd; b += blockDim.x) acc.div2 += pdiv[b].div2;
     __shared__ Partial res;
     block_reduce_partial(acc, &res);
     __syncthreads();
