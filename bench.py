@@ -57,7 +57,8 @@ def kernel_bytes(sc, esz=8):
         "fft_y": 2 * spec,
         "fft_z": 2 * spec,
         "fft_x_inv": spec + n * esz,
-        "filter": n * (8 * esz + 1),
+        "filter": n * (6 * esz + 1),                  # velocity: 3 fields in, 3 out
+        "filter_c": n * (2 * esz + 1),                # CO2
         # FP64: u* and p in, u out; FP32 form: u*, p_n, dp in, u and p out (FP64 arithmetic)
         "correct": n * (7 * esz + 1) if esz == 8 else n * (9 * esz + 1),
         "div": n * 4 * esz,
@@ -73,7 +74,7 @@ def step_bytes(sc, esz=8):
     poisson = kb["fft_x_fwd"] + y_passes * kb["fft_y"] + kb["fft_z"] + kb["fft_x_inv"]
     ib = kb["ib_rhs"] if (sc.beta == 0).any() else 0
     total = (4 * kb["mom_stage"] + kb["div"] + it * (poisson + ib) + kb["correct"]
-             + 4 * kb["scalar_stage"] + (kb["filter"] if sc.filter else 0))
+             + 4 * kb["scalar_stage"] + (kb["filter"] + kb["filter_c"] if sc.filter else 0))
     if esz == 4 and it > 0:
         total += kb["refine_res"] + poisson           # FP64 residual and one correction solve
     return total
@@ -144,6 +145,78 @@ def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7):
     return out
 
 
+# Kernel symbol (as rocprofv3 prints it) -> name in kernel_bytes.
+def kernel_key(sym):
+    import re
+    m = re.search(r"k_(\w+?)(_b)?(<([^>]*)>)?\(", sym)
+    if not m:
+        return None
+    base, targs = m.group(1), (m.group(4) or "")
+    if base == "mom_stage":
+        return "mom_stage"
+    if base == "sca_stage":
+        return "scalar_stage"
+    if base == "filter":
+        return "filter" if targs.endswith("3") else "filter_c"
+    if base == "fft_cols":
+        return "fft_z" if targs.endswith("2") else "fft_y"
+    if base in ("correct", "refine_correct"):
+        return "correct"
+    if base in ("div", "fft_x_fwd", "fft_x_inv", "ib_rhs", "refine_res"):
+        return base
+    return None
+
+
+def copy_probe(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of nbytes, reps times: the reference for
+    scaling rocprofv3's FETCH_SIZE and WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def pmc_per_kernel(csv_path, counter):
+    """Mean counter value (KiB per dispatch) per kernel symbol from a
+    rocprofv3 --pmc counter_collection.csv."""
+    import csv
+    acc = {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            k = row["Kernel_Name"]
+            s, n = acc.get(k, (0.0, 0))
+            acc[k] = (s + float(row["Counter_Value"]), n + 1)
+    return {k: s / n for k, (s, n) in acc.items()}
+
+
+def traffic_table(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes=1 << 30):
+    """Calibrated HBM bytes per launch of each kernel: FETCH_SIZE and
+    WRITE_SIZE scaled by what they read for the plain copy of copy_bytes."""
+    cf = max(pmc_per_kernel(copy_fetch_csv, "FETCH_SIZE").items(), key=lambda kv: kv[1])[1]
+    cw = max(pmc_per_kernel(copy_write_csv, "WRITE_SIZE").items(), key=lambda kv: kv[1])[1]
+    f_scale, w_scale = copy_bytes / (1024 * cf), copy_bytes / (1024 * cw)
+    out = {}
+    for counter, path, scale in (("FETCH_SIZE", fetch_csv, f_scale), ("WRITE_SIZE", write_csv, w_scale)):
+        sums = {}
+        for sym, v in pmc_per_kernel(path, counter).items():
+            key = kernel_key(sym)
+            if key is None:
+                continue
+            s, n = sums.get(key, (0.0, 0))
+            sums[key] = (s + v * 1024 * scale, n + 1)
+        for key, (s, n) in sums.items():
+            out.setdefault(key, {})["fetch_bytes" if counter == "FETCH_SIZE" else "write_bytes"] = s / n
+    for key, d in out.items():
+        d["bytes"] = d.get("fetch_bytes", 0.0) + d.get("write_bytes", 0.0)
+    return {"fetch_scale": f_scale, "write_scale": w_scale, "kernels": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,7 +228,29 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--serving", default="short", choices=["none", "short", "full"],
                     help="serving stream: short = 16 requests x 300 steps, full = 64 x 2000")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the plain 1 GiB device copy used to calibrate the PMC byte counters")
+    ap.add_argument("--traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="fold rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE outputs of this benchmark and of --copy-probe "
+                         "into profiles/traffic.json under <workload>/<precision> (no GPU needed)")
     args = ap.parse_args()
+    if args.traffic:
+        tfile = os.path.join(ROOT, "profiles", "traffic.json")
+        tab = {}
+        if os.path.exists(tfile):
+            with open(tfile) as f:
+                tab = json.load(f)
+        t = traffic_table(*args.traffic)
+        tab[f"{args.workload}/{args.precision}"] = {k: v["bytes"] for k, v in t["kernels"].items()}
+        tab[f"{args.workload}/{args.precision}/detail"] = t
+        os.makedirs(os.path.dirname(tfile), exist_ok=True)
+        with open(tfile, "w") as f:
+            json.dump(tab, f, indent=1, sort_keys=True)
+        print(json.dumps(t, indent=1))
+        return
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the step runs on a single MI355X and this build has "
               "no multi-GPU path (--gpus must be 1)", file=sys.stderr)

@@ -25,10 +25,11 @@ thread_local std::string g_thread_err;
 constexpr int RING_CAP = 4096;
 constexpr int PROF_POOL = 32768;
 
-enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_CORR, K_DIV, K_IB, K_FIN, K_REF,
-                K_COUNT };
+enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_FILTC, K_CORR, K_DIV, K_IB,
+                K_ADV, K_DIAG, K_REF, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {"mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z", "fft_x_inv",
-                                            "filter", "correct", "div", "ib_rhs", "finish", "refine_res"};
+                                            "filter", "filter_c", "correct", "div", "ib_rhs", "advance", "diag",
+                                            "refine_res"};
 
 bool is_2a3b(int n) {
     if (n < 1) return false;
@@ -58,8 +59,9 @@ struct Layout {
     StencilLaunch L1;      // one-cell-per-thread kernels (correct, div, rate)
     StencilLaunch LF;      // filter
     int nparts;            // partial-result slots (max block count of the reducing kernels)
+    int nfields;           // work fields: 13, plus 3 for the projected velocity when the filter is on
     // byte offsets inside the workspace
-    size_t off_flags, off_fields, off_spec, off_tw, off_s2, off_forced, off_part, off_pdiv, off_sc, off_ring;
+    size_t off_flags, off_fields, off_spec, off_tw, off_s2, off_forced, off_part, off_sc, off_ring;
     size_t total;
     int nforced_cap;
 };
@@ -167,14 +169,14 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     Lo.off_flags = take((size_t)g.n);
-    Lo.off_fields = take((size_t)13 * g.n * Lo.esz);
+    Lo.nfields = P->filter ? 16 : 13;
+    Lo.off_fields = take((size_t)Lo.nfields * g.n * Lo.esz);
     Lo.off_spec = take((size_t)Lo.sx * nlines * csz);
     Lo.off_tw = take((size_t)(Lo.m + P->ny + P->nz + Lo.m + 1) * csz);
     Lo.off_s2 = take((size_t)(Lo.m + 1 + P->ny + P->nz) * sizeof(double));
     Lo.nforced_cap = std::max(1, n_forced);
     Lo.off_forced = take((size_t)Lo.nforced_cap * (sizeof(long long) + 5 * sizeof(double)));
-    Lo.off_part = take((size_t)Lo.nparts * sizeof(Partial));
-    Lo.off_pdiv = take((size_t)Lo.nparts * sizeof(Partial));
+    Lo.off_part = take((size_t)PF_COUNT * Lo.nparts * sizeof(double));
     Lo.off_sc = take(sizeof(StepScalars));
     Lo.off_ring = take((size_t)RING_CAP * sizeof(DiagRec));
     Lo.total = off;
@@ -212,26 +214,35 @@ struct dnslab_ctx {
     void* ws;
     void *u, *v, *w, *p, *c;
     uint8_t* flags;
-    void* f[13];           // A0..2, B0..2, Cb0..2, R0, CA, CS1, CS2
+    void* f[16];           // A0..2, B0..2, Cb0..2, R0, CA, CS1, CS2, V0..2 (filter on)
     void* spec;
     void *wx, *wy, *wz, *tw;
     double *sx2, *sy2, *sz2;
     long long* fidx;
     double *fS, *fuset, *fcset;
     int nforced;
-    Partial *part, *pdiv;
+    PartSoA part;
     StepScalars* sc;
     DiagRec* ring;
     bool any_solid;
     void* ib_buf;          // near-solid list: idx (int), mask (uint8), saved r0 (field type)
-    IBList ib;
     void* ib_r0;
+    IBList ib;
     bool rate_valid;
     long long host_step;
     DiagRec* pinned;       // host staging for diagnostics
     StepScalars* pinned_sc;
     std::string err;
     Recorder* rec;         // non-NULL: launches are recorded for batched replay, not issued
+    hipStream_t cur;       // stream of the launches being enqueued (stream, or aux for the scalar work)
+    // The scalar transport of step n only needs the projected velocity of
+    // step n; it runs on a second stream, overlapping the pressure solves of
+    // step n + 1 (see one_step).
+    bool overlap;          // defer the scalar work to aux (plain contexts; not when recording)
+    hipStream_t aux;       // created on first use
+    hipEvent_t ev_fork, ev_join;
+    bool tail_pending;     // scalar work of the last step taken not yet enqueued
+    bool join_pending;     // stream has not yet waited for the last enqueued scalar work
     // profiling
     int prof_kid;
     std::vector<hipEvent_t> ev;
@@ -258,6 +269,7 @@ int fail(dnslab_ctx* ctx, int code, const std::string& msg) {
 int prof_flush(dnslab_ctx* x) {
     if (x->ev_used == 0) return DNSLAB_OK;
     HIPCHK(x, hipStreamSynchronize(x->stream));
+    if (x->aux) HIPCHK(x, hipStreamSynchronize(x->aux));
     for (int i = 0; i + 1 < x->ev_used; i += 2) {
         float ms = 0;
         HIPCHK(x, hipEventElapsedTime(&ms, x->ev[i], x->ev[i + 1]));
@@ -275,12 +287,12 @@ struct Prof {
     Prof(dnslab_ctx* x_, int kid) : x(x_), on(x_->prof_kid == kid && !x_->rec) {
         if (on) {
             if (x->ev_used + 2 > (int)x->ev.size()) prof_flush(x);
-            (void)hipEventRecord(x->ev[x->ev_used], x->stream);
+            (void)hipEventRecord(x->ev[x->ev_used], x->cur);
         }
     }
     ~Prof() {
         if (on) {
-            (void)hipEventRecord(x->ev[x->ev_used + 1], x->stream);
+            (void)hipEventRecord(x->ev[x->ev_used + 1], x->cur);
             x->ev_used += 2;
         }
     }
@@ -338,75 +350,100 @@ FFTArgs<T> fft_args(dnslab_ctx* x) {
 template <typename T>
 int poisson_solve(dnslab_ctx* x, const T* r, T* pout) {
     const FFTArgs<T> a = fft_args<T>(x);
-    LAUNCH(x, K_FXF, launch_fft_x_fwd<T>(a, r, x->stream, x->rec));
-    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, false, x->stream, x->rec));
-    LAUNCH(x, K_FZ, launch_fft_z_solve<T>(a, x->stream, x->rec));
-    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, true, x->stream, x->rec));
-    LAUNCH(x, K_FXI, launch_fft_x_inv<T>(a, pout, x->stream, x->rec));
+    LAUNCH(x, K_FXF, launch_fft_x_fwd<T>(a, r, x->cur, x->rec));
+    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, false, x->cur, x->rec));
+    LAUNCH(x, K_FZ, launch_fft_z_solve<T>(a, x->cur, x->rec));
+    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, true, x->cur, x->rec));
+    LAUNCH(x, K_FXI, launch_fft_x_inv<T>(a, pout, x->cur, x->rec));
     return DNSLAB_OK;
 }
 
-// Projection of Section 2.2: r0 = div u*, n IB iterations on the bound p, correction.
-// In the FP32 form the last solve is refined once in FP64 (iterative
-// refinement): its residual r_n - Lap_h p_n is formed in FP64 from the FP32
-// fields, solved for a correction dp, and the velocity correction
+// Projection of Section 2.2 in three parts: r0 = div u* (project_div), the n
+// IB iterations on the bound p (project_solve), and the velocity correction
+// (project_correct).  In the FP32 form the last solve is refined once in FP64
+// (iterative refinement): its residual r_n - Lap_h p_n is formed in FP64 from
+// the FP32 fields, solved for a correction dp, and the velocity correction
 // u = beta (u* - grad(p_n + dp)) is applied in FP64 arithmetic.
 template <typename T>
-int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
-    T* r0 = (T*)x->f[9];
-    T* p = (T*)x->p;
+int project_div(dnslab_ctx* x, const T* const us[3]) {
     DivArgs<T> d;
     for (int a = 0; a < 3; ++a) d.u[a] = us[a];
-    d.out = r0;
+    d.out = (T*)x->f[9];
     d.g = x->g;
-    LAUNCH(x, K_DIV, launch_div<T>(d, x->Lo.L1, x->stream, x->rec));
-    // With no solid cell the iterates are identical: one solve gives them all.
-    const int nit = x->any_solid ? x->P.n_piter : std::min(x->P.n_piter, 1);
-    constexpr bool fp32 = sizeof(T) == 4;
-    const bool refine = fp32 && x->P.precision == DNSLAB_FP32_REFINE && nit > 0;
+    LAUNCH(x, K_DIV, launch_div<T>(d, x->Lo.L1, x->cur, x->rec));
+    return DNSLAB_OK;
+}
+
+// With no solid cell the IB iterates are identical: one solve gives them all.
+int n_solves(const dnslab_ctx* x) { return x->any_solid ? x->P.n_piter : std::min(x->P.n_piter, 1); }
+bool refining(const dnslab_ctx* x) { return x->P.precision == DNSLAB_FP32_REFINE && n_solves(x) > 0; }
+
+template <typename T>
+int project_solve(dnslab_ctx* x, const T* const us[3]) {
+    T* r0 = (T*)x->f[9];
+    T* p = (T*)x->p;
+    const int nit = n_solves(x);
+    const bool refine = refining(x);
     T* p_last = refine ? (T*)x->f[3] : p;    // the last iterate goes to a scratch field when refining
     for (int it = 0; it < nit; ++it) {
-        if (x->any_solid) LAUNCH(x, K_IB, launch_ib_rhs<T>(x->ib, x->g, p, r0, (T*)x->ib_r0, it == 0, x->stream, x->rec));
+        if (x->any_solid) LAUNCH(x, K_IB, launch_ib_rhs<T>(x->ib, x->g, p, r0, (T*)x->ib_r0, it == 0, x->cur, x->rec));
         int rc = poisson_solve<T>(x, r0, it == nit - 1 ? p_last : p);
         if (rc) return rc;
     }
-    if constexpr (fp32) {
+    if constexpr (sizeof(T) == 4) {
         if (refine) {
-            float* res = (float*)x->f[4];
-            float* dp = (float*)x->f[5];
             RefineResArgs ra;
             for (int a = 0; a < 3; ++a) ra.us[a] = (const float*)us[a];
             ra.p3 = (const float*)p;
             ra.p4 = (const float*)p_last;
             ra.flags = x->flags;
-            ra.res = res;
+            ra.res = (float*)x->f[4];
             ra.g = x->g;
-            LAUNCH(x, K_REF, launch_refine_res(ra, x->Lo.L1, x->stream, x->rec));
-            int rc = poisson_solve<float>(x, res, dp);
+            LAUNCH(x, K_REF, launch_refine_res(ra, x->Lo.L1, x->cur, x->rec));
+            int rc = poisson_solve<float>(x, (const float*)x->f[4], (float*)x->f[5]);
             if (rc) return rc;
+        }
+    }
+    return DNSLAB_OK;
+}
+
+template <typename T>
+int project_correct(dnslab_ctx* x, const T* const us[3], T* const out[3], PartSoA part) {
+    if constexpr (sizeof(T) == 4) {
+        if (refining(x)) {
             RefineCorrArgs rc2;
             for (int a = 0; a < 3; ++a) { rc2.us[a] = (const float*)us[a]; rc2.out[a] = (float*)out[a]; }
-            rc2.p4 = (const float*)p_last;
-            rc2.dp = dp;
-            rc2.p = (float*)p;
+            rc2.p4 = (const float*)x->f[3];
+            rc2.dp = (const float*)x->f[5];
+            rc2.p = (float*)x->p;
             rc2.flags = x->flags;
             rc2.g = x->g;
-            LAUNCH(x, K_CORR, launch_refine_correct(rc2, x->Lo.L1, x->stream, x->rec));
+            rc2.part = part;
+            LAUNCH(x, K_CORR, launch_refine_correct(rc2, x->Lo.L1, x->cur, x->rec));
             return DNSLAB_OK;
         }
     }
     CorrArgs<T> ca;
     for (int a = 0; a < 3; ++a) { ca.us[a] = us[a]; ca.out[a] = out[a]; }
-    ca.p = p;
+    ca.p = (const T*)x->p;
     ca.flags = x->flags;
     ca.g = x->g;
-    LAUNCH(x, K_CORR, launch_correct<T>(ca, x->Lo.L1, x->stream, x->rec));
+    ca.part = part;
+    LAUNCH(x, K_CORR, launch_correct<T>(ca, x->Lo.L1, x->cur, x->rec));
     return DNSLAB_OK;
 }
 
 template <typename T>
-int scalar_rk4(dnslab_ctx* x, const T* const uvel[3], const double* dtp, double dt, T* cout, Partial* pdiv,
-               Partial* pdiag) {
+int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
+    int rc = project_div<T>(x, us);
+    if (!rc) rc = project_solve<T>(x, us);
+    if (!rc) rc = project_correct<T>(x, us, out, PartSoA{});
+    return rc;
+}
+
+template <typename T>
+int scalar_rk4(dnslab_ctx* x, const T* const uvel[3], const double* dtp, double dt, T* cout, PartSoA pdiv,
+               PartSoA psca) {
     T* C = (T*)x->c;
     T* CA = (T*)x->f[10];
     T* CS1 = (T*)x->f[11];
@@ -422,13 +459,13 @@ int scalar_rk4(dnslab_ctx* x, const T* const uvel[3], const double* dtp, double 
     s.acc = CA;
     const StencilLaunch& L = x->Lo.L;
     s.cs = C; s.out = CS1; s.part = pdiv;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FIRST, s, L, x->stream, x->rec));
-    s.cs = CS1; s.cn = C; s.out = CS2; s.part = nullptr;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_HALF, s, L, x->stream, x->rec));
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FIRST, s, L, x->cur, x->rec));
+    s.cs = CS1; s.cn = C; s.out = CS2; s.part = PartSoA{};
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_HALF, s, L, x->cur, x->rec));
     s.cs = CS2; s.cn = C; s.out = CS1;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FULL, s, L, x->stream, x->rec));
-    s.cs = CS1; s.cn = nullptr; s.out = cout; s.part = pdiag;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_LAST, s, L, x->stream, x->rec));
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FULL, s, L, x->cur, x->rec));
+    s.cs = CS1; s.cn = nullptr; s.out = cout; s.part = psca;
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_LAST, s, L, x->cur, x->rec));
     return DNSLAB_OK;
 }
 
@@ -436,15 +473,109 @@ template <typename T>
 int ensure_rate(dnslab_ctx* x) {
     if (x->rate_valid || x->rec) return DNSLAB_OK;
     HIPCHK(x, launch_rate<T>((const T*)x->u, (const T*)x->v, (const T*)x->w, x->g, x->part, x->Lo.L1, x->stream));
+    // launch_rate fills the rate partials of L1.nblocks blocks
     HIPCHK(x, launch_set_rate(x->part, x->Lo.L1.nblocks, x->sc, x->stream));
     x->rate_valid = true;
     return DNSLAB_OK;
 }
 
+// Projected velocity of the step just taken: the filter's input when the
+// filter is on, else the velocity fields themselves.
+template <typename T>
+void projected_velocity(dnslab_ctx* x, T* V[3]) {
+    const bool filt = x->P.filter != 0;
+    for (int a = 0; a < 3; ++a) V[a] = filt ? (T*)x->f[13 + a] : (T*)(a == 0 ? x->u : a == 1 ? x->v : x->w);
+}
+
+// Scalar half of a step (Section 2.4: the CO2 is advanced after the projection
+// with the projected velocity frozen): RK4 with the step's dt, the scalar's
+// filter, and the step's diagnostics record.  Reads the projected velocity and
+// the step scalars left by the velocity half; touches nothing else the
+// velocity half of the next step uses.
+template <typename T>
+int scalar_half(dnslab_ctx* x) {
+    const bool filt = x->P.filter != 0;
+    T* V[3];
+    projected_velocity<T>(x, V);
+    const T* Vc[3] = {V[0], V[1], V[2]};
+    T* C = (T*)x->c;
+    T* CS2 = (T*)x->f[12];
+    int rc = scalar_rk4<T>(x, Vc, &x->sc->last_dt, 0.0, filt ? CS2 : C, x->part, filt ? PartSoA{} : x->part);
+    if (rc) return rc;
+    if (filt) {
+        FiltArgs<T> fa = {};
+        fa.in[0] = CS2;
+        fa.out[0] = C;
+        fa.nf = 1;
+        fa.flags = x->flags;
+        fa.g = x->g;
+        fa.part = x->part;
+        LAUNCH(x, K_FILTC, launch_filter<T>(fa, x->Lo.LF, x->cur, x->rec));
+    }
+    DiagArgs d;
+    d.part = x->part;
+    d.np_vel = filt ? x->Lo.LF.nblocks : x->Lo.L1.nblocks;
+    d.np_sca = filt ? x->Lo.LF.nblocks : x->Lo.L.nblocks;
+    d.np_div = x->Lo.L.nblocks;
+    d.sc = x->sc;
+    d.ring = x->ring;
+    d.ring_cap = RING_CAP;
+    d.dv = x->g.dv;
+    LAUNCH(x, K_DIAG, launch_diag(d, x->cur, x->rec));
+    return DNSLAB_OK;
+}
+
+// Enqueue the deferred scalar half of the last step on the second stream,
+// ordered after everything enqueued so far on the main stream.
+template <typename T>
+int flush_scalar_half(dnslab_ctx* x) {
+    if (!x->tail_pending) return DNSLAB_OK;
+    x->tail_pending = false;
+    HIPCHK(x, hipEventRecord(x->ev_fork, x->stream));
+    HIPCHK(x, hipStreamWaitEvent(x->aux, x->ev_fork, 0));
+    x->cur = x->aux;
+    const int rc = scalar_half<T>(x);
+    x->cur = x->stream;
+    if (rc) return rc;
+    HIPCHK(x, hipEventRecord(x->ev_join, x->aux));
+    x->join_pending = true;
+    return DNSLAB_OK;
+}
+
+// Main stream waits for the scalar work enqueued on the second stream.
+int join_scalar_half(dnslab_ctx* x) {
+    if (!x->join_pending) return DNSLAB_OK;
+    HIPCHK(x, hipStreamWaitEvent(x->stream, x->ev_join, 0));
+    x->join_pending = false;
+    return DNSLAB_OK;
+}
+
+int ensure_aux(dnslab_ctx* x) {
+    if (x->aux) return DNSLAB_OK;
+    HIPCHK(x, hipStreamCreateWithFlags(&x->aux, hipStreamNonBlocking));
+    HIPCHK(x, hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming));
+    HIPCHK(x, hipEventCreateWithFlags(&x->ev_join, hipEventDisableTiming));
+    return DNSLAB_OK;
+}
+
+// One time step (Sections 2.1, 2.2, 2.4).  Velocity half on the main stream:
+// RK4 momentum to u*, div u*, the IB pressure iterations, the correction, the
+// velocity filter and the step advance (t, step, next dt from the new Courant
+// rate).  Scalar half: see scalar_half.  On a plain context the scalar half of
+// step n is enqueued on the second stream once div u* of step n + 1 is
+// enqueued, so that it runs beside that step's FFT pressure solves; the
+// correction of step n + 1, which overwrites the projected velocity the scalar
+// half reads, waits for it.  When recording for the pool both halves go, in
+// order, into one sequence.
 template <typename T>
 int one_step(dnslab_ctx* x) {
     int rc = ensure_rate<T>(x);
     if (rc) return rc;
+    const bool defer = x->overlap && !x->rec;
+    if (defer) {
+        rc = ensure_aux(x);
+        if (rc) return rc;
+    }
     T* U[3] = {(T*)x->u, (T*)x->v, (T*)x->w};
     T* A[3] = {(T*)x->f[0], (T*)x->f[1], (T*)x->f[2]};
     T* B[3] = {(T*)x->f[3], (T*)x->f[4], (T*)x->f[5]};
@@ -459,47 +590,55 @@ int one_step(dnslab_ctx* x) {
     m.g = x->g;
     // RK4 stages (Section 2.1), no pressure gradient
     for (int a = 0; a < 3; ++a) { m.us[a] = U[a]; m.acc[a] = A[a]; m.out[a] = B[a]; m.un[a] = nullptr; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FIRST, m, L, x->stream, x->rec));
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FIRST, m, L, x->cur, x->rec));
     for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = U[a]; m.out[a] = Cb[a]; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_HALF, m, L, x->stream, x->rec));
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_HALF, m, L, x->cur, x->rec));
     for (int a = 0; a < 3; ++a) { m.us[a] = Cb[a]; m.out[a] = B[a]; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FULL, m, L, x->stream, x->rec));
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FULL, m, L, x->cur, x->rec));
     for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = nullptr; m.out[a] = Cb[a]; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_LAST, m, L, x->stream, x->rec));
-    // projection: u* in Cb -> corrected velocity (into A when the filter follows)
-    const bool filt = x->P.filter != 0;
-    T* const* V = filt ? A : U;
-    rc = project<T>(x, Cb, V);
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_LAST, m, L, x->cur, x->rec));
+    // projection: u* in Cb -> projected velocity V
+    const T* const us[3] = {Cb[0], Cb[1], Cb[2]};
+    rc = project_div<T>(x, us);
+    if (!rc && defer) rc = flush_scalar_half<T>(x);
+    if (!rc) rc = project_solve<T>(x, us);
+    if (!rc) rc = join_scalar_half(x);
     if (rc) return rc;
-    // scalar RK4 with the projected velocity frozen
-    T* C = (T*)x->c;
-    T* CS2 = (T*)x->f[12];
-    rc = scalar_rk4<T>(x, V, &x->sc->dt, 0.0, filt ? CS2 : C, x->pdiv, filt ? nullptr : x->part);
+    const bool filt = x->P.filter != 0;
+    T* V[3];
+    projected_velocity<T>(x, V);
+    rc = project_correct<T>(x, us, V, filt ? PartSoA{} : x->part);
     if (rc) return rc;
     if (filt) {
         FiltArgs<T> fa = {};
-        for (int a = 0; a < 3; ++a) { fa.in[a] = A[a]; fa.out[a] = U[a]; }
-        fa.in[3] = CS2;
-        fa.out[3] = C;
-        fa.nf = 4;
+        for (int a = 0; a < 3; ++a) { fa.in[a] = V[a]; fa.out[a] = U[a]; }
+        fa.nf = 3;
         fa.flags = x->flags;
         fa.g = x->g;
         fa.part = x->part;
-        LAUNCH(x, K_FILT, launch_filter<T>(fa, x->Lo.LF, x->stream, x->rec));
+        LAUNCH(x, K_FILT, launch_filter<T>(fa, x->Lo.LF, x->cur, x->rec));
     }
-    const int np = filt ? x->Lo.LF.nblocks : L.nblocks;
-    FinishArgs fa2;
-    fa2.part = x->part;
-    fa2.np = np;
-    fa2.pdiv = x->pdiv;
-    fa2.nd = L.nblocks;
-    fa2.sc = x->sc;
-    fa2.ring = x->ring;
-    fa2.ring_cap = RING_CAP;
-    fa2.dv = x->g.dv;
-    LAUNCH(x, K_FIN, launch_finish(fa2, x->stream, x->rec));
+    AdvanceArgs av;
+    av.part = x->part;
+    av.np = filt ? x->Lo.LF.nblocks : x->Lo.L1.nblocks;
+    av.sc = x->sc;
+    LAUNCH(x, K_ADV, launch_advance(av, x->cur, x->rec));
+    if (defer) {
+        x->tail_pending = true;
+    } else {
+        rc = scalar_half<T>(x);
+        if (rc) return rc;
+    }
     if (!x->rec) x->host_step += 1;
     return DNSLAB_OK;
+}
+
+// Enqueue any deferred scalar work and order the main stream after it.
+template <typename T>
+int settle(dnslab_ctx* x) {
+    int rc = flush_scalar_half<T>(x);
+    if (!rc) rc = join_scalar_half(x);
+    return rc;
 }
 
 void diag_copy(const DiagRec& r, dnslab_diag* d) {
@@ -615,11 +754,10 @@ int upload_tables(dnslab_ctx* x) {
 
 template <typename T>
 int run_steps(dnslab_ctx* x, int nsteps) {
-    for (int s = 0; s < nsteps; ++s) {
-        int rc = one_step<T>(x);
-        if (rc) return rc;
-    }
-    return DNSLAB_OK;
+    int rc = DNSLAB_OK;
+    for (int s = 0; s < nsteps && !rc; ++s) rc = one_step<T>(x);
+    const int rc2 = settle<T>(x);
+    return rc ? rc : rc2;
 }
 
 int check_ctx(dnslab_ctx* x) {
@@ -640,7 +778,7 @@ int mom_rhs(dnslab_ctx* x, const void* u, const void* v, const void* w, void* fu
     m.nu = x->P.nu;
     for (int a = 0; a < 3; ++a) m.body[a] = x->P.body[a];
     m.g = x->g;
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_RHS, m, x->Lo.L, x->stream, x->rec));
+    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_RHS, m, x->Lo.L, x->cur, x->rec));
     return DNSLAB_OK;
 }
 template <typename T>
@@ -653,7 +791,7 @@ int sca_rhs(dnslab_ctx* x, const void* c, const void* u, const void* v, const vo
     s.frc = forcing_of<T>(x);
     s.alpha = x->P.alpha_c;
     s.g = x->g;
-    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_RHS, s, x->Lo.L, x->stream, x->rec));
+    LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_RHS, s, x->Lo.L, x->cur, x->rec));
     return DNSLAB_OK;
 }
 template <typename T>
@@ -664,7 +802,7 @@ int filt1(dnslab_ctx* x, const void* f, void* out) {
     a.nf = 1;
     a.flags = x->flags;
     a.g = x->g;
-    LAUNCH(x, K_FILT, launch_filter<T>(a, x->Lo.LF, x->stream, x->rec));
+    LAUNCH(x, K_FILT, launch_filter<T>(a, x->Lo.LF, x->cur, x->rec));
     return DNSLAB_OK;
 }
 }  // namespace
@@ -701,6 +839,8 @@ int dnslab_init(const dnslab_params* params, const uint8_t* beta_dev, int64_t n_
         x = new dnslab_ctx();
         x->P = *params;
         x->stream = (hipStream_t)params->stream;
+        x->cur = x->stream;
+        x->overlap = true;
         x->g = make_grid(params);
         x->Lo = make_layout(params, (int)n_forced);
         x->u = u; x->v = v; x->w = w; x->p = p; x->c = c;
@@ -714,7 +854,7 @@ int dnslab_init(const dnslab_params* params, const uint8_t* beta_dev, int64_t n_
         char* base = (char*)x->ws;
         const Layout& Lo = x->Lo;
         x->flags = (uint8_t*)(base + Lo.off_flags);
-        for (int i = 0; i < 13; ++i) x->f[i] = base + Lo.off_fields + (size_t)i * Lo.n * Lo.esz;
+        for (int i = 0; i < Lo.nfields; ++i) x->f[i] = base + Lo.off_fields + (size_t)i * Lo.n * Lo.esz;
         x->spec = base + Lo.off_spec;
         const size_t csz = 2 * Lo.esz;
         x->wx = base + Lo.off_tw;
@@ -728,8 +868,7 @@ int dnslab_init(const dnslab_params* params, const uint8_t* beta_dev, int64_t n_
         x->fS = (double*)(x->fidx + Lo.nforced_cap);
         x->fuset = x->fS + Lo.nforced_cap;
         x->fcset = x->fuset + 3 * (size_t)Lo.nforced_cap;
-        x->part = (Partial*)(base + Lo.off_part);
-        x->pdiv = (Partial*)(base + Lo.off_pdiv);
+        x->part = PartSoA{(double*)(base + Lo.off_part), Lo.nparts};
         x->sc = (StepScalars*)(base + Lo.off_sc);
         x->ring = (DiagRec*)(base + Lo.off_ring);
         if (hipHostMalloc((void**)&x->pinned, RING_CAP * sizeof(DiagRec), hipHostMallocDefault) != hipSuccess ||
@@ -793,7 +932,8 @@ int dnslab_step(dnslab_ctx* x, int32_t nsteps, dnslab_diag* diag) {
             HIPCHK(x, hipMemcpyAsync(x->pinned_sc, x->sc, sizeof(StepScalars), hipMemcpyDeviceToHost, x->stream));
             HIPCHK(x, hipStreamSynchronize(x->stream));
             diag_copy(x->pinned[0], diag);
-            if (x->pinned_sc->nonfinite) return fail(x, DNSLAB_ENONFINITE, "non-finite diagnostics");
+            if (x->pinned_sc->nonfinite || x->pinned_sc->nonfinite_diag)
+                return fail(x, DNSLAB_ENONFINITE, "non-finite diagnostics");
         }
         return DNSLAB_OK;
     } catch (...) {
@@ -838,10 +978,10 @@ int dnslab_scalar_step(dnslab_ctx* x, double dt) {
     if (!std::isfinite(dt)) return fail(x, DNSLAB_EINVAL, "dt not finite");
     if (x->Lo.esz == 8) {
         const double* U[3] = {(double*)x->u, (double*)x->v, (double*)x->w};
-        return scalar_rk4<double>(x, U, nullptr, dt, (double*)x->c, nullptr, nullptr);
+        return scalar_rk4<double>(x, U, nullptr, dt, (double*)x->c, PartSoA{}, PartSoA{});
     }
     const float* U[3] = {(float*)x->u, (float*)x->v, (float*)x->w};
-    return scalar_rk4<float>(x, U, nullptr, dt, (float*)x->c, nullptr, nullptr);
+    return scalar_rk4<float>(x, U, nullptr, dt, (float*)x->c, PartSoA{}, PartSoA{});
 }
 
 
@@ -872,6 +1012,7 @@ int dnslab_set_time(dnslab_ctx* x, double t, int64_t step) {
     s.t = t;
     s.step = step;
     s.nonfinite = 0;
+    s.nonfinite_diag = 0;
     *x->pinned_sc = s;
     HIPCHK(x, hipMemcpyAsync(x->sc, x->pinned_sc, sizeof(StepScalars), hipMemcpyHostToDevice, x->stream));
     x->host_step = step;
@@ -885,6 +1026,12 @@ int dnslab_set_time(dnslab_ctx* x, double t, int64_t step) {
 void dnslab_destroy(dnslab_ctx* x) {
     if (!x) return;
     (void)hipStreamSynchronize(x->stream);
+    if (x->aux) {
+        (void)hipStreamSynchronize(x->aux);
+        (void)hipStreamDestroy(x->aux);
+        (void)hipEventDestroy(x->ev_fork);
+        (void)hipEventDestroy(x->ev_join);
+    }
     for (hipEvent_t e : x->ev) (void)hipEventDestroy(e);
     if (x->ws) (void)hipFree(x->ws);
     if (x->ib_buf) (void)hipFree(x->ib_buf);
@@ -1215,7 +1362,9 @@ int dnslab_pool_admit(dnslab_pool* P, const dnslab_params* params, int64_t targe
         // dnslab_init has completed its work on the admission stream; from now on
         // the scenario is advanced on the pool's stream.
         S.ctx->stream = P->stream;
+        S.ctx->cur = P->stream;
         S.ctx->P.stream = P->stream;
+        S.ctx->overlap = false;   // the pool replays whole recorded steps on its one stream
         S.used = true;
         int slot = -1;
         for (size_t i = 0; i < P->slots.size(); ++i)

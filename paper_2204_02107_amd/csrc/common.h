@@ -42,8 +42,10 @@ struct StepScalars {
     double t;         // simulated time
     long long step;   // steps taken
     double dt_fixed, cfl, rate_floor;
-    int nonfinite;    // sticky flag: a diagnostic was NaN/Inf
-    int pad;
+    double last_dt;   // time step of the step just taken (the scalar transport of that step uses it)
+    double last_rate; // rate of the velocity that step started from
+    int nonfinite;    // sticky flag: the Courant rate was NaN/Inf
+    int nonfinite_diag;   // sticky flag: a diagnostic was NaN/Inf
 };
 
 // One diagnostics record, same layout as dnslab_diag.
@@ -52,11 +54,26 @@ struct DiagRec {
     long long step;
 };
 
-// Per-block partial results of the fused reductions.
+// Per-block partial results of the fused reductions (accumulated in registers).
 struct Partial {
     double ke, mass, room_num, room_den, rate;   // rate: max
     double div2;
-    double pad[2];
+};
+
+// The partials in memory, field-major: field f of block b at p[f * stride + b],
+// so that the single-block reductions read each field with coalesced loads.
+// Different kernels own different fields: the velocity ones (kinetic energy,
+// Courant rate), the scalar ones (CO2 mass and room sums) and the divergence.
+enum PartField { PF_KE = 0, PF_RATE, PF_MASS, PF_RNUM, PF_RDEN, PF_DIV2, PF_COUNT };
+enum : int {
+    PM_VEL = (1 << PF_KE) | (1 << PF_RATE),
+    PM_RATE = 1 << PF_RATE,
+    PM_SCA = (1 << PF_MASS) | (1 << PF_RNUM) | (1 << PF_RDEN),
+    PM_DIV = 1 << PF_DIV2,
+};
+struct PartSoA {
+    double* p;
+    int stride;
 };
 
 // Sparse forcing list (Section 2.1 source term), sorted by cell index.
@@ -107,7 +124,7 @@ __device__ __forceinline__ int batch_slot(const unsigned* __restrict__ starts, i
 
 // Kernel kinds of the step sequence (for recording and batched replay).
 enum KernelKind : int {
-    KK_MOM = 1, KK_SCA, KK_FILT, KK_CORR, KK_DIV, KK_REFRES, KK_REFCORR, KK_FINISH,   // stencil.hip
+    KK_MOM = 1, KK_SCA, KK_FILT, KK_CORR, KK_DIV, KK_REFRES, KK_REFCORR, KK_ADVANCE, KK_DIAG,   // stencil.hip
     KK_IB = 32, KK_FXF, KK_FXI, KK_COLS,                                              // fft.hip
 };
 __host__ __device__ constexpr int kind_code(int base, int mode, int fp32) { return (base << 8) | (mode << 1) | fp32; }
@@ -169,32 +186,28 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Block-wide deterministic reduction of a Partial (blockDim.x*y*z <= 1024).
-__device__ inline void block_reduce_partial(Partial p, Partial* out) {
-    __shared__ Partial sh[16];
+// Block-wide deterministic reduction of the fields MASK of a Partial; the
+// block's result goes to slot idx of out (blockDim.x*y*z <= 1024).
+template <int MASK>
+__device__ inline void block_reduce_partial(Partial p, PartSoA out, int idx) {
+    __shared__ double sh[16][PF_COUNT];
     const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
     const int nthr = blockDim.x * blockDim.y * blockDim.z;
     const int lane = tid & 63, wid = tid >> 6;
-    p.ke = wave_sum(p.ke);
-    p.mass = wave_sum(p.mass);
-    p.room_num = wave_sum(p.room_num);
-    p.room_den = wave_sum(p.room_den);
-    p.rate = wave_max(p.rate);
-    p.div2 = wave_sum(p.div2);
-    if (lane == 0) sh[wid] = p;
+    double v[PF_COUNT] = {p.ke, p.rate, p.mass, p.room_num, p.room_den, p.div2};
+#pragma unroll
+    for (int f = 0; f < PF_COUNT; ++f) {
+        if (!(MASK & (1 << f))) continue;
+        v[f] = f == PF_RATE ? wave_max(v[f]) : wave_sum(v[f]);
+        if (lane == 0) sh[wid][f] = v[f];
+    }
     __syncthreads();
-    if (tid == 0) {
-        Partial r = sh[0];
+    if (tid < PF_COUNT && (MASK & (1 << tid))) {
+        const int f = tid;
         const int nw = (nthr + 63) >> 6;
-        for (int w = 1; w < nw; ++w) {
-            r.ke += sh[w].ke;
-            r.mass += sh[w].mass;
-            r.room_num += sh[w].room_num;
-            r.room_den += sh[w].room_den;
-            r.rate = fmax(r.rate, sh[w].rate);
-            r.div2 += sh[w].div2;
-        }
-        *out = r;
+        double r = sh[0][f];
+        for (int w = 1; w < nw; ++w) r = f == PF_RATE ? fmax(r, sh[w][f]) : r + sh[w][f];
+        out.p[(size_t)f * out.stride + idx] = r;
     }
 }
 

@@ -44,18 +44,18 @@ struct ScaArgs {
     double alpha;
     Grid g;
     int kc;
-    Partial* part;    // ST_FIRST: div^2 partials; ST_LAST: step diagnostics partials
+    PartSoA part;     // ST_FIRST: div^2 partials; ST_LAST: CO2 diagnostics partials (p NULL: none)
 };
 
 template <typename T>
 struct FiltArgs {
-    const T* in[4];
-    T* out[4];
-    int nf;
+    const T* in[3];
+    T* out[3];
+    int nf;           // 3: the velocity (partials: kinetic energy, Courant rate); 1: a scalar (CO2 partials)
     const uint8_t* flags;
     Grid g;
     int kc;
-    Partial* part;    // step diagnostics of the outputs (nf == 4), or NULL
+    PartSoA part;     // diagnostics partials of the outputs (p NULL: none)
 };
 
 template <typename T>
@@ -66,6 +66,7 @@ struct CorrArgs {
     const uint8_t* flags;
     Grid g;
     int kc;
+    PartSoA part;     // kinetic energy and Courant rate partials of out (p NULL: none)
 };
 
 template <typename T>
@@ -98,6 +99,7 @@ struct RefineCorrArgs {
     const uint8_t* flags;
     Grid g;
     int kc;
+    PartSoA part;          // as CorrArgs::part
 };
 hipError_t launch_refine_res(const RefineResArgs& a, const struct StencilLaunch& L, hipStream_t s,
                              Recorder* rec = nullptr);
@@ -127,26 +129,35 @@ template <typename T> hipError_t launch_correct(const CorrArgs<T>& a, const Sten
 template <typename T> hipError_t launch_div(const DivArgs<T>& a, const StencilLaunch& L, hipStream_t s,
                                             Recorder* rec = nullptr);
 template <typename T> hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g,
-                                             Partial* part, const StencilLaunch& L, hipStream_t s);
+                                             PartSoA part, const StencilLaunch& L, hipStream_t s);
 
-// Reduce the partials of a step and advance the device step scalars.
-struct FinishArgs {
-    const Partial* part;
+// End of a step's velocity update (one block): reduce the Courant rate
+// partials of the new velocity, advance t and the step count, keep the step's
+// dt and starting rate for its diagnostics record, and set the next dt.
+struct AdvanceArgs {
+    PartSoA part;
     int np;
-    const Partial* pdiv;
-    int nd;
+    StepScalars* sc;
+};
+hipError_t launch_advance(const AdvanceArgs& a, hipStream_t s, Recorder* rec = nullptr);
+
+// Diagnostics record of the step just advanced (one block): reduce the kinetic
+// energy, CO2 and divergence partials and write the record into the ring.
+struct DiagArgs {
+    PartSoA part;
+    int np_vel, np_sca, np_div;
     StepScalars* sc;
     DiagRec* ring;
     int ring_cap;
     double dv;
 };
-hipError_t launch_finish(const FinishArgs& f, hipStream_t s, Recorder* rec = nullptr);
+hipError_t launch_diag(const DiagArgs& a, hipStream_t s, Recorder* rec = nullptr);
 
 // Batched replay of one recorded position over ns scenarios: tab holds ns
 // BRec<Args> entries (device), starts the ns+1 block offsets (device).
 hipError_t launch_batched_stencil(int kind, const void* tab, const unsigned* starts, int ns, unsigned total_blocks,
                                   dim3 block, size_t lds, hipStream_t s);
 // Reduce Courant partials only: sets sc->rate and the next dt.
-hipError_t launch_set_rate(const Partial* part, int np, StepScalars* sc, hipStream_t s);
+hipError_t launch_set_rate(PartSoA part, int np, StepScalars* sc, hipStream_t s);
 
 }  // namespace dnslab

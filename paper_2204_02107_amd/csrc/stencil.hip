@@ -188,7 +188,7 @@ __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockI
     const T* __restrict__ ux = a.u[0];
     const T* __restrict__ uy = a.u[1];
     const T* __restrict__ uz = a.u[2];
-    Partial part = {0, 0, 0, 0, 0, 0, {0, 0}};
+    Partial part = {0, 0, 0, 0, 0, 0};
 
     if (col.active) {
         T cm, c0, cp, wm, w0, wp;
@@ -229,7 +229,7 @@ __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockI
             if (MODE == ST_FIRST) {
                 a.acc[idx] = c0 + (dt / T(6)) * G;
                 a.out[idx] = c0 + (dt / T(2)) * G;
-                if (a.part) {
+                if (a.part.p) {
                     const double dv = ((double)uxp - (double)uxm) * g.inv2d[0] + ((double)vyp - (double)vym) * g.inv2d[1] +
                                       ((double)wp - (double)wm) * g.inv2d[2];
                     part.div2 += dv * dv;
@@ -241,13 +241,10 @@ __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockI
             } else if (MODE == ST_LAST) {
                 const T cnew = (f0 & F_FLUID) ? a.acc[idx] + (dt / T(6)) * G : T(0);
                 a.out[idx] = cnew;
-                if (a.part) {
-                    const double u = (double)ux[idx], v = (double)uy[idx], w = (double)w0;
+                if (a.part.p) {
                     const double b = (f0 & F_FLUID) ? 1.0 : 0.0;
-                    part.ke += b * (u * u + v * v + w * w);
                     part.mass += b * (double)cnew;
                     if (f0 & F_ROOM) { part.room_num += b * (double)cnew; part.room_den += b; }
-                    part.rate = fmax(part.rate, courant_rate(u, v, w, g));
                 }
             } else {
                 a.out[idx] = G;
@@ -255,7 +252,8 @@ __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockI
             cm = c0; c0 = cp; wm = w0; w0 = wp; fm = f0; f0 = fp;
         }
     }
-    if ((MODE == ST_FIRST || MODE == ST_LAST) && a.part) block_reduce_partial(part, a.part + (int)bi.hw);
+    if (MODE == ST_FIRST && a.part.p) block_reduce_partial<PM_DIV>(part, a.part, (int)bi.hw);
+    if (MODE == ST_LAST && a.part.p) block_reduce_partial<PM_SCA>(part, a.part, (int)bi.hw);
 }
 
 // ---------------------------------------------------------------------------
@@ -269,7 +267,7 @@ __device__ __forceinline__ void filter_body(const FiltArgs<T>& a, const BlockIdx
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T c6 = T(INV_PI6);
-    Partial part = {0, 0, 0, 0, 0, 0, {0, 0}};
+    Partial part = {0, 0, 0, 0, 0, 0};
     if (col.active) {
         int ix[7], jy[7];
 #pragma unroll
@@ -309,18 +307,21 @@ __device__ __forceinline__ void filter_body(const FiltArgs<T>& a, const BlockIdx
 #pragma unroll
                 for (int m = 0; m < 6; ++m) win[f][m] = win[f][m + 1];
             }
-            if (NF == 4 && a.part) {
-                const double u = (double)res[0], v = (double)res[1], w = (double)res[2];
-                const double c = (double)res[NF - 1];
+            if (a.part.p) {
                 const double b = (fl & F_FLUID) ? 1.0 : 0.0;
-                part.ke += b * (u * u + v * v + w * w);
-                part.mass += b * c;
-                if (fl & F_ROOM) { part.room_num += b * c; part.room_den += b; }
-                part.rate = fmax(part.rate, courant_rate(u, v, w, g));
+                if (NF == 3) {
+                    const double u = (double)res[0], v = (double)res[1], w = (double)res[2];
+                    part.ke += b * (u * u + v * v + w * w);
+                    part.rate = fmax(part.rate, courant_rate(u, v, w, g));
+                } else {
+                    const double c = (double)res[0];
+                    part.mass += b * c;
+                    if (fl & F_ROOM) { part.room_num += b * c; part.room_den += b; }
+                }
             }
         }
     }
-    if (NF == 4 && a.part) block_reduce_partial(part, a.part + (int)bi.hw);
+    if (a.part.p) block_reduce_partial<NF == 3 ? PM_VEL : PM_SCA>(part, a.part, (int)bi.hw);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,28 +331,37 @@ template <typename T>
 __device__ __forceinline__ void correct_body(const CorrArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
     const Col col = column(g, a.kc, bi);
-    if (!col.active) return;
-    const int k0 = col.k0, k1 = col.k1;
-    const unsigned nxy = (unsigned)g.nxy;
-    const T hx = T(g.inv2d[0]), hy = T(g.inv2d[1]), hz = T(g.inv2d[2]);
-    const T* __restrict__ p = a.p;
-    T pm = p[(unsigned)(k0 == 0 ? g.nz - 1 : k0 - 1) * nxy + col.row + col.i];
-    T p0 = p[(unsigned)k0 * nxy + col.row + col.i];
-    for (int k = k0; k < k1; ++k) {
-        const int kp = k + 1 == g.nz ? 0 : k + 1;
-        const unsigned base = (unsigned)k * nxy;
-        const unsigned idx = base + col.row + col.i;
-        const T pp = p[(unsigned)kp * nxy + col.row + col.i];
-        const T gx = (p[base + col.row + col.ip] - p[base + col.row + col.im]) * hx;
-        const T gy = (p[base + col.rowp + col.i] - p[base + col.rowm + col.i]) * hy;
-        const T gz = (pp - pm) * hz;
-        const bool fluid = a.flags[idx] & F_FLUID;
-        const T u = a.us[0][idx], v = a.us[1][idx], w = a.us[2][idx];
-        a.out[0][idx] = fluid ? u - gx : T(0);
-        a.out[1][idx] = fluid ? v - gy : T(0);
-        a.out[2][idx] = fluid ? w - gz : T(0);
-        pm = p0; p0 = pp;
+    Partial part = {0, 0, 0, 0, 0, 0};
+    if (col.active) {
+        const int k0 = col.k0, k1 = col.k1;
+        const unsigned nxy = (unsigned)g.nxy;
+        const T hx = T(g.inv2d[0]), hy = T(g.inv2d[1]), hz = T(g.inv2d[2]);
+        const T* __restrict__ p = a.p;
+        T pm = p[(unsigned)(k0 == 0 ? g.nz - 1 : k0 - 1) * nxy + col.row + col.i];
+        T p0 = p[(unsigned)k0 * nxy + col.row + col.i];
+        for (int k = k0; k < k1; ++k) {
+            const int kp = k + 1 == g.nz ? 0 : k + 1;
+            const unsigned base = (unsigned)k * nxy;
+            const unsigned idx = base + col.row + col.i;
+            const T pp = p[(unsigned)kp * nxy + col.row + col.i];
+            const T gx = (p[base + col.row + col.ip] - p[base + col.row + col.im]) * hx;
+            const T gy = (p[base + col.rowp + col.i] - p[base + col.rowm + col.i]) * hy;
+            const T gz = (pp - pm) * hz;
+            const bool fluid = a.flags[idx] & F_FLUID;
+            const T u = a.us[0][idx], v = a.us[1][idx], w = a.us[2][idx];
+            const T uo = fluid ? u - gx : T(0), vo = fluid ? v - gy : T(0), wo = fluid ? w - gz : T(0);
+            a.out[0][idx] = uo;
+            a.out[1][idx] = vo;
+            a.out[2][idx] = wo;
+            if (a.part.p) {
+                const double ud = (double)uo, vd = (double)vo, wd = (double)wo;
+                part.ke += fluid ? ud * ud + vd * vd + wd * wd : 0.0;
+                part.rate = fmax(part.rate, courant_rate(ud, vd, wd, g));
+            }
+            pm = p0; p0 = pp;
+        }
     }
+    if (a.part.p) block_reduce_partial<PM_VEL>(part, a.part, (int)bi.hw);
 }
 
 // ---------------------------------------------------------------------------
@@ -417,27 +427,38 @@ __device__ __forceinline__ void refine_res_body(const RefineResArgs& a, const Bl
 __device__ __forceinline__ void refine_correct_body(const RefineCorrArgs& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
     const Col col = column(g, a.kc, bi);
-    if (!col.active) return;
-    const int k0 = col.k0, k1 = col.k1;
-    const unsigned nxy = (unsigned)g.nxy;
-    auto P = [&](unsigned i) -> double { return (double)a.p4[i] + (double)a.dp[i]; };
-    double qm = P((unsigned)wrap(k0 - 1, g.nz) * nxy + col.row + col.i);
-    double q0 = P((unsigned)k0 * nxy + col.row + col.i);
-    for (int k = k0; k < k1; ++k) {
-        const unsigned base = (unsigned)k * nxy;
-        const unsigned idx = base + col.row + col.i;
-        const double qp = P((unsigned)wrap(k + 1, g.nz) * nxy + col.row + col.i);
-        const double gx = (P(base + col.row + col.ip) - P(base + col.row + col.im)) * g.inv2d[0];
-        const double gy = (P(base + col.rowp + col.i) - P(base + col.rowm + col.i)) * g.inv2d[1];
-        const double gz = (qp - qm) * g.inv2d[2];
-        const bool fluid = a.flags[idx] & F_FLUID;
-        const double u = a.us[0][idx], v = a.us[1][idx], w = a.us[2][idx];
-        a.out[0][idx] = fluid ? (float)(u - gx) : 0.0f;
-        a.out[1][idx] = fluid ? (float)(v - gy) : 0.0f;
-        a.out[2][idx] = fluid ? (float)(w - gz) : 0.0f;
-        a.p[idx] = (float)q0;
-        qm = q0; q0 = qp;
+    Partial part = {0, 0, 0, 0, 0, 0};
+    if (col.active) {
+        const int k0 = col.k0, k1 = col.k1;
+        const unsigned nxy = (unsigned)g.nxy;
+        auto P = [&](unsigned i) -> double { return (double)a.p4[i] + (double)a.dp[i]; };
+        double qm = P((unsigned)wrap(k0 - 1, g.nz) * nxy + col.row + col.i);
+        double q0 = P((unsigned)k0 * nxy + col.row + col.i);
+        for (int k = k0; k < k1; ++k) {
+            const unsigned base = (unsigned)k * nxy;
+            const unsigned idx = base + col.row + col.i;
+            const double qp = P((unsigned)wrap(k + 1, g.nz) * nxy + col.row + col.i);
+            const double gx = (P(base + col.row + col.ip) - P(base + col.row + col.im)) * g.inv2d[0];
+            const double gy = (P(base + col.rowp + col.i) - P(base + col.rowm + col.i)) * g.inv2d[1];
+            const double gz = (qp - qm) * g.inv2d[2];
+            const bool fluid = a.flags[idx] & F_FLUID;
+            const double u = a.us[0][idx], v = a.us[1][idx], w = a.us[2][idx];
+            const float uo = fluid ? (float)(u - gx) : 0.0f;
+            const float vo = fluid ? (float)(v - gy) : 0.0f;
+            const float wo = fluid ? (float)(w - gz) : 0.0f;
+            a.out[0][idx] = uo;
+            a.out[1][idx] = vo;
+            a.out[2][idx] = wo;
+            a.p[idx] = (float)q0;
+            if (a.part.p) {
+                const double ud = (double)uo, vd = (double)vo, wd = (double)wo;
+                part.ke += fluid ? ud * ud + vd * vd + wd * wd : 0.0;
+                part.rate = fmax(part.rate, courant_rate(ud, vd, wd, g));
+            }
+            qm = q0; q0 = qp;
+        }
     }
+    if (a.part.p) block_reduce_partial<PM_VEL>(part, a.part, (int)bi.hw);
 }
 
 // Divergence with central differences: out = sum_a D_a u_a (Section 2.2).
@@ -467,92 +488,112 @@ __device__ __forceinline__ void div_body(const DivArgs<T>& a, const BlockIdx3& b
 // Courant rate partials (max over cells), for the first step after (re)binding.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_rate(const T* u, const T* v, const T* w, const Grid g, int kc,
-                                              Partial* part) {
+                                              PartSoA part) {
     const BlockIdx3 bi = hw_block();
     const Col col = column(g, kc, bi);
     const int k0 = col.k0, k1 = col.k1;
-    Partial pp = {0, 0, 0, 0, 0, 0, {0, 0}};
+    Partial pp = {0, 0, 0, 0, 0, 0};
     if (col.active) {
         for (int k = k0; k < k1; ++k) {
             const unsigned idx = (unsigned)k * (unsigned)g.nxy + col.row + col.i;
             pp.rate = fmax(pp.rate, courant_rate((double)u[idx], (double)v[idx], (double)w[idx], g));
         }
     }
-    block_reduce_partial(pp, part + (int)bi.hw);
+    block_reduce_partial<PM_RATE>(pp, part, (int)bi.hw);
 }
 
 __device__ inline double next_dt(const StepScalars& s, double rate) {
     return s.dt_fixed > 0 ? s.dt_fixed : s.cfl / fmax(rate, s.rate_floor);
 }
 
-// One block: reduce the partials in a fixed order, write the diagnostics of
-// the step just taken, and advance t, the step count and dt.
-__device__ __forceinline__ void finish_body(const FinishArgs& f) {
-    const Partial* part = f.part;
-    const int np = f.np, nd = f.nd, ring_cap = f.ring_cap;
-    const Partial* pdiv = f.pdiv;
-    StepScalars* sc = f.sc;
-    DiagRec* ring = f.ring;
-    const double dv = f.dv;
-    Partial acc = {0, 0, 0, 0, 0, 0, {0, 0}};
-    // Four partials per thread in flight before any is summed: the block is
-    // alone on the chip, so the loads' latency, not their bytes, is the cost.
-    constexpr int U = 4;
+// One block: sum (or max) field f of the partials of n blocks in a fixed
+// order.  Each thread takes blocks tid, tid + nthr, ... four loads at a time;
+// the per-thread results are combined by block_reduce_partial.
+__device__ __forceinline__ double gather_partial(PartSoA part, int f, int n, bool is_max) {
+    const double* __restrict__ q = part.p + (size_t)f * part.stride;
     const int nthr = blockDim.x;
-    for (int b0 = threadIdx.x; b0 < np || b0 < nd; b0 += U * nthr) {
-        Partial q[U];
-        double dq[U];
+    constexpr int U = 4;
+    double acc = 0.0;
+    for (int b0 = threadIdx.x; b0 < n; b0 += U * nthr) {
+        double v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int b = b0 + u * nthr;
-            q[u] = b < np ? part[b] : Partial{0, 0, 0, 0, 0, 0, {0, 0}};
-            dq[u] = b < nd ? pdiv[b].div2 : 0.0;
+            v[u] = b < n ? q[b] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            acc.ke += q[u].ke; acc.mass += q[u].mass; acc.room_num += q[u].room_num;
-            acc.room_den += q[u].room_den;
-            acc.rate = fmax(acc.rate, q[u].rate);
-            acc.div2 += dq[u];
-        }
+        for (int u = 0; u < U; ++u) acc = is_max ? fmax(acc, v[u]) : acc + v[u];
     }
-    __shared__ Partial res;
-    block_reduce_partial(acc, &res);
+    return acc;
+}
+
+// Velocity side of the end of a step: the new velocity's Courant rate gives
+// the next dt; t and the step count advance by the step just taken, whose dt
+// and starting rate are kept for its diagnostics record.
+__device__ __forceinline__ void advance_body(const AdvanceArgs& a) {
+    Partial acc = {0, 0, 0, 0, 0, 0};
+    acc.rate = gather_partial(a.part, PF_RATE, a.np, true);
+    __shared__ double res[PF_COUNT];
+    PartSoA sh = {res, 1};
+    block_reduce_partial<PM_RATE>(acc, sh, 0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        StepScalars s = *sc;
-        DiagRec d;
-        d.dt = s.dt;
-        d.t = s.t + s.dt;
-        d.ke = 0.5 * res.ke * dv;
-        d.div_l2 = sqrt(res.div2 * dv);
-        d.co2_mass = res.mass * dv;
-        d.co2_room_mean = res.room_den > 0 ? res.room_num / res.room_den : 0.0;
-        d.cfl_max = s.dt * s.rate;
-        d.step = s.step + 1;
-        const bool bad = !isfinite(d.ke) || !isfinite(d.co2_mass) || !isfinite(d.div_l2) || !isfinite(res.rate);
-        s.nonfinite = s.nonfinite | (bad ? 1 : 0);
-        s.t = d.t;
-        s.step = d.step;
-        s.rate = res.rate;
-        s.dt = next_dt(s, res.rate);
-        *sc = s;
-        ring[(d.step - 1) % ring_cap] = d;
+        StepScalars* sc = a.sc;
+        const double rate = res[PF_RATE];
+        const double dt = sc->dt;
+        sc->last_dt = dt;
+        sc->last_rate = sc->rate;
+        sc->t = sc->t + dt;
+        sc->step = sc->step + 1;
+        sc->rate = rate;
+        sc->dt = next_dt(*sc, rate);
+        if (!isfinite(rate)) sc->nonfinite = 1;
     }
 }
 
-__global__ __launch_bounds__(1024) void k_set_rate(const Partial* part, int np, StepScalars* sc) {
-    Partial acc = {0, 0, 0, 0, 0, 0, {0, 0}};
-    for (int b = threadIdx.x; b < np; b += blockDim.x) acc.rate = fmax(acc.rate, part[b].rate);
-    __shared__ Partial res;
-    block_reduce_partial(acc, &res);
+// Diagnostics record of the step just advanced (after advance_body): kinetic
+// energy, divergence norm, CO2 mass and room mean from the partials.
+__device__ __forceinline__ void diag_body(const DiagArgs& a) {
+    Partial acc = {0, 0, 0, 0, 0, 0};
+    acc.ke = gather_partial(a.part, PF_KE, a.np_vel, false);
+    acc.mass = gather_partial(a.part, PF_MASS, a.np_sca, false);
+    acc.room_num = gather_partial(a.part, PF_RNUM, a.np_sca, false);
+    acc.room_den = gather_partial(a.part, PF_RDEN, a.np_sca, false);
+    acc.div2 = gather_partial(a.part, PF_DIV2, a.np_div, false);
+    __shared__ double res[PF_COUNT];
+    PartSoA sh = {res, 1};
+    block_reduce_partial<PM_SCA | PM_DIV | (1 << PF_KE)>(acc, sh, 0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        StepScalars s = *sc;
-        s.rate = res.rate;
-        s.dt = next_dt(s, res.rate);
-        if (!isfinite(res.rate)) s.nonfinite = 1;
-        *sc = s;
+        const StepScalars* sc = a.sc;
+        DiagRec d;
+        d.dt = sc->last_dt;
+        d.t = sc->t;
+        d.step = sc->step;
+        d.ke = 0.5 * res[PF_KE] * a.dv;
+        d.div_l2 = sqrt(res[PF_DIV2] * a.dv);
+        d.co2_mass = res[PF_MASS] * a.dv;
+        d.co2_room_mean = res[PF_RDEN] > 0 ? res[PF_RNUM] / res[PF_RDEN] : 0.0;
+        d.cfl_max = d.dt * sc->last_rate;
+        const bool bad = !isfinite(d.ke) || !isfinite(d.co2_mass) || !isfinite(d.div_l2);
+        if (bad) a.sc->nonfinite_diag = 1;
+        a.ring[(d.step - 1) % a.ring_cap] = d;
+    }
+}
+
+// Rate only (first step after binding a state): sets the rate and the next dt.
+__global__ __launch_bounds__(1024) void k_set_rate(PartSoA part, int np, StepScalars* sc) {
+    Partial acc = {0, 0, 0, 0, 0, 0};
+    acc.rate = gather_partial(part, PF_RATE, np, true);
+    __shared__ double res[PF_COUNT];
+    PartSoA sh = {res, 1};
+    block_reduce_partial<PM_RATE>(acc, sh, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double rate = res[PF_RATE];
+        sc->rate = rate;
+        sc->dt = next_dt(*sc, rate);
+        if (!isfinite(rate)) sc->nonfinite = 1;
     }
 }
 
@@ -631,12 +672,21 @@ __global__ __launch_bounds__(1024) void k_refine_correct_b(const BRec<RefineCorr
     const RefineCorrArgs a = tab[s_].a;
     refine_correct_body(a, bi_);
 }
-__global__ __launch_bounds__(1024) void k_finish(const FinishArgs f) { finish_body(f); }
-__global__ __launch_bounds__(1024) void k_finish_b(const BRec<FinishArgs>* __restrict__ tab,
-                                                   const unsigned* __restrict__ st, int ns) {
+__global__ __launch_bounds__(1024) void k_advance(const AdvanceArgs a) { advance_body(a); }
+__global__ __launch_bounds__(1024) void k_advance_b(const BRec<AdvanceArgs>* __restrict__ tab,
+                                                    const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
-    const FinishArgs f = tab[s_].a;
-    finish_body(f);
+    (void)bi_;
+    const AdvanceArgs a = tab[s_].a;
+    advance_body(a);
+}
+__global__ __launch_bounds__(1024) void k_diag(const DiagArgs a) { diag_body(a); }
+__global__ __launch_bounds__(1024) void k_diag_b(const BRec<DiagArgs>* __restrict__ tab,
+                                                 const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    (void)bi_;
+    const DiagArgs a = tab[s_].a;
+    diag_body(a);
 }
 
 }  // namespace
@@ -697,10 +747,10 @@ hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream
     FiltArgs<T> b = a;
     b.kc = L.kc;
     if (rec) {
-        record_launch(rec, kind_code(KK_FILT, a.nf == 4 ? 4 : 1, sizeof(T) == 4), L.grid, L.block, 0, b);
+        record_launch(rec, kind_code(KK_FILT, a.nf == 3 ? 3 : 1, sizeof(T) == 4), L.grid, L.block, 0, b);
         return hipSuccess;
     }
-    if (a.nf == 4) hipLaunchKernelGGL((k_filter<T, 4>), L.grid, L.block, 0, s, b);
+    if (a.nf == 3) hipLaunchKernelGGL((k_filter<T, 3>), L.grid, L.block, 0, s, b);
     else hipLaunchKernelGGL((k_filter<T, 1>), L.grid, L.block, 0, s, b);
     return hipGetLastError();
 }
@@ -730,7 +780,7 @@ hipError_t launch_div(const DivArgs<T>& a, const StencilLaunch& L, hipStream_t s
 }
 
 template <typename T>
-hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g, Partial* part,
+hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g, PartSoA part,
                        const StencilLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL((k_rate<T>), L.grid, L.block, 0, s, u, v, w, g, L.kc, part);
     return hipGetLastError();
@@ -758,12 +808,21 @@ hipError_t launch_refine_correct(const RefineCorrArgs& a, const StencilLaunch& L
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const FinishArgs& f, hipStream_t s, Recorder* rec) {
+hipError_t launch_advance(const AdvanceArgs& a, hipStream_t s, Recorder* rec) {
     if (rec) {
-        record_launch(rec, kind_code(KK_FINISH, 0, 0), dim3(1), dim3(1024), 0, f);
+        record_launch(rec, kind_code(KK_ADVANCE, 0, 0), dim3(1), dim3(1024), 0, a);
         return hipSuccess;
     }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, f);
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const DiagArgs& a, hipStream_t s, Recorder* rec) {
+    if (rec) {
+        record_launch(rec, kind_code(KK_DIAG, 0, 0), dim3(1), dim3(1024), 0, a);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_diag, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 
@@ -797,7 +856,7 @@ hipError_t batched_typed(int base, int mode, const void* tab, const unsigned* st
         }
         case KK_FILT: {
             auto t = (const BRec<FiltArgs<T>>*)tab;
-            if (mode == 4) hipLaunchKernelGGL((k_filter_b<T, 4>), grid, blk, 0, s, t, st, ns);
+            if (mode == 3) hipLaunchKernelGGL((k_filter_b<T, 3>), grid, blk, 0, s, t, st, ns);
             else hipLaunchKernelGGL((k_filter_b<T, 1>), grid, blk, 0, s, t, st, ns);
             break;
         }
@@ -826,15 +885,19 @@ hipError_t launch_batched_stencil(int kind, const void* tab, const unsigned* st,
         hipLaunchKernelGGL(k_refine_correct_b, dim3(nb), blk, 0, s, (const BRec<RefineCorrArgs>*)tab, st, ns);
         return hipGetLastError();
     }
-    if (base == KK_FINISH) {
-        hipLaunchKernelGGL(k_finish_b, dim3(nb), blk, 0, s, (const BRec<FinishArgs>*)tab, st, ns);
+    if (base == KK_ADVANCE) {
+        hipLaunchKernelGGL(k_advance_b, dim3(nb), blk, 0, s, (const BRec<AdvanceArgs>*)tab, st, ns);
+        return hipGetLastError();
+    }
+    if (base == KK_DIAG) {
+        hipLaunchKernelGGL(k_diag_b, dim3(nb), blk, 0, s, (const BRec<DiagArgs>*)tab, st, ns);
         return hipGetLastError();
     }
     return fp32 ? batched_typed<float>(base, mode, tab, st, ns, nb, blk, s)
                 : batched_typed<double>(base, mode, tab, st, ns, nb, blk, s);
 }
 
-hipError_t launch_set_rate(const Partial* part, int np, StepScalars* sc, hipStream_t s) {
+hipError_t launch_set_rate(PartSoA part, int np, StepScalars* sc, hipStream_t s) {
     hipLaunchKernelGGL(k_set_rate, dim3(1), dim3(1024), 0, s, part, np, sc);
     return hipGetLastError();
 }
@@ -845,7 +908,7 @@ hipError_t launch_set_rate(const Partial* part, int np, StepScalars* sc, hipStre
     template hipError_t launch_filter<T>(const FiltArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);        \
     template hipError_t launch_correct<T>(const CorrArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);       \
     template hipError_t launch_div<T>(const DivArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);            \
-    template hipError_t launch_rate<T>(const T*, const T*, const T*, const Grid&, Partial*,                        \
+    template hipError_t launch_rate<T>(const T*, const T*, const T*, const Grid&, PartSoA,                        \
                                        const StencilLaunch&, hipStream_t);
 DNSLAB_INST(double)
 DNSLAB_INST(float)
