@@ -117,7 +117,7 @@ Grid make_grid(const dnslab_params* P) {
 #define DNSLAB_KC 0            // z cells per thread (0: from the grid size)
 #endif
 #ifndef DNSLAB_FROWS
-#define DNSLAB_FROWS 4         // block height of the radius-3 filter
+#define DNSLAB_FROWS 8         // block height of the radius-3 filter
 #endif
 #ifndef DNSLAB_FKC
 #define DNSLAB_FKC 0

@@ -19,6 +19,17 @@ namespace {
 #ifndef DNSLAB_ZFAST
 #define DNSLAB_ZFAST 0
 #endif
+#ifndef DNSLAB_ZALT
+#define DNSLAB_ZALT 1
+#endif
+#ifndef DNSLAB_FILTER_LDS
+#define DNSLAB_FILTER_LDS 1
+#endif
+#ifndef DNSLAB_STENCIL_LDS
+#define DNSLAB_STENCIL_LDS 1
+#endif
+constexpr int FILT_LDS = 16;   // filter kind mode bit: LDS-tiled variant
+constexpr int STAGE_LDS = 8;   // RK4 stage kind mode bit: LDS-tiled variant
 
 constexpr double INV_PI6 = 1.0 / (3.14159265358979323846 * 3.14159265358979323846 *
                                   3.14159265358979323846 * 3.14159265358979323846 *
@@ -27,6 +38,7 @@ constexpr double INV_PI6 = 1.0 / (3.14159265358979323846 * 3.1415926535897932384
 struct Col {
     int i, j, im, ip, jm, jp;
     int k0, k1;
+    int dir;       // z march direction of the radius-3 filter: +1, or -1 on odd z chunks
     unsigned row, rowm, rowp;   // j*nx, jm*nx, jp*nx
     bool active;
 };
@@ -61,6 +73,10 @@ __device__ __forceinline__ Col column(const Grid& g, int kc, const BlockIdx3& bi
     c.j = by * blockDim.y + threadIdx.y;
     c.k0 = bz * kc;
     c.k1 = min(c.k0 + kc, g.nz);
+    // Neighbouring z chunks march towards (or away from) their common
+    // boundary at the same time, so the halo planes they both read are
+    // fetched once into the L2 instead of twice.
+    c.dir = (DNSLAB_ZALT && (bz & 1)) ? -1 : 1;
     c.active = c.i < g.nx && c.j < g.ny;
     if (!c.active) { c.i = 0; c.j = 0; }
     c.im = c.i == 0 ? g.nx - 1 : c.i - 1;
@@ -85,15 +101,46 @@ __device__ __forceinline__ double courant_rate(double u, double v, double w, con
 }
 
 // ---------------------------------------------------------------------------
+// LDS tiles of the z-marching kernels.  A block's tile of one plane (BX x BY
+// cells, all inside the grid) is held in LDS with its x and y halo of R cells
+// each side (no corners: every stencil here is a sum of one-axis differences),
+// as rows of W = BX + 2R values.  The interior comes from the threads' own z
+// register windows; stage_halo fetches the halo of one field.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <typename T, int R>
+__device__ __forceinline__ void stage_halo(T* tb, const T* __restrict__ src, unsigned base, int i0, int j0,
+                                           const Grid& g, int BX, int lgBX, int BY, int tid, int nthr) {
+    const int W = BX + 2 * R;
+    const int nhy = 2 * R * BX, nh = nhy + 2 * R * BY;
+    for (int r = tid; r < nh; r += nthr) {
+        int ly, lx;
+        if (r < nhy) {
+            const int hr = r >> lgBX;                 // halo row 0 .. 2R-1
+            ly = hr < R ? hr : BY + hr;
+            lx = R + (r - (hr << lgBX));
+        } else {
+            const int q = r - nhy, row = q / (2 * R), c = q - row * (2 * R);
+            ly = R + row;
+            lx = c < R ? c : BX + c;
+        }
+        // |offset| <= R <= n along both axes, so one wrap suffices
+        const int gi = wrap1(i0 + lx - R, g.nx), gj = wrap1(j0 + ly - R, g.ny);
+        tb[ly * W + lx] = src[base + (unsigned)gj * g.nx + gi];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Momentum RK4 stage.  k = beta [ -C(u) + nu L u + S (u_set - u)/tau_f + b ]
 // with the skew-symmetric convection written per axis as
 //   1/2 [D_a(u_a u_i) + u_a D_a u_i] = [(u_a+ + u_a0) u_i+ - (u_a- + u_a0) u_i-] / (4 dx_a).
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T, int MODE, bool LDS>
 __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
     const Col col = column(g, a.kc, bi);
-    if (!col.active) return;
+    if (!LDS && !col.active) return;      // the LDS variant only runs on tiles inside the grid
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T dt = (MODE == ST_RHS) ? T(0) : T(a.dtp ? *a.dtp : a.dt);
@@ -104,6 +151,14 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
     const T* __restrict__ u0p = a.us[0];
     const T* __restrict__ u1p = a.us[1];
     const T* __restrict__ u2p = a.us[2];
+    // LDS tiles (radius 1) of the three stage-input components, two planes
+    extern __shared__ unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int BX = blockDim.x, BY = blockDim.y, lgBX = __ffs(BX) - 1;
+    const int W = BX + 2, tsz = W * (BY + 2);
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty, nthr = BX * BY;
+    const int i0 = col.i - tx, j0 = col.j - ty;
+    int buf = 0;
 
     T zm[3], z0[3], zp[3];
     {
@@ -118,14 +173,34 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
         const unsigned base = (unsigned)k * nxy;
         const unsigned idx = base + col.row + col.i;
         const unsigned ipz = (unsigned)kp * nxy + col.row + col.i;
-        zp[0] = u0p[ipz]; zp[1] = u1p[ipz]; zp[2] = u2p[ipz];
         T xm[3], xp[3], ym[3], yp[3];
-        const unsigned ixm = base + col.row + col.im, ixp = base + col.row + col.ip;
-        const unsigned iym = base + col.rowm + col.i, iyp = base + col.rowp + col.i;
-        xm[0] = u0p[ixm]; xm[1] = u1p[ixm]; xm[2] = u2p[ixm];
-        xp[0] = u0p[ixp]; xp[1] = u1p[ixp]; xp[2] = u2p[ixp];
-        ym[0] = u0p[iym]; ym[1] = u1p[iym]; ym[2] = u2p[iym];
-        yp[0] = u0p[iyp]; yp[1] = u1p[iyp]; yp[2] = u2p[iyp];
+        if (LDS) {
+            T* tb = lds + buf * 3 * tsz;
+            buf ^= 1;
+            const int ctr = (ty + 1) * W + tx + 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) tb[c * tsz + ctr] = z0[c];
+            stage_halo<T, 1>(tb, u0p, base, i0, j0, g, BX, lgBX, BY, tid, nthr);
+            stage_halo<T, 1>(tb + tsz, u1p, base, i0, j0, g, BX, lgBX, BY, tid, nthr);
+            stage_halo<T, 1>(tb + 2 * tsz, u2p, base, i0, j0, g, BX, lgBX, BY, tid, nthr);
+            zp[0] = u0p[ipz]; zp[1] = u1p[ipz]; zp[2] = u2p[ipz];
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xm[c] = tb[c * tsz + ctr - 1];
+                xp[c] = tb[c * tsz + ctr + 1];
+                ym[c] = tb[c * tsz + ctr - W];
+                yp[c] = tb[c * tsz + ctr + W];
+            }
+        } else {
+            zp[0] = u0p[ipz]; zp[1] = u1p[ipz]; zp[2] = u2p[ipz];
+            const unsigned ixm = base + col.row + col.im, ixp = base + col.row + col.ip;
+            const unsigned iym = base + col.rowm + col.i, iyp = base + col.rowp + col.i;
+            xm[0] = u0p[ixm]; xm[1] = u1p[ixm]; xm[2] = u2p[ixm];
+            xp[0] = u0p[ixp]; xp[1] = u1p[ixp]; xp[2] = u2p[ixp];
+            ym[0] = u0p[iym]; ym[1] = u1p[iym]; ym[2] = u2p[iym];
+            yp[0] = u0p[iyp]; yp[1] = u1p[iyp]; yp[2] = u2p[iyp];
+        }
         const uint8_t fl = a.flags[idx];
 
         T kv[3];
@@ -275,18 +350,22 @@ __device__ __forceinline__ void filter_body(const FiltArgs<T>& a, const BlockIdx
             ix[m + 3] = wrap(col.i + m, g.nx);
             jy[m + 3] = wrap(col.j + m, g.ny) * g.nx;
         }
+        // win[f][m] holds plane k + (m - 3) dir; the z difference only uses the
+        // symmetric pairs (m, 6 - m), so either direction gives the same sums.
+        const int dir = col.dir;
+        const int ks = dir > 0 ? k0 : k1 - 1;
         T win[NF][7];
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
-                const int kk = wrap(k0 - 3 + m, g.nz);
+                const int kk = wrap(ks + (m - 3) * dir, g.nz);
                 win[f][m] = a.in[f][(unsigned)kk * nxy + col.row + col.i];
             }
-        for (int k = k0; k < k1; ++k) {
+        for (int k = ks, left = k1 - k0; left > 0; --left, k += dir) {
             const unsigned base = (unsigned)k * nxy;
             const unsigned idx = base + col.row + col.i;
-            const int kk = wrap(k + 3, g.nz);
+            const int kk = wrap(k + 3 * dir, g.nz);
             const uint8_t fl = a.flags[idx];
             T res[NF];
 #pragma unroll
@@ -318,6 +397,88 @@ __device__ __forceinline__ void filter_body(const FiltArgs<T>& a, const BlockIdx
                     part.mass += b * c;
                     if (fl & F_ROOM) { part.room_num += b * c; part.room_den += b; }
                 }
+            }
+        }
+    }
+    if (a.part.p) block_reduce_partial<NF == 3 ? PM_VEL : PM_SCA>(part, a.part, (int)bi.hw);
+}
+
+// The same filter with the x and y neighbours read from LDS.  The block's
+// tile of the current plane (BX x BY cells) plus its x and y halos (3 cells
+// each side, no corners) is staged in LDS per field; the interior comes from
+// the z register window, so only the halo is fetched from memory, and each
+// cell's twelve x/y neighbour loads become LDS reads.  Two tile buffers
+// alternate between planes, so one barrier per plane suffices.  Requires the
+// tile to divide the grid in x and y (nx % BX == 0, ny % BY == 0); the
+// arithmetic is that of filter_body term by term.
+template <typename T, int NF>
+__device__ __forceinline__ void filter_lds_body(const FiltArgs<T>& a, const BlockIdx3& bi) {
+    extern __shared__ unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const Grid& g = a.g;
+    const Col col = column(g, a.kc, bi);
+    const int BX = blockDim.x, BY = blockDim.y;
+    const int W = BX + 6, H = BY + 6;          // tile row length and rows
+    const int tsz = W * H;                     // one field's tile
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = tx + BX * ty, nthr = BX * BY;
+    const int i0 = col.i - tx, j0 = col.j - ty;   // tile origin (all columns active)
+    const int lgBX = __ffs(BX) - 1;
+    const unsigned nxy = (unsigned)g.nxy;
+    const T c6 = T(INV_PI6);
+    Partial part = {0, 0, 0, 0, 0, 0};
+    const int dir = col.dir;
+    const int k0 = col.k0, k1 = col.k1;
+    const int ks = dir > 0 ? k0 : k1 - 1;
+    T win[NF][7];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            const int kk = wrap(ks + (m - 3) * dir, g.nz);
+            win[f][m] = a.in[f][(unsigned)kk * nxy + col.row + col.i];
+        }
+    int buf = 0;
+    for (int k = ks, left = k1 - k0; left > 0; --left, k += dir, buf ^= 1) {
+        const unsigned base = (unsigned)k * nxy;
+        const unsigned idx = base + col.row + col.i;
+        T* tb = lds + buf * NF * tsz;
+        // stage: interior from the window, halo from memory
+#pragma unroll
+        for (int f = 0; f < NF; ++f) tb[f * tsz + (ty + 3) * W + tx + 3] = win[f][3];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) stage_halo<T, 3>(tb + f * tsz, a.in[f], base, i0, j0, g, BX, lgBX, BY, tid, nthr);
+        __syncthreads();
+        const int kk = wrap(k + 3 * dir, g.nz);
+        const uint8_t fl = a.flags[idx];
+        T res[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            win[f][6] = a.in[f][(unsigned)kk * nxy + col.row + col.i];
+            const T f0 = win[f][3];
+            const T* rowp = tb + f * tsz + (ty + 3) * W + tx;        // rowp[m] = x offset m - 3
+            const T* colp = tb + f * tsz + ty * W + tx + 3;          // colp[m W] = y offset m - 3
+            const T dx6 = (rowp[0] + rowp[6]) - T(6) * (rowp[1] + rowp[5]) +
+                          T(15) * (rowp[2] + rowp[4]) - T(20) * f0;
+            const T dy6 = (colp[0] + colp[6 * W]) - T(6) * (colp[W] + colp[5 * W]) +
+                          T(15) * (colp[2 * W] + colp[4 * W]) - T(20) * f0;
+            const T dz6 = (win[f][0] + win[f][6]) - T(6) * (win[f][1] + win[f][5]) +
+                          T(15) * (win[f][2] + win[f][4]) - T(20) * f0;
+            res[f] = (fl & F_FLUID) ? f0 + c6 * (dx6 + dy6 + dz6) : T(0);
+            a.out[f][idx] = res[f];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) win[f][m] = win[f][m + 1];
+        }
+        if (a.part.p) {
+            const double b = (fl & F_FLUID) ? 1.0 : 0.0;
+            if (NF == 3) {
+                const double u = (double)res[0], v = (double)res[1], w = (double)res[2];
+                part.ke += b * (u * u + v * v + w * w);
+                part.rate = fmax(part.rate, courant_rate(u, v, w, g));
+            } else {
+                const double c = (double)res[0];
+                part.mass += b * c;
+                if (fl & F_ROOM) { part.room_num += b * c; part.room_den += b; }
             }
         }
     }
@@ -611,14 +772,14 @@ __global__ __launch_bounds__(1024) void k_set_rate(PartSoA part, int np, StepSca
     bi_.gy = tab[s_].g[1];                              \
     bi_.gz = tab[s_].g[2];
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(1024) void k_mom_stage(const MomArgs<T> a) { mom_stage_body<T, MODE>(a, hw_block()); }
-template <typename T, int MODE>
+template <typename T, int MODE, bool LDS>
+__global__ __launch_bounds__(1024) void k_mom_stage(const MomArgs<T> a) { mom_stage_body<T, MODE, LDS>(a, hw_block()); }
+template <typename T, int MODE, bool LDS>
 __global__ __launch_bounds__(1024) void k_mom_stage_b(const BRec<MomArgs<T>>* __restrict__ tab,
                                                       const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const MomArgs<T> a = tab[s_].a;
-    mom_stage_body<T, MODE>(a, bi_);
+    mom_stage_body<T, MODE, LDS>(a, bi_);
 }
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) { sca_stage_body<T, MODE>(a, hw_block()); }
@@ -637,6 +798,15 @@ __global__ __launch_bounds__(1024) void k_filter_b(const BRec<FiltArgs<T>>* __re
     DNSLAB_BATCH_COORD(tab, st, ns)
     const FiltArgs<T> a = tab[s_].a;
     filter_body<T, NF>(a, bi_);
+}
+template <typename T, int NF>
+__global__ __launch_bounds__(1024) void k_filter_lds(const FiltArgs<T> a) { filter_lds_body<T, NF>(a, hw_block()); }
+template <typename T, int NF>
+__global__ __launch_bounds__(1024) void k_filter_lds_b(const BRec<FiltArgs<T>>* __restrict__ tab,
+                                                       const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const FiltArgs<T> a = tab[s_].a;
+    filter_lds_body<T, NF>(a, bi_);
 }
 template <typename T>
 __global__ __launch_bounds__(1024) void k_correct(const CorrArgs<T> a) { correct_body<T>(a, hw_block()); }
@@ -706,21 +876,34 @@ StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x) {
 #define MOM_KERNEL k_mom_stage
 #define SCA_KERNEL k_sca_stage
 
+// LDS variants of the z-marching kernels need the block's tile inside the grid.
+inline bool tile_divides(const Grid& g, const StencilLaunch& L) {
+    return g.nx % (int)L.block.x == 0 && g.ny % (int)L.block.y == 0;
+}
+
+template <typename T, bool LDS>
+void launch_mom_modes(int mode, const MomArgs<T>& b, const StencilLaunch& L, size_t lds, hipStream_t s) {
+    switch (mode) {
+        case ST_FIRST: hipLaunchKernelGGL((k_mom_stage<T, ST_FIRST, LDS>), L.grid, L.block, lds, s, b); break;
+        case ST_HALF: hipLaunchKernelGGL((k_mom_stage<T, ST_HALF, LDS>), L.grid, L.block, lds, s, b); break;
+        case ST_FULL: hipLaunchKernelGGL((k_mom_stage<T, ST_FULL, LDS>), L.grid, L.block, lds, s, b); break;
+        case ST_LAST: hipLaunchKernelGGL((k_mom_stage<T, ST_LAST, LDS>), L.grid, L.block, lds, s, b); break;
+        default: hipLaunchKernelGGL((k_mom_stage<T, ST_RHS, LDS>), L.grid, L.block, lds, s, b); break;
+    }
+}
+
 template <typename T>
 hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     MomArgs<T> b = a;
     b.kc = L.kc;
+    const bool use_lds = DNSLAB_STENCIL_LDS && tile_divides(a.g, L);
+    const size_t lds = use_lds ? (size_t)2 * 3 * (L.block.x + 2) * (L.block.y + 2) * sizeof(T) : 0;
     if (rec) {
-        record_launch(rec, kind_code(KK_MOM, mode, sizeof(T) == 4), L.grid, L.block, 0, b);
+        record_launch(rec, kind_code(KK_MOM, mode | (use_lds ? STAGE_LDS : 0), sizeof(T) == 4), L.grid, L.block, lds, b);
         return hipSuccess;
     }
-    switch (mode) {
-        case ST_FIRST: hipLaunchKernelGGL((k_mom_stage<T, ST_FIRST>), L.grid, L.block, 0, s, b); break;
-        case ST_HALF: hipLaunchKernelGGL((k_mom_stage<T, ST_HALF>), L.grid, L.block, 0, s, b); break;
-        case ST_FULL: hipLaunchKernelGGL((k_mom_stage<T, ST_FULL>), L.grid, L.block, 0, s, b); break;
-        case ST_LAST: hipLaunchKernelGGL((k_mom_stage<T, ST_LAST>), L.grid, L.block, 0, s, b); break;
-        default: hipLaunchKernelGGL((k_mom_stage<T, ST_RHS>), L.grid, L.block, 0, s, b); break;
-    }
+    if (use_lds) launch_mom_modes<T, true>(mode, b, L, lds, s);
+    else launch_mom_modes<T, false>(mode, b, L, 0, s);
     return hipGetLastError();
 }
 
@@ -746,12 +929,22 @@ template <typename T>
 hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     FiltArgs<T> b = a;
     b.kc = L.kc;
+    // the LDS-tiled variant when the tile divides the grid in x and y
+    const bool use_lds = DNSLAB_FILTER_LDS && tile_divides(a.g, L);
+    const int nf = a.nf == 3 ? 3 : 1;
+    const size_t lds = use_lds ? (size_t)2 * nf * (L.block.x + 6) * (L.block.y + 6) * sizeof(T) : 0;
     if (rec) {
-        record_launch(rec, kind_code(KK_FILT, a.nf == 3 ? 3 : 1, sizeof(T) == 4), L.grid, L.block, 0, b);
+        record_launch(rec, kind_code(KK_FILT, (a.nf == 3 ? 3 : 1) | (use_lds ? FILT_LDS : 0), sizeof(T) == 4), L.grid,
+                      L.block, lds, b);
         return hipSuccess;
     }
-    if (a.nf == 3) hipLaunchKernelGGL((k_filter<T, 3>), L.grid, L.block, 0, s, b);
-    else hipLaunchKernelGGL((k_filter<T, 1>), L.grid, L.block, 0, s, b);
+    if (use_lds) {
+        if (a.nf == 3) hipLaunchKernelGGL((k_filter_lds<T, 3>), L.grid, L.block, lds, s, b);
+        else hipLaunchKernelGGL((k_filter_lds<T, 1>), L.grid, L.block, lds, s, b);
+    } else {
+        if (a.nf == 3) hipLaunchKernelGGL((k_filter<T, 3>), L.grid, L.block, 0, s, b);
+        else hipLaunchKernelGGL((k_filter<T, 1>), L.grid, L.block, 0, s, b);
+    }
     return hipGetLastError();
 }
 
@@ -829,17 +1022,27 @@ hipError_t launch_diag(const DiagArgs& a, hipStream_t s, Recorder* rec) {
 namespace {
 template <typename T>
 hipError_t batched_typed(int base, int mode, const void* tab, const unsigned* st, int ns, unsigned nb, dim3 blk,
-                         hipStream_t s) {
+                         size_t lds, hipStream_t s) {
     const dim3 grid(nb);
     switch (base) {
         case KK_MOM: {
             auto t = (const BRec<MomArgs<T>>*)tab;
-            switch (mode) {
-                case ST_FIRST: hipLaunchKernelGGL((k_mom_stage_b<T, ST_FIRST>), grid, blk, 0, s, t, st, ns); break;
-                case ST_HALF: hipLaunchKernelGGL((k_mom_stage_b<T, ST_HALF>), grid, blk, 0, s, t, st, ns); break;
-                case ST_FULL: hipLaunchKernelGGL((k_mom_stage_b<T, ST_FULL>), grid, blk, 0, s, t, st, ns); break;
-                case ST_LAST: hipLaunchKernelGGL((k_mom_stage_b<T, ST_LAST>), grid, blk, 0, s, t, st, ns); break;
-                default: hipLaunchKernelGGL((k_mom_stage_b<T, ST_RHS>), grid, blk, 0, s, t, st, ns); break;
+            if (mode & STAGE_LDS) {
+                switch (mode & 7) {
+                    case ST_FIRST: hipLaunchKernelGGL((k_mom_stage_b<T, ST_FIRST, true>), grid, blk, lds, s, t, st, ns); break;
+                    case ST_HALF: hipLaunchKernelGGL((k_mom_stage_b<T, ST_HALF, true>), grid, blk, lds, s, t, st, ns); break;
+                    case ST_FULL: hipLaunchKernelGGL((k_mom_stage_b<T, ST_FULL, true>), grid, blk, lds, s, t, st, ns); break;
+                    case ST_LAST: hipLaunchKernelGGL((k_mom_stage_b<T, ST_LAST, true>), grid, blk, lds, s, t, st, ns); break;
+                    default: hipLaunchKernelGGL((k_mom_stage_b<T, ST_RHS, true>), grid, blk, lds, s, t, st, ns); break;
+                }
+            } else {
+                switch (mode & 7) {
+                    case ST_FIRST: hipLaunchKernelGGL((k_mom_stage_b<T, ST_FIRST, false>), grid, blk, 0, s, t, st, ns); break;
+                    case ST_HALF: hipLaunchKernelGGL((k_mom_stage_b<T, ST_HALF, false>), grid, blk, 0, s, t, st, ns); break;
+                    case ST_FULL: hipLaunchKernelGGL((k_mom_stage_b<T, ST_FULL, false>), grid, blk, 0, s, t, st, ns); break;
+                    case ST_LAST: hipLaunchKernelGGL((k_mom_stage_b<T, ST_LAST, false>), grid, blk, 0, s, t, st, ns); break;
+                    default: hipLaunchKernelGGL((k_mom_stage_b<T, ST_RHS, false>), grid, blk, 0, s, t, st, ns); break;
+                }
             }
             break;
         }
@@ -856,8 +1059,14 @@ hipError_t batched_typed(int base, int mode, const void* tab, const unsigned* st
         }
         case KK_FILT: {
             auto t = (const BRec<FiltArgs<T>>*)tab;
-            if (mode == 3) hipLaunchKernelGGL((k_filter_b<T, 3>), grid, blk, 0, s, t, st, ns);
-            else hipLaunchKernelGGL((k_filter_b<T, 1>), grid, blk, 0, s, t, st, ns);
+            const bool three = (mode & 7) == 3;
+            if (mode & FILT_LDS) {
+                if (three) hipLaunchKernelGGL((k_filter_lds_b<T, 3>), grid, blk, lds, s, t, st, ns);
+                else hipLaunchKernelGGL((k_filter_lds_b<T, 1>), grid, blk, lds, s, t, st, ns);
+            } else {
+                if (three) hipLaunchKernelGGL((k_filter_b<T, 3>), grid, blk, 0, s, t, st, ns);
+                else hipLaunchKernelGGL((k_filter_b<T, 1>), grid, blk, 0, s, t, st, ns);
+            }
             break;
         }
         case KK_CORR:
@@ -875,7 +1084,6 @@ hipError_t batched_typed(int base, int mode, const void* tab, const unsigned* st
 
 hipError_t launch_batched_stencil(int kind, const void* tab, const unsigned* st, int ns, unsigned nb, dim3 blk,
                                   size_t lds, hipStream_t s) {
-    (void)lds;
     const int base = kind >> 8, mode = (kind >> 1) & 127, fp32 = kind & 1;
     if (base == KK_REFRES) {
         hipLaunchKernelGGL(k_refine_res_b, dim3(nb), blk, 0, s, (const BRec<RefineResArgs>*)tab, st, ns);
@@ -893,8 +1101,8 @@ hipError_t launch_batched_stencil(int kind, const void* tab, const unsigned* st,
         hipLaunchKernelGGL(k_diag_b, dim3(nb), blk, 0, s, (const BRec<DiagArgs>*)tab, st, ns);
         return hipGetLastError();
     }
-    return fp32 ? batched_typed<float>(base, mode, tab, st, ns, nb, blk, s)
-                : batched_typed<double>(base, mode, tab, st, ns, nb, blk, s);
+    return fp32 ? batched_typed<float>(base, mode, tab, st, ns, nb, blk, lds, s)
+                : batched_typed<double>(base, mode, tab, st, ns, nb, blk, lds, s);
 }
 
 hipError_t launch_set_rate(PartSoA part, int np, StepScalars* sc, hipStream_t s) {
