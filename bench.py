@@ -66,17 +66,18 @@ def kernel_bytes(sc, esz=8):
     }
 
 
-def step_bytes(sc, esz=8):
+def step_bytes(sc, esz=8, per_stage=False):
     """Pass-model bytes of one whole step (launch counts of the step sequence)."""
     kb = kernel_bytes(sc, esz)
     it = sc.n_piter if (sc.beta == 0).any() else min(sc.n_piter, 1)
     y_passes = 2 if sc.ny > 1 else 0
     poisson = kb["fft_x_fwd"] + y_passes * kb["fft_y"] + kb["fft_z"] + kb["fft_x_inv"]
     ib = kb["ib_rhs"] if (sc.beta == 0).any() else 0
-    total = (4 * kb["mom_stage"] + kb["div"] + it * (poisson + ib) + kb["correct"]
-             + 4 * kb["scalar_stage"] + (kb["filter"] + kb["filter_c"] if sc.filter else 0))
+    projection = kb["div"] + it * (poisson + ib) + kb["correct"]
     if esz == 4 and it > 0:
-        total += kb["refine_res"] + poisson           # FP64 residual and one correction solve
+        projection += kb["refine_res"] + poisson      # FP64 residual and one correction solve
+    total = (4 * kb["mom_stage"] + (4 if per_stage else 1) * projection
+             + 4 * kb["scalar_stage"] + (kb["filter"] + kb["filter_c"] if sc.filter else 0))
     return total
 
 
@@ -226,6 +227,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--workload", default="room", choices=list(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--per-stage", action="store_true",
+                    help="the per-stage projection variant (a projection after every RK4 stage)")
     ap.add_argument("--serving", default="short", choices=["none", "short", "full"],
                     help="serving stream: short = 16 requests x 300 steps, full = 64 x 2000")
     ap.add_argument("--copy-probe", action="store_true",
@@ -263,7 +266,7 @@ def main():
     prec = m.FP64 if args.precision == "fp64" else m.FP32_REFINE
     esz = 8 if prec == m.FP64 else 4
     dev = torch.device("cuda:0")
-    S = m.Solver(sc, precision=prec, device=dev)
+    S = m.Solver(sc, precision=prec, device=dev, project_each_stage=args.per_stage)
     stream = S.stream
     print(f"[bench] workload {sc.name} cells={sc.ncells} warmup={args.warmup}", file=sys.stderr, flush=True)
     S.step(args.warmup, diag=False)
@@ -311,7 +314,7 @@ def main():
         except (OSError, ValueError):
             traffic = None
 
-    sbytes = step_bytes(sc, esz)
+    sbytes = step_bytes(sc, esz, args.per_stage)
     out = {
         "metric": "Gcell-steps/s (full step incl. FFT Poisson)",
         "value": value,
@@ -326,7 +329,8 @@ def main():
         "dtype": "f64" if prec == m.FP64 else "f32 (FP64 refinement and reductions)",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOADS[args.workload] + (", FP64" if prec == m.FP64 else ", FP32 + FP64 refinement"),
+            "workload": WORKLOADS[args.workload] + (", FP64" if prec == m.FP64 else ", FP32 + FP64 refinement")
+                        + (", projection after every RK4 stage" if args.per_stage else ""),
             "cells": sc.ncells,
             "forced_cells": int(len(sc.forced_idx)),
         },

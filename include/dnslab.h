@@ -81,6 +81,10 @@ typedef struct {
     int32_t filter;         /* 1: sixth-order filter at the end of each step */
     int32_t precision;      /* dnslab_precision */
     void* stream;           /* hipStream_t for all work of this context */
+    int32_t project_each_stage;  /* 1: project after every RK4 stage as well as at the end of
+                               the step (the alternative Section 2.1 mentions and the paper
+                               skips for speed: 4 projections per step, fourth order in
+                               time); 0: the paper's single projection per step */
 } dnslab_params;
 
 /* Per-step diagnostics, all FP64. */

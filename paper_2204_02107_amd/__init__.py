@@ -29,7 +29,7 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def make_params(case, precision=FP64, stream=None) -> Params:
+def make_params(case, precision=FP64, stream=None, project_each_stage=False) -> Params:
     P = Params()
     P.nx, P.ny, P.nz = int(case.nx), int(case.ny), int(case.nz)
     P.lx, P.ly, P.lz = float(case.lx), float(case.ly), float(case.lz)
@@ -39,6 +39,7 @@ def make_params(case, precision=FP64, stream=None) -> Params:
     P.cfl, P.dt_fixed, P.u_ref = float(case.cfl), float(case.dt_fixed), float(case.u_ref)
     P.n_piter, P.filter, P.precision = int(case.n_piter), int(bool(case.filter)), int(precision)
     P.stream = stream
+    P.project_each_stage = int(bool(project_each_stage))
     return P
 
 
@@ -58,7 +59,7 @@ class Solver:
     ``room_mask`` and the initial fields ``u, v, w, p, c``.
     """
 
-    def __init__(self, case, precision=FP64, device="cuda:0", stream=None):
+    def __init__(self, case, precision=FP64, device="cuda:0", stream=None, project_each_stage=False):
         torch = _torch()
         self.lib = load()
         self.device = torch.device(device)
@@ -84,7 +85,7 @@ class Solver:
         room = None
         if getattr(case, "room_mask", None) is not None:
             room = torch.as_tensor(case.room_mask, dtype=torch.uint8).reshape(self.shape).to(dev).contiguous()
-        self.params = make_params(case, precision, ctypes.c_void_p(stream.cuda_stream))
+        self.params = make_params(case, precision, ctypes.c_void_p(stream.cuda_stream), project_each_stage)
         ctx = ctypes.c_void_p()
         rc = self.lib.dnslab_init(
             ctypes.byref(self.params), _ptr(beta), n,

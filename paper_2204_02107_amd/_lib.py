@@ -36,6 +36,7 @@ class Params(ctypes.Structure):
         ("cfl", c_double), ("dt_fixed", c_double), ("u_ref", c_double),
         ("n_piter", c_int32), ("filter", c_int32), ("precision", c_int32),
         ("stream", c_void_p),
+        ("project_each_stage", c_int32),
     ]
 
 

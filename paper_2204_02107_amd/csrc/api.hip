@@ -84,6 +84,7 @@ int validate(const dnslab_params* P, std::string& why) {
     if (!(P->lx > 0 && P->ly > 0 && P->lz > 0)) { why = "box lengths must be positive"; return DNSLAB_EINVAL; }
     if (!(P->tau_f > 0)) { why = "tau_f must be positive"; return DNSLAB_EINVAL; }
     if (P->n_piter < 0 || P->n_piter > 64) { why = "n_piter out of range"; return DNSLAB_EINVAL; }
+    if (P->project_each_stage != 0 && P->project_each_stage != 1) { why = "project_each_stage must be 0 or 1"; return DNSLAB_EINVAL; }
     if (!(P->dt_fixed > 0)) {
         if (!(P->cfl > 0) || !(P->u_ref > 0)) { why = "adaptive dt needs cfl > 0 and u_ref > 0"; return DNSLAB_EINVAL; }
     }
@@ -122,6 +123,17 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_FKC
 #define DNSLAB_FKC 0
 #endif
+// FFT passes: x lines per block grow while the block stays within these
+// threads and LDS bytes; y/z column tiles within this much LDS.
+#ifndef DNSLAB_XPASS_THREADS
+#define DNSLAB_XPASS_THREADS 256
+#endif
+#ifndef DNSLAB_XPASS_LDS_KB
+#define DNSLAB_XPASS_LDS_KB 48
+#endif
+#ifndef DNSLAB_COL_LDS_KB
+#define DNSLAB_COL_LDS_KB 32
+#endif
 
 // z chunk: enough blocks to fill the chip, each walking at least 4 planes.
 int stencil_kc(const Grid& g, int rows, int forced) {
@@ -148,15 +160,15 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     const long long nlines = (long long)P->ny * P->nz;
     {
         int nl = 1;
-        while (nl * 2 * Lo.px.tpl <= 256 && ((size_t)nl * 2 * Lo.ls_x + 2 * Lo.m + 1) * csz <= 48 * 1024 &&
-               nl < nlines)
+        while (nl * 2 * Lo.px.tpl <= DNSLAB_XPASS_THREADS &&
+               ((size_t)nl * 2 * Lo.ls_x + 2 * Lo.m + 1) * csz <= DNSLAB_XPASS_LDS_KB * 1024 && nl < nlines)
             nl *= 2;
         Lo.nl_x = ilog2(nl);
     }
     auto pick_tx = [&](int n, const AxisPlan& ap) {
         int tx = 1;
         const int cap = std::min(64, pow2_floor(2LL * (Lo.m + 1) - 1));
-        while (tx * 2 <= cap && (size_t)tx * 2 * n * csz <= 32 * 1024 && tx * 2 * ap.tpl <= 1024) tx *= 2;
+        while (tx * 2 <= cap && (size_t)tx * 2 * n * csz <= DNSLAB_COL_LDS_KB * 1024 && tx * 2 * ap.tpl <= 1024) tx *= 2;
         return ilog2(tx);
     };
     Lo.lg_tx_y = pick_tx(P->ny, Lo.py);
@@ -378,13 +390,16 @@ int project_div(dnslab_ctx* x, const T* const us[3]) {
 int n_solves(const dnslab_ctx* x) { return x->any_solid ? x->P.n_piter : std::min(x->P.n_piter, 1); }
 bool refining(const dnslab_ctx* x) { return x->P.precision == DNSLAB_FP32_REFINE && n_solves(x) > 0; }
 
+// scr: three field-sized scratch arrays for the FP32 refinement (last iterate,
+// residual, correction), which must not alias us; by default the B stage buffers.
 template <typename T>
-int project_solve(dnslab_ctx* x, const T* const us[3]) {
+int project_solve(dnslab_ctx* x, const T* const us[3], void* const* scr = nullptr) {
+    void* const* S = scr ? scr : x->f + 3;
     T* r0 = (T*)x->f[9];
     T* p = (T*)x->p;
     const int nit = n_solves(x);
     const bool refine = refining(x);
-    T* p_last = refine ? (T*)x->f[3] : p;    // the last iterate goes to a scratch field when refining
+    T* p_last = refine ? (T*)S[0] : p;    // the last iterate goes to a scratch field when refining
     for (int it = 0; it < nit; ++it) {
         if (x->any_solid) LAUNCH(x, K_IB, launch_ib_rhs<T>(x->ib, x->g, p, r0, (T*)x->ib_r0, it == 0, x->cur, x->rec));
         int rc = poisson_solve<T>(x, r0, it == nit - 1 ? p_last : p);
@@ -397,10 +412,10 @@ int project_solve(dnslab_ctx* x, const T* const us[3]) {
             ra.p3 = (const float*)p;
             ra.p4 = (const float*)p_last;
             ra.flags = x->flags;
-            ra.res = (float*)x->f[4];
+            ra.res = (float*)S[1];
             ra.g = x->g;
             LAUNCH(x, K_REF, launch_refine_res(ra, x->Lo.L1, x->cur, x->rec));
-            int rc = poisson_solve<float>(x, (const float*)x->f[4], (float*)x->f[5]);
+            int rc = poisson_solve<float>(x, (const float*)S[1], (float*)S[2]);
             if (rc) return rc;
         }
     }
@@ -408,13 +423,14 @@ int project_solve(dnslab_ctx* x, const T* const us[3]) {
 }
 
 template <typename T>
-int project_correct(dnslab_ctx* x, const T* const us[3], T* const out[3], PartSoA part) {
+int project_correct(dnslab_ctx* x, const T* const us[3], T* const out[3], PartSoA part, void* const* scr = nullptr) {
+    void* const* S = scr ? scr : x->f + 3;
     if constexpr (sizeof(T) == 4) {
         if (refining(x)) {
             RefineCorrArgs rc2;
             for (int a = 0; a < 3; ++a) { rc2.us[a] = (const float*)us[a]; rc2.out[a] = (float*)out[a]; }
-            rc2.p4 = (const float*)x->f[3];
-            rc2.dp = (const float*)x->f[5];
+            rc2.p4 = (const float*)S[0];
+            rc2.dp = (const float*)S[2];
             rc2.p = (float*)x->p;
             rc2.flags = x->flags;
             rc2.g = x->g;
@@ -588,19 +604,37 @@ int one_step(dnslab_ctx* x) {
     m.nu = x->P.nu;
     for (int a = 0; a < 3; ++a) m.body[a] = x->P.body[a];
     m.g = x->g;
-    // RK4 stages (Section 2.1), no pressure gradient
+    // RK4 stages (Section 2.1), no pressure gradient.  In the per-stage
+    // variant each stage value u_1, u_2, u_3 is projected in place (div, IB
+    // iterations warm-started from the last pressure, correction) before the
+    // next stage evaluates F on it; the accumulator sums the k's as usual.
+    const bool per_stage = x->P.project_each_stage != 0;
+    bool forked = false;
+    // the refinement scratch is the stage buffer not being projected
+    auto project_stage = [&](T* const s[3], T* const other[3]) -> int {
+        const T* const sc[3] = {s[0], s[1], s[2]};
+        void* const scr[3] = {other[0], other[1], other[2]};
+        int r = project_div<T>(x, sc);
+        if (!r && defer && !forked) { r = flush_scalar_half<T>(x); forked = true; }
+        if (!r) r = project_solve<T>(x, sc, scr);
+        if (!r) r = project_correct<T>(x, sc, s, PartSoA{}, scr);
+        return r;
+    };
     for (int a = 0; a < 3; ++a) { m.us[a] = U[a]; m.acc[a] = A[a]; m.out[a] = B[a]; m.un[a] = nullptr; }
     LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FIRST, m, L, x->cur, x->rec));
+    if (per_stage && (rc = project_stage(B, Cb))) return rc;
     for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = U[a]; m.out[a] = Cb[a]; }
     LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_HALF, m, L, x->cur, x->rec));
+    if (per_stage && (rc = project_stage(Cb, B))) return rc;
     for (int a = 0; a < 3; ++a) { m.us[a] = Cb[a]; m.out[a] = B[a]; }
     LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FULL, m, L, x->cur, x->rec));
+    if (per_stage && (rc = project_stage(B, Cb))) return rc;
     for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = nullptr; m.out[a] = Cb[a]; }
     LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_LAST, m, L, x->cur, x->rec));
     // projection: u* in Cb -> projected velocity V
     const T* const us[3] = {Cb[0], Cb[1], Cb[2]};
     rc = project_div<T>(x, us);
-    if (!rc && defer) rc = flush_scalar_half<T>(x);
+    if (!rc && defer && !forked) rc = flush_scalar_half<T>(x);
     if (!rc) rc = project_solve<T>(x, us);
     if (!rc) rc = join_scalar_half(x);
     if (rc) return rc;
