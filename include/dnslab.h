@@ -174,11 +174,23 @@ const char* dnslab_last_error(const dnslab_ctx* ctx);
 
 /* Kernel timing for roofline measurements: when enabled, every launch of the
  * named kernel ("mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
- * "fft_x_inv", "filter", "correct", "div", "ib_rhs", "finish", "refine_res") is bracketed
- * by HIP events on the
- * context's stream, and the total and count accumulate.  Read synchronises. */
+ * "fft_x_inv", "filter", "filter_c", "correct", "div", "ib_rhs", "advance",
+ * "diag", "refine_res") is bracketed by HIP events on the stream it is
+ * launched on, and the total and count accumulate (kernel_name NULL: off).
+ * Steps are issued launch by launch while a kernel is profiled.  Read
+ * synchronises. */
 int dnslab_profile_enable(dnslab_ctx* ctx, const char* kernel_name);
 int dnslab_profile_read(dnslab_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Issue dnslab_step's work as replays of a HIP graph that holds k whole steps
+ * (captured on the first call that needs it; steps beyond a multiple of k are
+ * issued launch by launch).  The graph's launches are those of k calls of
+ * dnslab_step(ctx, 1) and compute the same results bit for bit; replay takes
+ * one host call per k steps instead of one per kernel, which matters for small
+ * grids.  k = 0 turns it off (the default).  Needs a stream other than the
+ * legacy default stream (NULL): returns DNSLAB_EINVAL otherwise, or for k < 0
+ * or k > 4096. */
+int dnslab_set_graph_steps(dnslab_ctx* ctx, int32_t k);
 
 /* ------------------------------------------------------------------------
  * Serving pool: many scenarios of different grid sizes resident at once,
@@ -211,6 +223,12 @@ int dnslab_pool_admit(dnslab_pool* pool, const dnslab_params* params, int64_t ta
 /* Advance every admitted scenario that has not reached its target by up to
  * nsteps steps (asynchronous; scenarios stop at their own target). */
 int dnslab_pool_step(dnslab_pool* pool, int32_t nsteps);
+
+/* enable = 1: replay each pool step from a HIP graph of its batched launches,
+ * captured again whenever the set of running scenarios changes (same
+ * results; one host call per step).  0: launch by launch (the default).
+ * Needs a pool stream other than NULL (DNSLAB_EINVAL otherwise). */
+int dnslab_pool_set_graph(dnslab_pool* pool, int32_t enable);
 
 /* Progress of a slot: the last step's diagnostics (zeros before the first
  * step), steps taken and whether the target is reached.  Synchronises. */

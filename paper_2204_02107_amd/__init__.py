@@ -59,7 +59,8 @@ class Solver:
     ``room_mask`` and the initial fields ``u, v, w, p, c``.
     """
 
-    def __init__(self, case, precision=FP64, device="cuda:0", stream=None, project_each_stage=False):
+    def __init__(self, case, precision=FP64, device="cuda:0", stream=None, project_each_stage=False,
+                 graph_steps=0):
         torch = _torch()
         self.lib = load()
         self.device = torch.device(device)
@@ -68,6 +69,8 @@ class Solver:
         self.shape = (int(case.nz), int(case.ny), int(case.nx))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
+            if graph_steps and stream.cuda_stream == 0:
+                stream = torch.cuda.Stream(self.device)   # graphs need a stream other than the legacy default
         self.stream = stream
         dev = self.device
 
@@ -96,6 +99,8 @@ class Solver:
             ctypes.byref(ctx))
         _lib.check(rc, None)
         self.ctx = ctx
+        if graph_steps:
+            self._check(self.lib.dnslab_set_graph_steps(self.ctx, int(graph_steps)))
 
     # -- life cycle ----------------------------------------------------------
     def close(self):
@@ -112,10 +117,23 @@ class Solver:
     def _check(self, rc):
         return _lib.check(rc, self.ctx)
 
+    def _call(self, fn, *args):
+        """Run a library call on the solver's stream, ordered after the work
+        torch has queued on its current stream and before what comes next."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        same = cur.cuda_stream == self.stream.cuda_stream
+        if not same:
+            self.stream.wait_stream(cur)
+        rc = fn(*args)
+        if not same:
+            cur.wait_stream(self.stream)
+        return self._check(rc)
+
     # -- the step ------------------------------------------------------------
     def step(self, nsteps: int = 1, diag: bool = True) -> Optional[dict]:
         d = Diag() if diag else None
-        self._check(self.lib.dnslab_step(self.ctx, int(nsteps), ctypes.byref(d) if diag else None))
+        self._call(self.lib.dnslab_step, self.ctx, int(nsteps), ctypes.byref(d) if diag else None)
         return d.as_dict() if diag else None
 
     def read_diags(self, n: int):
@@ -129,31 +147,31 @@ class Solver:
     # -- pieces of the step --------------------------------------------------
     def poisson(self, rhs, out=None):
         out = self._empty() if out is None else out
-        self._check(self.lib.dnslab_poisson(self.ctx, _ptr(self._dev(rhs)), _ptr(out)))
+        self._call(self.lib.dnslab_poisson, self.ctx, _ptr(self._dev(rhs)), _ptr(out))
         return out
 
     def project(self, u, v, w):
-        self._check(self.lib.dnslab_project(self.ctx, _ptr(u), _ptr(v), _ptr(w)))
+        self._call(self.lib.dnslab_project, self.ctx, _ptr(u), _ptr(v), _ptr(w))
 
     def scalar_step(self, dt: float):
-        self._check(self.lib.dnslab_scalar_step(self.ctx, float(dt)))
+        self._call(self.lib.dnslab_scalar_step, self.ctx, float(dt))
 
     def momentum_rhs(self, u, v, w):
         u, v, w = self._dev(u), self._dev(v), self._dev(w)
         out = [self._empty() for _ in range(3)]
-        self._check(self.lib.dnslab_momentum_rhs(self.ctx, _ptr(u), _ptr(v), _ptr(w), *map(_ptr, out)))
+        self._call(self.lib.dnslab_momentum_rhs, self.ctx, _ptr(u), _ptr(v), _ptr(w), *map(_ptr, out))
         return out
 
     def scalar_rhs(self, c, u, v, w):
         c, u, v, w = map(self._dev, (c, u, v, w))
         out = self._empty()
-        self._check(self.lib.dnslab_scalar_rhs(self.ctx, _ptr(c), _ptr(u), _ptr(v), _ptr(w), _ptr(out)))
+        self._call(self.lib.dnslab_scalar_rhs, self.ctx, _ptr(c), _ptr(u), _ptr(v), _ptr(w), _ptr(out))
         return out
 
     def filter(self, f):
         f = self._dev(f)
         out = self._empty()
-        self._check(self.lib.dnslab_filter(self.ctx, _ptr(f), _ptr(out)))
+        self._call(self.lib.dnslab_filter, self.ctx, _ptr(f), _ptr(out))
         return out
 
     # -- kernel timing -------------------------------------------------------

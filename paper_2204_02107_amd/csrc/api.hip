@@ -255,6 +255,10 @@ struct dnslab_ctx {
     hipEvent_t ev_fork, ev_join;
     bool tail_pending;     // scalar work of the last step taken not yet enqueued
     bool join_pending;     // stream has not yet waited for the last enqueued scalar work
+    // graph replay of whole steps
+    int graph_steps;       // k steps per graph (0: launch by launch)
+    hipGraphExec_t gexec;
+    int gexec_steps;
     // profiling
     int prof_kid;
     std::vector<hipEvent_t> ev;
@@ -786,9 +790,55 @@ int upload_tables(dnslab_ctx* x) {
     return DNSLAB_OK;
 }
 
+// Capture k whole steps (each step's deferred scalar half included and settled
+// at the end) into an executable graph.  Nothing runs during capture; the host
+// step counter is restored afterwards.
+template <typename T>
+int capture_steps(dnslab_ctx* x, int k) {
+    if (x->gexec) {
+        HIPCHK(x, hipGraphExecDestroy(x->gexec));
+        x->gexec = nullptr;
+    }
+    const long long hs = x->host_step;
+    HIPCHK(x, hipStreamBeginCapture(x->stream, hipStreamCaptureModeThreadLocal));
+    int rc = DNSLAB_OK;
+    for (int s = 0; s < k && !rc; ++s) rc = one_step<T>(x);
+    if (!rc) rc = settle<T>(x);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(x->stream, &g);
+    x->host_step = hs;
+    x->tail_pending = false;
+    x->join_pending = false;
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : fail(x, DNSLAB_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    const hipError_t e2 = hipGraphInstantiate(&x->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        x->gexec = nullptr;
+        return fail(x, DNSLAB_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    }
+    x->gexec_steps = k;
+    return DNSLAB_OK;
+}
+
 template <typename T>
 int run_steps(dnslab_ctx* x, int nsteps) {
     int rc = DNSLAB_OK;
+    const int k = x->graph_steps;
+    if (k > 0 && nsteps >= k && !x->rec && x->prof_kid == K_NONE) {
+        // first-step work (Courant rate, second stream) happens outside the graph
+        rc = ensure_rate<T>(x);
+        if (!rc && x->overlap) rc = ensure_aux(x);
+        if (!rc && (!x->gexec || x->gexec_steps != k)) rc = capture_steps<T>(x, k);
+        while (!rc && nsteps >= k) {
+            const hipError_t e = hipGraphLaunch(x->gexec, x->stream);
+            if (e != hipSuccess) return fail(x, DNSLAB_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+            x->host_step += k;
+            nsteps -= k;
+        }
+    }
     for (int s = 0; s < nsteps && !rc; ++s) rc = one_step<T>(x);
     const int rc2 = settle<T>(x);
     return rc ? rc : rc2;
@@ -1066,6 +1116,7 @@ void dnslab_destroy(dnslab_ctx* x) {
         (void)hipEventDestroy(x->ev_fork);
         (void)hipEventDestroy(x->ev_join);
     }
+    if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
     for (hipEvent_t e : x->ev) (void)hipEventDestroy(e);
     if (x->ws) (void)hipFree(x->ws);
     if (x->ib_buf) (void)hipFree(x->ib_buf);
@@ -1099,6 +1150,14 @@ int dnslab_profile_enable(dnslab_ctx* x, const char* name) {
     x->prof_kid = kid;
     x->prof_ms = 0;
     x->prof_n = 0;
+    return DNSLAB_OK;
+}
+
+int dnslab_set_graph_steps(dnslab_ctx* x, int32_t k) {
+    if (int rc = check_ctx(x)) return rc;
+    if (k < 0 || k > 4096) return fail(x, DNSLAB_EINVAL, "graph steps out of range");
+    if (k > 0 && !x->stream) return fail(x, DNSLAB_EINVAL, "graph replay needs a non-NULL stream");
+    x->graph_steps = k;
     return DNSLAB_OK;
 }
 
@@ -1161,6 +1220,8 @@ struct dnslab_pool {
     bool dirty = true;
     void* tab_dev = nullptr;
     size_t tab_cap = 0;
+    bool use_graph = false;
+    hipGraphExec_t gexec = nullptr;       // one pool step, for the current groups
     std::string err;
 };
 
@@ -1264,6 +1325,31 @@ int pool_rebuild(dnslab_pool* P, const std::vector<int>& active) {
     if (!host.empty()) PHIP(P, hipMemcpy(P->tab_dev, host.data(), host.size(), hipMemcpyHostToDevice));
     P->active_ids = active;
     P->dirty = false;
+    return DNSLAB_OK;
+}
+
+int pool_replay(dnslab_pool* P);
+
+// Capture one pool step (every group's batched launches) into a graph.
+int pool_capture(dnslab_pool* P) {
+    if (P->gexec) {
+        PHIP(P, hipGraphExecDestroy(P->gexec));
+        P->gexec = nullptr;
+    }
+    PHIP(P, hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = pool_replay(P);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(P->stream, &g);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : pfail(P, DNSLAB_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    const hipError_t e2 = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        P->gexec = nullptr;
+        return pfail(P, DNSLAB_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    }
     return DNSLAB_OK;
 }
 
@@ -1429,10 +1515,15 @@ int dnslab_pool_step(dnslab_pool* P, int32_t nsteps) {
             if (active.empty()) break;
             if (P->dirty || active != P->active_ids) {
                 int rc = pool_rebuild(P, active);
+                if (!rc && P->use_graph) rc = pool_capture(P);
                 if (rc) return rc;
             }
-            int rc = pool_replay(P);
-            if (rc) return rc;
+            if (P->use_graph) {
+                PHIP(P, hipGraphLaunch(P->gexec, P->stream));
+            } else {
+                int rc = pool_replay(P);
+                if (rc) return rc;
+            }
             for (int i : active) {
                 P->slots[i].done += 1;
                 P->slots[i].ctx->host_step += 1;
@@ -1509,6 +1600,15 @@ int dnslab_pool_usage(dnslab_pool* P, size_t* bytes_in_use, int32_t* active, int
     return DNSLAB_OK;
 }
 
+int dnslab_pool_set_graph(dnslab_pool* P, int32_t enable) {
+    if (!P) return pfail(nullptr, DNSLAB_EINVAL, "pool is NULL");
+    if (enable != 0 && enable != 1) return pfail(P, DNSLAB_EINVAL, "enable must be 0 or 1");
+    if (enable && !P->stream) return pfail(P, DNSLAB_EINVAL, "graph replay needs a non-NULL stream");
+    P->use_graph = enable != 0;
+    P->dirty = true;
+    return DNSLAB_OK;
+}
+
 const char* dnslab_pool_last_error(const dnslab_pool* P) { return P ? P->err.c_str() : g_thread_err.c_str(); }
 
 void dnslab_pool_destroy(dnslab_pool* P) {
@@ -1516,6 +1616,7 @@ void dnslab_pool_destroy(dnslab_pool* P) {
     (void)hipStreamSynchronize(P->stream);
     for (size_t i = 0; i < P->slots.size(); ++i)
         if (P->slots[i].used) dnslab_pool_release(P, (int)i);
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
     if (P->tab_dev) (void)hipFree(P->tab_dev);
     if (P->admit_stream) (void)hipStreamDestroy(P->admit_stream);
     if (P->stage) (void)hipFree(P->stage);

@@ -33,7 +33,7 @@ def _params(case, precision):
 
 
 class Pool:
-    def __init__(self, hbm_budget: int, precision=FP32_REFINE, stream=None):
+    def __init__(self, hbm_budget: int, precision=FP32_REFINE, stream=None, graph=False):
         import torch
         self.lib = _lib.load()
         self.precision = precision
@@ -45,6 +45,8 @@ class Pool:
                                                    ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
         self.h = h
         self._keep = {}
+        if graph:
+            self._check(self.lib.dnslab_pool_set_graph(self.h, 1))
 
     def _check(self, rc):
         return _lib.check_pool(rc, self.h)
@@ -112,7 +114,8 @@ class Pool:
             pass
 
 
-def serve(requests, cases, hbm_budget: int, precision=FP32_REFINE, chunk: int = 25, log=None) -> List[dict]:
+def serve(requests, cases, hbm_budget: int, precision=FP32_REFINE, chunk: int = 25, log=None,
+          graph: bool = True) -> List[dict]:
     """Run a request stream with continuous batching.
 
     ``requests``: dicts with ``id``, ``arrival`` (s from stream start) and
@@ -126,7 +129,7 @@ def serve(requests, cases, hbm_budget: int, precision=FP32_REFINE, chunk: int = 
     """
     import torch
     stream = torch.cuda.Stream()
-    pool = Pool(hbm_budget, precision, stream=stream)
+    pool = Pool(hbm_budget, precision, stream=stream, graph=graph)
     pending = deque(sorted(requests, key=lambda r: r["arrival"]))
     waiting = deque()
     running = {}
