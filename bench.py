@@ -130,17 +130,19 @@ def cpu_baseline(sc, budget_s=20.0):
 def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7):
     """The serving stream: Poisson arrivals of room scenarios of four grid
     sizes, served (a) with continuous batching in the pool (FP32 with FP64
-    refinement, HBM budget deliberately small so admission binds) and (b) FIFO
-    with the plain per-scenario FP64 loop.  Returns both summaries."""
+    refinement, and FP64; HBM budget deliberately small so admission binds)
+    and (b) FIFO with the plain per-scenario FP64 loop.  Returns the summaries."""
     import scenarios
     from paper_2204_02107_amd import serving, FP32_REFINE, FP64
     reqs = scenarios.serving_requests(n_req, seed=seed, mean_gap=mean_gap, n_steps=n_steps)
     cases = {r["id"]: scenarios.serving_scenario(r) for r in reqs}
     pooled = serving.serve(reqs, cases, int(budget_gib * (1 << 30)), FP32_REFINE)
+    pooled64 = serving.serve(reqs, cases, int(budget_gib * (1 << 30)), FP64)
     base = serving.fifo(reqs, cases, FP64)
     out = {
         "requests": n_req, "steps_each": n_steps, "mean_gap_s": mean_gap, "hbm_budget_GiB": budget_gib,
         "pool_fp32_refine": serving.summarize(pooled),
+        "pool_fp64": serving.summarize(pooled64),
         "fifo_fp64": serving.summarize(base),
     }
     return out
