@@ -131,6 +131,48 @@ __device__ __forceinline__ void stage_halo(T* tb, const T* __restrict__ src, uns
     }
 }
 
+// The same halo as stage_halo, as a per-thread map: this thread's halo cells
+// (at most HMAX of them) as in-plane source offsets and LDS destinations, so
+// that a kernel can load a plane's halo into registers one plane ahead of
+// storing it.  The launch guarantees 2R(BX + BY) <= HMAX * BX * BY.
+template <int HMAX>
+struct HaloMap {
+    unsigned src[HMAX];
+    int dst[HMAX];
+    int n;
+};
+template <int R, int HMAX>
+__device__ __forceinline__ HaloMap<HMAX> halo_map(int i0, int j0, const Grid& g, int BX, int lgBX, int BY,
+                                                  int tid, int nthr) {
+    HaloMap<HMAX> hm;
+    const int W = BX + 2 * R;
+    const int nhy = 2 * R * BX, nh = nhy + 2 * R * BY;
+    hm.n = 0;
+#pragma unroll
+    for (int h = 0; h < HMAX; ++h) {
+        const int r = tid + h * nthr;
+        hm.src[h] = 0;
+        hm.dst[h] = 0;
+        if (r < nh) {
+            int ly, lx;
+            if (r < nhy) {
+                const int hr = r >> lgBX;
+                ly = hr < R ? hr : BY + hr;
+                lx = R + (r - (hr << lgBX));
+            } else {
+                const int q = r - nhy, row = q / (2 * R), c = q - row * (2 * R);
+                ly = R + row;
+                lx = c < R ? c : BX + c;
+            }
+            const int gi = wrap1(i0 + lx - R, g.nx), gj = wrap1(j0 + ly - R, g.ny);
+            hm.src[h] = (unsigned)gj * g.nx + gi;
+            hm.dst[h] = ly * W + lx;
+            hm.n = h + 1;
+        }
+    }
+    return hm;
+}
+
 // ---------------------------------------------------------------------------
 // Momentum RK4 stage.  k = beta [ -C(u) + nu L u + S (u_set - u)/tau_f + b ]
 // with the skew-symmetric convection written per axis as
@@ -159,31 +201,61 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty, nthr = BX * BY;
     const int i0 = col.i - tx, j0 = col.j - ty;
     int buf = 0;
+    const unsigned cell = col.row + col.i;
+    // LDS variant: loads run one plane ahead of their use (the next z plane
+    // of the window, zq, and the next plane's halo, hv)
+    constexpr int HM = 2;
+    HaloMap<HM> hm;
+    T zq[3], hv[3][HM];
 
     T zm[3], z0[3], zp[3];
     {
         const int km = k0 == 0 ? g.nz - 1 : k0 - 1;
-        const unsigned im_ = (unsigned)km * nxy + col.row + col.i;
-        const unsigned i0_ = (unsigned)k0 * nxy + col.row + col.i;
+        const unsigned im_ = (unsigned)km * nxy + cell;
+        const unsigned i0_ = (unsigned)k0 * nxy + cell;
         zm[0] = u0p[im_]; zm[1] = u1p[im_]; zm[2] = u2p[im_];
         z0[0] = u0p[i0_]; z0[1] = u1p[i0_]; z0[2] = u2p[i0_];
+        if (LDS) {
+            const unsigned ip_ = (unsigned)wrap(k0 + 1, g.nz) * nxy + cell;
+            const unsigned iq_ = (unsigned)wrap(k0 + 2, g.nz) * nxy + cell;
+            zp[0] = u0p[ip_]; zp[1] = u1p[ip_]; zp[2] = u2p[ip_];
+            zq[0] = u0p[iq_]; zq[1] = u1p[iq_]; zq[2] = u2p[iq_];
+            hm = halo_map<1, HM>(i0, j0, g, BX, lgBX, BY, tid, nthr);
+            const unsigned b0 = (unsigned)k0 * nxy;
+#pragma unroll
+            for (int h = 0; h < HM; ++h) {
+                hv[0][h] = h < hm.n ? u0p[b0 + hm.src[h]] : T(0);
+                hv[1][h] = h < hm.n ? u1p[b0 + hm.src[h]] : T(0);
+                hv[2][h] = h < hm.n ? u2p[b0 + hm.src[h]] : T(0);
+            }
+        }
     }
     for (int k = k0; k < k1; ++k) {
         const int kp = k + 1 == g.nz ? 0 : k + 1;
         const unsigned base = (unsigned)k * nxy;
-        const unsigned idx = base + col.row + col.i;
-        const unsigned ipz = (unsigned)kp * nxy + col.row + col.i;
+        const unsigned idx = base + cell;
+        const unsigned ipz = (unsigned)kp * nxy + cell;
         T xm[3], xp[3], ym[3], yp[3];
         if (LDS) {
             T* tb = lds + buf * 3 * tsz;
             buf ^= 1;
             const int ctr = (ty + 1) * W + tx + 1;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) tb[c * tsz + ctr] = z0[c];
-            stage_halo<T, 1>(tb, u0p, base, i0, j0, g, BX, lgBX, BY, tid, nthr);
-            stage_halo<T, 1>(tb + tsz, u1p, base, i0, j0, g, BX, lgBX, BY, tid, nthr);
-            stage_halo<T, 1>(tb + 2 * tsz, u2p, base, i0, j0, g, BX, lgBX, BY, tid, nthr);
-            zp[0] = u0p[ipz]; zp[1] = u1p[ipz]; zp[2] = u2p[ipz];
+            for (int c = 0; c < 3; ++c) {
+                tb[c * tsz + ctr] = z0[c];
+#pragma unroll
+                for (int h = 0; h < HM; ++h)
+                    if (h < hm.n) tb[c * tsz + hm.dst[h]] = hv[c][h];
+            }
+            if (k + 1 < k1) {
+#pragma unroll
+                for (int h = 0; h < HM; ++h)
+                    if (h < hm.n) {
+                        hv[0][h] = u0p[ipz - cell + hm.src[h]];
+                        hv[1][h] = u1p[ipz - cell + hm.src[h]];
+                        hv[2][h] = u2p[ipz - cell + hm.src[h]];
+                    }
+            }
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -241,6 +313,14 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) { zm[c] = z0[c]; z0[c] = zp[c]; }
+        if (LDS) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) zp[c] = zq[c];
+            if (k + 2 < k1) {
+                const unsigned ir_ = (unsigned)wrap(k + 3, g.nz) * nxy + cell;
+                zq[0] = u0p[ir_]; zq[1] = u1p[ir_]; zq[2] = u2p[ir_];
+            }
+        }
     }
 }
 
@@ -425,36 +505,52 @@ __device__ __forceinline__ void filter_lds_body(const FiltArgs<T>& a, const Bloc
     const int i0 = col.i - tx, j0 = col.j - ty;   // tile origin (all columns active)
     const int lgBX = __ffs(BX) - 1;
     const unsigned nxy = (unsigned)g.nxy;
+    const unsigned cell = col.row + col.i;
     const T c6 = T(INV_PI6);
     Partial part = {0, 0, 0, 0, 0, 0};
     const int dir = col.dir;
     const int k0 = col.k0, k1 = col.k1;
     const int ks = dir > 0 ? k0 : k1 - 1;
-    T win[NF][7];
+    constexpr int HM = 2;
+    const HaloMap<HM> hm = halo_map<3, HM>(i0, j0, g, BX, lgBX, BY, tid, nthr);
+    // Loads run one plane ahead of their use: the window's next plane (pf)
+    // and the next plane's halo (hv) are fetched while this plane is computed.
+    T win[NF][7], pf[NF], hv[NF][HM];
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
+    for (int f = 0; f < NF; ++f) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            const int kk = wrap(ks + (m - 3) * dir, g.nz);
-            win[f][m] = a.in[f][(unsigned)kk * nxy + col.row + col.i];
-        }
+        for (int m = 0; m < 7; ++m) win[f][m] = a.in[f][(unsigned)wrap(ks + (m - 3) * dir, g.nz) * nxy + cell];
+        pf[f] = a.in[f][(unsigned)wrap(ks + 4 * dir, g.nz) * nxy + cell];
+#pragma unroll
+        for (int h = 0; h < HM; ++h)
+            hv[f][h] = h < hm.n ? a.in[f][(unsigned)ks * nxy + hm.src[h]] : T(0);
+    }
     int buf = 0;
     for (int k = ks, left = k1 - k0; left > 0; --left, k += dir, buf ^= 1) {
         const unsigned base = (unsigned)k * nxy;
-        const unsigned idx = base + col.row + col.i;
+        const unsigned idx = base + cell;
         T* tb = lds + buf * NF * tsz;
-        // stage: interior from the window, halo from memory
+        // stage this plane: interior from the window, halo from the prefetch
 #pragma unroll
-        for (int f = 0; f < NF; ++f) tb[f * tsz + (ty + 3) * W + tx + 3] = win[f][3];
+        for (int f = 0; f < NF; ++f) {
+            tb[f * tsz + (ty + 3) * W + tx + 3] = win[f][3];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) stage_halo<T, 3>(tb + f * tsz, a.in[f], base, i0, j0, g, BX, lgBX, BY, tid, nthr);
+            for (int h = 0; h < HM; ++h)
+                if (h < hm.n) tb[f * tsz + hm.dst[h]] = hv[f][h];
+        }
+        if (left > 1) {
+            const unsigned nb = (unsigned)wrap(k + dir, g.nz) * nxy;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int h = 0; h < HM; ++h)
+                    if (h < hm.n) hv[f][h] = a.in[f][nb + hm.src[h]];
+        }
         __syncthreads();
-        const int kk = wrap(k + 3 * dir, g.nz);
         const uint8_t fl = a.flags[idx];
         T res[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            win[f][6] = a.in[f][(unsigned)kk * nxy + col.row + col.i];
             const T f0 = win[f][3];
             const T* rowp = tb + f * tsz + (ty + 3) * W + tx;        // rowp[m] = x offset m - 3
             const T* colp = tb + f * tsz + ty * W + tx + 3;          // colp[m W] = y offset m - 3
@@ -468,6 +564,8 @@ __device__ __forceinline__ void filter_lds_body(const FiltArgs<T>& a, const Bloc
             a.out[f][idx] = res[f];
 #pragma unroll
             for (int m = 0; m < 6; ++m) win[f][m] = win[f][m + 1];
+            win[f][6] = pf[f];
+            if (left > 1) pf[f] = a.in[f][(unsigned)wrap(k + 5 * dir, g.nz) * nxy + cell];
         }
         if (a.part.p) {
             const double b = (fl & F_FLUID) ? 1.0 : 0.0;
@@ -877,8 +975,10 @@ StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x) {
 #define SCA_KERNEL k_sca_stage
 
 // LDS variants of the z-marching kernels need the block's tile inside the grid.
-inline bool tile_divides(const Grid& g, const StencilLaunch& L) {
-    return g.nx % (int)L.block.x == 0 && g.ny % (int)L.block.y == 0;
+// radius: the halo width; every thread loads at most two halo cells per field.
+inline bool tile_divides(const Grid& g, const StencilLaunch& L, int radius) {
+    const int bx = (int)L.block.x, by = (int)L.block.y;
+    return g.nx % bx == 0 && g.ny % by == 0 && 2 * radius * (bx + by) <= 2 * bx * by;
 }
 
 template <typename T, bool LDS>
@@ -896,7 +996,7 @@ template <typename T>
 hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     MomArgs<T> b = a;
     b.kc = L.kc;
-    const bool use_lds = DNSLAB_STENCIL_LDS && tile_divides(a.g, L);
+    const bool use_lds = DNSLAB_STENCIL_LDS && tile_divides(a.g, L, 1);
     const size_t lds = use_lds ? (size_t)2 * 3 * (L.block.x + 2) * (L.block.y + 2) * sizeof(T) : 0;
     if (rec) {
         record_launch(rec, kind_code(KK_MOM, mode | (use_lds ? STAGE_LDS : 0), sizeof(T) == 4), L.grid, L.block, lds, b);
@@ -930,7 +1030,7 @@ hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream
     FiltArgs<T> b = a;
     b.kc = L.kc;
     // the LDS-tiled variant when the tile divides the grid in x and y
-    const bool use_lds = DNSLAB_FILTER_LDS && tile_divides(a.g, L);
+    const bool use_lds = DNSLAB_FILTER_LDS && tile_divides(a.g, L, 3);
     const int nf = a.nf == 3 ? 3 : 1;
     const size_t lds = use_lds ? (size_t)2 * nf * (L.block.x + 6) * (L.block.y + 6) * sizeof(T) : 0;
     if (rec) {
