@@ -159,7 +159,7 @@ def kernel_key(sym):
         return "mom_stage"
     if base == "sca_stage":
         return "scalar_stage"
-    if base == "filter":
+    if base in ("filter", "filter_lds"):
         return "filter" if targs.endswith("3") else "filter_c"
     if base == "fft_cols":
         return "fft_z" if targs.endswith("2") else "fft_y"

@@ -123,6 +123,9 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_FKC
 #define DNSLAB_FKC 0
 #endif
+#ifndef DNSLAB_FKC_MIN
+#define DNSLAB_FKC_MIN 12       // least z cells per thread of the filter
+#endif
 // FFT passes: x lines per block grow while the block stays within these
 // threads and LDS bytes; y/z column tiles within this much LDS.
 #ifndef DNSLAB_XPASS_THREADS
@@ -175,7 +178,9 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     Lo.lg_tx_z = pick_tx(P->nz, Lo.pz);
     Lo.L = stencil_launch(g, DNSLAB_ROWS, stencil_kc(g, DNSLAB_ROWS, DNSLAB_KC), 1);
     Lo.L1 = Lo.L;
-    Lo.LF = stencil_launch(g, DNSLAB_FROWS, stencil_kc(g, DNSLAB_FROWS, DNSLAB_FKC), 1);
+    // the radius-3 filter re-reads 6 halo planes per z chunk: longer chunks
+    Lo.LF = stencil_launch(g, DNSLAB_FROWS,
+                           std::max(stencil_kc(g, DNSLAB_FROWS, DNSLAB_FKC), std::min(DNSLAB_FKC_MIN, P->nz)), 1);
     Lo.nparts = std::max(std::max(Lo.L.nblocks, Lo.L1.nblocks), Lo.LF.nblocks);
     // workspace layout
     size_t off = 0;
