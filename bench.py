@@ -127,7 +127,7 @@ def cpu_baseline(sc, budget_s=20.0):
     }
 
 
-def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7):
+def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7, log=None):
     """The serving stream: Poisson arrivals of room scenarios of four grid
     sizes, served (a) with continuous batching in the pool (FP32 with FP64
     refinement, and FP64; HBM budget deliberately small so admission binds)
@@ -136,9 +136,9 @@ def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7):
     from paper_2204_02107_amd import serving, FP32_REFINE, FP64
     reqs = scenarios.serving_requests(n_req, seed=seed, mean_gap=mean_gap, n_steps=n_steps)
     cases = {r["id"]: scenarios.serving_scenario(r) for r in reqs}
-    pooled = serving.serve(reqs, cases, int(budget_gib * (1 << 30)), FP32_REFINE)
-    pooled64 = serving.serve(reqs, cases, int(budget_gib * (1 << 30)), FP64)
-    base = serving.fifo(reqs, cases, FP64)
+    pooled = serving.serve(reqs, cases, int(budget_gib * (1 << 30)), FP32_REFINE, log=log)
+    pooled64 = serving.serve(reqs, cases, int(budget_gib * (1 << 30)), FP64, log=log)
+    base = serving.fifo(reqs, cases, FP64, log=log)
     out = {
         "requests": n_req, "steps_each": n_steps, "mean_gap_s": mean_gap, "hbm_budget_GiB": budget_gib,
         "pool_fp32_refine": serving.summarize(pooled),
@@ -354,7 +354,8 @@ def main():
     if args.serving != "none" and args.workload == "room" and prec == m.FP64:
         n_req, n_steps = (16, 300) if args.serving == "short" else (64, 2000)
         print(f"[bench] serving stream {n_req} x {n_steps} ...", file=sys.stderr, flush=True)
-        out["serving"] = serving_bench(n_req, n_steps, budget_gib=1.0)
+        out["serving"] = serving_bench(n_req, n_steps, budget_gib=1.0,
+                                       log=lambda msg: print("[serving] " + msg, file=sys.stderr, flush=True))
         print("[bench] serving: " + json.dumps(out["serving"]), file=sys.stderr, flush=True)
     if not args.no_cpu and args.workload == "room":
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
