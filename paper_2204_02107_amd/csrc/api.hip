@@ -1208,8 +1208,12 @@ struct BatchPos {
 struct BatchGroup {
     std::vector<int> slots;
     std::vector<BatchPos> seq;
-    bool direct = false;   // one scenario: its own context issues plain launches (no table lookups)
+    // Direct groups issue each scenario's own plain step: a group of one (no
+    // batched-table lookups), or scenarios large enough to fill the GPU alone,
+    // which then also overlap their scalar half with their next pressure solve.
+    bool direct = false;
 };
+constexpr long long POOL_DIRECT_CELLS = 1LL << 20;
 
 }  // namespace
 
@@ -1228,6 +1232,13 @@ struct dnslab_pool {
     size_t tab_cap = 0;
     bool use_graph = false;
     hipGraphExec_t gexec = nullptr;       // one pool step, for the current groups
+    // Groups (scenarios of one launch sequence) are independent of each other:
+    // each step they run on separate streams, forked from and joined back into
+    // the pool's stream, so that groups of different grid sizes fill each
+    // other's idle time.
+    std::vector<hipStream_t> gs;
+    std::vector<hipEvent_t> gev;          // join events, one per group stream
+    hipEvent_t fork_ev = nullptr;
     std::string err;
 };
 
@@ -1320,7 +1331,7 @@ int pool_rebuild(dnslab_pool* P, const std::vector<int>& active) {
             bp.st_off = put(starts.data(), starts.size() * sizeof(unsigned));
         }
         for (int& q : G.slots) q = active[q];   // back to slot ids
-        G.direct = G.slots.size() == 1;
+        G.direct = G.slots.size() == 1 || P->slots[G.slots[0]].ctx->g.n >= POOL_DIRECT_CELLS;
     }
     if (host.size() > P->tab_cap) {
         if (P->tab_dev) (void)hipFree(P->tab_dev);
@@ -1360,27 +1371,85 @@ int pool_capture(dnslab_pool* P) {
     return DNSLAB_OK;
 }
 
+constexpr int POOL_GROUP_STREAMS = 4;
+
+int pool_streams(dnslab_pool* P) {
+    if (!P->gs.empty()) return DNSLAB_OK;
+    PHIP(P, hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
+    for (int i = 0; i < POOL_GROUP_STREAMS; ++i) {
+        hipStream_t st;
+        hipEvent_t ev;
+        PHIP(P, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        P->gs.push_back(st);
+        PHIP(P, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        P->gev.push_back(ev);
+    }
+    return DNSLAB_OK;
+}
+
+hipStream_t slot_stream(dnslab_pool* P, int slot) {
+    return P->gs.empty() ? P->stream : P->gs[slot % (int)P->gs.size()];
+}
+
+// Enqueue the deferred scalar halves of direct scenarios and join every group
+// stream back into the pool's stream.
+int pool_settle(dnslab_pool* P) {
+    for (size_t i = 0; i < P->slots.size(); ++i) {
+        PoolSlot& S = P->slots[i];
+        if (!S.used || !(S.ctx->tail_pending || S.ctx->join_pending)) continue;
+        dnslab_ctx* x = S.ctx;
+        x->stream = x->cur = slot_stream(P, (int)i);
+        const int rc = x->Lo.esz == 8 ? settle<double>(x) : settle<float>(x);
+        x->stream = x->cur = P->stream;
+        if (rc) return pfail(P, rc, "settle failed: " + x->err);
+    }
+    for (size_t i = 0; i < P->gs.size(); ++i) {
+        PHIP(P, hipEventRecord(P->gev[i], P->gs[i]));
+        PHIP(P, hipStreamWaitEvent(P->stream, P->gev[i], 0));
+    }
+    return DNSLAB_OK;
+}
+
+// One pool step: batched group g on group stream g mod 4, direct scenarios on
+// their slot's stream, all forked from and joined back into the pool's stream.
 int pool_replay(dnslab_pool* P) {
     char* base = (char*)P->tab_dev;
-    for (const BatchGroup& G : P->groups) {
+    const int ngs = (int)P->gs.size();
+    if (ngs > 0) {
+        PHIP(P, hipEventRecord(P->fork_ev, P->stream));
+        for (int i = 0; i < ngs; ++i) PHIP(P, hipStreamWaitEvent(P->gs[i], P->fork_ev, 0));
+    }
+    for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+        const BatchGroup& G = P->groups[gi];
+        const hipStream_t st_g = ngs > 0 ? P->gs[gi % ngs] : P->stream;
         if (G.direct) {
-            // a batch of one: the plain step of that scenario (same kernels, so
-            // the same result), without the batched kernels' table lookups
-            dnslab_ctx* x = P->slots[G.slots[0]].ctx;
-            const long long hs = x->host_step;
-            const int rc = x->Lo.esz == 8 ? one_step<double>(x) : one_step<float>(x);
-            x->host_step = hs;   // the pool counts the step
-            if (rc) return pfail(P, rc, "step failed: " + x->err);
+            // each scenario's plain step (same kernels, so the same result), on
+            // a stream fixed per slot so that a step's deferred scalar half is
+            // ordered after it; pool_settle enqueues the last one
+            for (int slot : G.slots) {
+                dnslab_ctx* x = P->slots[slot].ctx;
+                const long long hs = x->host_step;
+                x->stream = x->cur = slot_stream(P, slot);
+                x->overlap = !P->use_graph;
+                const int rc = x->Lo.esz == 8 ? one_step<double>(x) : one_step<float>(x);
+                x->stream = x->cur = P->stream;
+                x->host_step = hs;   // the pool counts the step
+                if (rc) return pfail(P, rc, "step failed: " + x->err);
+            }
             continue;
         }
         for (const BatchPos& bp : G.seq) {
             const void* tab = base + bp.tab_off;
             const unsigned* st = (const unsigned*)(base + bp.st_off);
             hipError_t e = is_stencil_kind(bp.kind)
-                               ? launch_batched_stencil(bp.kind, tab, st, bp.ns, bp.total, bp.block, bp.lds, P->stream)
-                               : launch_batched_fft(bp.kind, tab, st, bp.ns, bp.total, bp.block, bp.lds, P->stream);
+                               ? launch_batched_stencil(bp.kind, tab, st, bp.ns, bp.total, bp.block, bp.lds, st_g)
+                               : launch_batched_fft(bp.kind, tab, st, bp.ns, bp.total, bp.block, bp.lds, st_g);
             if (e != hipSuccess) return pfail(P, DNSLAB_EHIP, std::string("batched launch: ") + hipGetErrorString(e));
         }
+    }
+    for (int i = 0; i < ngs; ++i) {
+        PHIP(P, hipEventRecord(P->gev[i], P->gs[i]));
+        PHIP(P, hipStreamWaitEvent(P->stream, P->gev[i], 0));
     }
     return DNSLAB_OK;
 }
@@ -1531,7 +1600,9 @@ int dnslab_pool_step(dnslab_pool* P, int32_t nsteps) {
                 if (P->slots[i].used && P->slots[i].done < P->slots[i].target) active.push_back((int)i);
             if (active.empty()) break;
             if (P->dirty || active != P->active_ids) {
-                int rc = pool_rebuild(P, active);
+                int rc = pool_streams(P);
+                if (!rc) rc = pool_settle(P);
+                if (!rc) rc = pool_rebuild(P, active);
                 if (!rc && P->use_graph) rc = pool_capture(P);
                 if (rc) return rc;
             }
@@ -1546,7 +1617,7 @@ int dnslab_pool_step(dnslab_pool* P, int32_t nsteps) {
                 P->slots[i].ctx->host_step += 1;
             }
         }
-        return DNSLAB_OK;
+        return pool_settle(P);
     } catch (...) {
         return pfail(P, DNSLAB_ENOMEM, "host allocation failed");
     }
@@ -1634,6 +1705,12 @@ void dnslab_pool_destroy(dnslab_pool* P) {
     for (size_t i = 0; i < P->slots.size(); ++i)
         if (P->slots[i].used) dnslab_pool_release(P, (int)i);
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    for (hipStream_t st : P->gs) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t ev : P->gev) (void)hipEventDestroy(ev);
+    if (P->fork_ev) (void)hipEventDestroy(P->fork_ev);
     if (P->tab_dev) (void)hipFree(P->tab_dev);
     if (P->admit_stream) (void)hipStreamDestroy(P->admit_stream);
     if (P->stage) (void)hipFree(P->stage);

@@ -132,3 +132,39 @@ def test_pooled_scenario_matches_oracle():
     d, _, _ = pool.query(slot)
     assert abs(d["co2_room_mean"] - diags[-1]["co2_room_mean"]) < 1e-10 * diags[-1]["co2_room_mean"]
     pool.close()
+
+
+def test_pool_large_scenarios_direct_equal_plain():
+    """Scenarios of at least 2^20 cells run their own plain step inside the pool
+    (with the scalar half deferred onto a second stream across pool steps);
+    two of them plus a small one, admitted at different times, must end bitwise
+    equal to plain runs."""
+    torch, m = need_gpu()
+    from paper_2204_02107_amd.serving import Pool
+    big = [scenarios.room(128, 128, 64, dx=DX, u_in=1.0, n_boxes=4, seed=21, box_max_frac=0.4),
+           scenarios.room(128, 128, 64, dx=DX, u_in=0.1, n_boxes=2, seed=22, box_max_frac=0.4)]
+    cs = big + [cases()[0]]
+    steps = 7
+    announce("pool direct large vs plain")
+    alone = []
+    for c in cs:
+        S = m.Solver(c)
+        S.step(steps, diag=False)
+        alone.append(S.state())
+        S.close()
+    pool = Pool(8 << 30, m.FP64, stream=torch.cuda.Stream())
+    slots = [None] * len(cs)
+    t = 0
+    while True:
+        for q, c in enumerate(cs):
+            if slots[q] is None and t >= (0, 2, 1)[q]:
+                slots[q] = pool.admit(c, steps)
+        if all(s is not None for s in slots) and pool.usage()[1] == 0:
+            break
+        pool.step(3)           # several steps per call: the deferred scalar half crosses steps
+        t += 1
+    for q, c in enumerate(cs):
+        got = pool.state(slots[q], c.shape)
+        for k in ("u", "v", "w", "p", "c"):
+            assert np.array_equal(got[k], alone[q][k]), (q, k)
+    pool.close()
