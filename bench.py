@@ -127,6 +127,34 @@ def cpu_baseline(sc, budget_s=20.0):
     }
 
 
+def particle_bench(S, sc, esz, n=1 << 20, steps=100, seed=5):
+    """Lagrangian particles (Section 2.3) in the solver's current velocity: n
+    particles of 1-100 um spread over the room, `steps` implicit-Euler steps.
+    Algorithmic bytes per particle-step: position, velocity (read and write)
+    and diameter (13 x 8 B) plus the 24 interpolation gathers (24 x esz)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    dev = S.device
+    box = (sc.lx, sc.ly, sc.lz)
+    pos = torch.as_tensor(np.stack([rng.uniform(0, box[a], n) for a in range(3)]), device=dev).contiguous()
+    vel = torch.zeros((3, n), dtype=torch.float64, device=dev)
+    diam = torch.as_tensor(rng.uniform(1e-6, 100e-6, n), device=dev)
+    S.particles_step(pos, vel, diam, dt=1e-3)
+    torch.cuda.synchronize()
+    S.profile("particles")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S.particles_step(pos, vel, diam, dt=1e-3)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, nl = S.profile_read()
+    S.profile(None)
+    per = 1e-3 * ms / max(nl, 1)
+    b = n * (13 * 8 + 24 * esz)
+    return {"particles": n, "steps": steps, "Mparticle_steps_per_s": n * steps / el / 1e6,
+            "kernel_avg_us": 1e6 * per, "algorithmic_GBs": b / per / 1e9, "bytes_per_particle_step": 13 * 8 + 24 * esz}
+
+
 def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7, log=None):
     """The serving stream: Poisson arrivals of room scenarios of four grid
     sizes, served (a) with continuous batching in the pool (FP32 with FP64
@@ -350,6 +378,8 @@ def main():
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["GBs"], 1),
                         "launches_per_step": v["launches_per_step"]} for k, v in per.items()},
     }
+    out["particles"] = particle_bench(S, sc, esz)
+    print("[bench] particles: " + json.dumps(out["particles"]), file=sys.stderr, flush=True)
     S.close()
     if args.serving != "none" and args.workload == "room" and prec == m.FP64:
         n_req, n_steps = (16, 300) if args.serving == "short" else (64, 2000)

@@ -172,10 +172,33 @@ void dnslab_destroy(dnslab_ctx* ctx);
  * thread (for failed dnslab_init calls).  Never NULL. */
 const char* dnslab_last_error(const dnslab_ctx* ctx);
 
+/* Lagrangian particles (Section 2.3): drag du_p/dt = (C_d/tau_p)(u_f - u_p) + g
+ * with tau_p = rho_p d^2 / (18 rho_f nu) (d the diameter), Re_p = |u_f - u_p| d/nu,
+ * C_d = 1 + Re_p^(2/3)/6, one-way coupled to the bound velocity (trilinear
+ * interpolation of the cell values, cell (i, j, k) at (i dx, j dy, k dz),
+ * periodic).  Implicit Euler with C_d from the start of the step:
+ * u_p' = (u_p + dt (C_d/tau_p) u_f + dt g) / (1 + dt C_d/tau_p), x' = x + dt u_p',
+ * wrapped into the periodic box. */
+typedef struct {
+    double rho_p;           /* particle density [kg/m^3] */
+    double rho_f;           /* fluid density [kg/m^3] */
+    double g[3];            /* gravitational acceleration [m/s^2] */
+} dnslab_particle_params;
+
+/* Advance n particles by one step on the context's stream.  pos and vel are
+ * device FP64 arrays of 3n values, structure of arrays (x[0..n), y[0..n),
+ * z[0..n)), updated in place; diam holds n diameters [m].  dt > 0 is the step;
+ * dt <= 0 takes the time step of the last dnslab_step (read on the device, no
+ * synchronisation).  Call after dnslab_step to move the particles with the new
+ * velocity.  DNSLAB_EINVAL for n < 0, n >= 2^40, NULL arrays with n > 0, or
+ * non-positive densities. */
+int dnslab_particles_step(dnslab_ctx* ctx, int64_t n, double* pos, double* vel, const double* diam,
+                          const dnslab_particle_params* pp, double dt);
+
 /* Kernel timing for roofline measurements: when enabled, every launch of the
  * named kernel ("mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
  * "fft_x_inv", "filter", "filter_c", "correct", "div", "ib_rhs", "advance",
- * "diag", "refine_res") is bracketed by HIP events on the stream it is
+ * "diag", "refine_res", "particles") is bracketed by HIP events on the stream it is
  * launched on, and the total and count accumulate (kernel_name NULL: off).
  * Steps are issued launch by launch while a kernel is profiled.  Read
  * synchronises. */

@@ -174,6 +174,20 @@ class Solver:
         self._call(self.lib.dnslab_filter, self.ctx, _ptr(f), _ptr(out))
         return out
 
+    # -- Lagrangian particles (Section 2.3) ----------------------------------
+    def particles_step(self, pos, vel, diam, rho_p=1000.0, rho_f=1.225, g=(0.0, 0.0, -9.81), dt=0.0):
+        """Advance particles in place: pos, vel are FP64 device tensors of shape
+        (3, n) (x, y, z rows), diam of shape (n,).  dt <= 0 uses the last step's dt."""
+        n = int(diam.numel())
+        for t in (pos, vel, diam):
+            if t.dtype != _torch().float64 or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("particle arrays must be contiguous float64 tensors on the solver's device")
+        if tuple(pos.shape) != (3, n) or tuple(vel.shape) != (3, n):
+            raise ValueError("pos and vel must have shape (3, n)")
+        pp = _lib.ParticleParams(float(rho_p), float(rho_f), (ctypes.c_double * 3)(*map(float, g)))
+        self._call(self.lib.dnslab_particles_step, self.ctx, n, _ptr(pos), _ptr(vel), _ptr(diam),
+                   ctypes.byref(pp), float(dt))
+
     # -- kernel timing -------------------------------------------------------
     def profile(self, kernel: Optional[str]):
         self._check(self.lib.dnslab_profile_enable(self.ctx, kernel.encode() if kernel else None))

@@ -15,6 +15,7 @@
 
 #include "common.h"
 #include "fft.h"
+#include "particles.h"
 #include "stencil.h"
 
 using namespace dnslab;
@@ -26,10 +27,10 @@ constexpr int RING_CAP = 4096;
 constexpr int PROF_POOL = 32768;
 
 enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_FILTC, K_CORR, K_DIV, K_IB,
-                K_ADV, K_DIAG, K_REF, K_COUNT };
+                K_ADV, K_DIAG, K_REF, K_PART, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {"mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z", "fft_x_inv",
                                             "filter", "filter_c", "correct", "div", "ib_rhs", "advance", "diag",
-                                            "refine_res"};
+                                            "refine_res", "particles"};
 
 bool is_2a3b(int n) {
     if (n < 1) return false;
@@ -1155,6 +1156,43 @@ int dnslab_profile_enable(dnslab_ctx* x, const char* name) {
     x->prof_kid = kid;
     x->prof_ms = 0;
     x->prof_n = 0;
+    return DNSLAB_OK;
+}
+
+int dnslab_particles_step(dnslab_ctx* x, int64_t n, double* pos, double* vel, const double* diam,
+                          const dnslab_particle_params* pp, double dt) {
+    if (int rc = check_ctx(x)) return rc;
+    if (n < 0 || n >= (1LL << 40)) return fail(x, DNSLAB_EINVAL, "bad particle count");
+    if (!pp || (n > 0 && (!pos || !vel || !diam))) return fail(x, DNSLAB_EINVAL, "NULL pointer");
+    if (!(pp->rho_p > 0) || !(pp->rho_f > 0) || !std::isfinite(pp->g[0]) || !std::isfinite(pp->g[1]) ||
+        !std::isfinite(pp->g[2]) || !std::isfinite(dt))
+        return fail(x, DNSLAB_EINVAL, "bad particle parameters");
+    if (!(x->P.nu > 0)) return fail(x, DNSLAB_EINVAL, "particles need nu > 0");
+    auto fill = [&](auto& a) {
+        a.g = x->g;
+        a.box[0] = x->P.lx; a.box[1] = x->P.ly; a.box[2] = x->P.lz;
+        a.px = pos; a.py = pos + n; a.pz = pos + 2 * n;
+        a.vx = vel; a.vy = vel + n; a.vz = vel + 2 * n;
+        a.diam = diam;
+        a.n = n;
+        a.nu = x->P.nu;
+        a.rho_p = pp->rho_p;
+        a.rho_f = pp->rho_f;
+        for (int i = 0; i < 3; ++i) a.g_acc[i] = pp->g[i];
+        a.dtp = dt > 0 ? nullptr : &x->sc->last_dt;
+        a.dt = dt;
+    };
+    if (x->Lo.esz == 8) {
+        ParticleArgs<double> a;
+        a.u = (const double*)x->u; a.v = (const double*)x->v; a.w = (const double*)x->w;
+        fill(a);
+        LAUNCH(x, K_PART, launch_particles<double>(a, x->stream));
+    } else {
+        ParticleArgs<float> a;
+        a.u = (const float*)x->u; a.v = (const float*)x->v; a.w = (const float*)x->w;
+        fill(a);
+        LAUNCH(x, K_PART, launch_particles<float>(a, x->stream));
+    }
     return DNSLAB_OK;
 }
 

@@ -1,0 +1,110 @@
+"""Lagrangian particles (Section 2.3) on the GPU against the particle oracle."""
+import numpy as np
+import pytest
+
+from oracle import particles as P
+import scenarios
+from gpu_util import announce, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+RHO_P, RHO_F = 1000.0, 1.225
+G = (0.05, -0.02, -9.81)
+
+
+def periodic_err(a, b, box):
+    e = 0.0
+    for ax in range(3):
+        dd = np.abs(a[ax] - b[ax])
+        dd = np.minimum(dd, box[ax] - dd)
+        e = max(e, float(dd.max()))
+    return e
+
+
+def setup(precision_name="fp64", n=100_000, seed=1):
+    torch, m = need_gpu()
+    prec = m.FP64 if precision_name == "fp64" else m.FP32_REFINE
+    sc = scenarios.room(64, 48, 36, dx=0.0390625, n_boxes=3, seed=2204)
+    rng = np.random.default_rng(seed)
+    b = sc.beta.astype(np.float64)
+    sc.u, sc.v, sc.w = [rng.standard_normal(sc.shape) * 0.5 * b for _ in range(3)]
+    box = (sc.lx, sc.ly, sc.lz)
+    pos = np.stack([rng.uniform(0, box[a], n) for a in range(3)])
+    vel = rng.standard_normal((3, n)) * 0.1
+    diam = rng.uniform(1e-6, 100e-6, n)
+    S = m.Solver(sc, precision=prec)
+    dev = S.device
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    return torch, m, sc, S, box, pos, vel, diam, t
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_particles_vs_oracle(precision):
+    torch, m, sc, S, box, pos, vel, diam, t = setup(precision)
+    announce(f"particles vs oracle {precision}")
+    fields = [S.u, S.v, S.w]
+    u = [f.double().cpu().numpy() for f in fields]       # the field values the kernel reads
+    gp, gv, gd = t(pos), t(vel), t(diam)
+    dt = 0.004
+    for _ in range(10):
+        S.particles_step(gp, gv, gd, RHO_P, RHO_F, G, dt)
+        pos, vel = P.step(pos, vel, diam, u, sc.spacing, box, sc.nu, RHO_P, RHO_F, G, dt)
+    got_p, got_v = gp.cpu().numpy(), gv.cpu().numpy()
+    assert periodic_err(got_p, pos, box) < 1e-12
+    assert np.abs(got_v - vel).max() < 1e-11 * max(1.0, np.abs(vel).max())
+    S.close()
+
+
+def test_particles_follow_fluid_steps_with_device_dt():
+    """Coupled use: a fluid step, then a particle step with dt <= 0 (the step's
+    own dt, read on the device) in the new velocity."""
+    torch, m, sc, S, box, pos, vel, diam, t = setup("fp64", n=20_000, seed=2)
+    announce("particles after fluid steps")
+    gp, gv, gd = t(pos), t(vel), t(diam)
+    for _ in range(3):
+        d = S.step(1)
+        u = [f.double().cpu().numpy() for f in (S.u, S.v, S.w)]
+        S.particles_step(gp, gv, gd, RHO_P, RHO_F, G, 0.0)
+        pos, vel = P.step(pos, vel, diam, u, sc.spacing, box, sc.nu, RHO_P, RHO_F, G, d["dt"])
+    assert periodic_err(gp.cpu().numpy(), pos, box) < 1e-12
+    assert np.abs(gv.cpu().numpy() - vel).max() < 1e-11
+    S.close()
+
+
+def test_settling_speed_in_still_air():
+    """Particles in still air settle at the terminal speed (the scheme's fixed point)."""
+    torch, m = need_gpu()
+    sc = scenarios.taylor_green(16)
+    sc.u[:] = 0.0
+    sc.v[:] = 0.0
+    sc.w[:] = 0.0
+    announce("particle settling")
+    S = m.Solver(sc)
+    diam = np.array([5e-6, 10e-6, 30e-6])
+    dev = S.device
+    gp = torch.full((3, 3), 1.0, dtype=torch.float64, device=dev)
+    gv = torch.zeros((3, 3), dtype=torch.float64, device=dev)
+    gd = torch.as_tensor(diam, dtype=torch.float64, device=dev)
+    for _ in range(400):
+        S.particles_step(gp, gv, gd, RHO_P, RHO_F, (0.0, 0.0, -9.81), 0.01)
+    v = gv.cpu().numpy()
+    for q in range(3):
+        ref = P.terminal_speed(diam[q], sc.nu, RHO_P, RHO_F, 9.81)
+        assert abs(-v[2, q] / ref - 1) < 1e-9
+    S.close()
+
+
+def test_particles_reject_bad_arguments():
+    torch, m = need_gpu()
+    from paper_2204_02107_amd import _lib
+    import ctypes
+    sc = scenarios.taylor_green(8)
+    S = m.Solver(sc)
+    lib = _lib.load()
+    pp = _lib.ParticleParams(1000.0, 1.2, (ctypes.c_double * 3)(0, 0, -9.81))
+    assert lib.dnslab_particles_step(S.ctx, -1, None, None, None, ctypes.byref(pp), 0.01) == -1
+    assert lib.dnslab_particles_step(S.ctx, 5, None, None, None, ctypes.byref(pp), 0.01) == -1
+    bad = _lib.ParticleParams(0.0, 1.2, (ctypes.c_double * 3)(0, 0, -9.81))
+    assert lib.dnslab_particles_step(S.ctx, 0, None, None, None, ctypes.byref(bad), 0.01) == -1
+    assert lib.dnslab_particles_step(S.ctx, 0, None, None, None, ctypes.byref(pp), 0.01) == 0
+    S.close()
