@@ -195,6 +195,17 @@ typedef struct {
 int dnslab_particles_step(dnslab_ctx* ctx, int64_t n, double* pos, double* vel, const double* diam,
                           const dnslab_particle_params* pp, double dt);
 
+/* CO2 distribution over the room (Section 3.3): counts of the fluid cells of
+ * the room region per bin of the bound c, nbins equal bins over [lo, hi)
+ * (bin floor((c - lo) / (hi - lo) * nbins) in FP64, clamped into the end
+ * bins).  counts_host receives nbins values.  1 <= nbins <= 4096 and lo < hi,
+ * else DNSLAB_EINVAL.  Synchronises the stream. */
+int dnslab_co2_histogram(dnslab_ctx* ctx, int32_t nbins, double lo, double hi, int64_t* counts_host);
+
+/* Running sums for time averages: sums_dev (FP64 device array of 5 n values,
+ * field-major u, v, w, p, c) += the bound fields.  Asynchronous. */
+int dnslab_accumulate(dnslab_ctx* ctx, double* sums_dev);
+
 /* Kernel timing for roofline measurements: when enabled, every launch of the
  * named kernel ("mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
  * "fft_x_inv", "filter", "filter_c", "correct", "div", "ib_rhs", "advance",

@@ -188,6 +188,21 @@ class Solver:
         self._call(self.lib.dnslab_particles_step, self.ctx, n, _ptr(pos), _ptr(vel), _ptr(diam),
                    ctypes.byref(pp), float(dt))
 
+    # -- post-processing (Sections 3.3-3.4) ----------------------------------
+    def co2_histogram(self, nbins=60, lo=400.0, hi=1000.0):
+        """Counts of room fluid cells per CO2 bin (numpy int64, nbins values)."""
+        import numpy as np
+        out = np.zeros(int(nbins), dtype=np.int64)
+        self._call(self.lib.dnslab_co2_histogram, self.ctx, int(nbins), float(lo), float(hi),
+                   out.ctypes.data_as(ctypes.c_void_p))
+        return out
+
+    def accumulate(self, sums):
+        """sums (FP64 device tensor of shape (5,) + grid shape) += (u, v, w, p, c)."""
+        if sums.dtype != _torch().float64 or not sums.is_contiguous() or tuple(sums.shape) != (5,) + self.shape:
+            raise ValueError("sums must be a contiguous float64 tensor of shape (5, nz, ny, nx)")
+        self._call(self.lib.dnslab_accumulate, self.ctx, _ptr(sums))
+
     # -- kernel timing -------------------------------------------------------
     def profile(self, kernel: Optional[str]):
         self._check(self.lib.dnslab_profile_enable(self.ctx, kernel.encode() if kernel else None))

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdnslab.so")
-SOURCES = ["api.hip", "stencil.hip", "fft.hip", "particles.hip"]
+SOURCES = ["api.hip", "stencil.hip", "fft.hip", "particles.hip", "postproc.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for all device code.

@@ -16,6 +16,7 @@
 #include "common.h"
 #include "fft.h"
 #include "particles.h"
+#include "postproc.h"
 #include "stencil.h"
 
 using namespace dnslab;
@@ -248,6 +249,8 @@ struct dnslab_ctx {
     IBList ib;
     bool rate_valid;
     long long host_step;
+    unsigned long long* hist_dev;   // histogram counters (allocated on first use)
+    unsigned long long* hist_host;
     DiagRec* pinned;       // host staging for diagnostics
     StepScalars* pinned_sc;
     std::string err;
@@ -1126,6 +1129,8 @@ void dnslab_destroy(dnslab_ctx* x) {
     for (hipEvent_t e : x->ev) (void)hipEventDestroy(e);
     if (x->ws) (void)hipFree(x->ws);
     if (x->ib_buf) (void)hipFree(x->ib_buf);
+    if (x->hist_dev) (void)hipFree(x->hist_dev);
+    if (x->hist_host) (void)hipHostFree(x->hist_host);
     if (x->pinned) (void)hipHostFree(x->pinned);
     if (x->pinned_sc) (void)hipHostFree(x->pinned_sc);
     delete x;
@@ -1193,6 +1198,51 @@ int dnslab_particles_step(dnslab_ctx* x, int64_t n, double* pos, double* vel, co
         fill(a);
         LAUNCH(x, K_PART, launch_particles<float>(a, x->stream));
     }
+    return DNSLAB_OK;
+}
+
+int dnslab_co2_histogram(dnslab_ctx* x, int32_t nbins, double lo, double hi, int64_t* counts_host) {
+    if (int rc = check_ctx(x)) return rc;
+    if (nbins < 1 || nbins > HIST_MAX_BINS || !(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi) || !counts_host)
+        return fail(x, DNSLAB_EINVAL, "bad histogram arguments");
+    if (!x->hist_dev) {
+        if (hipMalloc((void**)&x->hist_dev, HIST_MAX_BINS * sizeof(unsigned long long)) != hipSuccess ||
+            hipHostMalloc((void**)&x->hist_host, HIST_MAX_BINS * sizeof(unsigned long long), hipHostMallocDefault) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            return fail(x, DNSLAB_ENOMEM, "histogram buffers");
+        }
+    }
+    hipError_t e;
+    if (x->Lo.esz == 8) {
+        HistArgs<double> a = {(const double*)x->c, x->flags, x->g.n, nbins, lo, hi, x->hist_dev};
+        e = launch_histogram<double>(a, x->stream);
+    } else {
+        HistArgs<float> a = {(const float*)x->c, x->flags, x->g.n, nbins, lo, hi, x->hist_dev};
+        e = launch_histogram<float>(a, x->stream);
+    }
+    if (e != hipSuccess) return fail(x, DNSLAB_EHIP, std::string("histogram: ") + hipGetErrorString(e));
+    HIPCHK(x, hipMemcpyAsync(x->hist_host, x->hist_dev, nbins * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             x->stream));
+    HIPCHK(x, hipStreamSynchronize(x->stream));
+    for (int b = 0; b < nbins; ++b) counts_host[b] = (int64_t)x->hist_host[b];
+    return DNSLAB_OK;
+}
+
+int dnslab_accumulate(dnslab_ctx* x, double* sums_dev) {
+    if (int rc = check_ctx(x)) return rc;
+    if (!sums_dev) return fail(x, DNSLAB_EINVAL, "NULL pointer");
+    hipError_t e;
+    if (x->Lo.esz == 8) {
+        AccArgs<double> a = {{(const double*)x->u, (const double*)x->v, (const double*)x->w, (const double*)x->p,
+                              (const double*)x->c}, sums_dev, x->g.n};
+        e = launch_accumulate<double>(a, x->stream);
+    } else {
+        AccArgs<float> a = {{(const float*)x->u, (const float*)x->v, (const float*)x->w, (const float*)x->p,
+                             (const float*)x->c}, sums_dev, x->g.n};
+        e = launch_accumulate<float>(a, x->stream);
+    }
+    if (e != hipSuccess) return fail(x, DNSLAB_EHIP, std::string("accumulate: ") + hipGetErrorString(e));
     return DNSLAB_OK;
 }
 

@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2204_02107_amd", "libdnslab.so")
 
 def header_symbols():
     text = open(os.path.join(ROOT, "include", "dnslab.h")).read()
-    return sorted(set(re.findall(r"\b(dnslab_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(dnslab_[a-z0-9_]+)\s*\(", text)))
 
 
 needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libdnslab.so not built")
