@@ -105,36 +105,14 @@ __device__ __forceinline__ double courant_rate(double u, double v, double w, con
 // cells, all inside the grid) is held in LDS with its x and y halo of R cells
 // each side (no corners: every stencil here is a sum of one-axis differences),
 // as rows of W = BX + 2R values.  The interior comes from the threads' own z
-// register windows; stage_halo fetches the halo of one field.
+// register windows; halo_map gives each thread its share of the halo.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-template <typename T, int R>
-__device__ __forceinline__ void stage_halo(T* tb, const T* __restrict__ src, unsigned base, int i0, int j0,
-                                           const Grid& g, int BX, int lgBX, int BY, int tid, int nthr) {
-    const int W = BX + 2 * R;
-    const int nhy = 2 * R * BX, nh = nhy + 2 * R * BY;
-    for (int r = tid; r < nh; r += nthr) {
-        int ly, lx;
-        if (r < nhy) {
-            const int hr = r >> lgBX;                 // halo row 0 .. 2R-1
-            ly = hr < R ? hr : BY + hr;
-            lx = R + (r - (hr << lgBX));
-        } else {
-            const int q = r - nhy, row = q / (2 * R), c = q - row * (2 * R);
-            ly = R + row;
-            lx = c < R ? c : BX + c;
-        }
-        // |offset| <= R <= n along both axes, so one wrap suffices
-        const int gi = wrap1(i0 + lx - R, g.nx), gj = wrap1(j0 + ly - R, g.ny);
-        tb[ly * W + lx] = src[base + (unsigned)gj * g.nx + gi];
-    }
-}
-
-// The same halo as stage_halo, as a per-thread map: this thread's halo cells
-// (at most HMAX of them) as in-plane source offsets and LDS destinations, so
-// that a kernel can load a plane's halo into registers one plane ahead of
-// storing it.  The launch guarantees 2R(BX + BY) <= HMAX * BX * BY.
+// The halo cells of this thread (at most HMAX of them) as in-plane source
+// offsets and LDS destinations, so that a kernel can load a plane's halo into
+// registers one plane ahead of storing it (the rows above and below the tile
+// columns).  The launch guarantees 2R(BX + BY) <= HMAX * BX * BY.
 template <int HMAX>
 struct HaloMap {
     unsigned src[HMAX];
@@ -971,8 +949,6 @@ StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x) {
     return L;
 }
 
-#define MOM_KERNEL k_mom_stage
-#define SCA_KERNEL k_sca_stage
 
 // LDS variants of the z-marching kernels need the block's tile inside the grid.
 // radius: the halo width; every thread loads at most two halo cells per field.
