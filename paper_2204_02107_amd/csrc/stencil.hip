@@ -112,7 +112,8 @@ __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >
 // The halo cells of this thread (at most HMAX of them) as in-plane source
 // offsets and LDS destinations, so that a kernel can load a plane's halo into
 // registers one plane ahead of storing it (the rows above and below the tile
-// columns).  The launch guarantees 2R(BX + BY) <= HMAX * BX * BY.
+// first, then the columns left and right of it).  The launch guarantees
+// 2R(BX + BY) <= HMAX * BX * BY.
 template <int HMAX>
 struct HaloMap {
     unsigned src[HMAX];
