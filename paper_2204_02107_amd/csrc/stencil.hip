@@ -186,6 +186,7 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
     constexpr int HM = 2;
     HaloMap<HM> hm;
     T zq[3], hv[3][HM];
+    T pa[3] = {T(0), T(0), T(0)}, pn[3] = {T(0), T(0), T(0)};   // acc, u^n of the current plane
 
     T zm[3], z0[3], zp[3];
     {
@@ -200,6 +201,11 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
             zp[0] = u0p[ip_]; zp[1] = u1p[ip_]; zp[2] = u2p[ip_];
             zq[0] = u0p[iq_]; zq[1] = u1p[iq_]; zq[2] = u2p[iq_];
             hm = halo_map<1, HM>(i0, j0, g, BX, lgBX, BY, tid, nthr);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (MODE == ST_HALF || MODE == ST_FULL || MODE == ST_LAST) pa[c] = a.acc[c][i0_];
+                if (MODE == ST_HALF || MODE == ST_FULL) pn[c] = a.un[c][i0_];
+            }
             const unsigned b0 = (unsigned)k0 * nxy;
 #pragma unroll
             for (int h = 0; h < HM; ++h) {
@@ -277,17 +283,27 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
 
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+            // LDS variant: acc and u^n of this cell were loaded one plane ahead
+            const T accv = (MODE == ST_HALF || MODE == ST_FULL || MODE == ST_LAST)
+                               ? (LDS ? pa[c] : a.acc[c][idx]) : T(0);
             if (MODE == ST_FIRST) {
                 a.acc[c][idx] = z0[c] + (dt / T(6)) * kv[c];
                 a.out[c][idx] = z0[c] + (dt / T(2)) * kv[c];
             } else if (MODE == ST_HALF || MODE == ST_FULL) {
-                const T un = a.un[c][idx];
-                a.acc[c][idx] = a.acc[c][idx] + (dt / T(3)) * kv[c];
+                const T un = LDS ? pn[c] : a.un[c][idx];
+                a.acc[c][idx] = accv + (dt / T(3)) * kv[c];
                 a.out[c][idx] = un + (MODE == ST_HALF ? dt / T(2) : dt) * kv[c];
             } else if (MODE == ST_LAST) {
-                a.out[c][idx] = a.acc[c][idx] + (dt / T(6)) * kv[c];
+                a.out[c][idx] = accv + (dt / T(6)) * kv[c];
             } else {
                 a.out[c][idx] = kv[c];
+            }
+        }
+        if (LDS && k + 1 < k1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (MODE == ST_HALF || MODE == ST_FULL || MODE == ST_LAST) pa[c] = a.acc[c][idx + nxy];
+                if (MODE == ST_HALF || MODE == ST_FULL) pn[c] = a.un[c][idx + nxy];
             }
         }
 #pragma unroll
