@@ -165,15 +165,17 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     const long long nlines = (long long)P->ny * P->nz;
     {
         int nl = 1;
+        // (the LDS bounds count FP64 complex values in both precisions: the FP32
+        // form keeps the FP64 tile shapes, hence as many blocks)
         while (nl * 2 * Lo.px.tpl <= DNSLAB_XPASS_THREADS &&
-               ((size_t)nl * 2 * Lo.ls_x + 2 * Lo.m + 1) * csz <= DNSLAB_XPASS_LDS_KB * 1024 && nl < nlines)
+               ((size_t)nl * 2 * Lo.ls_x + 2 * Lo.m + 1) * 16 <= DNSLAB_XPASS_LDS_KB * 1024 && nl < nlines)
             nl *= 2;
         Lo.nl_x = ilog2(nl);
     }
     auto pick_tx = [&](int n, const AxisPlan& ap, size_t lds_cap) {
         int tx = 1;
         const int cap = std::min(64, pow2_floor(2LL * (Lo.m + 1) - 1));
-        while (tx * 2 <= cap && (size_t)tx * 2 * n * csz <= lds_cap && tx * 2 * ap.tpl <= 1024) tx *= 2;
+        while (tx * 2 <= cap && (size_t)tx * 2 * n * 16 <= lds_cap && tx * 2 * ap.tpl <= 1024) tx *= 2;
         return ilog2(tx);
     };
     Lo.lg_tx_y = pick_tx(P->ny, Lo.py, DNSLAB_COL_LDS_KB * 1024);
