@@ -56,6 +56,7 @@ def kernel_bytes(sc, esz=8):
         "fft_x_fwd": n * esz + spec,                  # r in, spectrum out
         "fft_y": 2 * spec,
         "fft_z": 2 * spec,
+        "fft_yz": 2 * spec,                           # fused y/z pass: one read, one write
         "fft_x_inv": spec + n * esz,
         "filter": n * (6 * esz + 1),                  # velocity: 3 fields in, 3 out
         "filter_c": n * (2 * esz + 1),                # CO2
@@ -66,12 +67,14 @@ def kernel_bytes(sc, esz=8):
     }
 
 
-def step_bytes(sc, esz=8, per_stage=False):
-    """Pass-model bytes of one whole step (launch counts of the step sequence)."""
+def step_bytes(sc, esz=8, per_stage=False, fused_yz=False):
+    """Pass-model bytes of one whole step (launch counts of the step sequence;
+    fused_yz: the y/z passes of a solve run as one fused pass)."""
     kb = kernel_bytes(sc, esz)
     it = sc.n_piter if (sc.beta == 0).any() else min(sc.n_piter, 1)
     y_passes = 2 if sc.ny > 1 else 0
-    poisson = kb["fft_x_fwd"] + y_passes * kb["fft_y"] + kb["fft_z"] + kb["fft_x_inv"]
+    yz = kb["fft_yz"] if fused_yz else y_passes * kb["fft_y"] + kb["fft_z"]
+    poisson = kb["fft_x_fwd"] + yz + kb["fft_x_inv"]
     ib = kb["ib_rhs"] if (sc.beta == 0).any() else 0
     projection = kb["div"] + it * (poisson + ib) + kb["correct"]
     if esz == 4 and it > 0:
@@ -191,6 +194,8 @@ def kernel_key(sym):
         return "filter" if targs.endswith("3") else "filter_c"
     if base == "fft_cols":
         return "fft_z" if targs.endswith("2") else "fft_y"
+    if base == "fft_yz":
+        return "fft_yz"
     if base in ("correct", "refine_correct"):
         return "correct"
     if base in ("div", "fft_x_fwd", "fft_x_inv", "ib_rhs", "refine_res"):
@@ -344,7 +349,7 @@ def main():
         except (OSError, ValueError):
             traffic = None
 
-    sbytes = step_bytes(sc, esz, args.per_stage)
+    sbytes = step_bytes(sc, esz, args.per_stage, fused_yz="fft_yz" in per)
     out = {
         "metric": "Gcell-steps/s (full step incl. FFT Poisson)",
         "value": value,

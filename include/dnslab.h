@@ -207,7 +207,7 @@ int dnslab_co2_histogram(dnslab_ctx* ctx, int32_t nbins, double lo, double hi, i
 int dnslab_accumulate(dnslab_ctx* ctx, double* sums_dev);
 
 /* Kernel timing for roofline measurements: when enabled, every launch of the
- * named kernel ("mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z",
+ * named kernel ("mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z", "fft_yz",
  * "fft_x_inv", "filter", "filter_c", "correct", "div", "ib_rhs", "advance",
  * "diag", "refine_res", "particles") is bracketed by HIP events on the stream it is
  * launched on, and the total and count accumulate (kernel_name NULL: off).

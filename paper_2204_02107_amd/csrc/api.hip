@@ -28,10 +28,10 @@ constexpr int RING_CAP = 4096;
 constexpr int PROF_POOL = 32768;
 
 enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_FILTC, K_CORR, K_DIV, K_IB,
-                K_ADV, K_DIAG, K_REF, K_PART, K_COUNT };
+                K_ADV, K_DIAG, K_REF, K_PART, K_FYZ, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {"mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z", "fft_x_inv",
                                             "filter", "filter_c", "correct", "div", "ib_rhs", "advance", "diag",
-                                            "refine_res", "particles"};
+                                            "refine_res", "particles", "fft_yz"};
 
 bool is_2a3b(int n) {
     if (n < 1) return false;
@@ -56,6 +56,7 @@ struct Layout {
     long long n;
     int m, sx;            // fft
     int nl_x, ls_x, lg_tx_y, lg_tx_z;
+    int yz, lg_ca, lg_cb;  // fused plane pass (plane-major spectrum) and its LDS chunks
     AxisPlan px, py, pz;
     StencilLaunch L;       // momentum and scalar stage kernels
     StencilLaunch L1;      // one-cell-per-thread kernels (correct, div, rate)
@@ -136,6 +137,18 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_XPASS_LDS_KB
 #define DNSLAB_XPASS_LDS_KB 48
 #endif
+#ifndef DNSLAB_YZ
+#define DNSLAB_YZ 1            // fused y/z pass when a (ky, kz) plane fits one block
+#endif
+#ifndef DNSLAB_YZ_LDS_KB
+#define DNSLAB_YZ_LDS_KB 160
+#endif
+#ifndef DNSLAB_YZ_MAX_PLANE
+#define DNSLAB_YZ_MAX_PLANE 4096   // largest ny * nz given to the fused pass
+#endif
+#ifndef DNSLAB_OVERLAP
+#define DNSLAB_OVERLAP 1       // run the scalar half of a step on a second stream
+#endif
 #ifndef DNSLAB_COL_LDS_KB
 #define DNSLAB_COL_LDS_KB 32
 #endif
@@ -184,6 +197,35 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     // pass, whose tiles are read with the larger row stride, is not)
     if ((1 << Lo.lg_tx_y) <= 4) Lo.lg_tx_y = pick_tx(P->ny, Lo.py, 2 * DNSLAB_COL_LDS_KB * 1024);
     Lo.lg_tx_z = pick_tx(P->nz, Lo.pz, DNSLAB_COL_LDS_KB * 1024);
+    // Fused plane pass: each of the nx/2 + 1 kx planes (ny * nz values) held
+    // by one block in registers, its y and z lines transformed in LDS chunks.
+    // It cuts two of the three column passes and their launches, but one
+    // block per plane serialises a plane's work on one CU: measured 10%
+    // faster steps for planes of 64 x 64, 3% slower for 96 x 64 and 8% for
+    // 128 x 96 (FP64), hence the plane-size limit.
+    {
+        const int nthr = yz_threads(P->ny);
+        const int q = Lo.esz == 8 ? YZ_Q64 : YZ_Q32;
+        if (DNSLAB_YZ && P->ny > 1 && P->nz > 1 && nthr > 0 && (long long)P->ny * P->nz <= DNSLAB_YZ_MAX_PLANE &&
+            (long long)q * nthr >= (long long)P->ny * P->nz &&
+            Lo.py.tpl <= nthr && Lo.pz.tpl <= nthr) {
+            const size_t cap = (size_t)DNSLAB_YZ_LDS_KB * 1024;
+            const size_t tw = (size_t)(P->ny + P->nz) * csz;
+            auto lines = [&](int n, int other, const AxisPlan& ap) {
+                int nl = 1;
+                while (nl * 2 <= other && (long long)nl * 2 * ap.tpl <= nthr &&
+                       tw + (size_t)n * (nl * 2 + 1) * csz <= cap)
+                    nl *= 2;
+                return tw + (size_t)n * (nl + 1) * csz <= cap ? nl : 0;
+            };
+            const int ca = lines(P->ny, P->nz, Lo.py), cb = lines(P->nz, P->ny, Lo.pz);
+            if (ca > 0 && cb > 0) {
+                Lo.yz = 1;
+                Lo.lg_ca = ilog2(ca);
+                Lo.lg_cb = ilog2(cb);
+            }
+        }
+    }
     Lo.L = stencil_launch(g, DNSLAB_ROWS, stencil_kc(g, DNSLAB_ROWS, DNSLAB_KC), 1);
     Lo.L1 = Lo.L;
     // the radius-3 filter re-reads 6 halo planes per z chunk: longer chunks
@@ -358,6 +400,7 @@ FFTArgs<T> fft_args(dnslab_ctx* x) {
     a.g = x->g;
     a.m = x->Lo.m;
     a.sx = x->Lo.sx;
+    a.ps = x->Lo.yz ? x->g.ny * x->g.nz : 0;
     a.spec = (C2<T>*)x->spec;
     a.px = x->Lo.px;
     a.py = x->Lo.py;
@@ -374,6 +417,8 @@ FFTArgs<T> fft_args(dnslab_ctx* x) {
     a.ls_x = x->Lo.ls_x;
     a.lg_tx_y = x->Lo.lg_tx_y;
     a.lg_tx_z = x->Lo.lg_tx_z;
+    a.lg_ca = x->Lo.lg_ca;
+    a.lg_cb = x->Lo.lg_cb;
     return a;
 }
 
@@ -382,9 +427,13 @@ template <typename T>
 int poisson_solve(dnslab_ctx* x, const T* r, T* pout) {
     const FFTArgs<T> a = fft_args<T>(x);
     LAUNCH(x, K_FXF, launch_fft_x_fwd<T>(a, r, x->cur, x->rec));
-    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, false, x->cur, x->rec));
-    LAUNCH(x, K_FZ, launch_fft_z_solve<T>(a, x->cur, x->rec));
-    if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, true, x->cur, x->rec));
+    if (x->Lo.yz) {
+        LAUNCH(x, K_FYZ, launch_fft_yz_solve<T>(a, x->cur, x->rec));
+    } else {
+        if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, false, x->cur, x->rec));
+        LAUNCH(x, K_FZ, launch_fft_z_solve<T>(a, x->cur, x->rec));
+        if (x->g.ny > 1) LAUNCH(x, K_FY, launch_fft_y<T>(a, true, x->cur, x->rec));
+    }
     LAUNCH(x, K_FXI, launch_fft_x_inv<T>(a, pout, x->cur, x->rec));
     return DNSLAB_OK;
 }
@@ -939,7 +988,7 @@ int dnslab_init(const dnslab_params* params, const uint8_t* beta_dev, int64_t n_
         x->P = *params;
         x->stream = (hipStream_t)params->stream;
         x->cur = x->stream;
-        x->overlap = true;
+        x->overlap = DNSLAB_OVERLAP != 0;
         x->g = make_grid(params);
         x->Lo = make_layout(params, (int)n_forced);
         x->u = u; x->v = v; x->w = w; x->p = p; x->c = c;

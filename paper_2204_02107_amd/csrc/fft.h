@@ -15,13 +15,17 @@ struct AxisPlan {
     int tpl;        // threads per line = n / rad[0] (1 if n == 1)
 };
 
-// Spectrum layout: complex, row (kx = 0..nx/2) stride sx elements, rows
-// ordered (ky, kz) with ky fastest: element (kx, ky, kz) at kx + sx*(ky + ny*kz).
+// Spectrum layouts (complex):
+//  - row-major (ps == 0): row (kx = 0..nx/2) stride sx elements, rows ordered
+//    (ky, kz) with ky fastest: element (kx, ky, kz) at kx + sx*(ky + ny*kz);
+//  - plane-major (ps > 0), used when a whole (ky, kz) plane fits one block:
+//    element (kx, ky, kz) at kx*ps + ky + ny*kz with ps = ny*nz.
 template <typename T>
 struct FFTArgs {
     Grid g;
     int m;              // nx/2 (complex length along x)
-    int sx;             // padded row stride of the spectrum
+    int sx;             // padded row stride of the spectrum (row-major)
+    int ps;             // plane stride (plane-major), 0 for row-major
     C2<T>* spec;
     AxisPlan px, py, pz;
     const C2<T>* wx;    // W_m^j, j < m
@@ -37,7 +41,17 @@ struct FFTArgs {
     int ls_x;           // LDS line stride (odd, >= m + 1)
     // y / z passes
     int lg_tx_y, lg_tx_z;
+    // fused plane pass: lines per LDS chunk of the y and the z transforms
+    int lg_ca, lg_cb;
 };
+
+// Fused plane pass: complex values held in registers per thread, and the
+// block size for ny (a multiple of ny, at most YZ_THREADS; two waves per SIMD
+// leave room for the plane and the butterflies in registers).
+constexpr int YZ_THREADS = 512;
+constexpr int YZ_Q64 = 24;
+constexpr int YZ_Q32 = 32;
+inline int yz_threads(int ny) { return ny > YZ_THREADS ? 0 : ny * (YZ_THREADS / ny); }
 
 // Cells next to a solid, where the immersed-boundary term div((1-beta) grad p)
 // can be nonzero (Section 2.2), with the solid face neighbours as bits
@@ -87,6 +101,10 @@ hipError_t launch_fft_y(const FFTArgs<T>& a, bool inverse, hipStream_t s, Record
 // z pass: forward, divide by lambda * ntot (zero on the null modes), inverse.
 template <typename T>
 hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec = nullptr);
+// Plane-major layout only: y forward, z solve and y inverse of each kx plane
+// in one block (one read and one write of the spectrum).
+template <typename T>
+hipError_t launch_fft_yz_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec = nullptr);
 // Inverse x pass: C2R along x into p.
 template <typename T>
 hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s, Recorder* rec = nullptr);

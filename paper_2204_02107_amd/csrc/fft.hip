@@ -13,7 +13,9 @@
 // there (mixed radix 8/4/2/3), so each pass touches HBM once for reading and
 // once for writing.  Strided y/z lines are loaded as tiles of TX consecutive
 // kx columns (TX complex values contiguous per row) to keep the accesses
-// coalesced.
+// coalesced.  Grids with small (ky, kz) planes instead store the spectrum
+// plane by plane and run y-forward, z-solve and y-inverse as one fused pass
+// with one block per kx plane.
 #include "fft.h"
 
 #include <algorithm>
@@ -261,6 +263,34 @@ __device__ __forceinline__ void fft_chain(C2<T>* s, const C2<T>* W, int es, int 
 
 // In-place transform of all lines held in LDS; specialised chains for the
 // common lengths, the runtime plan otherwise.
+// Inlined form for kernels that keep data in registers across the transform
+// (a call would spill them around it).
+template <typename T, bool INV>
+__device__ __forceinline__ void fft_lds_inl(C2<T>* s, const AxisPlan& ap, const C2<T>* W, int es, int ls, int lg_nl,
+                                            int tid, int nthr) {
+    switch (ap.n) {
+        case 1: return;
+        case 16: fft_chain<T, INV, 16, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 32: fft_chain<T, INV, 32, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 48: fft_chain<T, INV, 48, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 64: fft_chain<T, INV, 64, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 96: fft_chain<T, INV, 96, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        case 128: fft_chain<T, INV, 128, 0>(s, W, es, ls, lg_nl, tid, nthr); return;
+        default: {
+            int ns = 1;
+            for (int p = 0; p < ap.npass; ++p) {
+                const int R = ap.rad[p];
+                if (R == 8) stockham_pass<T, 8, 1, INV>(s, ap.n, ns, W, es, ls, lg_nl, tid, nthr);
+                else if (R == 4) stockham_pass<T, 4, 2, INV>(s, ap.n, ns, W, es, ls, lg_nl, tid, nthr);
+                else if (R == 2) stockham_pass<T, 2, 4, INV>(s, ap.n, ns, W, es, ls, lg_nl, tid, nthr);
+                else stockham_pass<T, 3, 3, INV>(s, ap.n, ns, W, es, ls, lg_nl, tid, nthr);
+                ns *= R;
+            }
+            return;
+        }
+    }
+}
+
 template <typename T, bool INV>
 __device__ void fft_lds(C2<T>* s, const AxisPlan& ap, const C2<T>* W, int es, int ls, int lg_nl, int tid, int nthr) {
     switch (ap.n) {
@@ -399,17 +429,22 @@ __device__ __forceinline__ void fft_x_fwd_body(const FxfArgs<T>& A, unsigned blk
     __syncthreads();
     fft_lds<T, false>(s, a.px, wl, 1, ls, lg, tid, nthr);
     const int half = m / 2 + 1;
+    // row-major: consecutive threads take consecutive kx of a line; plane-major:
+    // consecutive lines of one kx (contiguous there)
+    const bool pm = a.ps > 0;
+    const size_t ks = pm ? (size_t)a.ps : 1, lstr = pm ? 1 : (size_t)a.sx;
     for (int e = tid; e < (half << lg); e += nthr) {
-        const int l = e / half;
-        const int k = e - l * half;
+        int l, k;
+        if (pm) { l = e & ((1 << lg) - 1); k = e >> lg; }
+        else { l = e / half; k = e - l * half; }
         const int L = line0 + l;
         if (L >= nlines) continue;
         const C2<T>* zl = s + l * ls;
-        C2<T>* out = a.spec + (size_t)L * a.sx;
+        C2<T>* out = a.spec + (size_t)L * lstr;
         const C2<T> za = zl[k];
         const C2<T> zb = zl[k == 0 ? 0 : m - k];
-        out[k] = r2c_post(za, zb, tl[k]);
-        if (m - k != k) out[m - k] = r2c_post(zb, za, tl[m - k]);
+        out[k * ks] = r2c_post(za, zb, tl[k]);
+        if (m - k != k) out[(m - k) * ks] = r2c_post(zb, za, tl[m - k]);
     }
 }
 
@@ -431,24 +466,35 @@ __device__ __forceinline__ void fft_x_inv_body(const FxiArgs<T>& A, unsigned blk
     for (int j = tid; j <= m; j += nthr) tl[j] = a.tw[j];
     {
         const int tot = m1 << lg;
+        // element e -> (line l, kx k): kx fastest for the row-major spectrum,
+        // line fastest for the plane-major one (contiguous in either)
+        const bool pm = a.ps > 0;
+        const size_t ks = pm ? (size_t)a.ps : 1, lstr = pm ? 1 : (size_t)a.sx;
+        auto split = [&](int e, int& l, int& k) {
+            if (pm) { l = e & ((1 << lg) - 1); k = e >> lg; }
+            else { l = e / m1; k = e - l * m1; }
+        };
         C2<T> buf[STAGE_MAX];
 #pragma unroll
         for (int q = 0; q < STAGE_MAX; ++q) {
             const int e = tid + q * nthr;
-            const int l = e / m1, k = e - l * m1;
+            int l, k;
+            split(e, l, k);
             buf[q] = C2<T>{T(0), T(0)};
-            if (e < tot && line0 + l < nlines) buf[q] = a.spec[(size_t)(line0 + l) * a.sx + k];
+            if (e < tot && line0 + l < nlines) buf[q] = a.spec[(size_t)(line0 + l) * lstr + k * ks];
         }
 #pragma unroll
         for (int q = 0; q < STAGE_MAX; ++q) {
             const int e = tid + q * nthr;
-            const int l = e / m1, k = e - l * m1;
+            int l, k;
+            split(e, l, k);
             if (e < tot) s[l * ls + k] = buf[q];
         }
         // elements beyond STAGE_MAX per thread (only when nthr * STAGE_MAX < tot)
         for (int e = tid + STAGE_MAX * nthr; e < tot; e += nthr) {
-            const int l = e / m1, k = e - l * m1;
-            s[l * ls + k] = line0 + l < nlines ? a.spec[(size_t)(line0 + l) * a.sx + k] : C2<T>{T(0), T(0)};
+            int l, k;
+            split(e, l, k);
+            s[l * ls + k] = line0 + l < nlines ? a.spec[(size_t)(line0 + l) * lstr + k * ks] : C2<T>{T(0), T(0)};
         }
     }
     __syncthreads();
@@ -572,6 +618,99 @@ __device__ __forceinline__ void fft_cols_body(const FFTArgs<T>& a, unsigned blk)
 }
 
 
+// Fused plane pass (plane-major spectrum): block kx holds the whole (ky, kz)
+// plane of that kx in registers, Q values per thread.  The block size is a
+// multiple of ny, so thread t keeps one y = t mod ny and the z values
+// t / ny + q * (nthr / ny).  The y transforms run on chunks of z lines
+// and the z transforms on chunks of y lines staged through LDS (line-
+// interleaved, padded row stride against bank conflicts); the spectral divide
+// happens between the forward and inverse z transforms of a chunk.  One read
+// and one write of the spectrum replace three passes.
+template <typename T, int Q, bool INV>
+__device__ __forceinline__ void yz_y_phase(const FFTArgs<T>& a, C2<T> (&v)[Q], C2<T>* d, const C2<T>* wyl, int yt,
+                                           int zt, int zs, int tid, int nthr) {
+    const int nz = a.g.nz;
+    for (int z0 = 0; z0 < nz;) {
+        const int lg = min(a.lg_ca, 31 - __clz(nz - z0));
+        const int nl = 1 << lg, es = nl + 1;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const unsigned zl = (unsigned)(zt + q * zs - z0);
+            if (zl < (unsigned)nl) d[yt * es + zl] = v[q];
+        }
+        __syncthreads();
+        fft_lds_inl<T, INV>(d, a.py, wyl, es, 1, lg, tid, nthr);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const unsigned zl = (unsigned)(zt + q * zs - z0);
+            if (zl < (unsigned)nl) v[q] = d[yt * es + zl];
+        }
+        __syncthreads();
+        z0 += nl;
+    }
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ void fft_yz_body(const FFTArgs<T>& a, unsigned blk) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<T>* s = reinterpret_cast<C2<T>*>(smem_raw);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int ny = a.g.ny, nz = a.g.nz;
+    const int kx = (int)blk;
+    C2<T>* __restrict__ plane = a.spec + (size_t)kx * a.ps;
+    const int yt = tid % ny, zt = tid / ny, zs = nthr / ny;
+    C2<T>* wyl = s;
+    C2<T>* wzl = s + ny;
+    C2<T>* d = wzl + nz;
+    for (int j = tid; j < ny; j += nthr) wyl[j] = a.wy[j];
+    for (int j = tid; j < nz; j += nthr) wzl[j] = a.wz[j];
+    C2<T> v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int z = zt + q * zs;
+        v[q] = z < nz ? plane[yt + ny * z] : C2<T>{T(0), T(0)};
+    }
+    // (the twiddle tables are visible after the first barrier of the y phase)
+    yz_y_phase<T, Q, false>(a, v, d, wyl, yt, zt, zs, tid, nthr);
+    for (int y0 = 0; y0 < ny;) {
+        const int lg = min(a.lg_cb, 31 - __clz(ny - y0));
+        const int nl = 1 << lg, es = nl + 1;
+        const unsigned yl = (unsigned)(yt - y0);
+        if (yl < (unsigned)nl) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int z = zt + q * zs;
+                if (z < nz) d[z * es + yl] = v[q];
+            }
+        }
+        __syncthreads();
+        fft_lds_inl<T, false>(d, a.pz, wzl, es, 1, lg, tid, nthr);
+        for (int e = tid; e < (nz << lg); e += nthr) {
+            const int kz = e >> lg, c = e & (nl - 1);
+            const double lam = (a.sz2[kz] + a.sy2[y0 + c]) + a.sx2[kx];   // -lambda
+            const T f = lam == 0.0 ? T(0) : T(-a.inv_ntot * recip(lam));
+            d[kz * es + c] = cscale(d[kz * es + c], f);
+        }
+        __syncthreads();
+        fft_lds_inl<T, true>(d, a.pz, wzl, es, 1, lg, tid, nthr);
+        if (yl < (unsigned)nl) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int z = zt + q * zs;
+                if (z < nz) v[q] = d[z * es + yl];
+            }
+        }
+        __syncthreads();
+        y0 += nl;
+    }
+    yz_y_phase<T, Q, true>(a, v, d, wyl, yt, zt, zs, tid, nthr);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int z = zt + q * zs;
+        if (z < nz) plane[yt + ny * z] = v[q];
+    }
+}
+
 // Plain and batched launch wrappers (see stencil.hip).
 #define DNSLAB_BATCH_BLOCK(st, ns)         \
     const int s_ = batch_slot(st, ns);     \
@@ -612,6 +751,18 @@ __global__ __launch_bounds__(1024) void k_fft_cols_b(const BRec<FFTArgs<T>>* __r
     DNSLAB_BATCH_BLOCK(st, ns)
     const FFTArgs<T> a = tab[s_].a;
     fft_cols_body<T, MODE>(a, blk_);
+}
+
+template <typename T>
+__global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const FFTArgs<T> a) {
+    fft_yz_body<T, sizeof(T) == 8 ? YZ_Q64 : YZ_Q32>(a, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(YZ_THREADS) void k_fft_yz_b(const BRec<FFTArgs<T>>* __restrict__ tab,
+                                                   const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_BLOCK(st, ns)
+    const FFTArgs<T> a = tab[s_].a;
+    fft_yz_body<T, sizeof(T) == 8 ? YZ_Q64 : YZ_Q32>(a, blk_);
 }
 
 inline int round64(int t) { return ((t + 63) / 64) * 64; }
@@ -728,6 +879,25 @@ hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec)
     return launch_cols<T>(a, 2, s, rec);
 }
 
+template <typename T>
+hipError_t launch_fft_yz_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec) {
+    const int nthr = yz_threads(a.g.ny);
+    const int q = sizeof(T) == 8 ? YZ_Q64 : YZ_Q32;
+    if (a.ps != a.g.ny * a.g.nz || nthr <= 0 || (long long)q * nthr < (long long)a.g.ny * a.g.nz ||
+        ((long long)a.py.tpl << a.lg_ca) > nthr || ((long long)a.pz.tpl << a.lg_cb) > nthr)
+        return hipErrorInvalidValue;
+    const dim3 grid(a.m + 1), block(nthr);
+    const size_t lds = ((size_t)a.g.ny + a.g.nz +
+                        std::max((size_t)a.g.ny * ((1 << a.lg_ca) + 1), (size_t)a.g.nz * ((1 << a.lg_cb) + 1))) *
+                       sizeof(C2<T>);
+    if (rec) {
+        record_launch(rec, kind_code(KK_COLS, 3, sizeof(T) == 4), grid, block, lds, a);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL((k_fft_yz<T>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
 namespace {
 template <typename T>
 hipError_t fft_batched_typed(int base, int mode, const void* tab, const unsigned* st, int ns, unsigned nb, dim3 blk,
@@ -747,7 +917,8 @@ hipError_t fft_batched_typed(int base, int mode, const void* tab, const unsigned
             auto t = (const BRec<FFTArgs<T>>*)tab;
             if (mode == 0) hipLaunchKernelGGL((k_fft_cols_b<T, 0>), grid, blk, lds, s, t, st, ns);
             else if (mode == 1) hipLaunchKernelGGL((k_fft_cols_b<T, 1>), grid, blk, lds, s, t, st, ns);
-            else hipLaunchKernelGGL((k_fft_cols_b<T, 2>), grid, blk, lds, s, t, st, ns);
+            else if (mode == 2) hipLaunchKernelGGL((k_fft_cols_b<T, 2>), grid, blk, lds, s, t, st, ns);
+            else hipLaunchKernelGGL((k_fft_yz_b<T>), grid, blk, lds, s, t, st, ns);
             break;
         }
         default:
@@ -770,7 +941,8 @@ hipError_t launch_batched_fft(int kind, const void* tab, const unsigned* st, int
                                          Recorder*);                                                    \
     template hipError_t launch_fft_x_inv<T>(const FFTArgs<T>&, T*, hipStream_t, Recorder*);              \
     template hipError_t launch_fft_y<T>(const FFTArgs<T>&, bool, hipStream_t, Recorder*);                \
-    template hipError_t launch_fft_z_solve<T>(const FFTArgs<T>&, hipStream_t, Recorder*);
+    template hipError_t launch_fft_z_solve<T>(const FFTArgs<T>&, hipStream_t, Recorder*);                \
+    template hipError_t launch_fft_yz_solve<T>(const FFTArgs<T>&, hipStream_t, Recorder*);
 DNSLAB_INST(double)
 DNSLAB_INST(float)
 #undef DNSLAB_INST

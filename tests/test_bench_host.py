@@ -19,6 +19,7 @@ def test_kernel_key_mapping():
     assert k("void dnslab::(anonymous namespace)::k_filter<double, 1>(dnslab::FiltArgs<double>)") == "filter_c"
     assert k("void dnslab::(anonymous namespace)::k_fft_cols<double, 2>(dnslab::FFTArgs<double>)") == "fft_z"
     assert k("void dnslab::(anonymous namespace)::k_fft_cols<float, 1>(dnslab::FFTArgs<float>)") == "fft_y"
+    assert k("void dnslab::(anonymous namespace)::k_fft_yz<double>(dnslab::FFTArgs<double>)") == "fft_yz"
     assert k("dnslab::(anonymous namespace)::k_refine_correct(dnslab::RefineCorrArgs)") == "correct"
     assert k("dnslab::(anonymous namespace)::k_advance(dnslab::AdvanceArgs)") is None
     assert k("__amd_rocclr_copyBuffer") is None
@@ -65,5 +66,8 @@ def test_step_byte_model():
     ib = bench.near_solid_cells(sc) * (4 + 1 + 24) / n
     expect = 4 * 97 + 4 * 57 + 32 + 57 + 49 + 17 + 4 * (solve + ib)
     assert abs(per - expect) < 1e-9, (per, expect)
+    # the fused y/z pass reads and writes the spectrum once instead of three times
+    fused = bench.step_bytes(sc, 8, fused_yz=True) / n
+    assert abs(per - fused - 4 * (2 * 2 * 8.25)) < 1e-9
     assert bench.step_bytes(sc, 8, per_stage=True) > 2 * bench.step_bytes(sc, 8)
     assert bench.step_bytes(sc, 4) < 0.6 * bench.step_bytes(sc, 8)
