@@ -348,6 +348,89 @@ def channel2d(ny_fluid=16, nx=8, wall=2, nu=0.01, bx=1e-3, dt=0.01) -> Scenario:
         w=z.copy(), p=z.copy(), c=z.copy(), meta={"kind": "channel", "wall": wall})
 
 
+def _fft_size_at_least(n: int) -> int:
+    """Smallest 2^a 3^b >= n (the FFT lengths the solver accepts)."""
+    m = max(1, int(n))
+    while True:
+        r = m
+        for f in (2, 3):
+            while r % f == 0:
+                r //= f
+        if r == 1:
+            return m
+        m += 1
+
+
+def cube_channel(n_h=30, re_ob=84.0, u_max=1.5, cfl=0.3, filter=True, n_piter=4,
+                 perturb=0.01, seed=2204) -> Scenario:
+    """Square obstacle in a 2D channel with a forced parabolic inflow
+    (Section 3.1.1, Tables 1 and 2): channel width D = 2 pi between solid
+    walls, obstacle edge h = D/6 resolved by n_h cells, obstacle centred at
+    (1.2 D, D/2) downstream of the inflow, Re_ob = U_b h / nu with the bulk
+    velocity U_b = 2/3 U_max.
+
+    Grid (nz = 1, dx = dy = h/n_h): ny = 6 n_h fluid cells plus two equal
+    solid wall slabs of at least 2 cells (the paper's 0.05 D walls, thinner
+    here: a solid slab's thickness does not enter the flow), nx about 8.8 D;
+    both are FFT lengths 2^a 3^b.  The inflow is the source term of Section 2.1
+    across the whole channel in a band of width h centred on the periodic seam
+    x = 0, with u_set the parabola U_max 4 y (D' - y) / D'^2, where y is
+    measured from the centre of the last wall cell and D' = (6 n_h + 1) dx
+    (where the masked central-difference operators put the no-slip wall).
+    Initial state: the same parabola in every fluid cell plus a small seeded
+    cross-stream perturbation that breaks the symmetry; c = 0."""
+    D = 2.0 * np.pi
+    h = D / 6.0
+    d = h / n_h
+    nf = 6 * n_h
+    ny = _fft_size_at_least(nf + 4)
+    while (ny - nf) % 2:
+        ny = _fft_size_at_least(ny + 1)
+    wall = (ny - nf) // 2
+    target = 8.8 * nf
+    lo = _fft_size_at_least(int(np.floor(target * 0.9)))
+    cands = [lo]
+    while cands[-1] < 1.1 * target:
+        cands.append(_fft_size_at_least(cands[-1] + 1))
+    nx = min(cands, key=lambda n: abs(n - target))
+    shape = (1, ny, nx)
+    u_b = 2.0 * u_max / 3.0
+    nu = u_b * h / re_ob
+    beta = np.ones(shape, np.uint8)
+    beta[:, :wall, :] = 0
+    beta[:, wall + nf:, :] = 0
+    xc = 1.2 * nf                      # obstacle centre, in cells from the seam
+    i0, i1 = int(np.rint(xc - n_h / 2)), int(np.rint(xc + n_h / 2))
+    j0, j1 = wall + (nf - n_h) // 2, wall + (nf - n_h) // 2 + n_h
+    beta[:, j0:j1, i0:i1] = 0
+    # parabolic profile from the centre of the last wall cell
+    y = (np.arange(ny) - wall + 1) * d
+    dp = (nf + 1) * d
+    prof = np.where((np.arange(ny) >= wall) & (np.arange(ny) < wall + nf), u_max * 4.0 * y * (dp - y) / dp ** 2, 0.0)
+    fx = tanh_factor(periodic_distance(np.arange(nx) * d, 0.0, nx * d), h / 2, TANH_B)
+    S = np.broadcast_to(fx[None, None, :], shape)
+    sel = np.flatnonzero((S.ravel() > 1e-6) & (beta.ravel() == 1))
+    jj = (sel // nx) % ny
+    uset = np.zeros((sel.size, 3))
+    uset[:, 0] = prof[jj]
+    rng = np.random.default_rng(seed)
+    b = beta.astype(np.float64)
+    u = prof[None, :, None] * b
+    x = np.arange(nx) * d
+    v = perturb * u_max * np.sin(2 * np.pi * x / (nx * d))[None, None, :] * rng.uniform(0.5, 1.5) * b
+    v = np.broadcast_to(v, shape).copy()
+    z = np.zeros(shape)
+    return Scenario(
+        name=f"cube_channel{n_h}", nx=nx, ny=ny, nz=1, lx=nx * d, ly=ny * d, lz=d,
+        nu=nu, alpha_c=nu, tau_f=2.0 * cfl * d / u_max, body=(0.0, 0.0, 0.0), cfl=cfl,
+        dt_fixed=0.0, u_ref=u_max, n_piter=n_piter, filter=filter, beta=beta,
+        forced_idx=sel.astype(np.int64), forced_S=S.ravel()[sel].astype(np.float64),
+        forced_uset=uset, forced_cset=np.zeros(sel.size), room_mask=None,
+        u=u, v=v, w=z.copy(), p=z.copy(), c=z.copy(),
+        meta={"kind": "cube_channel", "n_h": n_h, "h": h, "D": D, "u_b": u_b, "u_max": u_max,
+              "wall": wall, "obstacle_cells": (i0, i1, j0, j1, 0, 1)})
+
+
 def random_fields(shape, seed, scale=1.0, beta=None):
     """Smooth-ish random periodic fields (u, v, w, p, c) for operator tests."""
     rng = np.random.default_rng(seed)

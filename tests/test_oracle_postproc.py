@@ -71,3 +71,67 @@ def test_histogram_brute_force():
                     b = int(np.floor((c[k, j, i] - lo) / (hi - lo) * nb))
                     want[min(max(b, 0), nb - 1)] += 1
     assert np.array_equal(PP.co2_histogram(c, beta, room, nb, lo, hi), want)
+
+
+def _block_case(nx=20, ny=16, nz=1, box=(6, 11, 5, 9, 0, 1), d=(0.1, 0.2, 0.3)):
+    beta = np.ones((nz, ny, nx), np.uint8)
+    i0, i1, j0, j1, k0, k1 = box
+    beta[k0:k1, j0:j1, i0:i1] = 0
+    return beta
+
+
+def test_body_force_linear_pressure_closed_form():
+    """Kinematic pressure G x (p = G x dt): the force on the obstacle is
+    minus G times its volume (the buoyancy law), whatever the box around it;
+    no y force, no viscous force at rest."""
+    d = (0.1, 0.2, 0.3)
+    box = (6, 11, 5, 9, 0, 1)
+    beta = _block_case(box=box, d=d)
+    nz, ny, nx = beta.shape
+    G, dt = 2.5, 0.04
+    x = np.arange(nx) * d[0]
+    p = np.broadcast_to(G * dt * x[None, None, :], beta.shape).copy()
+    z = np.zeros(beta.shape)
+    fp, fv = PP.body_force(p, z, z, z, beta, (5, 12, 4, 10, 0, 1), d, nu=0.7, dt=dt)
+    i0, i1, j0, j1, _, _ = box
+    expect = -G * (i1 - i0) * d[0] * (j1 - j0) * d[1] * d[2]
+    assert abs(fp[0] - expect) < 1e-12 * abs(expect)
+    fp2, _ = PP.body_force(p, z, z, z, beta, box, d, nu=0.7, dt=dt)
+    assert abs(fp2[0] - expect) < 1e-12 * abs(expect)
+    assert abs(fp[1]) < 1e-12 and fp[2] == 0.0 and np.all(fv == 0.0)
+    # uniform pressure: a closed body feels nothing
+    fp0, _ = PP.body_force(np.full(beta.shape, 3.0), z, z, z, beta, (5, 12, 4, 10, 0, 1), d, nu=0.7, dt=dt)
+    assert np.all(np.abs(fp0) < 1e-12)
+
+
+def test_body_force_uniform_stream_closed_form():
+    """u = U everywhere in the fluid, p = 0: the viscous force is nu U times
+    the sum over the faces of area / spacing: 2 (j1 - j0) dy dz / dx over the
+    x faces and 2 (i1 - i0) dx dz / dy over the y faces (nz = 1: the z
+    neighbours are the cell itself, solid); a box that also holds fluid cells
+    and misses none of the obstacle gives the same."""
+    d = (0.1, 0.2, 0.3)
+    box = (6, 11, 5, 9, 0, 1)
+    beta = _block_case(box=box, d=d)
+    U, nu = 1.7, 0.05
+    u = U * beta.astype(np.float64)
+    z = np.zeros(beta.shape)
+    i0, i1, j0, j1, _, _ = box
+    expect = nu * U * (2 * (j1 - j0) * d[1] * d[2] / d[0] + 2 * (i1 - i0) * d[0] * d[2] / d[1])
+    for b in (box, (0, 20, 0, 16, 0, 1)):
+        fp, fv = PP.body_force(z, u, z, z, beta, b, d, nu=nu, dt=0.1)
+        assert abs(fv[0] - expect) < 1e-12 * expect
+        assert fv[1] == 0.0 and fv[2] == 0.0 and np.all(fp == 0.0)
+
+
+def test_shedding_frequency_of_sinusoids():
+    """Known frequency recovered from irregularly spaced samples, with an
+    offset and a second harmonic (upward crossings of the mean stay one per
+    period when the harmonic is small)."""
+    rng = np.random.default_rng(3)
+    for f in (0.21, 1.0, 3.7):
+        t = np.cumsum(rng.uniform(0.5, 1.5, 20000)) * (0.002 / f)
+        y = 4.0 + np.sin(2 * np.pi * f * t + 0.3) + 0.2 * np.sin(4 * np.pi * f * t)
+        est = PP.shedding_frequency(t, y)
+        assert abs(est / f - 1) < 1e-4, (f, est)
+    assert PP.shedding_frequency(np.arange(10.0), np.ones(10)) == 0.0
