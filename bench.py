@@ -179,6 +179,56 @@ def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7, log=None):
     return out
 
 
+# Obstacle in the channel (Section 3.1.1, Table 2): the paper's St and C_D
+# per obstacle resolution.
+CUBE_PAPER = {30: {"St": 0.2097, "C_D": 3.12}, 60: {"St": 0.2094, "C_D": 3.05}}
+
+
+def cube_bench(n_h, t_end, every=20, precision="fp64", chunk=512):
+    """Run the obstacle-in-channel case to t_end (units of h / U_b), sampling
+    the obstacle force every ``every`` steps on the device, and report the
+    step throughput with the drag coefficient and Strouhal number over the
+    second half of the run."""
+    import torch
+    import scenarios
+    import paper_2204_02107_amd as m
+    from paper_2204_02107_amd import postproc
+    sc = scenarios.cube_channel(n_h)
+    h, u_b = sc.meta["h"], sc.meta["u_b"]
+    prec = m.FP64 if precision == "fp64" else m.FP32_REFINE
+    S = m.Solver(sc, precision=prec)
+    i0, i1, j0, j1, _, _ = sc.meta["obstacle_cells"]
+    box = (i0 - 1, i1 + 1, j0 - 1, j1 + 1, 0, 1)
+    buf = torch.zeros((chunk, 8), dtype=torch.float64, device=S.device)
+    recs = []
+    steps = 0
+    t_stop = t_end * h / u_b
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        for r in range(chunk):
+            S.step(every, diag=False)
+            S.body_force(box, buf, r)
+        steps += every * chunk
+        part = buf.cpu().numpy()
+        recs.append(part)
+        t_sim = part[-1, 6]
+        print(f"[cube] n_h={n_h} steps={steps} t={t_sim * u_b / h:.1f} h/U_b "
+              f"F=({part[-1, 0] + part[-1, 3]:.4e}, {part[-1, 1] + part[-1, 4]:.4e}) "
+              f"wall={time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        if not np.isfinite(part).all() or t_sim >= t_stop:
+            break
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    S.close()
+    rec = np.concatenate(recs)
+    coef = postproc.obstacle_coefficients(rec, h, u_b, sc.lz)
+    return {"workload": f"obstacle in channel, {n_h} cells per edge, {sc.nx}x{sc.ny}, Re_ob 84", "cells": sc.ncells,
+            "precision": precision, "steps": steps, "t_end_h_over_Ub": float(rec[-1, 6] * u_b / h),
+            "wall_s": el, "Gcell_steps_s": sc.ncells * steps / el / 1e9, **coef,
+            "paper_DNSLABIB": CUBE_PAPER.get(n_h)}
+
+
 # Kernel symbol (as rocprofv3 prints it) -> name in kernel_bytes.
 def kernel_key(sym):
     import re
@@ -266,6 +316,9 @@ def main():
                     help="the per-stage projection variant (a projection after every RK4 stage)")
     ap.add_argument("--serving", default="short", choices=["none", "short", "full"],
                     help="serving stream: short = 16 requests x 300 steps, full = 64 x 2000")
+    ap.add_argument("--cube", type=int, nargs="*", metavar="N_H",
+                    help="only run the obstacle-in-channel validation at these resolutions (cells per obstacle edge)")
+    ap.add_argument("--cube-t-end", type=float, default=300.0, help="simulated time in units of h / U_b")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain 1 GiB device copy used to calibrate the PMC byte counters")
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -288,6 +341,10 @@ def main():
         return
     if args.copy_probe:
         copy_probe()
+        return
+    if args.cube is not None:
+        for n_h in args.cube or [30]:
+            print(json.dumps(cube_bench(n_h, args.cube_t_end, precision=args.precision)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the step runs on a single MI355X and this build has "

@@ -206,6 +206,24 @@ int dnslab_co2_histogram(dnslab_ctx* ctx, int32_t nbins, double lo, double hi, i
  * field-major u, v, w, p, c) += the bound fields.  Asynchronous. */
 int dnslab_accumulate(dnslab_ctx* ctx, double* sums_dev);
 
+/* Force of the fluid on an obstacle (Section 3.1.1, Table 2: drag
+ * coefficient and Strouhal number of the obstacle in the channel), per unit
+ * density.  The obstacle is the set of solid cells (beta = 0) inside the index
+ * box i0 <= i < i1, j0 <= j < j1, k0 <= k < k1 (box = {i0, i1, j0, j1, k0,
+ * k1}, each range non-empty and inside the grid, else DNSLAB_EINVAL).
+ * Pressure part: -dV sum over the obstacle cells of the central gradient of
+ * P = p / dt (the bound p holds dt times the kinematic pressure, the
+ * correction being u = u* - grad p): the obstacle's share of the momentum the
+ * pressure gradient takes from the fluid, equal to face pressures averaged
+ * over the two cells of each face.  Viscous part: every face between an
+ * obstacle cell and a fluid cell adds nu u_f A / dx_a (A the face area), the
+ * flux of the masked second difference into the solid cell.  out_dev (device,
+ * 8 doubles, caller-owned) receives Fp_x, Fp_y, Fp_z, Fv_x, Fv_y, Fv_z, then
+ * the simulated time t and the dt of the last step.  Asynchronous on the
+ * stream; one block walks the box, so the sum is reproducible bit for bit and
+ * the call suits obstacle-sized boxes. */
+int dnslab_body_force(dnslab_ctx* ctx, const int32_t box[6], double* out_dev);
+
 /* Kernel timing for roofline measurements: when enabled, every launch of the
  * named kernel ("mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z", "fft_yz",
  * "fft_x_inv", "filter", "filter_c", "correct", "div", "ib_rhs", "advance",

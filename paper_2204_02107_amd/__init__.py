@@ -203,6 +203,18 @@ class Solver:
             raise ValueError("sums must be a contiguous float64 tensor of shape (5, nz, ny, nx)")
         self._call(self.lib.dnslab_accumulate, self.ctx, _ptr(sums))
 
+    def body_force(self, box, out, row=0):
+        """Force on the solid cells of box = (i0, i1, j0, j1, k0, k1) into
+        out[row] (FP64 device tensor of shape (rows, 8): pressure force,
+        viscous force, t, dt), asynchronously, so that a run can sample it
+        every few steps without a host round trip."""
+        if out.dtype != _torch().float64 or not out.is_contiguous() or out.dim() != 2 or out.shape[1] != 8:
+            raise ValueError("out must be a contiguous float64 tensor of shape (rows, 8)")
+        if not 0 <= row < out.shape[0]:
+            raise IndexError("row out of range")
+        b = (ctypes.c_int32 * 6)(*[int(q) for q in box])
+        self._call(self.lib.dnslab_body_force, self.ctx, b, ctypes.c_void_p(out.data_ptr() + 64 * int(row)))
+
     # -- kernel timing -------------------------------------------------------
     def profile(self, kernel: Optional[str]):
         self._check(self.lib.dnslab_profile_enable(self.ctx, kernel.encode() if kernel else None))

@@ -1301,6 +1301,39 @@ int dnslab_accumulate(dnslab_ctx* x, double* sums_dev) {
     return DNSLAB_OK;
 }
 
+int dnslab_body_force(dnslab_ctx* x, const int32_t box[6], double* out_dev) {
+    if (int rc = check_ctx(x)) return rc;
+    if (!box || !out_dev) return fail(x, DNSLAB_EINVAL, "NULL pointer");
+    const int nn[3] = {x->g.nx, x->g.ny, x->g.nz};
+    for (int a = 0; a < 3; ++a)
+        if (box[2 * a] < 0 || box[2 * a] >= box[2 * a + 1] || box[2 * a + 1] > nn[a])
+            return fail(x, DNSLAB_EINVAL, "box outside the grid or empty");
+    hipError_t e;
+    auto fill = [&](auto& a) {
+        for (int q = 0; q < 6; ++q) a.box[q] = box[q];
+        a.flags = x->flags;
+        a.g = x->g;
+        a.nu = x->P.nu;
+        a.sc = x->sc;
+        a.out = out_dev;
+    };
+    if (x->Lo.esz == 8) {
+        ForceArgs<double> a;
+        a.vel[0] = (const double*)x->u; a.vel[1] = (const double*)x->v; a.vel[2] = (const double*)x->w;
+        a.p = (const double*)x->p;
+        fill(a);
+        e = launch_body_force<double>(a, x->stream);
+    } else {
+        ForceArgs<float> a;
+        a.vel[0] = (const float*)x->u; a.vel[1] = (const float*)x->v; a.vel[2] = (const float*)x->w;
+        a.p = (const float*)x->p;
+        fill(a);
+        e = launch_body_force<float>(a, x->stream);
+    }
+    if (e != hipSuccess) return fail(x, DNSLAB_EHIP, std::string("body force: ") + hipGetErrorString(e));
+    return DNSLAB_OK;
+}
+
 int dnslab_set_graph_steps(dnslab_ctx* x, int32_t k) {
     if (int rc = check_ctx(x)) return rc;
     if (k < 0 || k > 4096) return fail(x, DNSLAB_EINVAL, "graph steps out of range");

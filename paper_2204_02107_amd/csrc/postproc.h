@@ -25,8 +25,24 @@ struct AccArgs {
     long long n;
 };
 
+// Force of the fluid on the solid cells inside an index box (pressure and
+// viscous parts, per unit density), and the step's time, into out[0..7].
+template <typename T>
+struct ForceArgs {
+    const T* vel[3];
+    const T* p;
+    const uint8_t* flags;
+    Grid g;
+    int box[6];                   // i0, i1, j0, j1, k0, k1
+    double nu;
+    const StepScalars* sc;        // t and the dt p belongs to
+    double* out;                  // Fp (3), Fv (3), t, dt
+};
+
 template <typename T>
 hipError_t launch_histogram(const HistArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_body_force(const ForceArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_accumulate(const AccArgs<T>& a, hipStream_t s);
 

@@ -1,8 +1,8 @@
-"""Host side of the post-processing of Sections 3.3-3.4.
+"""Host side of the post-processing of Sections 3.1.1 and 3.3-3.4.
 
-The heavy parts run on the device (``Solver.co2_histogram``,
-``Solver.accumulate``); these functions turn their results and the per-step
-diagnostics into the quantities the paper reports.
+The heavy parts run on the device (``Solver.body_force``,
+``Solver.co2_histogram``, ``Solver.accumulate``); these functions turn their
+results and the per-step diagnostics into the quantities the paper reports.
 """
 from __future__ import annotations
 
@@ -38,3 +38,35 @@ def infection_risk(quanta_per_m3: float, breathing_m3_per_h: float, ach_per_h: f
     else:
         dose = quanta_per_m3 * breathing_m3_per_h * (-math.expm1(-ach_per_h * hours)) / ach_per_h
     return -math.expm1(-dose)
+
+
+def shedding_frequency(t, signal) -> float:
+    """Frequency of a periodic signal sampled at increasing times t: the number
+    of periods between its first and last upward crossing of the mean,
+    crossings placed by linear interpolation between samples."""
+    t = np.asarray(t, dtype=np.float64)
+    y = np.asarray(signal, dtype=np.float64)
+    y = y - np.mean(y)
+    up = np.nonzero((y[:-1] < 0.0) & (y[1:] >= 0.0))[0]
+    if up.size < 2:
+        return 0.0
+    tc = t[up] - y[up] * (t[up + 1] - t[up]) / (y[up + 1] - y[up])
+    return float((up.size - 1) / (tc[-1] - tc[0]))
+
+
+def obstacle_coefficients(records, h: float, u_b: float, depth: float, start_frac: float = 0.5) -> dict:
+    """Drag and lift coefficients and Strouhal number of an obstacle (Section
+    3.1.1, Table 2) from ``Solver.body_force`` records (rows: pressure force,
+    viscous force, t, dt), over the records after ``start_frac`` of the run:
+    C_D = mean F_x / (U_b^2 h depth / 2), C_L' = rms of the lift coefficient,
+    St = f h / U_b with f the frequency of the lift."""
+    r = np.asarray(records, dtype=np.float64)
+    r = r[int(len(r) * start_frac):]
+    fx = r[:, 0] + r[:, 3]
+    fy = r[:, 1] + r[:, 4]
+    q = 0.5 * u_b ** 2 * h * depth
+    cl = fy / q
+    f = shedding_frequency(r[:, 6], fy)
+    return {"C_D": float(np.mean(fx) / q), "C_D_pressure": float(np.mean(r[:, 0]) / q),
+            "C_L_rms": float(np.sqrt(np.mean((cl - cl.mean()) ** 2))), "St": f * h / u_b,
+            "t0": float(r[0, 6]), "t1": float(r[-1, 6]), "samples": int(len(r))}
