@@ -67,8 +67,8 @@ typedef struct dnslab_pool dnslab_pool;   /* opaque */
 /* Case parameters (the paper's case-setup script, Section 2.4). */
 typedef struct {
     int32_t nx, ny, nz;     /* cells; nx = 2^a 3^b with a >= 1 and nx >= 4; ny, nz = 1 or
-                               2^a 3^b >= 2; nx <= 2048 and ny, nz <= 1024 in FP64
-                               (4096 and 2048 in FP32); fewer than 2^31 cells */
+                               2^a 3^b >= 2; nx <= 4096 and ny, nz <= 2048 in FP64
+                               (8192 and 4096 in FP32); fewer than 2^31 cells */
     double lx, ly, lz;      /* periodic box lengths [m]; dx = lx/nx etc. */
     double nu;              /* kinematic viscosity [m^2/s] */
     double alpha_c;         /* scalar diffusivity [m^2/s] */

@@ -72,16 +72,18 @@ struct Layout {
 int validate(const dnslab_params* P, std::string& why) {
     if (!P) { why = "params is NULL"; return DNSLAB_EINVAL; }
     if (P->precision != DNSLAB_FP64 && P->precision != DNSLAB_FP32_REFINE) { why = "bad precision"; return DNSLAB_EINVAL; }
-    // FFT lines are staged whole in LDS: lengths up to 2048 (FP64) / 4096 (FP32)
-    // along x and 1024 / 2048 along y and z.
+    // FFT lines are staged whole in LDS (160 KB per CU on gfx950): lengths up
+    // to 4096 (FP64) / 8192 (FP32) along x (a half-length complex line, its
+    // twiddles and the real-transform twist: 98 KB at the limit) and 2048 /
+    // 4096 along y and z (a column and its twiddles: 64 KB).
     const int fp64 = P->precision == DNSLAB_FP64;
-    const int maxx = fp64 ? 2048 : 4096, maxyz = fp64 ? 1024 : 2048;
+    const int maxx = fp64 ? 4096 : 8192, maxyz = fp64 ? 2048 : 4096;
     if (P->nx < 4 || P->nx % 2 != 0 || !is_2a3b(P->nx) || P->nx > maxx) {
-        why = "nx must be even, 2^a 3^b, 4 <= nx <= 2048 (FP64) / 4096 (FP32)";
+        why = "nx must be even, 2^a 3^b, 4 <= nx <= 4096 (FP64) / 8192 (FP32)";
         return DNSLAB_EUNSUPPORTED;
     }
     for (int n : {P->ny, P->nz})
-        if (!is_2a3b(n) || n > maxyz) { why = "ny, nz must be 1 or 2^a 3^b <= 1024 (FP64) / 2048 (FP32)"; return DNSLAB_EUNSUPPORTED; }
+        if (!is_2a3b(n) || n > maxyz) { why = "ny, nz must be 1 or 2^a 3^b <= 2048 (FP64) / 4096 (FP32)"; return DNSLAB_EUNSUPPORTED; }
     const long long n = (long long)P->nx * P->ny * P->nz;
     if (n >= (1LL << 31)) { why = "grid too large (>= 2^31 cells)"; return DNSLAB_EUNSUPPORTED; }
     if (!(P->lx > 0 && P->ly > 0 && P->lz > 0)) { why = "box lengths must be positive"; return DNSLAB_EINVAL; }

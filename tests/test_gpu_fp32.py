@@ -46,6 +46,17 @@ def test_fp32_operators(shape):
     assert rel_err(to_np(S.poisson(r)), ops.poisson_solve(r, sc.spacing)) < 1e-5
 
 
+@pytest.mark.parametrize("shape", [(2, 2, 8192), (4096, 2, 4), (2, 4096, 4)])
+def test_fp32_poisson_longest_lines(shape):
+    """FP32 lines at the length limits (x 8192, y and z 4096)."""
+    torch, m = need_gpu()
+    sc = make_case(shape, 23, masked=False, forced=False, filt=False)
+    announce(f"fp32 poisson long lines {shape}")
+    S = m.Solver(sc, precision=m.FP32_REFINE)
+    r = np.random.default_rng(3).standard_normal(shape)
+    assert rel_err(to_np(S.poisson(r)), ops.poisson_solve(r, sc.spacing)) < 1e-5
+
+
 @pytest.mark.parametrize("masked", [False, True])
 def test_fp32_project_refined(masked):
     """The refined projection matches the FP64 projection to FP32 storage

@@ -94,6 +94,20 @@ def test_poisson(shape):
     assert rel_err(got, ref) < 1e-11, rel_err(got, ref)
 
 
+@pytest.mark.parametrize("shape", [(2, 3, 4096), (4, 2, 3072), (2, 2048, 4), (1536, 2, 6)])
+def test_poisson_longest_lines(shape):
+    """Lines at the FP64 length limits (x 4096, y and z 2048) and a long
+    mixed-radix line, each staged whole in LDS."""
+    torch, m = need_gpu()
+    sc = make_case(shape, 15, masked=False, forced=False, filt=False)
+    announce(f"poisson long lines shape={shape}")
+    S = m.Solver(sc)
+    r = np.random.default_rng(6).standard_normal(shape)
+    got = to_np(S.poisson(r))
+    ref = ops.poisson_solve(r, sc.spacing)
+    assert rel_err(got, ref) < 1e-11, rel_err(got, ref)
+
+
 @pytest.mark.parametrize("shape", [(32, 32, 32), (48, 36, 24), (1, 8, 16), (12, 1, 6)])
 def test_project_masked(shape):
     torch, m = need_gpu()
