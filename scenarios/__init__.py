@@ -362,7 +362,7 @@ def _fft_size_at_least(n: int) -> int:
 
 
 def cube_channel(n_h=30, re_ob=84.0, u_max=1.5, cfl=0.3, filter=True, n_piter=4,
-                 perturb=0.01, seed=2204) -> Scenario:
+                 perturb=0.01, seed=2204, length_d=8.8, band_h=1.0) -> Scenario:
     """Square obstacle in a 2D channel with a forced parabolic inflow
     (Section 3.1.1, Tables 1 and 2): channel width D = 2 pi between solid
     walls, obstacle edge h = D/6 resolved by n_h cells, obstacle centred at
@@ -371,10 +371,11 @@ def cube_channel(n_h=30, re_ob=84.0, u_max=1.5, cfl=0.3, filter=True, n_piter=4,
 
     Grid (nz = 1, dx = dy = h/n_h): ny = 6 n_h fluid cells plus two equal
     solid wall slabs of at least 2 cells (the paper's 0.05 D walls, thinner
-    here: a solid slab's thickness does not enter the flow), nx about 8.8 D;
-    both are FFT lengths 2^a 3^b.  The inflow is the source term of Section 2.1
-    across the whole channel in a band of width h centred on the periodic seam
-    x = 0, with u_set the parabola U_max 4 y (D' - y) / D'^2, where y is
+    here: a solid slab's thickness does not enter the flow), nx about
+    length_d D (the paper's 8.8 D by default); both are FFT lengths 2^a 3^b,
+    nx even.  The inflow is the source term of Section 2.1 across the whole
+    channel in a band of width band_h h centred on the periodic seam x = 0,
+    with u_set the parabola U_max 4 y (D' - y) / D'^2, where y is
     measured from the centre of the last wall cell and D' = (6 n_h + 1) dx
     (where the masked central-difference operators put the no-slip wall).
     Initial state: the same parabola in every fluid cell plus a small seeded
@@ -387,12 +388,11 @@ def cube_channel(n_h=30, re_ob=84.0, u_max=1.5, cfl=0.3, filter=True, n_piter=4,
     while (ny - nf) % 2:
         ny = _fft_size_at_least(ny + 1)
     wall = (ny - nf) // 2
-    target = 8.8 * nf
-    lo = _fft_size_at_least(int(np.floor(target * 0.9)))
-    cands = [lo]
+    target = length_d * nf
+    cands = [_fft_size_at_least(int(np.floor(target * 0.9)))]
     while cands[-1] < 1.1 * target:
         cands.append(_fft_size_at_least(cands[-1] + 1))
-    nx = min(cands, key=lambda n: abs(n - target))
+    nx = min((n for n in cands if n % 2 == 0), key=lambda n: abs(n - target))
     shape = (1, ny, nx)
     u_b = 2.0 * u_max / 3.0
     nu = u_b * h / re_ob
@@ -407,7 +407,7 @@ def cube_channel(n_h=30, re_ob=84.0, u_max=1.5, cfl=0.3, filter=True, n_piter=4,
     y = (np.arange(ny) - wall + 1) * d
     dp = (nf + 1) * d
     prof = np.where((np.arange(ny) >= wall) & (np.arange(ny) < wall + nf), u_max * 4.0 * y * (dp - y) / dp ** 2, 0.0)
-    fx = tanh_factor(periodic_distance(np.arange(nx) * d, 0.0, nx * d), h / 2, TANH_B)
+    fx = tanh_factor(periodic_distance(np.arange(nx) * d, 0.0, nx * d), band_h * h / 2, TANH_B)
     S = np.broadcast_to(fx[None, None, :], shape)
     sel = np.flatnonzero((S.ravel() > 1e-6) & (beta.ravel() == 1))
     jj = (sel // nx) % ny
