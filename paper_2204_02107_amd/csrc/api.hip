@@ -129,7 +129,10 @@ Grid make_grid(const dnslab_params* P) {
 #define DNSLAB_FKC 0
 #endif
 #ifndef DNSLAB_FKC_MIN
-#define DNSLAB_FKC_MIN 12       // least z cells per thread of the filter
+#define DNSLAB_FKC_MIN 12       // least z cells per thread of the filter (FP64)
+#endif
+#ifndef DNSLAB_FKC_MIN32
+#define DNSLAB_FKC_MIN32 8      // the same for the FP32 form (half the bytes per cell: more, shorter chunks)
 #endif
 // FFT passes: x lines per block grow while the block stays within these
 // threads and LDS bytes; y/z column tiles within this much LDS.
@@ -231,8 +234,9 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     Lo.L = stencil_launch(g, DNSLAB_ROWS, stencil_kc(g, DNSLAB_ROWS, DNSLAB_KC), 1);
     Lo.L1 = Lo.L;
     // the radius-3 filter re-reads 6 halo planes per z chunk: longer chunks
+    const int fkc_min = Lo.esz == 8 ? DNSLAB_FKC_MIN : DNSLAB_FKC_MIN32;
     Lo.LF = stencil_launch(g, DNSLAB_FROWS,
-                           std::max(stencil_kc(g, DNSLAB_FROWS, DNSLAB_FKC), std::min(DNSLAB_FKC_MIN, P->nz)), 1);
+                           std::max(stencil_kc(g, DNSLAB_FROWS, DNSLAB_FKC), std::min(fkc_min, P->nz)), 1);
     Lo.nparts = std::max(std::max(Lo.L.nblocks, Lo.L1.nblocks), Lo.LF.nblocks);
     // workspace layout
     size_t off = 0;
@@ -484,6 +488,7 @@ int project_solve(dnslab_ctx* x, const T* const us[3], void* const* scr = nullpt
             ra.flags = x->flags;
             ra.res = (float*)S[1];
             ra.g = x->g;
+            ra.ib = x->ib;
             LAUNCH(x, K_REF, launch_refine_res(ra, x->Lo.L1, x->cur, x->rec));
             int rc = poisson_solve<float>(x, (const float*)S[1], (float*)S[2]);
             if (rc) return rc;

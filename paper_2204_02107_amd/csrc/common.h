@@ -34,6 +34,15 @@ struct Grid {
     double dv;         // cell volume
 };
 
+// Cells next to a solid, where the immersed-boundary term div((1-beta) grad p)
+// can be nonzero (Section 2.2), with the solid face neighbours as bits
+// (+x, -x, +y, -y, +z, -z) = (1, 2, 4, 8, 16, 32).
+struct IBList {
+    const int* idx;
+    const uint8_t* mask;
+    int n;
+};
+
 // Scalars of the running step, resident in device memory so that an adaptive
 // dt never needs a host round trip.
 struct StepScalars {

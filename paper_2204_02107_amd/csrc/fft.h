@@ -53,15 +53,6 @@ constexpr int YZ_Q64 = 24;
 constexpr int YZ_Q32 = 32;
 inline int yz_threads(int ny) { return ny > YZ_THREADS ? 0 : ny * (YZ_THREADS / ny); }
 
-// Cells next to a solid, where the immersed-boundary term div((1-beta) grad p)
-// can be nonzero (Section 2.2), with the solid face neighbours as bits
-// (+x, -x, +y, -y, +z, -z) = (1, 2, 4, 8, 16, 32).
-struct IBList {
-    const int* idx;
-    const uint8_t* mask;
-    int n;
-};
-
 // Arguments of the kernels that take more than the FFT description.
 template <typename T>
 struct IbArgs {

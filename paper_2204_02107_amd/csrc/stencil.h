@@ -88,6 +88,7 @@ struct RefineResArgs {
     float* res;
     Grid g;
     int kc;
+    IBList ib;             // the cells next to a solid (their residual has the IB term)
 };
 // u = beta (u* - grad(p4 + dp)) and p = p4 + dp, in FP64 arithmetic.
 struct RefineCorrArgs {

@@ -622,6 +622,11 @@ __device__ __forceinline__ void correct_body(const CorrArgs<T>& a, const BlockId
 // FP64 residual of the last FP32 pressure solve (iterative refinement):
 // res = div u* + div((1-beta) grad p3) - div grad p4, all in FP64.  The
 // radius-2 operator div grad p4 = sum_a (p4(x+2e) - 2 p4 + p4(x-2e)) / (4 dx_a^2).
+// The dense kernel writes the cells without a solid face neighbour (no IB
+// term); the cells of the immersed-boundary list, whose IB term needs the
+// solid neighbours and p3, get their whole residual from a sparse kernel
+// over that list, so the dense march carries no gathers that depend on
+// loaded flags.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void refine_res_body(const RefineResArgs& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
@@ -651,30 +656,45 @@ __device__ __forceinline__ void refine_res_body(const RefineResArgs& a, const Bl
             ((double)a.p4[base + col.row + ixp2] - 2.0 * p0 + (double)a.p4[base + col.row + ixm2]) * (h2[0] * h2[0]) +
             ((double)a.p4[base + rowp2 + col.i] - 2.0 * p0 + (double)a.p4[base + rowm2 + col.i]) * (h2[1] * h2[1]) +
             (pz[4] - 2.0 * p0 + pz[0]) * (h2[2] * h2[2]);
-        double ib = 0.0;
-        if (a.flags[idx] & F_NEAR_SOLID) {
-            // div((1-beta) grad p3) from the face neighbours that are solid
-            const int c0[3] = {col.i, col.j, k};
-            const int nn[3] = {g.nx, g.ny, g.nz};
-            const double q0 = (double)a.p3[idx];
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                int c[3] = {c0[0], c0[1], c0[2]};
-                auto at = [&](int off) -> unsigned {
-                    c[ax] = wrap(c0[ax] + off, nn[ax]);
-                    const unsigned r = (unsigned)c[0] + (unsigned)g.nx * ((unsigned)c[1] + (unsigned)g.ny * c[2]);
-                    c[ax] = c0[ax];
-                    return r;
-                };
-                if (!(a.flags[at(1)] & F_FLUID)) ib += (((double)a.p3[at(2)] - q0) * h2[ax]) * h2[ax];
-                if (!(a.flags[at(-1)] & F_FLUID)) ib -= ((q0 - (double)a.p3[at(-2)]) * h2[ax]) * h2[ax];
-            }
-        }
-        a.res[idx] = (float)(div + ib - lap);
+        if (!(a.flags[idx] & F_NEAR_SOLID)) a.res[idx] = (float)(div - lap);
         wz[0] = wz[1]; wz[1] = wz[2];
 #pragma unroll
         for (int m = 0; m < 4; ++m) pz[m] = pz[m + 1];
     }
+}
+
+// The listed cells: div u* - div grad p4 as in the dense kernel, plus
+// div((1-beta) grad p3) from the faces whose neighbour is solid (mask bits
+// +x, -x, +y, -y, +z, -z = 1, 2, 4, 8, 16, 32).
+__device__ __forceinline__ void refine_res_ib_body(const RefineResArgs& a, unsigned blk) {
+    const int e = blk * blockDim.x + threadIdx.x;
+    if (e >= a.ib.n) return;
+    const Grid& g = a.g;
+    const unsigned idx = (unsigned)a.ib.idx[e];
+    const unsigned mask = a.ib.mask[e];
+    const unsigned nx = g.nx, ny = g.ny, nz = g.nz, nxy = nx * ny;
+    const unsigned i = idx % nx, jk = idx / nx;
+    const unsigned j = jk % ny, k = jk / ny;
+    auto sx = [&](int d) { return idx - i + (unsigned)wrap((int)i + d, (int)nx); };
+    auto sy = [&](int d) { return idx + ((unsigned)wrap((int)j + d, (int)ny) - j) * nx; };
+    auto sz = [&](int d) { return idx + ((unsigned)wrap((int)k + d, (int)nz) - k) * nxy; };
+    const double h2[3] = {g.inv2d[0], g.inv2d[1], g.inv2d[2]};
+    const double div = ((double)a.us[0][sx(1)] - (double)a.us[0][sx(-1)]) * h2[0] +
+                       ((double)a.us[1][sy(1)] - (double)a.us[1][sy(-1)]) * h2[1] +
+                       ((double)a.us[2][sz(1)] - (double)a.us[2][sz(-1)]) * h2[2];
+    const double p0 = (double)a.p4[idx];
+    const double lap = ((double)a.p4[sx(2)] - 2.0 * p0 + (double)a.p4[sx(-2)]) * (h2[0] * h2[0]) +
+                       ((double)a.p4[sy(2)] - 2.0 * p0 + (double)a.p4[sy(-2)]) * (h2[1] * h2[1]) +
+                       ((double)a.p4[sz(2)] - 2.0 * p0 + (double)a.p4[sz(-2)]) * (h2[2] * h2[2]);
+    const double q0 = (double)a.p3[idx];
+    double ib = 0.0;
+    if (mask & 1u) ib += (((double)a.p3[sx(2)] - q0) * h2[0]) * h2[0];
+    if (mask & 2u) ib -= ((q0 - (double)a.p3[sx(-2)]) * h2[0]) * h2[0];
+    if (mask & 4u) ib += (((double)a.p3[sy(2)] - q0) * h2[1]) * h2[1];
+    if (mask & 8u) ib -= ((q0 - (double)a.p3[sy(-2)]) * h2[1]) * h2[1];
+    if (mask & 16u) ib += (((double)a.p3[sz(2)] - q0) * h2[2]) * h2[2];
+    if (mask & 32u) ib -= ((q0 - (double)a.p3[sz(-2)]) * h2[2]) * h2[2];
+    a.res[idx] = (float)(div + ib - lap);
 }
 
 // u = beta (u* - grad(p4 + dp)), p = p4 + dp, FP64 arithmetic, FP32 storage.
@@ -926,6 +946,13 @@ __global__ __launch_bounds__(1024) void k_refine_res_b(const BRec<RefineResArgs>
     const RefineResArgs a = tab[s_].a;
     refine_res_body(a, bi_);
 }
+__global__ __launch_bounds__(256) void k_refine_res_ib(const RefineResArgs a) { refine_res_ib_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_refine_res_ib_b(const BRec<RefineResArgs>* __restrict__ tab,
+                                                         const unsigned* __restrict__ st, int ns) {
+    const int s_ = batch_slot(st, ns);
+    const RefineResArgs a = tab[s_].a;
+    refine_res_ib_body(a, blockIdx.x - st[s_]);
+}
 __global__ __launch_bounds__(1024) void k_refine_correct(const RefineCorrArgs a) {
     refine_correct_body(a, hw_block());
 }
@@ -1075,11 +1102,14 @@ hipError_t launch_rate(const T* u, const T* v, const T* w, const Grid& g, PartSo
 hipError_t launch_refine_res(const RefineResArgs& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     RefineResArgs b = a;
     b.kc = L.kc;
+    const dim3 gib((unsigned)((a.ib.n + 255) / 256)), bib(256);
     if (rec) {
         record_launch(rec, kind_code(KK_REFRES, 0, 1), L.grid, L.block, 0, b);
+        if (a.ib.n > 0) record_launch(rec, kind_code(KK_REFRES, 1, 1), gib, bib, 0, b);
         return hipSuccess;
     }
     hipLaunchKernelGGL(k_refine_res, L.grid, L.block, 0, s, b);
+    if (a.ib.n > 0) hipLaunchKernelGGL(k_refine_res_ib, gib, bib, 0, s, b);
     return hipGetLastError();
 }
 
@@ -1179,7 +1209,8 @@ hipError_t launch_batched_stencil(int kind, const void* tab, const unsigned* st,
                                   size_t lds, hipStream_t s) {
     const int base = kind >> 8, mode = (kind >> 1) & 127, fp32 = kind & 1;
     if (base == KK_REFRES) {
-        hipLaunchKernelGGL(k_refine_res_b, dim3(nb), blk, 0, s, (const BRec<RefineResArgs>*)tab, st, ns);
+        if (mode == 1) hipLaunchKernelGGL(k_refine_res_ib_b, dim3(nb), blk, 0, s, (const BRec<RefineResArgs>*)tab, st, ns);
+        else hipLaunchKernelGGL(k_refine_res_b, dim3(nb), blk, 0, s, (const BRec<RefineResArgs>*)tab, st, ns);
         return hipGetLastError();
     }
     if (base == KK_REFCORR) {
