@@ -113,3 +113,22 @@ def test_fp32_room_50_steps():
     assert excess < 1e-7, excess
     assert abs(dg["co2_room_mean"] / diags[-1]["co2_room_mean"] - 1) < 1e-6
     assert abs(dg["t"] / diags[-1]["t"] - 1) < 1e-6
+
+
+def test_fp32_channel_case_close_to_oracle():
+    """FP32 form on the obstacle-in-channel case (2D, masked walls and
+    obstacle, forced inflow) against the FP64 oracle over 30 steps: fluid-cell
+    fields to FP32 rounding level."""
+    torch, m = need_gpu()
+    sc = scenarios.cube_channel(8)
+    announce("fp32 channel case x30 vs oracle")
+    S = m.Solver(sc, precision=m.FP32_REFINE)
+    S.step(30, diag=False)
+    got = S.state()
+    S.close()
+    O = Oracle.from_scenario(sc)
+    st, _ = O.run(Oracle.state_from_scenario(sc), 30)
+    fluid = sc.beta == 1
+    for k in ("u", "v"):
+        a, b = got[k][fluid], getattr(st, k)[fluid]
+        assert np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)) < 1e-4, k

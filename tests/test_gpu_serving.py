@@ -168,3 +168,31 @@ def test_pool_large_scenarios_direct_equal_plain():
         for k in ("u", "v", "w", "p", "c"):
             assert np.array_equal(got[k], alone[q][k]), (q, k)
     pool.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pool_mix_with_channel_case(precision):
+    """A 2D obstacle-in-channel scenario (nz = 1) pooled with two small rooms
+    whose (ky, kz) planes take the fused y/z FFT pass and one larger room
+    (column passes): each ends bitwise equal to its pool of one."""
+    torch, m = need_gpu()
+    from paper_2204_02107_amd.serving import Pool
+    prec = m.FP64 if precision == "fp64" else m.FP32_REFINE
+    cs = [scenarios.cube_channel(8), cases()[0], cases()[1],
+          scenarios.room(96, 96, 64, dx=DX, u_in=1.0, n_boxes=2, seed=14, box_max_frac=0.4)]
+    steps = 8
+    announce(f"pool {precision} mix with channel case")
+    alone = []
+    for c in cs:
+        pool = Pool(8 << 30, prec)
+        s = pool.admit(c, steps)
+        pool.step(steps)
+        alone.append(pool.state(s, c.shape))
+        pool.close()
+    pool = Pool(8 << 30, prec)
+    slots = run_mixed(pool, cs, steps, stagger=(0, 2, 1, 4))
+    for q, c in enumerate(cs):
+        got = pool.state(slots[q], c.shape)
+        for k in ("u", "v", "w", "p", "c"):
+            assert np.array_equal(got[k], alone[q][k]), (q, k)
+    pool.close()
