@@ -153,9 +153,26 @@ def particle_bench(S, sc, esz, n=1 << 20, steps=100, seed=5):
     ms, nl = S.profile_read()
     S.profile(None)
     per = 1e-3 * ms / max(nl, 1)
+    # the same particles sorted by cell once (their gathers then coalesce)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    S.particles_sort(pos, vel, diam)
+    torch.cuda.synchronize()
+    sort_s = time.perf_counter() - t1
+    S.profile("particles")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S.particles_step(pos, vel, diam, dt=1e-3)
+    torch.cuda.synchronize()
+    el_s = time.perf_counter() - t0
+    ms_s, nl_s = S.profile_read()
+    S.profile(None)
+    per_s = 1e-3 * ms_s / max(nl_s, 1)
     b = n * (13 * 8 + 24 * esz)
     return {"particles": n, "steps": steps, "Mparticle_steps_per_s": n * steps / el / 1e6,
-            "kernel_avg_us": 1e6 * per, "algorithmic_GBs": b / per / 1e9, "bytes_per_particle_step": 13 * 8 + 24 * esz}
+            "kernel_avg_us": 1e6 * per, "algorithmic_GBs": b / per / 1e9, "bytes_per_particle_step": 13 * 8 + 24 * esz,
+            "sorted": {"sort_ms": 1e3 * sort_s, "Mparticle_steps_per_s": n * steps / el_s / 1e6,
+                       "kernel_avg_us": 1e6 * per_s, "algorithmic_GBs": b / per_s / 1e9}}
 
 
 def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7, log=None):

@@ -195,6 +195,18 @@ typedef struct {
 int dnslab_particles_step(dnslab_ctx* ctx, int64_t n, double* pos, double* vel, const double* diam,
                           const dnslab_particle_params* pp, double dt);
 
+/* Reorder n particles (same arrays as dnslab_particles_step; diam is
+ * permuted too) by the linear index i + nx (j + ny k) of the cell holding
+ * each one, cell (i, j, k) = floor(x / dx) etc. wrapped into the grid, with a
+ * stable sort: particles in one cell keep their relative order, so the result
+ * is unique.  Particles carry no identity in the model (Section 2.3), so the
+ * order is free; sorted particles gather their fluid velocities from
+ * neighbouring cells, which the step kernel turns into coalesced reads.  On
+ * the context's stream; allocates device scratch on first use and when n
+ * grows (then synchronises the stream first).  0 <= n < 2^32, else
+ * DNSLAB_EINVAL. */
+int dnslab_particles_sort(dnslab_ctx* ctx, int64_t n, double* pos, double* vel, double* diam);
+
 /* CO2 distribution over the room (Section 3.3): counts of the fluid cells of
  * the room region per bin of the bound c, nbins equal bins over [lo, hi)
  * (bin floor((c - lo) / (hi - lo) * nbins) in FP64, clamped into the end

@@ -188,6 +188,17 @@ class Solver:
         self._call(self.lib.dnslab_particles_step, self.ctx, n, _ptr(pos), _ptr(vel), _ptr(diam),
                    ctypes.byref(pp), float(dt))
 
+    def particles_sort(self, pos, vel, diam):
+        """Reorder the particles in place by the cell holding each one (stable),
+        so that the step kernel's velocity gathers are coalesced."""
+        n = int(diam.numel())
+        for t in (pos, vel, diam):
+            if t.dtype != _torch().float64 or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("particle arrays must be contiguous float64 tensors on the solver's device")
+        if tuple(pos.shape) != (3, n) or tuple(vel.shape) != (3, n):
+            raise ValueError("pos and vel must have shape (3, n)")
+        self._call(self.lib.dnslab_particles_sort, self.ctx, n, _ptr(pos), _ptr(vel), _ptr(diam))
+
     # -- post-processing (Sections 3.3-3.4) ----------------------------------
     def co2_histogram(self, nbins=60, lo=400.0, hi=1000.0):
         """Counts of room fluid cells per CO2 bin (numpy int64, nbins values)."""

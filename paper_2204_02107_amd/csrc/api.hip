@@ -305,6 +305,8 @@ struct dnslab_ctx {
     long long host_step;
     unsigned long long* hist_dev;   // histogram counters (allocated on first use)
     unsigned long long* hist_host;
+    void* psort_buf;       // particle-sort scratch (allocated on first use, grown as needed)
+    size_t psort_bytes;    // its size
     DiagRec* pinned;       // host staging for diagnostics
     StepScalars* pinned_sc;
     std::string err;
@@ -1193,6 +1195,7 @@ void dnslab_destroy(dnslab_ctx* x) {
     if (x->ib_buf) (void)hipFree(x->ib_buf);
     if (x->hist_dev) (void)hipFree(x->hist_dev);
     if (x->hist_host) (void)hipHostFree(x->hist_host);
+    if (x->psort_buf) (void)hipFree(x->psort_buf);
     if (x->pinned) (void)hipHostFree(x->pinned);
     if (x->pinned_sc) (void)hipHostFree(x->pinned_sc);
     delete x;
@@ -1260,6 +1263,43 @@ int dnslab_particles_step(dnslab_ctx* x, int64_t n, double* pos, double* vel, co
         fill(a);
         LAUNCH(x, K_PART, launch_particles<float>(a, x->stream));
     }
+    return DNSLAB_OK;
+}
+
+int dnslab_particles_sort(dnslab_ctx* x, int64_t n, double* pos, double* vel, double* diam) {
+    if (int rc = check_ctx(x)) return rc;
+    if (n < 0 || n >= (1LL << 32)) return fail(x, DNSLAB_EINVAL, "bad particle count");
+    if (n > 0 && (!pos || !vel || !diam)) return fail(x, DNSLAB_EINVAL, "NULL pointer");
+    if (n == 0) return DNSLAB_OK;
+    size_t sort_bytes = 0;
+    HIPCHK(x, particle_sort_bytes(n, &sort_bytes));
+    const size_t b_key = align_up((size_t)n * sizeof(unsigned), 256), b_tmp = align_up((size_t)n * sizeof(double), 256);
+    const size_t need = 4 * b_key + b_tmp + align_up(sort_bytes, 256);
+    if (need > x->psort_bytes) {
+        if (x->psort_buf) {
+            // an earlier sort on the stream may still use the old scratch
+            HIPCHK(x, hipStreamSynchronize(x->stream));
+            (void)hipFree(x->psort_buf);
+            x->psort_buf = nullptr;
+            x->psort_bytes = 0;
+        }
+        if (hipMalloc(&x->psort_buf, need) != hipSuccess) {
+            (void)hipGetLastError();
+            x->psort_buf = nullptr;
+            return fail(x, DNSLAB_ENOMEM, "particle sort scratch");
+        }
+        x->psort_bytes = need;
+    }
+    char* b = (char*)x->psort_buf;
+    ParticleSortScratch sc;
+    sc.keys[0] = (unsigned*)b;
+    sc.keys[1] = (unsigned*)(b + b_key);
+    sc.vals[0] = (unsigned*)(b + 2 * b_key);
+    sc.vals[1] = (unsigned*)(b + 3 * b_key);
+    sc.tmp = (double*)(b + 4 * b_key);
+    sc.sort_tmp = b + 4 * b_key + b_tmp;
+    sc.sort_bytes = sort_bytes;
+    HIPCHK(x, sort_particles(x->g, n, pos, vel, diam, sc, x->stream));
     return DNSLAB_OK;
 }
 

@@ -31,4 +31,21 @@ struct ParticleArgs {
 template <typename T>
 hipError_t launch_particles(const ParticleArgs<T>& a, hipStream_t s);
 
+// Reordering of particles by the cell that holds them (so that neighbouring
+// threads of the step kernel gather from neighbouring cells).  Scratch sizes
+// for n particles; the buffers are the caller's.
+struct ParticleSortScratch {
+    unsigned* keys[2];     // n cell indices each
+    unsigned* vals[2];     // n particle indices each
+    double* tmp;           // n doubles
+    void* sort_tmp;        // radix-sort temporary storage
+    size_t sort_bytes;
+};
+// Bytes of radix-sort temporary storage for n particles.
+hipError_t particle_sort_bytes(long long n, size_t* bytes);
+// Stable sort of the n particles (SoA pos, vel: 3 n doubles each; diam: n)
+// by the linear index of the containing cell; every array is permuted in place.
+hipError_t sort_particles(const Grid& g, long long n, double* pos, double* vel, double* diam,
+                          const ParticleSortScratch& s, hipStream_t st);
+
 }  // namespace dnslab

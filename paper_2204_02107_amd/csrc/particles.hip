@@ -2,6 +2,8 @@
 // drag and gravity, advanced by implicit Euler in the bound velocity field.
 #include "particles.h"
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 namespace dnslab {
 namespace {
 
@@ -26,6 +28,14 @@ __device__ __forceinline__ double interp3(const T* __restrict__ f, const Grid& g
         }
     }
     return out;
+}
+
+// Index of the cell holding position x along an axis of n cells of size d
+// (the lower interpolation corner, wrapped periodically).
+__device__ __forceinline__ int cell_of(double x, double d, int n) {
+    long long i0 = (long long)floor(x / d) % n;
+    if (i0 < 0) i0 += n;
+    return (int)i0;
 }
 
 // Wrap into [0, L) like a floored modulo.
@@ -77,6 +87,24 @@ __global__ __launch_bounds__(256) void k_particles(const ParticleArgs<T> a) {
     a.vx[q] = vn[0]; a.vy[q] = vn[1]; a.vz[q] = vn[2];
 }
 
+__global__ __launch_bounds__(256) void k_particle_keys(const double* __restrict__ pos, long long n, Grid g,
+                                                       unsigned* __restrict__ keys, unsigned* __restrict__ vals) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int i = cell_of(pos[q], g.d[0], g.nx);
+    const int j = cell_of(pos[n + q], g.d[1], g.ny);
+    const int k = cell_of(pos[2 * n + q], g.d[2], g.nz);
+    keys[q] = (unsigned)i + (unsigned)g.nx * ((unsigned)j + (unsigned)g.ny * (unsigned)k);
+    vals[q] = (unsigned)q;
+}
+
+// out[q] = in[perm[q]]
+__global__ __launch_bounds__(256) void k_gather(const double* __restrict__ in, const unsigned* __restrict__ perm,
+                                                long long n, double* __restrict__ out) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) out[q] = in[perm[q]];
+}
+
 }  // namespace
 
 template <typename T>
@@ -84,6 +112,36 @@ hipError_t launch_particles(const ParticleArgs<T>& a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
     const long long nb = (a.n + 255) / 256;
     hipLaunchKernelGGL((k_particles<T>), dim3((unsigned)nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t particle_sort_bytes(long long n, size_t* bytes) {
+    *bytes = 0;
+    return rocprim::radix_sort_pairs(nullptr, *bytes, (const unsigned*)nullptr, (unsigned*)nullptr,
+                                     (const unsigned*)nullptr, (unsigned*)nullptr, (size_t)n);
+}
+
+hipError_t sort_particles(const Grid& g, long long n, double* pos, double* vel, double* diam,
+                          const ParticleSortScratch& s, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_particle_keys, dim3(nb), dim3(256), 0, st, pos, n, g, s.keys[0], s.vals[0]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // cell indices are below nx ny nz < 2^31: sort on the bits that can be set
+    unsigned end_bit = 1;
+    while (end_bit < 32 && ((unsigned long long)1 << end_bit) < (unsigned long long)g.n) ++end_bit;
+    size_t bytes = s.sort_bytes;
+    e = rocprim::radix_sort_pairs(s.sort_tmp, bytes, s.keys[0], s.keys[1], s.vals[0], s.vals[1], (size_t)n, 0u,
+                                  end_bit, st);
+    if (e != hipSuccess) return e;
+    double* arrays[7] = {pos, pos + n, pos + 2 * n, vel, vel + n, vel + 2 * n, diam};
+    for (double* a : arrays) {
+        hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, st, (const double*)a, (const unsigned*)s.vals[1], n,
+                           s.tmp);
+        e = hipMemcpyAsync(a, s.tmp, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
     return hipGetLastError();
 }
 

@@ -108,3 +108,45 @@ def test_particles_reject_bad_arguments():
     assert lib.dnslab_particles_step(S.ctx, 0, None, None, None, ctypes.byref(bad), 0.01) == -1
     assert lib.dnslab_particles_step(S.ctx, 0, None, None, None, ctypes.byref(pp), 0.01) == 0
     S.close()
+
+
+def test_particles_sort_is_the_stable_cell_order():
+    """The device sort permutes every array by numpy's stable argsort of the
+    cell index (cell = floor(x / dx) wrapped, x fastest); a step of the
+    sorted set equals the same step of the unsorted set, permuted (bitwise:
+    each particle is advanced on its own); growing n reallocates the scratch;
+    n = 0 and n = 1 are no-ops."""
+    torch, m, sc, S, box, pos, vel, diam, t = setup(n=50_000, seed=9)
+    announce("particles sort")
+    d = sc.spacing
+    # a few particles exactly on cell faces, outside the box and negative
+    pos[0, :3] = [d[0] * 5, -d[0] * 0.5, box[0] + d[0] * 2.25]
+    def keys(p):
+        idx = [np.floor(p[a] / d[a]).astype(np.int64) % n_ax for a, n_ax in enumerate((sc.nx, sc.ny, sc.nz))]
+        return idx[0] + sc.nx * (idx[1] + sc.ny * idx[2])
+    order = np.argsort(keys(pos), kind="stable")
+    tp, tv, td = t(pos), t(vel), t(diam)
+    S.particles_sort(tp, tv, td)
+    assert np.array_equal(tp.cpu().numpy(), pos[:, order])
+    assert np.array_equal(tv.cpu().numpy(), vel[:, order])
+    assert np.array_equal(td.cpu().numpy(), diam[order])
+    # stepping commutes with the permutation
+    up, uv, ud = t(pos), t(vel), t(diam)
+    S.particles_step(up, uv, ud, RHO_P, RHO_F, G, dt=2e-3)
+    S.particles_step(tp, tv, td, RHO_P, RHO_F, G, dt=2e-3)
+    assert np.array_equal(tp.cpu().numpy(), up.cpu().numpy()[:, order])
+    assert np.array_equal(tv.cpu().numpy(), uv.cpu().numpy()[:, order])
+    # a larger set after a smaller one, then the trivial sizes
+    rng = np.random.default_rng(4)
+    n2 = 120_000
+    p2 = np.stack([rng.uniform(0, box[a], n2) for a in range(3)])
+    v2, d2 = rng.standard_normal((3, n2)), rng.uniform(1e-6, 1e-4, n2)
+    tp2, tv2, td2 = t(p2), t(v2), t(d2)
+    S.particles_sort(tp2, tv2, td2)
+    o2 = np.argsort(keys(p2), kind="stable")
+    assert np.array_equal(tp2.cpu().numpy(), p2[:, o2]) and np.array_equal(td2.cpu().numpy(), d2[o2])
+    for k in (0, 1):
+        a, b, c = t(pos[:, :k]), t(vel[:, :k]), t(diam[:k])
+        S.particles_sort(a, b, c)
+        assert np.array_equal(a.cpu().numpy(), pos[:, :k])
+    S.close()
