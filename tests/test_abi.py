@@ -75,3 +75,27 @@ def test_header_documents_every_entry_point():
         before = text[:m.start()].rstrip()
         # each declaration follows a comment, or shares one with the entry point above it
         assert before.endswith("*/") or before.endswith(");"), s
+
+
+@needs_lib
+def test_fft_length_limits():
+    """Lines are staged whole in LDS: x up to 4096 (FP64) / 8192 (FP32), y and
+    z up to 2048 / 4096; one step beyond is DNSLAB_EUNSUPPORTED."""
+    import paper_2204_02107_amd as m
+    from paper_2204_02107_amd._lib import DnslabError
+    base = scenarios.room(64, 32, 24, dx=0.05, n_boxes=1)
+
+    def shaped(nx, ny, nz):
+        c = base.copy()
+        c.nx, c.ny, c.nz = nx, ny, nz
+        return c
+    ok = [((4096, 2, 2), m.FP64), ((8192, 2, 2), m.FP32_REFINE), ((4, 2048, 2), m.FP64),
+          ((4, 2, 2048), m.FP64), ((4, 4096, 2), m.FP32_REFINE), ((4, 2, 4096), m.FP32_REFINE)]
+    bad = [((4608, 2, 2), m.FP64), ((9216, 2, 2), m.FP32_REFINE), ((4, 2304, 2), m.FP64),
+           ((4, 2, 4608), m.FP32_REFINE), ((2, 4, 4), m.FP64), ((4, 10, 4), m.FP64)]
+    for shape, prec in ok:
+        assert m.workspace_bytes(shaped(*shape), prec) > 0, shape
+    for shape, prec in bad:
+        with pytest.raises(DnslabError) as e:
+            m.workspace_bytes(shaped(*shape), prec)
+        assert e.value.code == -3, shape
