@@ -265,7 +265,7 @@ def kernel_key(sym):
         return "fft_yz"
     if base in ("correct", "refine_correct"):
         return "correct"
-    if base in ("div", "fft_x_fwd", "fft_x_inv", "ib_rhs", "refine_res"):
+    if base in ("div", "fft_x_fwd", "fft_x_inv", "ib_rhs", "refine_res", "refine_res_ib"):
         return base
     return None
 

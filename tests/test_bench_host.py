@@ -21,6 +21,8 @@ def test_kernel_key_mapping():
     assert k("void dnslab::(anonymous namespace)::k_fft_cols<float, 1>(dnslab::FFTArgs<float>)") == "fft_y"
     assert k("void dnslab::(anonymous namespace)::k_fft_yz<double>(dnslab::FFTArgs<double>)") == "fft_yz"
     assert k("dnslab::(anonymous namespace)::k_refine_correct(dnslab::RefineCorrArgs)") == "correct"
+    assert k("dnslab::(anonymous namespace)::k_refine_res(dnslab::RefineResArgs)") == "refine_res"
+    assert k("dnslab::(anonymous namespace)::k_refine_res_ib(dnslab::RefineResArgs)") == "refine_res_ib"
     assert k("dnslab::(anonymous namespace)::k_advance(dnslab::AdvanceArgs)") is None
     assert k("__amd_rocclr_copyBuffer") is None
 
