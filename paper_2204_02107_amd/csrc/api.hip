@@ -151,6 +151,9 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_YZ_MAX_PLANE
 #define DNSLAB_YZ_MAX_PLANE 4096   // largest ny * nz given to the fused pass
 #endif
+#ifndef DNSLAB_FORK_EARLY_CELLS
+#define DNSLAB_FORK_EARLY_CELLS (1LL << 23)   // from this grid size the scalar half forks before the momentum stages
+#endif
 #ifndef DNSLAB_OVERLAP
 #define DNSLAB_OVERLAP 1       // run the scalar half of a step on a second stream
 #endif
@@ -656,10 +659,10 @@ int ensure_aux(dnslab_ctx* x) {
 // velocity filter and the step advance (t, step, next dt from the new Courant
 // rate).  Scalar half: see scalar_half.  On a plain context the scalar half of
 // step n is enqueued on the second stream once div u* of step n + 1 is
-// enqueued, so that it runs beside that step's FFT pressure solves; the
-// correction of step n + 1, which overwrites the projected velocity the scalar
-// half reads, waits for it.  When recording for the pool both halves go, in
-// order, into one sequence.
+// enqueued (on large grids: before the momentum stages of step n + 1), so
+// that it runs beside that step's work; the correction of step n + 1, which
+// overwrites the projected velocity the scalar half reads, waits for it.
+// When recording for the pool both halves go, in order, into one sequence.
 template <typename T>
 int one_step(dnslab_ctx* x) {
     int rc = ensure_rate<T>(x);
@@ -687,6 +690,19 @@ int one_step(dnslab_ctx* x) {
     // next stage evaluates F on it; the accumulator sums the k's as usual.
     const bool per_stage = x->P.project_each_stage != 0;
     bool forked = false;
+    // Where the scalar half of the last step forks: after div u* its work
+    // overlaps the pressure solves only, whose passes leave the memory system
+    // idle between their load and store phases (best when the solves are
+    // long against the scalar half: the 256x128x96 room loses 7% forking
+    // earlier); on large grids the solves run closer to the bandwidth and the
+    // scalar half outlasts them, stalling the correction that waits for it,
+    // so it forks before the momentum stages (512x256x192: +3% in FP64 and
+    // FP32; 1024x512x256: +0.5% / +1.3%).
+    if (defer && x->g.n >= DNSLAB_FORK_EARLY_CELLS) {
+        rc = flush_scalar_half<T>(x);
+        if (rc) return rc;
+        forked = true;
+    }
     // the refinement scratch is the stage buffer not being projected
     auto project_stage = [&](T* const s[3], T* const other[3]) -> int {
         const T* const sc[3] = {s[0], s[1], s[2]};
