@@ -135,3 +135,28 @@ def test_shedding_frequency_of_sinusoids():
         est = PP.shedding_frequency(t, y)
         assert abs(est / f - 1) < 1e-4, (f, est)
     assert PP.shedding_frequency(np.arange(10.0), np.ones(10)) == 0.0
+
+
+def test_body_force_is_what_the_pressure_gradient_takes_from_the_fluid():
+    """Reading of the obstacle force: over the whole periodic grid the central
+    pressure gradient sums to zero, so the pressure force on all solid cells
+    equals dV times the sum of grad P over the fluid cells (what the
+    correction u = u* - dt grad P removes from the fluid), for any p and any
+    mask (the central differences written out with np.roll)."""
+    rng = np.random.default_rng(8)
+    shape = (6, 10, 12)
+    d = (0.3, 0.2, 0.1)
+    beta = np.ones(shape, np.uint8)
+    beta[1:3, 2:5, 3:7] = 0
+    beta[4:6, 6:9, 8:11] = 0
+    p = rng.standard_normal(shape)
+    dt = 0.05
+    z = np.zeros(shape)
+    fp, _ = PP.body_force(p, z, z, z, beta, (0, 12, 0, 10, 0, 6), d, nu=0.0, dt=dt)
+    P = p / dt
+    dv = d[0] * d[1] * d[2]
+    fluid = beta == 1
+    for a, ax in ((0, 2), (1, 1), (2, 0)):
+        grad = (np.roll(P, -1, axis=ax) - np.roll(P, 1, axis=ax)) / (2 * d[a])
+        want = dv * grad[fluid].sum()
+        assert abs(fp[a] - want) < 1e-10 * np.abs(grad).sum() * dv, (a, fp[a], want)
