@@ -246,6 +246,42 @@ def cube_bench(n_h, t_end, every=20, precision="fp64", chunk=512):
             "paper_DNSLABIB": CUBE_PAPER.get(n_h)}
 
 
+def consistency_run(workload_name="room", steps=2000, chunk=400):
+    """The workload run `steps` steps in FP64 and in the FP32 form with FP64
+    refinement: the room-mean CO2, its fitted decay rate (ACH) and the kinetic
+    energy of both, and their differences (the accuracy statement of the FP32
+    form over a long horizon)."""
+    import torch
+    import paper_2204_02107_amd as m
+    from paper_2204_02107_amd import postproc
+    sc = workload(workload_name)
+    out = {"workload": WORKLOADS[workload_name], "steps": steps}
+    for name, prec in (("fp64", m.FP64), ("fp32_refine", m.FP32_REFINE)):
+        S = m.Solver(sc, precision=prec)
+        diags = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            k = min(chunk, steps - done)
+            S.step(k, diag=False)
+            diags += S.read_diags(k)
+            done += k
+            print(f"[consistency] {name} steps={done} t={diags[-1]['t']:.3f}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        S.close()
+        d = diags[-1]
+        out[name] = {"t_end_s": d["t"], "wall_s": el, "Gcell_steps_s": sc.ncells * steps / el / 1e9, "ke": d["ke"],
+                     "co2_room_mean_end": d["co2_room_mean"], "ach_fit_per_h": postproc.fitted_ach(diags[steps // 10:]),
+                     "div_l2_end": d["div_l2"]}
+    a, b = out["fp64"], out["fp32_refine"]
+    out["ach_rel_diff"] = abs(b["ach_fit_per_h"] - a["ach_fit_per_h"]) / abs(a["ach_fit_per_h"])
+    out["co2_mean_diff_ppm"] = b["co2_room_mean_end"] - a["co2_room_mean_end"]
+    out["ke_rel_diff"] = abs(b["ke"] - a["ke"]) / abs(a["ke"])
+    return out
+
+
 # Kernel symbol (as rocprofv3 prints it) -> name in kernel_bytes.
 def kernel_key(sym):
     import re
@@ -336,6 +372,8 @@ def main():
     ap.add_argument("--cube", type=int, nargs="*", metavar="N_H",
                     help="only run the obstacle-in-channel validation at these resolutions (cells per obstacle edge)")
     ap.add_argument("--cube-t-end", type=float, default=300.0, help="simulated time in units of h / U_b")
+    ap.add_argument("--consistency", type=int, metavar="STEPS",
+                    help="only run the workload STEPS steps in FP64 and in the FP32 form and compare them")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain 1 GiB device copy used to calibrate the PMC byte counters")
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -358,6 +396,9 @@ def main():
         return
     if args.copy_probe:
         copy_probe()
+        return
+    if args.consistency:
+        print(json.dumps(consistency_run(args.workload, args.consistency)), flush=True)
         return
     if args.cube is not None:
         for n_h in args.cube or [30]:
