@@ -75,3 +75,28 @@ def test_pool_graph_equals_launches():
         pool.close()
     for a, b in zip(*out):
         same_state(a, b)
+
+
+def test_graph_and_early_fork_on_a_large_grid():
+    """2^23 cells: the scalar half forks before the momentum stages; graph
+    replay and eager issue agree bit for bit, and both agree with the same
+    scenario run through a pool of one (a direct group there, on the pool's
+    own streams)."""
+    torch, m = need_gpu()
+    from paper_2204_02107_amd.serving import Pool
+    sc = scenarios.room(256, 256, 128, dx=10.0 / 256, n_boxes=4, seed=6)
+    assert sc.ncells == 1 << 23
+    announce("graph vs eager vs pool, 256x256x128")
+    E = m.Solver(sc)
+    G = m.Solver(sc, graph_steps=3)
+    E.step(7, diag=False)
+    G.step(7, diag=False)
+    se, sg = E.state(), G.state()
+    same_state(se, sg)
+    E.close()
+    G.close()
+    pool = Pool(8 << 30, m.FP64)
+    s = pool.admit(sc, 7)
+    pool.step(7)
+    same_state(se, pool.state(s, sc.shape))
+    pool.close()
