@@ -151,6 +151,9 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_YZ_MAX_PLANE
 #define DNSLAB_YZ_MAX_PLANE 4096   // largest ny * nz given to the fused pass
 #endif
+#ifndef DNSLAB_YZ_MAX_PLANE32
+#define DNSLAB_YZ_MAX_PLANE32 16384   // the same for the FP32 form (1024-thread blocks)
+#endif
 #ifndef DNSLAB_FORK_EARLY_CELLS
 #define DNSLAB_FORK_EARLY_CELLS (1LL << 23)   // from this grid size the scalar half forks before the momentum stages
 #endif
@@ -210,11 +213,13 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     // It cuts two of the three column passes and their launches, but one
     // block per plane serialises a plane's work on one CU: measured 10%
     // faster steps for planes of 64 x 64, 3% slower for 96 x 64 and 8% for
-    // 128 x 96 (FP64), hence the plane-size limit.
+    // 128 x 96 (FP64), hence the plane-size limit.  The FP32 form runs
+    // 1024-thread blocks and gains on every plane up to 128 x 96 (6-9%).
     {
-        const int nthr = yz_threads(P->ny);
+        const int nthr = yz_threads(P->ny, Lo.esz == 4);
         const int q = Lo.esz == 8 ? YZ_Q64 : YZ_Q32;
-        if (DNSLAB_YZ && P->ny > 1 && P->nz > 1 && nthr > 0 && (long long)P->ny * P->nz <= DNSLAB_YZ_MAX_PLANE &&
+        const long long max_plane = Lo.esz == 8 ? DNSLAB_YZ_MAX_PLANE : DNSLAB_YZ_MAX_PLANE32;
+        if (DNSLAB_YZ && P->ny > 1 && P->nz > 1 && nthr > 0 && (long long)P->ny * P->nz <= max_plane &&
             (long long)q * nthr >= (long long)P->ny * P->nz &&
             Lo.py.tpl <= nthr && Lo.pz.tpl <= nthr) {
             const size_t cap = (size_t)DNSLAB_YZ_LDS_KB * 1024;

@@ -46,12 +46,24 @@ struct FFTArgs {
 };
 
 // Fused plane pass: complex values held in registers per thread, and the
-// block size for ny (a multiple of ny, at most YZ_THREADS; two waves per SIMD
-// leave room for the plane and the butterflies in registers).
-constexpr int YZ_THREADS = 512;
-constexpr int YZ_Q64 = 24;
-constexpr int YZ_Q32 = 32;
-inline int yz_threads(int ny) { return ny > YZ_THREADS ? 0 : ny * (YZ_THREADS / ny); }
+// block size for ny (a multiple of ny, at most YZ_THREADS).  FP64 keeps two
+// waves per SIMD (room for the plane and the butterflies in registers); FP32
+// values take half the registers, so four waves per SIMD fit, and the extra
+// waves hide the LDS and barrier latency of the one block per plane.
+#ifndef DNSLAB_YZ_THREADS32
+#define DNSLAB_YZ_THREADS32 1024
+#endif
+#ifndef DNSLAB_YZ_THREADS64
+#define DNSLAB_YZ_THREADS64 512
+#endif
+constexpr int YZ_THREADS = DNSLAB_YZ_THREADS64;     // FP64
+constexpr int YZ_THREADS32 = DNSLAB_YZ_THREADS32;   // FP32
+constexpr int YZ_Q64 = 12288 / YZ_THREADS;
+constexpr int YZ_Q32 = 16384 / YZ_THREADS32;
+inline int yz_threads(int ny, bool fp32 = false) {
+    const int cap = fp32 ? YZ_THREADS32 : YZ_THREADS;
+    return ny > cap ? 0 : ny * (cap / ny);
+}
 
 // Arguments of the kernels that take more than the FFT description.
 template <typename T>

@@ -754,11 +754,11 @@ __global__ __launch_bounds__(1024) void k_fft_cols_b(const BRec<FFTArgs<T>>* __r
 }
 
 template <typename T>
-__global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const FFTArgs<T> a) {
+__global__ __launch_bounds__(sizeof(T) == 8 ? YZ_THREADS : YZ_THREADS32) void k_fft_yz(const FFTArgs<T> a) {
     fft_yz_body<T, sizeof(T) == 8 ? YZ_Q64 : YZ_Q32>(a, blockIdx.x);
 }
 template <typename T>
-__global__ __launch_bounds__(YZ_THREADS) void k_fft_yz_b(const BRec<FFTArgs<T>>* __restrict__ tab,
+__global__ __launch_bounds__(sizeof(T) == 8 ? YZ_THREADS : YZ_THREADS32) void k_fft_yz_b(const BRec<FFTArgs<T>>* __restrict__ tab,
                                                    const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_BLOCK(st, ns)
     const FFTArgs<T> a = tab[s_].a;
@@ -881,7 +881,7 @@ hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec)
 
 template <typename T>
 hipError_t launch_fft_yz_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec) {
-    const int nthr = yz_threads(a.g.ny);
+    const int nthr = yz_threads(a.g.ny, sizeof(T) == 4);
     const int q = sizeof(T) == 8 ? YZ_Q64 : YZ_Q32;
     if (a.ps != a.g.ny * a.g.nz || nthr <= 0 || (long long)q * nthr < (long long)a.g.ny * a.g.nz ||
         ((long long)a.py.tpl << a.lg_ca) > nthr || ((long long)a.pz.tpl << a.lg_cb) > nthr)
