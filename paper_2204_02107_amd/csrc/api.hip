@@ -213,8 +213,8 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     // It cuts two of the three column passes and their launches, but one
     // block per plane serialises a plane's work on one CU: measured 10%
     // faster steps for planes of 64 x 64, 3% slower for 96 x 64 and 8% for
-    // 128 x 96 (FP64), hence the plane-size limit.  The FP32 form runs
-    // 1024-thread blocks and gains on every plane up to 128 x 96 (6-9%).
+    // 128 x 96 (FP64, 512-thread blocks), hence the plane-size limit; with
+    // 1024-thread blocks (smaller planes, FP32) the pass gains 7-9% more.
     {
         const int nthr = yz_threads(P->ny, Lo.esz == 4);
         const int q = Lo.esz == 8 ? YZ_Q64 : YZ_Q32;

@@ -46,19 +46,22 @@ struct FFTArgs {
 };
 
 // Fused plane pass: complex values held in registers per thread, and the
-// block size for ny (a multiple of ny, at most YZ_THREADS).  FP64 keeps two
-// waves per SIMD (room for the plane and the butterflies in registers); FP32
-// values take half the registers, so four waves per SIMD fit, and the extra
-// waves hide the LDS and barrier latency of the one block per plane.
+// block size for ny (a multiple of ny, at most YZ_THREADS).  1024-thread
+// blocks (four waves per SIMD) hide the LDS and barrier latency of the one
+// block per plane; that leaves 128 registers per thread, enough for planes of
+// 4096 FP64 or 16384 FP32 values.
 #ifndef DNSLAB_YZ_THREADS32
 #define DNSLAB_YZ_THREADS32 1024
 #endif
 #ifndef DNSLAB_YZ_THREADS64
-#define DNSLAB_YZ_THREADS64 512
+#define DNSLAB_YZ_THREADS64 1024
 #endif
 constexpr int YZ_THREADS = DNSLAB_YZ_THREADS64;     // FP64
 constexpr int YZ_THREADS32 = DNSLAB_YZ_THREADS32;   // FP32
-constexpr int YZ_Q64 = 12288 / YZ_THREADS;
+#ifndef DNSLAB_YZ_Q64
+#define DNSLAB_YZ_Q64 (4096 / DNSLAB_YZ_THREADS64)
+#endif
+constexpr int YZ_Q64 = DNSLAB_YZ_Q64;
 constexpr int YZ_Q32 = 16384 / YZ_THREADS32;
 inline int yz_threads(int ny, bool fp32 = false) {
     const int cap = fp32 ? YZ_THREADS32 : YZ_THREADS;
