@@ -149,7 +149,7 @@ Grid make_grid(const dnslab_params* P) {
 #define DNSLAB_YZ_LDS_KB 160
 #endif
 #ifndef DNSLAB_YZ_MAX_PLANE
-#define DNSLAB_YZ_MAX_PLANE 4096   // largest ny * nz given to the fused pass
+#define DNSLAB_YZ_MAX_PLANE 8192   // largest ny * nz given to the fused pass (FP64)
 #endif
 #ifndef DNSLAB_YZ_MAX_PLANE32
 #define DNSLAB_YZ_MAX_PLANE32 16384   // the same for the FP32 form (1024-thread blocks)
@@ -217,10 +217,9 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     // 1024-thread blocks (smaller planes, FP32) the pass gains 7-9% more.
     {
         const int nthr = yz_threads(P->ny, Lo.esz == 4);
-        const int q = Lo.esz == 8 ? YZ_Q64 : YZ_Q32;
         const long long max_plane = Lo.esz == 8 ? DNSLAB_YZ_MAX_PLANE : DNSLAB_YZ_MAX_PLANE32;
         if (DNSLAB_YZ && P->ny > 1 && P->nz > 1 && nthr > 0 && (long long)P->ny * P->nz <= max_plane &&
-            (long long)q * nthr >= (long long)P->ny * P->nz &&
+            yz_values(Lo.esz == 4, nthr, (long long)P->ny * P->nz) > 0 &&
             Lo.py.tpl <= nthr && Lo.pz.tpl <= nthr) {
             const size_t cap = (size_t)DNSLAB_YZ_LDS_KB * 1024;
             const size_t tw = (size_t)(P->ny + P->nz) * csz;

@@ -49,7 +49,7 @@ struct FFTArgs {
 // block size for ny (a multiple of ny, at most YZ_THREADS).  1024-thread
 // blocks (four waves per SIMD) hide the LDS and barrier latency of the one
 // block per plane; that leaves 128 registers per thread, enough for planes of
-// 4096 FP64 or 16384 FP32 values.
+// 8192 FP64 or 16384 FP32 values.
 #ifndef DNSLAB_YZ_THREADS32
 #define DNSLAB_YZ_THREADS32 1024
 #endif
@@ -58,14 +58,19 @@ struct FFTArgs {
 #endif
 constexpr int YZ_THREADS = DNSLAB_YZ_THREADS64;     // FP64
 constexpr int YZ_THREADS32 = DNSLAB_YZ_THREADS32;   // FP32
-#ifndef DNSLAB_YZ_Q64
-#define DNSLAB_YZ_Q64 (4096 / DNSLAB_YZ_THREADS64)
-#endif
-constexpr int YZ_Q64 = DNSLAB_YZ_Q64;
+constexpr int YZ_Q64 = 4;      // planes up to 4096 FP64 values
+constexpr int YZ_Q64B = 8;     // up to 8192 (a few registers spill, so the small planes keep 4)
 constexpr int YZ_Q32 = 16384 / YZ_THREADS32;
 inline int yz_threads(int ny, bool fp32 = false) {
     const int cap = fp32 ? YZ_THREADS32 : YZ_THREADS;
     return ny > cap ? 0 : ny * (cap / ny);
+}
+// Values per thread for a plane of `plane` values on nthr threads (the kernel
+// instance), 0 if no instance holds it.
+inline int yz_values(bool fp32, int nthr, long long plane) {
+    if (fp32) return (long long)YZ_Q32 * nthr >= plane ? YZ_Q32 : 0;
+    if ((long long)YZ_Q64 * nthr >= plane) return YZ_Q64;
+    return (long long)YZ_Q64B * nthr >= plane ? YZ_Q64B : 0;
 }
 
 // Arguments of the kernels that take more than the FFT description.

@@ -753,16 +753,16 @@ __global__ __launch_bounds__(1024) void k_fft_cols_b(const BRec<FFTArgs<T>>* __r
     fft_cols_body<T, MODE>(a, blk_);
 }
 
-template <typename T>
+template <typename T, int Q>
 __global__ __launch_bounds__(sizeof(T) == 8 ? YZ_THREADS : YZ_THREADS32) void k_fft_yz(const FFTArgs<T> a) {
-    fft_yz_body<T, sizeof(T) == 8 ? YZ_Q64 : YZ_Q32>(a, blockIdx.x);
+    fft_yz_body<T, Q>(a, blockIdx.x);
 }
-template <typename T>
+template <typename T, int Q>
 __global__ __launch_bounds__(sizeof(T) == 8 ? YZ_THREADS : YZ_THREADS32) void k_fft_yz_b(const BRec<FFTArgs<T>>* __restrict__ tab,
                                                    const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_BLOCK(st, ns)
     const FFTArgs<T> a = tab[s_].a;
-    fft_yz_body<T, sizeof(T) == 8 ? YZ_Q64 : YZ_Q32>(a, blk_);
+    fft_yz_body<T, Q>(a, blk_);
 }
 
 inline int round64(int t) { return ((t + 63) / 64) * 64; }
@@ -882,19 +882,23 @@ hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec)
 template <typename T>
 hipError_t launch_fft_yz_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec) {
     const int nthr = yz_threads(a.g.ny, sizeof(T) == 4);
-    const int q = sizeof(T) == 8 ? YZ_Q64 : YZ_Q32;
-    if (a.ps != a.g.ny * a.g.nz || nthr <= 0 || (long long)q * nthr < (long long)a.g.ny * a.g.nz ||
+    const int q = yz_values(sizeof(T) == 4, nthr, (long long)a.g.ny * a.g.nz);
+    if (a.ps != a.g.ny * a.g.nz || nthr <= 0 || q == 0 ||
         ((long long)a.py.tpl << a.lg_ca) > nthr || ((long long)a.pz.tpl << a.lg_cb) > nthr)
         return hipErrorInvalidValue;
     const dim3 grid(a.m + 1), block(nthr);
     const size_t lds = ((size_t)a.g.ny + a.g.nz +
                         std::max((size_t)a.g.ny * ((1 << a.lg_ca) + 1), (size_t)a.g.nz * ((1 << a.lg_cb) + 1))) *
                        sizeof(C2<T>);
+    // kind mode 3: the smaller per-thread value count, 4: the larger one
+    const bool big = sizeof(T) == 8 && q == YZ_Q64B;
     if (rec) {
-        record_launch(rec, kind_code(KK_COLS, 3, sizeof(T) == 4), grid, block, lds, a);
+        record_launch(rec, kind_code(KK_COLS, big ? 4 : 3, sizeof(T) == 4), grid, block, lds, a);
         return hipSuccess;
     }
-    hipLaunchKernelGGL((k_fft_yz<T>), grid, block, lds, s, a);
+    if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_fft_yz<T, YZ_Q32>), grid, block, lds, s, a);
+    else if (big) hipLaunchKernelGGL((k_fft_yz<T, YZ_Q64B>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_fft_yz<T, YZ_Q64>), grid, block, lds, s, a);
     return hipGetLastError();
 }
 
@@ -918,7 +922,9 @@ hipError_t fft_batched_typed(int base, int mode, const void* tab, const unsigned
             if (mode == 0) hipLaunchKernelGGL((k_fft_cols_b<T, 0>), grid, blk, lds, s, t, st, ns);
             else if (mode == 1) hipLaunchKernelGGL((k_fft_cols_b<T, 1>), grid, blk, lds, s, t, st, ns);
             else if (mode == 2) hipLaunchKernelGGL((k_fft_cols_b<T, 2>), grid, blk, lds, s, t, st, ns);
-            else hipLaunchKernelGGL((k_fft_yz_b<T>), grid, blk, lds, s, t, st, ns);
+            else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_Q32>), grid, blk, lds, s, t, st, ns);
+            else if (mode == 3) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_Q64>), grid, blk, lds, s, t, st, ns);
+            else hipLaunchKernelGGL((k_fft_yz_b<T, YZ_Q64B>), grid, blk, lds, s, t, st, ns);
             break;
         }
         default:

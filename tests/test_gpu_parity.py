@@ -82,7 +82,7 @@ def test_filter(shape):
     assert rel_err(got, ref) < 1e-13
 
 
-@pytest.mark.parametrize("shape", SHAPES + [(1, 1, 4), (8, 2, 4), (24, 48, 12), (36, 18, 54)])
+@pytest.mark.parametrize("shape", SHAPES + [(1, 1, 4), (8, 2, 4), (24, 48, 12), (36, 18, 54), (128, 64, 16), (72, 96, 8)])
 def test_poisson(shape):
     torch, m = need_gpu()
     sc = make_case(shape, 14, masked=False, forced=False)
