@@ -12,12 +12,12 @@ numpy float64, periodic shifts with ``np.roll`` and ``numpy.fft.rfftn`` /
 ``irfftn`` for the Poisson solve.  Arrays have shape (nz, ny, nx) (x fastest);
 axis a = 0, 1, 2 means x, y, z.
 
-Parity status of each function is stated in its docstring.  Everything here
-is pinned by the tests under ``tests/test_oracle_*.py`` (closed forms,
-invariants, brute-force loops on tiny grids, dense linear algebra), except the
-immersed-boundary iteration on masked grids, whose converged value has no
-closed form: it is pinned through its fixed point and monotone error
-decrease, and beyond that invariant level its parity is unpinned.
+Parity status: everything here is pinned by the tests under ``tests/test_oracle_*.py`` (closed forms,
+invariants, brute-force loops on tiny grids, dense linear algebra).  The
+immersed-boundary iteration on masked grids is pinned iterate by iterate
+against the same iteration written with dense difference matrices built from
+the cell indices and a dense pseudo-inverse, and its fixed point against a
+dense solve of the masked pressure equation.
 """
 from .ops import (shift, ddx, div, grad, lap, conv_skew, conv_scalar, lap_masked,
                   delta6, filter6, poisson_symbol, poisson_solve, ib_rhs)

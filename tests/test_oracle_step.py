@@ -213,6 +213,56 @@ def test_ib_iteration_fixed_point_and_monotone_error():
     assert np.sqrt(sum(np.sum(x * x) for x in bg)) < 0.05 * e0
 
 
+def _central_difference_matrices(shape, d):
+    """Periodic central first differences (p[i+1] - p[i-1]) / (2 d_a) along x, y
+    and z as dense matrices, entry by entry from the cell indices (no use of
+    the oracle's stencils)."""
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    mats = []
+    for a, (na, da) in enumerate(zip((nx, ny, nz), d)):
+        G = np.zeros((n, n))
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    row = (k * ny + j) * nx + i
+                    c = [i, j, k]
+                    for sgn in (1, -1):
+                        q = list(c)
+                        q[a] = (q[a] + sgn) % na
+                        G[row, (q[2] * ny + q[1]) * nx + q[0]] += sgn / (2.0 * da)
+        mats.append(G)
+    return mats
+
+
+@pytest.mark.parametrize("n_iter", [1, 4])
+def test_ib_iterates_equal_dense_iteration(n_iter):
+    """Section 2.2: each iterate is the minimum-norm solution of
+    Div Grad p^{k+1} = Div u* + Div((1 - beta) Grad p^k).  With Div, Grad and
+    the pseudo-inverse written as dense matrices on a tiny masked grid, the
+    oracle's n iterates from a random warm start must match one by one (the
+    null modes of Div Grad carry no pressure in either)."""
+    shape = (4, 5, 6)
+    d = (0.3, 0.45, 0.7)
+    beta = scenarios.random_beta(shape, 21, n_boxes=2, max_size=2)
+    O = make(shape, (d[0] * shape[2], d[1] * shape[1], d[2] * shape[0]), beta=beta)
+    assert np.allclose(O.P.d, d)
+    rng = np.random.default_rng(22)
+    us = [rng.standard_normal(shape) * beta for _ in range(3)]
+    p = rng.standard_normal(shape).ravel()
+    G = _central_difference_matrices(shape, d)
+    omb = np.diag(1.0 - beta.astype(np.float64).ravel())
+    A = sum(Ga @ Ga for Ga in G)
+    M = sum(Ga @ omb @ Ga for Ga in G)
+    r0 = sum(Ga @ u.ravel() for Ga, u in zip(G, us))
+    Ainv = np.linalg.pinv(A)
+    its = O.pressure(us, p.reshape(shape), n_iter=n_iter)
+    assert len(its) == n_iter
+    for got in its:
+        p = Ainv @ (r0 + M @ p)
+        np.testing.assert_allclose(got.ravel(), p, atol=1e-11 * np.abs(p).max())
+
+
 def test_tgv3d_early_decay():
     """3D Taylor-Green, 32^3, Re = 100: kinetic energy follows the viscous
     decay of the discrete Laplacian to within 1e-3 at t = 0.1 (convection
