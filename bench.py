@@ -92,6 +92,12 @@ WORKLOADS = {
     "hall": "hall 1024x512x256 (40x20x10 m), ceiling plenum, 4 forced inlets, 2 outlets, 64 seeded boxes, "
             "1 m/s, CFL 0.3, filter on, 4 IB pressure iterations",
 }
+# Smaller rooms (the grid sizes of the serving stream), where the y/z passes of
+# each solve run as one fused pass: 10 m long, 4 seeded boxes, otherwise as the room.
+SMALL_ROOMS = {"room64": (64, 64, 64), "room128": (128, 64, 64), "room192": (192, 96, 64)}
+for _k, _g in SMALL_ROOMS.items():
+    WORKLOADS[_k] = (f"room {_g[0]}x{_g[1]}x{_g[2]} (10 m long), 4 seeded boxes, 1 m/s duct, CFL 0.3, "
+                     "filter on, 4 IB pressure iterations")
 
 
 def workload(name="room"):
@@ -102,6 +108,9 @@ def workload(name="room"):
         return scenarios.room(512, 256, 192, dx=10.0 / 512)
     if name == "hall":
         return scenarios.hall()
+    if name in SMALL_ROOMS:
+        g = SMALL_ROOMS[name]
+        return scenarios.room(*g, dx=10.0 / g[0], n_boxes=4)
     raise ValueError(name)
 
 
