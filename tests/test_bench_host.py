@@ -20,6 +20,8 @@ def test_kernel_key_mapping():
     assert k("void dnslab::(anonymous namespace)::k_fft_cols<double, 2>(dnslab::FFTArgs<double>)") == "fft_z"
     assert k("void dnslab::(anonymous namespace)::k_fft_cols<float, 1>(dnslab::FFTArgs<float>)") == "fft_y"
     assert k("void dnslab::(anonymous namespace)::k_fft_yz<double>(dnslab::FFTArgs<double>)") == "fft_yz"
+    assert k("void dnslab::(anonymous namespace)::k_fft_yz<double, 8>(dnslab::FFTArgs<double>)") == "fft_yz"
+    assert k("void dnslab::(anonymous namespace)::k_fft_yz_b<float, 16>(dnslab::BRec<...> const*)") == "fft_yz"
     assert k("dnslab::(anonymous namespace)::k_refine_correct(dnslab::RefineCorrArgs)") == "correct"
     assert k("dnslab::(anonymous namespace)::k_refine_res(dnslab::RefineResArgs)") == "refine_res"
     assert k("dnslab::(anonymous namespace)::k_refine_res_ib(dnslab::RefineResArgs)") == "refine_res_ib"
@@ -73,3 +75,13 @@ def test_step_byte_model():
     assert abs(per - fused - 4 * (2 * 2 * 8.25)) < 1e-9
     assert bench.step_bytes(sc, 8, per_stage=True) > 2 * bench.step_bytes(sc, 8)
     assert bench.step_bytes(sc, 4) < 0.6 * bench.step_bytes(sc, 8)
+
+
+def test_small_room_workloads():
+    """The serving-stream room sizes are bench workloads of their own: 10 m
+    long rooms with 4 boxes, each with a description naming its grid."""
+    for name, g in bench.SMALL_ROOMS.items():
+        sc = bench.workload(name)
+        assert (sc.nx, sc.ny, sc.nz) == g
+        assert np.isclose(sc.spacing[0] * sc.nx, 10.0)
+        assert f"{g[0]}x{g[1]}x{g[2]}" in bench.WORKLOADS[name]
