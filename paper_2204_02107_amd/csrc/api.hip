@@ -219,7 +219,7 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
         const int nthr = yz_threads(P->ny, Lo.esz == 4);
         const long long max_plane = Lo.esz == 8 ? DNSLAB_YZ_MAX_PLANE : DNSLAB_YZ_MAX_PLANE32;
         if (DNSLAB_YZ && P->ny > 1 && P->nz > 1 && nthr > 0 && (long long)P->ny * P->nz <= max_plane &&
-            yz_values(Lo.esz == 4, nthr, (long long)P->ny * P->nz) > 0 &&
+            yz_instance(Lo.esz == 4, nthr, (long long)P->ny * P->nz) >= 0 &&
             Lo.py.tpl <= nthr && Lo.pz.tpl <= nthr) {
             const size_t cap = (size_t)DNSLAB_YZ_LDS_KB * 1024;
             const size_t tw = (size_t)(P->ny + P->nz) * csz;

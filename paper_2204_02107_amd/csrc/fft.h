@@ -58,19 +58,22 @@ struct FFTArgs {
 #endif
 constexpr int YZ_THREADS = DNSLAB_YZ_THREADS64;     // FP64
 constexpr int YZ_THREADS32 = DNSLAB_YZ_THREADS32;   // FP32
-constexpr int YZ_Q64 = 4;      // planes up to 4096 FP64 values
-constexpr int YZ_Q64B = 8;     // up to 8192 (a few registers spill, so the small planes keep 4)
-constexpr int YZ_Q32 = 16384 / YZ_THREADS32;
+// Values per thread of the kernel instances: the smallest that holds the plane
+// is used, since the larger ones need more registers (FP64 with 8 spills a few).
+constexpr int YZ_QS[3] = {4, 8, 16};
+constexpr int YZ_NQ64 = 2;     // FP64: 4 and 8 (planes up to 8192 values)
+constexpr int YZ_NQ32 = 3;     // FP32: 4, 8 and 16 (planes up to 16384 values)
 inline int yz_threads(int ny, bool fp32 = false) {
     const int cap = fp32 ? YZ_THREADS32 : YZ_THREADS;
     return ny > cap ? 0 : ny * (cap / ny);
 }
-// Values per thread for a plane of `plane` values on nthr threads (the kernel
-// instance), 0 if no instance holds it.
-inline int yz_values(bool fp32, int nthr, long long plane) {
-    if (fp32) return (long long)YZ_Q32 * nthr >= plane ? YZ_Q32 : 0;
-    if ((long long)YZ_Q64 * nthr >= plane) return YZ_Q64;
-    return (long long)YZ_Q64B * nthr >= plane ? YZ_Q64B : 0;
+// Index into YZ_QS of the instance for a plane of `plane` values on nthr
+// threads, -1 if no instance holds it.
+inline int yz_instance(bool fp32, int nthr, long long plane) {
+    const int nq = fp32 ? YZ_NQ32 : YZ_NQ64;
+    for (int i = 0; i < nq; ++i)
+        if ((long long)YZ_QS[i] * nthr >= plane) return i;
+    return -1;
 }
 
 // Arguments of the kernels that take more than the FFT description.

@@ -731,7 +731,7 @@ template <typename T>
 __global__ __launch_bounds__(1024) void k_fft_x_fwd_b(const BRec<FxfArgs<T>>* __restrict__ tab,
                                                       const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_BLOCK(st, ns)
-    const FxfArgs<T> a = tab[s_].a;
+    const FxfArgs<T>& a = tab[s_].a;
     fft_x_fwd_body<T>(a, blk_);
 }
 template <typename T>
@@ -740,7 +740,7 @@ template <typename T>
 __global__ __launch_bounds__(1024) void k_fft_x_inv_b(const BRec<FxiArgs<T>>* __restrict__ tab,
                                                       const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_BLOCK(st, ns)
-    const FxiArgs<T> a = tab[s_].a;
+    const FxiArgs<T>& a = tab[s_].a;
     fft_x_inv_body<T>(a, blk_);
 }
 template <typename T, int MODE>
@@ -749,7 +749,7 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_fft_cols_b(const BRec<FFTArgs<T>>* __restrict__ tab,
                                                      const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_BLOCK(st, ns)
-    const FFTArgs<T> a = tab[s_].a;
+    const FFTArgs<T>& a = tab[s_].a;   // read in place: a private copy of the plan would sit in scratch
     fft_cols_body<T, MODE>(a, blk_);
 }
 
@@ -761,7 +761,7 @@ template <typename T, int Q>
 __global__ __launch_bounds__(sizeof(T) == 8 ? YZ_THREADS : YZ_THREADS32) void k_fft_yz_b(const BRec<FFTArgs<T>>* __restrict__ tab,
                                                    const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_BLOCK(st, ns)
-    const FFTArgs<T> a = tab[s_].a;
+    const FFTArgs<T>& a = tab[s_].a;   // read in place: a private copy of the plan would sit in scratch
     fft_yz_body<T, Q>(a, blk_);
 }
 
@@ -882,23 +882,23 @@ hipError_t launch_fft_z_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec)
 template <typename T>
 hipError_t launch_fft_yz_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec) {
     const int nthr = yz_threads(a.g.ny, sizeof(T) == 4);
-    const int q = yz_values(sizeof(T) == 4, nthr, (long long)a.g.ny * a.g.nz);
-    if (a.ps != a.g.ny * a.g.nz || nthr <= 0 || q == 0 ||
+    const int qi = nthr > 0 ? yz_instance(sizeof(T) == 4, nthr, (long long)a.g.ny * a.g.nz) : -1;
+    if (a.ps != a.g.ny * a.g.nz || nthr <= 0 || qi < 0 ||
         ((long long)a.py.tpl << a.lg_ca) > nthr || ((long long)a.pz.tpl << a.lg_cb) > nthr)
         return hipErrorInvalidValue;
     const dim3 grid(a.m + 1), block(nthr);
     const size_t lds = ((size_t)a.g.ny + a.g.nz +
                         std::max((size_t)a.g.ny * ((1 << a.lg_ca) + 1), (size_t)a.g.nz * ((1 << a.lg_cb) + 1))) *
                        sizeof(C2<T>);
-    // kind mode 3: the smaller per-thread value count, 4: the larger one
-    const bool big = sizeof(T) == 8 && q == YZ_Q64B;
+    // kind modes 3, 4, 5: the instances with YZ_QS[0], [1], [2] values per thread
     if (rec) {
-        record_launch(rec, kind_code(KK_COLS, big ? 4 : 3, sizeof(T) == 4), grid, block, lds, a);
+        record_launch(rec, kind_code(KK_COLS, 3 + qi, sizeof(T) == 4), grid, block, lds, a);
         return hipSuccess;
     }
-    if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_fft_yz<T, YZ_Q32>), grid, block, lds, s, a);
-    else if (big) hipLaunchKernelGGL((k_fft_yz<T, YZ_Q64B>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_fft_yz<T, YZ_Q64>), grid, block, lds, s, a);
+    if (qi == 0) hipLaunchKernelGGL((k_fft_yz<T, YZ_QS[0]>), grid, block, lds, s, a);
+    else if (qi == 1) hipLaunchKernelGGL((k_fft_yz<T, YZ_QS[1]>), grid, block, lds, s, a);
+    else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_fft_yz<T, YZ_QS[2]>), grid, block, lds, s, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -922,9 +922,10 @@ hipError_t fft_batched_typed(int base, int mode, const void* tab, const unsigned
             if (mode == 0) hipLaunchKernelGGL((k_fft_cols_b<T, 0>), grid, blk, lds, s, t, st, ns);
             else if (mode == 1) hipLaunchKernelGGL((k_fft_cols_b<T, 1>), grid, blk, lds, s, t, st, ns);
             else if (mode == 2) hipLaunchKernelGGL((k_fft_cols_b<T, 2>), grid, blk, lds, s, t, st, ns);
-            else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_Q32>), grid, blk, lds, s, t, st, ns);
-            else if (mode == 3) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_Q64>), grid, blk, lds, s, t, st, ns);
-            else hipLaunchKernelGGL((k_fft_yz_b<T, YZ_Q64B>), grid, blk, lds, s, t, st, ns);
+            else if (mode == 3) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_QS[0]>), grid, blk, lds, s, t, st, ns);
+            else if (mode == 4) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_QS[1]>), grid, blk, lds, s, t, st, ns);
+            else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_QS[2]>), grid, blk, lds, s, t, st, ns);
+            else return hipErrorInvalidValue;
             break;
         }
         default:
