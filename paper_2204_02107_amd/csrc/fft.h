@@ -60,9 +60,15 @@ constexpr int YZ_THREADS = DNSLAB_YZ_THREADS64;     // FP64
 constexpr int YZ_THREADS32 = DNSLAB_YZ_THREADS32;   // FP32
 // Values per thread of the kernel instances: the smallest that holds the plane
 // is used, since the larger ones need more registers (FP64 with 8 spills a few).
-constexpr int YZ_QS[3] = {4, 8, 16};
-constexpr int YZ_NQ64 = 2;     // FP64: 4 and 8 (planes up to 8192 values)
-constexpr int YZ_NQ32 = 3;     // FP32: 4, 8 and 16 (planes up to 16384 values)
+// FP64: 4, 6, 8 (planes up to 8192 values); FP32: 4, 8, 12, 16 (up to 16384).
+// The FP64 table repeats its last entry so that both have YZ_NQ_MAX entries.
+constexpr int YZ_NQ_MAX = 4;
+constexpr int YZ_QS64[YZ_NQ_MAX] = {4, 6, 8, 8};
+constexpr int YZ_QS32[YZ_NQ_MAX] = {4, 8, 12, 16};
+constexpr int YZ_NQ64 = 3;
+constexpr int YZ_NQ32 = 4;
+template <typename T>
+constexpr int yz_q(int i) { return sizeof(T) == 8 ? YZ_QS64[i] : YZ_QS32[i]; }
 inline int yz_threads(int ny, bool fp32 = false) {
     const int cap = fp32 ? YZ_THREADS32 : YZ_THREADS;
     return ny > cap ? 0 : ny * (cap / ny);
@@ -72,7 +78,7 @@ inline int yz_threads(int ny, bool fp32 = false) {
 inline int yz_instance(bool fp32, int nthr, long long plane) {
     const int nq = fp32 ? YZ_NQ32 : YZ_NQ64;
     for (int i = 0; i < nq; ++i)
-        if ((long long)YZ_QS[i] * nthr >= plane) return i;
+        if ((long long)(fp32 ? YZ_QS32[i] : YZ_QS64[i]) * nthr >= plane) return i;
     return -1;
 }
 

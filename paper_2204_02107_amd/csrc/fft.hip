@@ -890,15 +890,18 @@ hipError_t launch_fft_yz_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec
     const size_t lds = ((size_t)a.g.ny + a.g.nz +
                         std::max((size_t)a.g.ny * ((1 << a.lg_ca) + 1), (size_t)a.g.nz * ((1 << a.lg_cb) + 1))) *
                        sizeof(C2<T>);
-    // kind modes 3, 4, 5: the instances with YZ_QS[0], [1], [2] values per thread
+    // kind modes 3 + i: the instance with yz_q<T>(i) values per thread
     if (rec) {
         record_launch(rec, kind_code(KK_COLS, 3 + qi, sizeof(T) == 4), grid, block, lds, a);
         return hipSuccess;
     }
-    if (qi == 0) hipLaunchKernelGGL((k_fft_yz<T, YZ_QS[0]>), grid, block, lds, s, a);
-    else if (qi == 1) hipLaunchKernelGGL((k_fft_yz<T, YZ_QS[1]>), grid, block, lds, s, a);
-    else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_fft_yz<T, YZ_QS[2]>), grid, block, lds, s, a);
-    else return hipErrorInvalidValue;
+    switch (qi) {
+        case 0: hipLaunchKernelGGL((k_fft_yz<T, yz_q<T>(0)>), grid, block, lds, s, a); break;
+        case 1: hipLaunchKernelGGL((k_fft_yz<T, yz_q<T>(1)>), grid, block, lds, s, a); break;
+        case 2: hipLaunchKernelGGL((k_fft_yz<T, yz_q<T>(2)>), grid, block, lds, s, a); break;
+        case 3: hipLaunchKernelGGL((k_fft_yz<T, yz_q<T>(3)>), grid, block, lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -922,9 +925,10 @@ hipError_t fft_batched_typed(int base, int mode, const void* tab, const unsigned
             if (mode == 0) hipLaunchKernelGGL((k_fft_cols_b<T, 0>), grid, blk, lds, s, t, st, ns);
             else if (mode == 1) hipLaunchKernelGGL((k_fft_cols_b<T, 1>), grid, blk, lds, s, t, st, ns);
             else if (mode == 2) hipLaunchKernelGGL((k_fft_cols_b<T, 2>), grid, blk, lds, s, t, st, ns);
-            else if (mode == 3) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_QS[0]>), grid, blk, lds, s, t, st, ns);
-            else if (mode == 4) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_QS[1]>), grid, blk, lds, s, t, st, ns);
-            else if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_fft_yz_b<T, YZ_QS[2]>), grid, blk, lds, s, t, st, ns);
+            else if (mode == 3) hipLaunchKernelGGL((k_fft_yz_b<T, yz_q<T>(0)>), grid, blk, lds, s, t, st, ns);
+            else if (mode == 4) hipLaunchKernelGGL((k_fft_yz_b<T, yz_q<T>(1)>), grid, blk, lds, s, t, st, ns);
+            else if (mode == 5) hipLaunchKernelGGL((k_fft_yz_b<T, yz_q<T>(2)>), grid, blk, lds, s, t, st, ns);
+            else if (mode == 6) hipLaunchKernelGGL((k_fft_yz_b<T, yz_q<T>(3)>), grid, blk, lds, s, t, st, ns);
             else return hipErrorInvalidValue;
             break;
         }

@@ -57,6 +57,18 @@ def test_fp32_poisson_longest_lines(shape):
     assert rel_err(to_np(S.poisson(r)), ops.poisson_solve(r, sc.spacing)) < 1e-5
 
 
+@pytest.mark.parametrize("shape", [(64, 64, 8), (96, 64, 8), (96, 128, 8), (128, 128, 4), (144, 96, 4)])
+def test_fp32_poisson_fused_plane_sizes(shape):
+    """Planes of 4096, 6144, 12288, 16384 and 13824 (960-thread block) FP32
+    values: each instance of the fused y/z pass, up to the largest plane."""
+    torch, m = need_gpu()
+    sc = make_case(shape, 24, masked=False, forced=False, filt=False)
+    announce(f"fp32 poisson fused planes {shape}")
+    S = m.Solver(sc, precision=m.FP32_REFINE)
+    r = np.random.default_rng(4).standard_normal(shape)
+    assert rel_err(to_np(S.poisson(r)), ops.poisson_solve(r, sc.spacing)) < 1e-5
+
+
 @pytest.mark.parametrize("masked", [False, True])
 def test_fp32_project_refined(masked):
     """The refined projection matches the FP64 projection to FP32 storage
