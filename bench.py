@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the full projection time step on one MI355X.
 
-Workload: the ventilated room, 256 x 128 x 96 cells (10 x 5 x 3.75 m, dx = 3.9 cm),
-2-cell solid walls, a 0.3 m duct blowing 1 m/s through the periodic seam, 8
-seeded obstacles, CO2 1000 ppm inside and 400 ppm supply, FP64, CFL 0.3,
-sixth-order filter on, four immersed-boundary FFT pressure iterations per step.
-A step is the whole hot path: dt, momentum RK4, divergence, 4 x (IB right-hand
-side + 3D real FFT + spectral solve + inverse FFT), correction, scalar RK4,
-filter, FP64 diagnostics.
+Default workload: the hall, 1024 x 512 x 256 cells (134M; 40 x 20 x 10 m,
+dx = 3.9 cm), 2-cell solid walls, a ceiling slab with a 16-cell return plenum,
+4 forced inlet vents blowing 1 m/s down, 2 outlet vents, 64 seeded obstacles,
+CO2 1000 ppm in the hall and 400 ppm supply, CFL 0.3, sixth-order filter on,
+four immersed-boundary FFT pressure iterations per step; FP64 (the headline),
+then the same workload in the FP32 form with FP64 refinement.  A step is the
+whole hot path: dt, momentum RK4, divergence, 4 x (IB right-hand side + 3D
+real FFT + spectral solve + inverse FFT), correction, scalar RK4, filter, FP64
+diagnostics.
 
 Prints one JSON line.  ``value`` is Gcell-steps/s with all inputs resident in
 HBM.  ``roofline`` prices the dominant kernel's algorithmic bytes per launch
 against its average launch time, measured with HIP events recorded by the
-library on its own stream.  ``cpu_baseline`` times the FP64 CPU oracle on a
-bounded sample of the same workload on this host.
+library on the stream each launch goes to.  ``cpu_baseline`` times the FP64
+CPU oracle on whole steps of the same workload on this host, in a child
+process that runs beside the GPU measurements.  ``serving`` runs the request
+stream of 64 room scenarios x 2000 steps.
 """
 from __future__ import annotations
 
@@ -114,28 +118,66 @@ def workload(name="room"):
     raise ValueError(name)
 
 
-def cpu_baseline(sc, budget_s=20.0):
-    """Time the oracle (plain numpy FP64, single thread) on whole steps of the
-    same workload until about budget_s seconds have passed."""
+def cpu_baseline_child(workload_name, steps):
+    """Run in a child process (``bench.py --cpu-oracle WORKLOAD STEPS``): time
+    the oracle (plain numpy FP64) on whole steps of the workload from its
+    initial state and print one JSON line.  Set-up (scenario generation,
+    dense forcing arrays) is not timed."""
     from oracle.step import Oracle
+    sc = workload(workload_name)
     O = Oracle.from_scenario(sc)
     st = Oracle.state_from_scenario(sc)
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
+    times = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
         st, _ = O.step(st)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or steps >= 10:
-            break
+        times.append(time.perf_counter() - t0)
+        print(f"[cpu-oracle] {workload_name} step {len(times)}/{steps}: {times[-1]:.1f} s", file=sys.stderr,
+              flush=True)
+    el = sum(times)
+    try:
+        import resource
+        rss_gb = resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 1e6
+    except Exception:
+        rss_gb = None
+    print(json.dumps({"cells": sc.ncells, "steps": steps, "seconds": el, "step_s": times, "rss_GB": rss_gb}),
+          flush=True)
+
+
+def start_cpu_baseline(workload_name, steps):
+    """Start the oracle timing in a child process (before this process touches
+    the GPU); returns the Popen."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-oracle", workload_name, str(steps)],
+                            stdout=subprocess.PIPE, stderr=None, env=env, cwd=ROOT)
+
+
+def finish_cpu_baseline(proc, workload_name, timeout_s):
+    """Collect the child's timing (waiting at most timeout_s); None if it did
+    not finish in time or failed."""
+    import subprocess
+    try:
+        out, _ = proc.communicate(timeout=max(1.0, timeout_s))
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        proc.communicate()
+        print("[bench] the CPU oracle did not finish in time; no cpu_baseline", file=sys.stderr, flush=True)
+        return None
+    if proc.returncode != 0:
+        print(f"[bench] the CPU oracle failed (exit {proc.returncode}); no cpu_baseline", file=sys.stderr, flush=True)
+        return None
+    r = json.loads(out.decode().strip().splitlines()[-1])
+    el = r["seconds"]
     return {
-        "value": sc.ncells * steps / el / 1e9,
+        "value": r["cells"] * r["steps"] / el / 1e9,
         "unit": "Gcell-steps/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{steps} full steps of the same 256x128x96 room from its initial state, "
-                  f"{el:.1f} s wall on 1 of {os.cpu_count()} host cores (numpy elementwise and "
-                  f"pocketfft run single-threaded)",
+        "sample": f"{r['steps']} full step(s) of the same workload ({WORKLOADS[workload_name]}, FP64) from its "
+                  f"initial state, {el:.1f} s wall in a child process on 1 of {os.cpu_count()} host cores (numpy "
+                  f"elementwise and pocketfft run single-threaded), beside the GPU measurements; peak host "
+                  f"memory {r['rss_GB']:.1f} GB",
     }
 
 
@@ -184,24 +226,34 @@ def particle_bench(S, sc, esz, n=1 << 20, steps=100, seed=5):
                        "kernel_avg_us": 1e6 * per_s, "algorithmic_GBs": b / per_s / 1e9}}
 
 
-def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7, log=None):
+SERVING_POLICIES = ("pool_fp32_refine", "pool_fp64", "fifo_fp64")
+
+
+def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7, log=None,
+                  policies=("pool_fp32_refine", "fifo_fp64")):
     """The serving stream: Poisson arrivals of room scenarios of four grid
-    sizes, served (a) with continuous batching in the pool (FP32 with FP64
-    refinement, and FP64; HBM budget deliberately small so admission binds)
-    and (b) FIFO with the plain per-scenario FP64 loop.  Returns the summaries."""
+    sizes, served with continuous batching in the pool (FP32 with FP64
+    refinement, or FP64; HBM budget deliberately small so admission binds)
+    and FIFO with the plain per-scenario FP64 loop.  Returns the summaries."""
     import scenarios
     from paper_2204_02107_amd import serving, FP32_REFINE, FP64
     reqs = scenarios.serving_requests(n_req, seed=seed, mean_gap=mean_gap, n_steps=n_steps)
     cases = {r["id"]: scenarios.serving_scenario(r) for r in reqs}
-    pooled = serving.serve(reqs, cases, int(budget_gib * (1 << 30)), FP32_REFINE, log=log)
-    pooled64 = serving.serve(reqs, cases, int(budget_gib * (1 << 30)), FP64, log=log)
-    base = serving.fifo(reqs, cases, FP64, log=log)
-    out = {
-        "requests": n_req, "steps_each": n_steps, "mean_gap_s": mean_gap, "hbm_budget_GiB": budget_gib,
-        "pool_fp32_refine": serving.summarize(pooled),
-        "pool_fp64": serving.summarize(pooled64),
-        "fifo_fp64": serving.summarize(base),
-    }
+    out = {"requests": n_req, "steps_each": n_steps, "mean_gap_s": mean_gap, "hbm_budget_GiB": budget_gib,
+           "stream_seed": seed, "cells_total": int(sum(c.ncells for c in cases.values()))}
+    budget = int(budget_gib * (1 << 30))
+    for pol in policies:
+        if pol == "pool_fp32_refine":
+            rec = serving.serve(reqs, cases, budget, FP32_REFINE, log=log)
+        elif pol == "pool_fp64":
+            rec = serving.serve(reqs, cases, budget, FP64, log=log)
+        elif pol == "fifo_fp64":
+            rec = serving.fifo(reqs, cases, FP64, log=log)
+        else:
+            raise ValueError(pol)
+        out[pol] = serving.summarize(rec)
+        if log:
+            log(f"{pol}: " + json.dumps(out[pol]))
     return out
 
 
@@ -282,7 +334,7 @@ def consistency_run(workload_name="room", steps=2000, chunk=400):
         S.close()
         d = diags[-1]
         out[name] = {"t_end_s": d["t"], "wall_s": el, "Gcell_steps_s": sc.ncells * steps / el / 1e9, "ke": d["ke"],
-                     "co2_room_mean_end": d["co2_room_mean"], "ach_fit_per_h": postproc.fitted_ach(diags[steps // 10:]),
+                     "co2_room_mean_end": d["co2_room_mean"], "ach_fit_per_h": postproc.fitted_ach(diags[steps // 10:], c_out=400.0),
                      "div_l2_end": d["div_l2"]}
     a, b = out["fp64"], out["fp32_refine"]
     out["ach_rel_diff"] = abs(b["ach_fit_per_h"] - a["ach_fit_per_h"]) / abs(a["ach_fit_per_h"])
@@ -365,19 +417,100 @@ def traffic_table(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_byt
     return {"fetch_scale": f_scale, "write_scale": w_scale, "kernels": out}
 
 
+def measure(sc, prec, args, label):
+    """Time args.steps whole steps (after args.warmup) of one workload in one
+    precision, then each kernel's launches with HIP events: once in the step's
+    own two-stream schedule, once with every launch alone on one stream."""
+    import torch
+    import paper_2204_02107_amd as m
+    esz = 8 if prec == m.FP64 else 4
+    dev = torch.device("cuda:0")
+    S = m.Solver(sc, precision=prec, device=dev, project_each_stage=args.per_stage)
+    print(f"[bench] {label}: workload {sc.name} cells={sc.ncells} warmup={args.warmup}", file=sys.stderr, flush=True)
+    S.step(args.warmup, diag=False)
+    torch.cuda.synchronize()
+    # timed region: exactly K steps, bracketed by synchronisation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(args.steps, diag=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hist = S.read_diags(1)[0]
+    value = sc.ncells * args.steps / el / 1e9
+    print(f"[bench] {label}: {args.steps} steps in {el:.3f} s -> {value:.3f} Gcell-steps/s; "
+          f"t={hist['t']:.4f} ke={hist['ke']:.4e} co2_mean={hist['co2_room_mean']:.4f}",
+          file=sys.stderr, flush=True)
+    kb = kernel_bytes(sc, esz)
+
+    def per_kernel():
+        per = {}
+        for name in kb:
+            if name == "refine_res" and prec == m.FP64:
+                continue
+            S.profile(name)
+            S.step(args.profile_steps, diag=False)
+            ms, nl = S.profile_read()
+            S.profile(None)
+            if nl:
+                per[name] = {"avg_us": 1e3 * ms / nl, "launches_per_step": nl / args.profile_steps,
+                             "ms_per_step": ms / args.profile_steps, "GBs": kb[name] / (1e-3 * ms / nl) / 1e9}
+        return per
+
+    per = per_kernel()
+    S.set_overlap(False)
+    alone = per_kernel()
+    S.set_overlap(True)
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    dom = max(per, key=lambda k: per[k]["ms_per_step"])
+    print(f"[bench] {label} per-kernel: " + json.dumps({k: {kk: round(vv, 3) for kk, vv in v.items()}
+                                                       for k, v in per.items()}), file=sys.stderr, flush=True)
+    sbytes = step_bytes(sc, esz, args.per_stage, fused_yz="fft_yz" in per)
+    rnd = lambda d: {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["GBs"], 1),
+                         "frac": round(v["GBs"] / HBM_PEAK_GBS, 3), "launches_per_step": v["launches_per_step"]}
+                     for k, v in d.items()}
+    return {
+        "value": value, "ms_per_step": 1e3 * el / args.steps, "steps": args.steps,
+        "step_bytes_per_cell": sbytes / sc.ncells,
+        "hbm_frac_end_to_end": sbytes * (value * 1e9 / sc.ncells) / (HBM_PEAK_GBS * 1e9),
+        "dominant": dom, "dominant_GBs": per[dom]["GBs"],
+        "kernels": rnd(per), "kernels_alone": rnd(alone),
+    }
+
+
+def traffic_of(workload_name, precision, kernel):
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tfile):
+        return None
+    try:
+        with open(tfile) as f:
+            tr = json.load(f)
+        return tr.get(f"{workload_name}/{precision}", {}).get(kernel)
+    except (OSError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--profile-steps", type=int, default=50)
-    ap.add_argument("--workload", default="room", choices=list(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--cpu-steps", type=int, default=1, help="whole oracle steps timed for cpu_baseline")
+    ap.add_argument("--cpu-oracle", nargs=2, metavar=("WORKLOAD", "STEPS"), help=argparse.SUPPRESS)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--workload", default="hall", choices=list(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the headline value (the other form is measured too unless --one-form)")
+    ap.add_argument("--one-form", action="store_true", help="measure only the headline precision")
     ap.add_argument("--per-stage", action="store_true",
                     help="the per-stage projection variant (a projection after every RK4 stage)")
-    ap.add_argument("--serving", default="short", choices=["none", "short", "full"],
-                    help="serving stream: short = 16 requests x 300 steps, full = 64 x 2000")
+    ap.add_argument("--no-particles", action="store_true")
+    ap.add_argument("--serving", default="config4", choices=["none", "short", "config4", "config4-all"],
+                    help="serving stream: config4 = 64 requests x 2000 steps, pool FP32 form vs FIFO FP64; "
+                         "config4-all adds the pool in FP64; short = 16 x 300")
+    ap.add_argument("--serving-seeds", type=int, nargs="*", default=[7], help="stream seeds of the serving leg")
     ap.add_argument("--cube", type=int, nargs="*", metavar="N_H",
                     help="only run the obstacle-in-channel validation at these resolutions (cells per obstacle edge)")
     ap.add_argument("--cube-t-end", type=float, default=300.0, help="simulated time in units of h / U_b")
@@ -389,6 +522,9 @@ def main():
                     help="fold rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE outputs of this benchmark and of --copy-probe "
                          "into profiles/traffic.json under <workload>/<precision> (no GPU needed)")
     args = ap.parse_args()
+    if args.cpu_oracle:
+        cpu_baseline_child(args.cpu_oracle[0], int(args.cpu_oracle[1]))
+        return
     if args.traffic:
         tfile = os.path.join(ROOT, "profiles", "traffic.json")
         tab = {}
@@ -418,83 +554,43 @@ def main():
               "no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
+    t_start = time.perf_counter()
+    # the oracle's timing starts first, in a child process, before this
+    # process touches the GPU; it runs beside the GPU measurements
+    cpu_proc = None if args.no_cpu else start_cpu_baseline(args.workload, args.cpu_steps)
+
     import torch
     import paper_2204_02107_amd as m
 
     sc = workload(args.workload)
-    prec = m.FP64 if args.precision == "fp64" else m.FP32_REFINE
-    esz = 8 if prec == m.FP64 else 4
-    dev = torch.device("cuda:0")
-    S = m.Solver(sc, precision=prec, device=dev, project_each_stage=args.per_stage)
-    stream = S.stream
-    print(f"[bench] workload {sc.name} cells={sc.ncells} warmup={args.warmup}", file=sys.stderr, flush=True)
-    S.step(args.warmup, diag=False)
-    torch.cuda.synchronize()
-
-    # timed region: exactly K steps, bracketed by synchronisation
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    S.step(args.steps, diag=False)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    hist = S.read_diags(1)[0]
-    value = sc.ncells * args.steps / el / 1e9
-    print(f"[bench] {args.steps} steps in {el:.3f} s -> {value:.3f} Gcell-steps/s; "
-          f"t={hist['t']:.3f} ke={hist['ke']:.4e} co2_mean={hist['co2_room_mean']:.3f}",
-          file=sys.stderr, flush=True)
-
-    # per-kernel launch times from HIP events on the library's stream
-    kb = kernel_bytes(sc, esz)
-    per = {}
-    for name in kb:
-        if name == "refine_res" and prec == m.FP64:
-            continue
-        S.profile(name)
-        S.step(args.profile_steps, diag=False)
-        ms, nl = S.profile_read()
-        S.profile(None)
-        if nl:
-            per[name] = {"avg_us": 1e3 * ms / nl, "launches_per_step": nl / args.profile_steps,
-                         "ms_per_step": ms / args.profile_steps,
-                         "GBs": kb[name] / (1e-3 * ms / nl) / 1e9}
-    dom = max(per, key=lambda k: per[k]["ms_per_step"])
-    pk = per[dom]
-    achieved = pk["GBs"]
-    print("[bench] per-kernel: " + json.dumps({k: {kk: round(vv, 3) for kk, vv in v.items()}
-                                               for k, v in per.items()}), file=sys.stderr, flush=True)
-
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tfile):
-        try:
-            with open(tfile) as f:
-                tr = json.load(f)
-            traffic = tr.get(f"{args.workload}/{args.precision}", {}).get(dom)
-        except (OSError, ValueError):
-            traffic = None
-
-    sbytes = step_bytes(sc, esz, args.per_stage, fused_yz="fft_yz" in per)
+    forms = [args.precision] + ([] if args.one_form else [("fp32" if args.precision == "fp64" else "fp64")])
+    res = {}
+    for form in forms:
+        res[form] = measure(sc, m.FP64 if form == "fp64" else m.FP32_REFINE, args, form)
+    head = res[args.precision]
+    dom = head["dominant"]
+    achieved = head["dominant_GBs"]
     out = {
         "metric": "Gcell-steps/s (full step incl. FFT Poisson)",
-        "value": value,
+        "value": head["value"],
         "unit": "Gcell-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * el / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == m.FP64 else "f32 (FP64 refinement and reductions)",
+        "dtype": "f64" if args.precision == "fp64" else "f32 (FP64 refinement and reductions)",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOADS[args.workload] + (", FP64" if prec == m.FP64 else ", FP32 + FP64 refinement")
+            "workload": WORKLOADS[args.workload] + (", FP64" if args.precision == "fp64" else ", FP32 + FP64 refinement")
                         + (", projection after every RK4 stage" if args.per_stage else ""),
             "cells": sc.ncells,
             "forced_cells": int(len(sc.forced_idx)),
         },
-        "step_bytes_per_cell": sbytes / sc.ncells,
-        "hbm_frac_end_to_end": sbytes * (value * 1e9 / sc.ncells) / (HBM_PEAK_GBS * 1e9),
+        "step_bytes_per_cell": head["step_bytes_per_cell"],
+        "hbm_frac_end_to_end": head["hbm_frac_end_to_end"],
         "roofline": {
             "kernel": dom,
             "bound": "hbm",
@@ -502,23 +598,44 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
+            "traffic": traffic_of(args.workload, args.precision, dom),
         },
-        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["GBs"], 1),
-                        "launches_per_step": v["launches_per_step"]} for k, v in per.items()},
+        "kernels": head["kernels"],
+        "kernels_alone": head["kernels_alone"],
     }
-    out["particles"] = particle_bench(S, sc, esz)
-    print("[bench] particles: " + json.dumps(out["particles"]), file=sys.stderr, flush=True)
-    S.close()
-    if args.serving != "none" and args.workload == "room" and prec == m.FP64:
+    for form in forms[1:]:
+        r = res[form]
+        out["fp32_refine" if form == "fp32" else "fp64"] = {
+            "value": r["value"], "unit": "Gcell-steps/s", "ms_per_step": r["ms_per_step"],
+            "step_bytes_per_cell": r["step_bytes_per_cell"], "hbm_frac_end_to_end": r["hbm_frac_end_to_end"],
+            "roofline": {"kernel": r["dominant"], "achieved": r["dominant_GBs"],
+                         "frac": r["dominant_GBs"] / HBM_PEAK_GBS,
+                         "traffic": traffic_of(args.workload, form, r["dominant"])},
+            "kernels": r["kernels"], "kernels_alone": r["kernels_alone"],
+        }
+    if not args.no_particles:
+        S = m.Solver(sc, precision=m.FP64 if args.precision == "fp64" else m.FP32_REFINE)
+        S.step(args.warmup, diag=False)
+        out["particles"] = particle_bench(S, sc, 8 if args.precision == "fp64" else 4)
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        print("[bench] particles: " + json.dumps(out["particles"]), file=sys.stderr, flush=True)
+    if args.serving != "none":
         n_req, n_steps = (16, 300) if args.serving == "short" else (64, 2000)
-        print(f"[bench] serving stream {n_req} x {n_steps} ...", file=sys.stderr, flush=True)
-        out["serving"] = serving_bench(n_req, n_steps, budget_gib=1.0,
-                                       log=lambda msg: print("[serving] " + msg, file=sys.stderr, flush=True))
-        print("[bench] serving: " + json.dumps(out["serving"]), file=sys.stderr, flush=True)
-    if not args.no_cpu and args.workload == "room":
-        print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(sc)
+        pols = SERVING_POLICIES if args.serving == "config4-all" else ("pool_fp32_refine", "fifo_fp64")
+        runs = []
+        for seed in args.serving_seeds:
+            print(f"[bench] serving stream {n_req} x {n_steps}, seed {seed} ...", file=sys.stderr, flush=True)
+            runs.append(serving_bench(n_req, n_steps, budget_gib=1.0, seed=seed, policies=pols,
+                                      log=lambda msg: print("[serving] " + msg, file=sys.stderr, flush=True)))
+        out["serving"] = runs[0] if len(runs) == 1 else runs
+    if cpu_proc is not None:
+        print("[bench] waiting for the CPU oracle ...", file=sys.stderr, flush=True)
+        # bounded: the whole run stays within about 9 minutes
+        cb = finish_cpu_baseline(cpu_proc, args.workload, 540.0 - (time.perf_counter() - t_start))
+        if cb is not None:
+            out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

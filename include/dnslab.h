@@ -36,8 +36,11 @@
  *     argument or state error nothing is enqueued.  No C++ exception crosses
  *     this interface.  dnslab_last_error() gives a message.
  *   - One context per stream; a context is not thread-safe.  The context owns
- *     its workspace (device memory it allocates with hipMalloc); the bound
- *     state buffers stay owned by the caller and must outlive the context.
+ *     only its workspace, device memory it obtains through params.alloc (the
+ *     caller's allocator, e.g. PyTorch's caching allocator) or, when that is
+ *     NULL, with hipMalloc; it returns every block through params.free_ (or
+ *     hipFree) after synchronising the streams that used it.  The bound state
+ *     buffers stay owned by the caller and must outlive the context.
  *   - Units are SI; the scalar is a plain number (ppm in the room cases).
  */
 #ifndef DNSLAB_H
@@ -85,6 +88,17 @@ typedef struct {
                                the step (the alternative Section 2.1 mentions and the paper
                                skips for speed: 4 projections per step, fourth order in
                                time); 0: the paper's single projection per step */
+    /* Device memory of the context (workspace, list of cells next to a solid,
+     * particle-sort scratch, histogram counters).  alloc(bytes, alloc_user)
+     * returns a block of at least bytes device bytes, 256-byte aligned, on the
+     * current device, or NULL when it cannot (the call then fails with
+     * DNSLAB_ENOMEM; a misaligned block is returned through free_ and counts
+     * as a failure); free_(ptr, alloc_user) takes it back.  Called only from
+     * the thread that calls the library, never from a stream callback.  Both
+     * NULL: hipMalloc / hipFree.  One NULL and the other not: DNSLAB_EINVAL. */
+    void* (*alloc)(size_t bytes, void* alloc_user);
+    void (*free_)(void* ptr, void* alloc_user);
+    void* alloc_user;
 } dnslab_params;
 
 /* Per-step diagnostics, all FP64. */
@@ -256,6 +270,14 @@ int dnslab_profile_read(dnslab_ctx* ctx, double* total_ms, int64_t* launches);
  * or k > 4096. */
 int dnslab_set_graph_steps(dnslab_ctx* ctx, int32_t k);
 
+/* enable = 1 (the default): the scalar half of a step (scalar RK4, its filter
+ * and the diagnostics record) runs on a second stream of the context beside
+ * the next step's velocity work, as the data dependences allow.  0: every
+ * launch of a step runs in order on the context's stream (for timing
+ * kernels alone).  Results are bitwise the same either way.  Enqueues any
+ * deferred scalar work first.  DNSLAB_EINVAL unless enable is 0 or 1. */
+int dnslab_set_overlap(dnslab_ctx* ctx, int32_t enable);
+
 /* ------------------------------------------------------------------------
  * Serving pool: many scenarios of different grid sizes resident at once,
  * admitted against an HBM budget and advanced together.  Each step of the
@@ -267,9 +289,16 @@ int dnslab_set_graph_steps(dnslab_ctx* ctx, int32_t k);
  * not thread-safe.
  * ------------------------------------------------------------------------ */
 
-/* Create an empty pool with hbm_budget bytes of device memory for scenarios
- * (state + workspace), all of the given precision, working on stream. */
-int dnslab_pool_create(size_t hbm_budget, int32_t precision, void* stream, dnslab_pool** out);
+/* Create an empty pool with hbm_budget bytes of device memory, all scenarios
+ * of the given precision, working on stream.  The budget covers each
+ * scenario's state and workspace plus a 64 KiB share of the batched launch
+ * tables, and the device staging buffer of admission (kept between
+ * admissions, sized for the largest one so far).  alloc, free_, alloc_user:
+ * the allocator of every device block the pool and its scenarios use, with
+ * the meaning of the dnslab_params fields of the same names (both NULL:
+ * hipMalloc / hipFree; the allocators in admitted params are ignored). */
+int dnslab_pool_create(size_t hbm_budget, int32_t precision, void* stream, void* (*alloc)(size_t, void*),
+                       void (*free_)(void*, void*), void* alloc_user, dnslab_pool** out);
 
 /* Admit a scenario that will run target_steps steps.  All arrays are HOST
  * memory with the layouts of dnslab_init (initial fields in FP64, converted to

@@ -7,8 +7,10 @@
 - Time averages of the fields: plain running sums (divided by the count when
   read).
 - The air-change rate fitted to the mean CO2 decay (Section 3.3, Table 4):
-  reading: least squares of log(<c> - c_out) against t with the outdoor level
-  c_out = 400 ppm known (the paper fits C0 exp(-ACH t) + C1); ACH in 1/h.
+  the paper's three-parameter fit C0 exp(-ACH t) + C1 (least squares, all
+  three free), and, for short records where C1 cannot be told apart from C0
+  (ACH t << 1), the same model with the outdoor level C1 = c_out known: least
+  squares of log(<c> - c_out) against t.  ACH in 1/h.
 - Theoretical ACH = volume flow / room volume (Section 3.3).
 - Wells-Riley risk with decaying quanta (Section 3.4):
   P = 1 - exp(-Q), Q(t) = (C0 p / ACH) (1 - exp(-ACH t)), and Q = C0 p t
@@ -33,7 +35,8 @@
 
 Parity status: pinned by ``tests/test_oracle_postproc.py`` (the paper's
 theoretical ACH values and printed infection risks, brute-force bin counts,
-exact recovery of a synthetic exponential decay, closed-form forces of a
+exact recovery of synthetic exponential decays (with the asymptote known,
+and free at a level other than the outdoor one), closed-form forces of a
 linear pressure field (buoyancy: minus the gradient times the obstacle's
 volume) and of a uniform stream on a rectangular obstacle, the frequency of
 synthetic sinusoids).
@@ -53,12 +56,44 @@ def co2_histogram(c, beta, room, nbins, lo, hi):
 
 
 def ach_fit(t_s, mean_c, c_out=400.0):
-    """Air changes per hour from <c>(t) = c_out + A exp(-ACH t)."""
+    """Air changes per hour from <c>(t) = c_out + A exp(-ACH t) with the
+    outdoor level c_out known: least squares of log(<c> - c_out) in t.
+    Undefined (ValueError) once <c> <= c_out."""
     t = np.asarray(t_s, dtype=np.float64)
-    y = np.log(np.asarray(mean_c, dtype=np.float64) - c_out)
+    c = np.asarray(mean_c, dtype=np.float64)
+    if np.any(c <= c_out):
+        raise ValueError("mean CO2 at or below the outdoor level: log fit undefined")
+    y = np.log(c - c_out)
     A = np.vstack([t, np.ones_like(t)]).T
     slope = np.linalg.lstsq(A, y, rcond=None)[0][0]
     return -slope * 3600.0
+
+
+def ach_fit3(t_s, mean_c):
+    """Air changes per hour from the three-parameter fit of Section 3.3,
+    <c>(t) = C0 exp(-ACH t) + C1 with C0, ACH and C1 all free, least squares.
+    For a fixed rate the model is linear in (C0, C1) and numpy's lstsq solves
+    it; the rate with the smallest residual is found on a log-spaced scan over
+    1e-3 .. 1e3 decays per record length, then refined with scipy's bounded
+    scalar minimiser between the scan's neighbours of the best point."""
+    from scipy.optimize import minimize_scalar
+    t = np.asarray(t_s, dtype=np.float64)
+    t = t - t[0]
+    y = np.asarray(mean_c, dtype=np.float64)
+    span = t[-1]
+
+    def sse(logk):
+        A = np.vstack([np.exp(-np.exp(logk) * t), np.ones_like(t)]).T
+        coef = np.linalg.lstsq(A, y, rcond=None)[0]
+        r = A @ coef - y
+        return float(r @ r)
+
+    grid = np.linspace(np.log(1e-3 / span), np.log(1e3 / span), 601)
+    vals = [sse(g) for g in grid]
+    i = int(np.argmin(vals))
+    lo, hi = grid[max(i - 1, 0)], grid[min(i + 1, len(grid) - 1)]
+    best = minimize_scalar(sse, bounds=(lo, hi), method="bounded", options={"xatol": 1e-12})
+    return float(np.exp(best.x)) * 3600.0
 
 
 def theoretical_ach(flow_area_m2, speed_m_s, volume_m3):

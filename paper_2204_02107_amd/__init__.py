@@ -89,6 +89,11 @@ class Solver:
         if getattr(case, "room_mask", None) is not None:
             room = torch.as_tensor(case.room_mask, dtype=torch.uint8).reshape(self.shape).to(dev).contiguous()
         self.params = make_params(case, precision, ctypes.c_void_p(stream.cuda_stream), project_each_stage)
+        # the context's workspace comes from torch's caching allocator, so that
+        # torch and the library see one pool of HBM
+        self._alloc = _lib.TorchAllocator(dev.index if dev.index is not None else torch.cuda.current_device(),
+                                          stream.cuda_stream)
+        self._alloc.fill(self.params)
         ctx = ctypes.c_void_p()
         rc = self.lib.dnslab_init(
             ctypes.byref(self.params), _ptr(beta), n,
@@ -107,6 +112,9 @@ class Solver:
         if getattr(self, "ctx", None):
             self.lib.dnslab_destroy(self.ctx)
             self.ctx = None
+        if getattr(self, "_alloc", None) is not None:
+            self._alloc.close()
+            self._alloc = None
 
     def __del__(self):
         try:
@@ -225,6 +233,12 @@ class Solver:
             raise IndexError("row out of range")
         b = (ctypes.c_int32 * 6)(*[int(q) for q in box])
         self._call(self.lib.dnslab_body_force, self.ctx, b, ctypes.c_void_p(out.data_ptr() + 64 * int(row)))
+
+    def set_overlap(self, enable: bool):
+        """True (the default): the scalar half of a step runs on a second
+        stream beside the next step's velocity work; False: one stream, every
+        kernel alone (same results)."""
+        self._check(self.lib.dnslab_set_overlap(self.ctx, int(bool(enable))))
 
     # -- kernel timing -------------------------------------------------------
     def profile(self, kernel: Optional[str]):

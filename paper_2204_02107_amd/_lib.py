@@ -3,7 +3,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import CFUNCTYPE, POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdnslab.so")
@@ -20,12 +20,17 @@ EXPORTS = [
     "dnslab_workspace_bytes", "dnslab_init", "dnslab_step", "dnslab_read_diags", "dnslab_poisson",
     "dnslab_project", "dnslab_scalar_step", "dnslab_momentum_rhs", "dnslab_scalar_rhs",
     "dnslab_filter", "dnslab_set_time", "dnslab_destroy", "dnslab_last_error",
-    "dnslab_profile_enable", "dnslab_profile_read", "dnslab_set_graph_steps", "dnslab_pool_set_graph",
+    "dnslab_profile_enable", "dnslab_profile_read", "dnslab_set_graph_steps", "dnslab_set_overlap", "dnslab_pool_set_graph",
     "dnslab_particles_step", "dnslab_particles_sort", "dnslab_co2_histogram", "dnslab_accumulate", "dnslab_body_force",
     "dnslab_pool_create", "dnslab_pool_admit", "dnslab_pool_step", "dnslab_pool_query",
     "dnslab_pool_read_field", "dnslab_pool_release", "dnslab_pool_usage", "dnslab_pool_last_error",
     "dnslab_pool_destroy",
 ]
+
+
+# Allocator callbacks of dnslab_params / dnslab_pool_create.
+ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = CFUNCTYPE(None, c_void_p, c_void_p)
 
 
 class Params(ctypes.Structure):
@@ -38,6 +43,7 @@ class Params(ctypes.Structure):
         ("n_piter", c_int32), ("filter", c_int32), ("precision", c_int32),
         ("stream", c_void_p),
         ("project_each_stage", c_int32),
+        ("alloc", ALLOC_FN), ("free_", FREE_FN), ("alloc_user", c_void_p),
     ]
 
 
@@ -91,13 +97,14 @@ def load():
         "dnslab_profile_enable": (c_int, [V, c_char_p]),
         "dnslab_profile_read": (c_int, [V, P(c_double), P(c_int64)]),
         "dnslab_set_graph_steps": (c_int, [V, c_int32]),
+        "dnslab_set_overlap": (c_int, [V, c_int32]),
         "dnslab_particles_step": (c_int, [V, c_int64, V, V, V, P(ParticleParams), c_double]),
         "dnslab_particles_sort": (c_int, [V, c_int64, V, V, V]),
         "dnslab_co2_histogram": (c_int, [V, c_int32, c_double, c_double, V]),
         "dnslab_accumulate": (c_int, [V, V]),
         "dnslab_body_force": (c_int, [V, P(c_int32), V]),
         "dnslab_pool_set_graph": (c_int, [V, c_int32]),
-        "dnslab_pool_create": (c_int, [c_size_t, c_int32, V, P(V)]),
+        "dnslab_pool_create": (c_int, [c_size_t, c_int32, V, ALLOC_FN, FREE_FN, V, P(V)]),
         "dnslab_pool_admit": (c_int, [V, P(Params), c_int64, V, c_int64, V, V, V, V, V, V, V, V, V, V,
                                       P(c_int32)]),
         "dnslab_pool_step": (c_int, [V, c_int32]),
@@ -128,3 +135,55 @@ def check_pool(rc, pool=None):
         msg = load().dnslab_pool_last_error(pool)
         raise DnslabError(rc, msg.decode() if msg else "")
     return rc
+
+
+# ---------------------------------------------------------------------------
+# Device memory for the library from PyTorch's caching allocator: the library
+# calls these back (on the calling thread) for its workspace and releases the
+# blocks after synchronising the streams that used them.
+_TORCH_USERS = {}     # key -> (device index, stream handle)
+
+
+def _torch_alloc(nbytes, user):
+    try:
+        import torch
+        dev, stream = _TORCH_USERS[int(user or 0)]
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=stream)
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, user):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+TORCH_ALLOC = ALLOC_FN(_torch_alloc)     # kept alive for the life of the module
+TORCH_FREE = FREE_FN(_torch_free)
+
+
+class TorchAllocator:
+    """(alloc, free_, alloc_user) for one device and stream."""
+
+    _next = 1
+
+    def __init__(self, device_index: int, stream_handle: int):
+        self.key = TorchAllocator._next
+        TorchAllocator._next += 1
+        _TORCH_USERS[self.key] = (int(device_index), int(stream_handle))
+        self.user = c_void_p(self.key)
+
+    def fill(self, params):
+        params.alloc = TORCH_ALLOC
+        params.free_ = TORCH_FREE
+        params.alloc_user = self.user
+        return params
+
+    def triple(self):
+        return TORCH_ALLOC, TORCH_FREE, self.user
+
+    def close(self):
+        _TORCH_USERS.pop(self.key, None)

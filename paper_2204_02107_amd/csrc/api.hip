@@ -51,6 +51,47 @@ int ilog2(int v) {
 }
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Device memory of a context or pool: the caller's allocator when one is
+// given (e.g. PyTorch's caching allocator), else hipMalloc / hipFree.  Every
+// block must be 256-byte aligned (the workspace layout relies on it).
+struct DevAlloc {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*free_)(void*, void*) = nullptr;
+    void* user = nullptr;
+};
+
+void* dev_alloc(const DevAlloc& a, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    void* p = nullptr;
+    if (a.alloc) {
+        p = a.alloc(bytes, a.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (p && (reinterpret_cast<uintptr_t>(p) & 255u) != 0) {
+        // unusable: the kernels' vector loads and the layout need 256-byte alignment
+        if (a.free_) a.free_(p, a.user);
+        else (void)hipFree(p);
+        p = nullptr;
+    }
+    return p;
+}
+
+void dev_free(const DevAlloc& a, void* p) {
+    if (!p) return;
+    if (a.free_) a.free_(p, a.user);
+    else (void)hipFree(p);
+}
+
+DevAlloc alloc_of(const dnslab_params* P) {
+    DevAlloc a;
+    a.alloc = P->alloc;
+    a.free_ = P->free_;
+    a.user = P->alloc_user;
+    return a;
+}
+
 struct Layout {
     size_t esz;           // field element size
     long long n;
@@ -90,6 +131,7 @@ int validate(const dnslab_params* P, std::string& why) {
     if (!(P->tau_f > 0)) { why = "tau_f must be positive"; return DNSLAB_EINVAL; }
     if (P->n_piter < 0 || P->n_piter > 64) { why = "n_piter out of range"; return DNSLAB_EINVAL; }
     if (P->project_each_stage != 0 && P->project_each_stage != 1) { why = "project_each_stage must be 0 or 1"; return DNSLAB_EINVAL; }
+    if ((P->alloc == nullptr) != (P->free_ == nullptr)) { why = "alloc and free_ must both be set or both be NULL"; return DNSLAB_EINVAL; }
     if (!(P->dt_fixed > 0)) {
         if (!(P->cfl > 0) || !(P->u_ref > 0)) { why = "adaptive dt needs cfl > 0 and u_ref > 0"; return DNSLAB_EINVAL; }
     }
@@ -288,6 +330,7 @@ void sin2_table(int n, int count, double h, double* out) {
 
 struct dnslab_ctx {
     dnslab_params P;
+    DevAlloc da;           // device memory: the caller's allocator or hipMalloc
     hipStream_t stream;
     Grid g;
     Layout Lo;
@@ -845,10 +888,8 @@ int build_flags(dnslab_ctx* x, const uint8_t* beta_dev, const long long* fidx_ho
     const size_t nib = ibidx.size();
     if (nib > 0) {
         const size_t b_idx = align_up(nib * sizeof(int), 256), b_mask = align_up(nib, 256);
-        if (hipMalloc(&x->ib_buf, b_idx + b_mask + nib * x->Lo.esz) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(x, DNSLAB_ENOMEM, "hipMalloc of the immersed-boundary list failed");
-        }
+        x->ib_buf = dev_alloc(x->da, b_idx + b_mask + nib * x->Lo.esz);
+        if (!x->ib_buf) return fail(x, DNSLAB_ENOMEM, "allocation of the immersed-boundary list failed");
         char* b = (char*)x->ib_buf;
         HIPCHK(x, hipMemcpy(b, ibidx.data(), nib * sizeof(int), hipMemcpyHostToDevice));
         HIPCHK(x, hipMemcpy(b + b_idx, ibmask.data(), nib, hipMemcpyHostToDevice));
@@ -1015,6 +1056,7 @@ int dnslab_init(const dnslab_params* params, const uint8_t* beta_dev, int64_t n_
         *out = nullptr;
         x = new dnslab_ctx();
         x->P = *params;
+        x->da = alloc_of(params);
         x->stream = (hipStream_t)params->stream;
         x->cur = x->stream;
         x->overlap = DNSLAB_OVERLAP != 0;
@@ -1023,10 +1065,10 @@ int dnslab_init(const dnslab_params* params, const uint8_t* beta_dev, int64_t n_
         x->u = u; x->v = v; x->w = w; x->p = p; x->c = c;
         x->prof_kid = K_NONE;
         x->nforced = (int)n_forced;
-        if (hipMalloc(&x->ws, x->Lo.total) != hipSuccess) {
-            (void)hipGetLastError();
+        x->ws = dev_alloc(x->da, x->Lo.total);
+        if (!x->ws) {
             delete x;
-            return fail(nullptr, DNSLAB_ENOMEM, "hipMalloc of the workspace failed");
+            return fail(nullptr, DNSLAB_ENOMEM, "allocation of the workspace failed");
         }
         char* base = (char*)x->ws;
         const Layout& Lo = x->Lo;
@@ -1211,11 +1253,11 @@ void dnslab_destroy(dnslab_ctx* x) {
     }
     if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
     for (hipEvent_t e : x->ev) (void)hipEventDestroy(e);
-    if (x->ws) (void)hipFree(x->ws);
-    if (x->ib_buf) (void)hipFree(x->ib_buf);
-    if (x->hist_dev) (void)hipFree(x->hist_dev);
+    dev_free(x->da, x->ws);
+    dev_free(x->da, x->ib_buf);
+    dev_free(x->da, x->hist_dev);
     if (x->hist_host) (void)hipHostFree(x->hist_host);
-    if (x->psort_buf) (void)hipFree(x->psort_buf);
+    dev_free(x->da, x->psort_buf);
     if (x->pinned) (void)hipHostFree(x->pinned);
     if (x->pinned_sc) (void)hipHostFree(x->pinned_sc);
     delete x;
@@ -1299,15 +1341,12 @@ int dnslab_particles_sort(dnslab_ctx* x, int64_t n, double* pos, double* vel, do
         if (x->psort_buf) {
             // an earlier sort on the stream may still use the old scratch
             HIPCHK(x, hipStreamSynchronize(x->stream));
-            (void)hipFree(x->psort_buf);
+            dev_free(x->da, x->psort_buf);
             x->psort_buf = nullptr;
             x->psort_bytes = 0;
         }
-        if (hipMalloc(&x->psort_buf, need) != hipSuccess) {
-            (void)hipGetLastError();
-            x->psort_buf = nullptr;
-            return fail(x, DNSLAB_ENOMEM, "particle sort scratch");
-        }
+        x->psort_buf = dev_alloc(x->da, need);
+        if (!x->psort_buf) return fail(x, DNSLAB_ENOMEM, "particle sort scratch");
         x->psort_bytes = need;
     }
     char* b = (char*)x->psort_buf;
@@ -1328,11 +1367,15 @@ int dnslab_co2_histogram(dnslab_ctx* x, int32_t nbins, double lo, double hi, int
     if (nbins < 1 || nbins > HIST_MAX_BINS || !(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi) || !counts_host)
         return fail(x, DNSLAB_EINVAL, "bad histogram arguments");
     if (!x->hist_dev) {
-        if (hipMalloc((void**)&x->hist_dev, HIST_MAX_BINS * sizeof(unsigned long long)) != hipSuccess ||
-            hipHostMalloc((void**)&x->hist_host, HIST_MAX_BINS * sizeof(unsigned long long), hipHostMallocDefault) !=
-                hipSuccess) {
+        x->hist_dev = (unsigned long long*)dev_alloc(x->da, HIST_MAX_BINS * sizeof(unsigned long long));
+        if (!x->hist_dev) return fail(x, DNSLAB_ENOMEM, "histogram counters");
+    }
+    if (!x->hist_host) {
+        if (hipHostMalloc((void**)&x->hist_host, HIST_MAX_BINS * sizeof(unsigned long long), hipHostMallocDefault) !=
+            hipSuccess) {
             (void)hipGetLastError();
-            return fail(x, DNSLAB_ENOMEM, "histogram buffers");
+            x->hist_host = nullptr;
+            return fail(x, DNSLAB_ENOMEM, "histogram host buffer");
         }
     }
     hipError_t e;
@@ -1409,6 +1452,24 @@ int dnslab_set_graph_steps(dnslab_ctx* x, int32_t k) {
     return DNSLAB_OK;
 }
 
+int dnslab_set_overlap(dnslab_ctx* x, int32_t enable) {
+    if (int rc = check_ctx(x)) return rc;
+    if (enable != 0 && enable != 1) return fail(x, DNSLAB_EINVAL, "enable must be 0 or 1");
+    try {
+        // the deferred scalar half of the last step is enqueued and joined first
+        int rc = x->Lo.esz == 8 ? settle<double>(x) : settle<float>(x);
+        if (rc) return rc;
+    } catch (...) {
+        return fail(x, DNSLAB_ENOMEM, "host allocation failed");
+    }
+    if (x->overlap != (enable != 0) && x->gexec) {
+        HIPCHK(x, hipGraphExecDestroy(x->gexec));   // captured with the other schedule
+        x->gexec = nullptr;
+    }
+    x->overlap = enable != 0;
+    return DNSLAB_OK;
+}
+
 int dnslab_profile_read(dnslab_ctx* x, double* total_ms, int64_t* launches) {
     if (int rc = check_ctx(x)) return rc;
     int rc = prof_flush(x);
@@ -1457,11 +1518,15 @@ struct BatchGroup {
     bool direct = false;
 };
 constexpr long long POOL_DIRECT_CELLS = 1LL << 20;
+// Budget reserved per scenario for its share of the batched launch tables
+// (about 70 launch records of at most ~0.5 KB per step sequence).
+constexpr size_t POOL_TABLE_RESERVE = 64 * 1024;
 
 }  // namespace
 
 struct dnslab_pool {
-    size_t budget = 0, used = 0;
+    size_t budget = 0, used = 0;          // used: scenarios (with their table reserve) + the staging buffer
+    DevAlloc da;                          // device memory of every scenario and of the pool itself
     int precision = 0;
     hipStream_t stream = nullptr;
     hipStream_t admit_stream = nullptr;   // init work of new scenarios, off the stepping stream
@@ -1577,10 +1642,11 @@ int pool_rebuild(dnslab_pool* P, const std::vector<int>& active) {
         G.direct = G.slots.size() == 1 || P->slots[G.slots[0]].ctx->g.n >= POOL_DIRECT_CELLS;
     }
     if (host.size() > P->tab_cap) {
-        if (P->tab_dev) (void)hipFree(P->tab_dev);
+        dev_free(P->da, P->tab_dev);
         P->tab_dev = nullptr;
         P->tab_cap = 0;
-        PHIP(P, hipMalloc(&P->tab_dev, host.size()));
+        P->tab_dev = dev_alloc(P->da, host.size());
+        if (!P->tab_dev) return pfail(P, DNSLAB_ENOMEM, "allocation of the batched launch tables failed");
         P->tab_cap = host.size();
     }
     if (!host.empty()) PHIP(P, hipMemcpy(P->tab_dev, host.data(), host.size(), hipMemcpyHostToDevice));
@@ -1707,13 +1773,18 @@ size_t count_near_solid(const uint8_t* beta, int nx, int ny, int nz) {
 
 extern "C" {
 
-int dnslab_pool_create(size_t hbm_budget, int32_t precision, void* stream, dnslab_pool** out) {
+int dnslab_pool_create(size_t hbm_budget, int32_t precision, void* stream, void* (*alloc)(size_t, void*),
+                       void (*free_)(void*, void*), void* alloc_user, dnslab_pool** out) {
     if (!out) return pfail(nullptr, DNSLAB_EINVAL, "out is NULL");
     if (precision != DNSLAB_FP64 && precision != DNSLAB_FP32_REFINE) return pfail(nullptr, DNSLAB_EINVAL, "bad precision");
+    if ((alloc == nullptr) != (free_ == nullptr)) return pfail(nullptr, DNSLAB_EINVAL, "alloc and free_ must both be set or both be NULL");
     try {
         dnslab_pool* P = new dnslab_pool();
         P->budget = hbm_budget;
         P->precision = precision;
+        P->da.alloc = alloc;
+        P->da.free_ = free_;
+        P->da.user = alloc_user;
         P->stream = (hipStream_t)stream;
         if (hipStreamCreateWithFlags(&P->admit_stream, hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();
@@ -1743,16 +1814,26 @@ int dnslab_pool_admit(dnslab_pool* P, const dnslab_params* params, int64_t targe
             return pfail(P, DNSLAB_EINVAL, "bad forcing arguments");
         dnslab_params prm = *params;
         prm.stream = P->admit_stream;
+        prm.alloc = P->da.alloc;       // the pool's memory, whatever the scenario's params say
+        prm.free_ = P->da.free_;
+        prm.alloc_user = P->da.user;
         const Layout Lo = make_layout(&prm, (int)n_forced);
         const size_t n = (size_t)Lo.n, esz = Lo.esz;
         const size_t field = align_up(n * esz, 256);
         const size_t nib = count_near_solid(beta_host, prm.nx, prm.ny, prm.nz);
-        const size_t bytes = 5 * field + Lo.total + align_up(nib * 4, 256) + align_up(nib, 256) + nib * esz;
-        if (P->used + bytes > P->budget) return pfail(P, DNSLAB_EAGAIN, "HBM budget exhausted");
+        const size_t bytes = 5 * field + Lo.total + align_up(nib * 4, 256) + align_up(nib, 256) + nib * esz +
+                             POOL_TABLE_RESERVE;
+        // static inputs go through a device staging buffer (dnslab_init copies
+        // them); it is kept between admissions and counted in the budget
+        const size_t nf = (size_t)n_forced;
+        const size_t tb = align_up(n, 256) + (room_host ? align_up(n, 256) : 0) + nf * (8 + 8 + 24 + 8) + 1024;
+        const size_t stage_growth = tb > P->stage_cap ? tb - P->stage_cap : 0;
+        if (P->used + bytes + stage_growth > P->budget) return pfail(P, DNSLAB_EAGAIN, "HBM budget exhausted");
         PoolSlot S;
         S.bytes = bytes;
         S.target = target_steps;
-        PHIP(P, hipMalloc(&S.state, 5 * field));
+        S.state = dev_alloc(P->da, 5 * field);
+        if (!S.state) return pfail(P, DNSLAB_ENOMEM, "allocation of the scenario state failed");
         // upload the initial fields in the field type
         std::vector<unsigned char> tmp(n * esz);
         const double* src[5] = {u0, v0, w0, p0, c0};
@@ -1763,23 +1844,22 @@ int dnslab_pool_admit(dnslab_pool* P, const dnslab_params* params, int64_t targe
             else
                 for (size_t i = 0; i < n; ++i) ((float*)tmp.data())[i] = (float)src[f][i];
             if (hipMemcpy(dst[f], tmp.data(), n * esz, hipMemcpyHostToDevice) != hipSuccess) {
-                (void)hipFree(S.state);
+                dev_free(P->da, S.state);
                 return pfail(P, DNSLAB_EHIP, "uploading initial fields failed");
             }
         }
-        // static inputs through temporary device buffers (dnslab_init copies them)
-        const size_t nf = (size_t)n_forced;
-        const size_t tb = align_up(n, 256) + (room_host ? align_up(n, 256) : 0) + nf * (8 + 8 + 24 + 8) + 1024;
         if (tb > P->stage_cap) {
-            if (P->stage) (void)hipFree(P->stage);
+            dev_free(P->da, P->stage);
+            P->used -= P->stage_cap;
             P->stage = nullptr;
             P->stage_cap = 0;
-            if (hipMalloc(&P->stage, tb) != hipSuccess) {
-                (void)hipGetLastError();
-                (void)hipFree(S.state);
+            P->stage = dev_alloc(P->da, tb);
+            if (!P->stage) {
+                dev_free(P->da, S.state);
                 return pfail(P, DNSLAB_ENOMEM, "staging allocation failed");
             }
             P->stage_cap = tb;
+            P->used += tb;
         }
         char* t = (char*)P->stage;
         uint8_t* beta_d = (uint8_t*)t;
@@ -1799,13 +1879,13 @@ int dnslab_pool_admit(dnslab_pool* P, const dnslab_params* params, int64_t targe
             ok = ok && hipMemcpy(fcs_d, fcset_host, nf * 8, hipMemcpyHostToDevice) == hipSuccess;
         }
         if (!ok) {
-            (void)hipFree(S.state);
+            dev_free(P->da, S.state);
             return pfail(P, DNSLAB_EHIP, "uploading inputs failed");
         }
         rc = dnslab_init(&prm, beta_d, n_forced, nf ? fidx_d : nullptr, nf ? fS_d : nullptr, nf ? fus_d : nullptr,
                          nf ? fcs_d : nullptr, room_d, dst[0], dst[1], dst[2], dst[3], dst[4], &S.ctx);
         if (rc) {
-            (void)hipFree(S.state);
+            dev_free(P->da, S.state);
             return pfail(P, rc, std::string("init: ") + dnslab_last_error(nullptr));
         }
         // dnslab_init has completed its work on the admission stream; from now on
@@ -1910,7 +1990,7 @@ int dnslab_pool_release(dnslab_pool* P, int32_t slot) {
     if (slot < 0 || slot >= (int)P->slots.size() || !P->slots[slot].used) return pfail(P, DNSLAB_EINVAL, "bad slot");
     PoolSlot& S = P->slots[slot];
     dnslab_destroy(S.ctx);      // synchronises the stream
-    (void)hipFree(S.state);
+    dev_free(P->da, S.state);
     P->used -= S.bytes;
     S = PoolSlot();
     P->dirty = true;
@@ -1954,9 +2034,9 @@ void dnslab_pool_destroy(dnslab_pool* P) {
     }
     for (hipEvent_t ev : P->gev) (void)hipEventDestroy(ev);
     if (P->fork_ev) (void)hipEventDestroy(P->fork_ev);
-    if (P->tab_dev) (void)hipFree(P->tab_dev);
+    dev_free(P->da, P->tab_dev);
     if (P->admit_stream) (void)hipStreamDestroy(P->admit_stream);
-    if (P->stage) (void)hipFree(P->stage);
+    dev_free(P->da, P->stage);
     delete P;
 }
 

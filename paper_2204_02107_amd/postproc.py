@@ -7,7 +7,7 @@ results and the per-step diagnostics into the quantities the paper reports.
 from __future__ import annotations
 
 import math
-from typing import Sequence
+from typing import Optional, Sequence
 
 import numpy as np
 
@@ -20,14 +20,55 @@ def pdf(counts, lo, hi):
     return counts / (total * width) if total > 0 else counts
 
 
-def fitted_ach(diags: Sequence[dict], c_out: float = 400.0) -> float:
-    """Air changes per hour from the room-mean CO2 of a run of diagnostics:
-    the decay rate of <c> - c_out, least squares in log space (Section 3.3)."""
-    t = np.array([d["t"] for d in diags])
-    y = np.log(np.array([d["co2_room_mean"] for d in diags]) - c_out)
-    tm, ym = t.mean(), y.mean()
-    slope = np.sum((t - tm) * (y - ym)) / np.sum((t - tm) ** 2)
-    return -slope * 3600.0
+def fitted_ach(diags: Sequence[dict], c_out: Optional[float] = None) -> float:
+    """Air changes per hour from the room-mean CO2 of a run of diagnostics
+    (Section 3.3, Table 4).
+
+    c_out None: the paper's fit <c>(t) = C0 exp(-ACH t) + C1 with all three
+    parameters free.  For a given rate k the best C0 and C1 are a straight
+    line fit of <c> on e = exp(-k t), whose residual is n (var c - cov(e, c)^2
+    / var e); k maximises cov(e, c)^2 / var e, found on a coarse log scan and
+    refined by golden-section search.
+
+    c_out given: the asymptote is the known outdoor level and the rate is the
+    least-squares slope of log(<c> - c_out) against t; this suits records much
+    shorter than 1/ACH, where C0 and C1 cannot be told apart.  ValueError if
+    <c> reaches c_out (the logarithm is undefined)."""
+    t = np.array([d["t"] for d in diags], dtype=np.float64)
+    c = np.array([d["co2_room_mean"] for d in diags], dtype=np.float64)
+    if c_out is not None:
+        if np.any(c <= c_out):
+            raise ValueError("room-mean CO2 at or below c_out: the log-linear ACH fit is undefined")
+        y = np.log(c - c_out)
+        tm, ym = t.mean(), y.mean()
+        slope = np.sum((t - tm) * (y - ym)) / np.sum((t - tm) ** 2)
+        return float(-slope * 3600.0)
+    tr = t - t[0]
+    cc = c - c.mean()
+
+    def score(lk):
+        e = np.exp(-math.exp(lk) * tr)
+        e = e - e.mean()
+        ve = float(e @ e)
+        return float(e @ cc) ** 2 / ve if ve > 0 else 0.0
+
+    lo, hi = math.log(1e-3 / tr[-1]), math.log(1e3 / tr[-1])
+    scan = np.linspace(lo, hi, 241)
+    i = int(np.argmax([score(q) for q in scan]))
+    a, b = scan[max(i - 1, 0)], scan[min(i + 1, scan.size - 1)]
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+    x1, x2 = b - g * (b - a), a + g * (b - a)
+    f1, f2 = score(x1), score(x2)
+    while b - a > 1e-13 * max(1.0, abs(a)):
+        if f1 >= f2:
+            b, x2, f2 = x2, x1, f1
+            x1 = b - g * (b - a)
+            f1 = score(x1)
+        else:
+            a, x1, f1 = x1, x2, f2
+            x2 = a + g * (b - a)
+            f2 = score(x2)
+    return float(math.exp(0.5 * (a + b)) * 3600.0)
 
 
 def infection_risk(quanta_per_m3: float, breathing_m3_per_h: float, ach_per_h: float, hours: float) -> float:

@@ -41,8 +41,11 @@ class Pool:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = ctypes.c_void_p()
+        # every device block of the pool comes from torch's caching allocator
+        self._alloc = _lib.TorchAllocator(torch.cuda.current_device(), stream.cuda_stream)
         _lib.check_pool(self.lib.dnslab_pool_create(int(hbm_budget), int(precision),
-                                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+                                                   ctypes.c_void_p(stream.cuda_stream), *self._alloc.triple(),
+                                                   ctypes.byref(h)))
         self.h = h
         self._keep = {}
         if graph:
@@ -106,6 +109,9 @@ class Pool:
         if getattr(self, "h", None):
             self.lib.dnslab_pool_destroy(self.h)
             self.h = None
+        if getattr(self, "_alloc", None) is not None:
+            self._alloc.close()
+            self._alloc = None
 
     def __del__(self):
         try:

@@ -99,3 +99,47 @@ def test_fft_length_limits():
         with pytest.raises(DnslabError) as e:
             m.workspace_bytes(shaped(*shape), prec)
         assert e.value.code == -3, shape
+
+
+@needs_lib
+def test_allocator_pair_must_be_complete():
+    """alloc and free_ are both set or both NULL (host-side validation)."""
+    import paper_2204_02107_amd as m
+    from paper_2204_02107_amd import _lib
+    sc = scenarios.room(64, 32, 24, dx=0.05, n_boxes=1)
+    lib = m.load()
+    P = m.make_params(sc)
+    out = ctypes.c_size_t()
+    assert lib.dnslab_workspace_bytes(ctypes.byref(P), ctypes.byref(out)) == 0
+    P.alloc = _lib.TORCH_ALLOC
+    assert lib.dnslab_workspace_bytes(ctypes.byref(P), ctypes.byref(out)) == -1
+    assert b"alloc" in lib.dnslab_last_error(None)
+    P.free_ = _lib.TORCH_FREE
+    assert lib.dnslab_workspace_bytes(ctypes.byref(P), ctypes.byref(out)) == 0
+    h = ctypes.c_void_p()
+    assert lib.dnslab_pool_create(1 << 20, 0, None, _lib.TORCH_ALLOC, _lib.FREE_FN(), None, ctypes.byref(h)) == -1
+    assert not h.value
+
+
+def test_params_struct_matches_header_field_order():
+    """The ctypes mirror of dnslab_params lists the header's fields in order."""
+    from paper_2204_02107_amd._lib import Params
+    text = open(os.path.join(ROOT, "include", "dnslab.h")).read()
+    body = text[text.index("typedef struct {\n    int32_t nx, ny, nz;"):text.index("} dnslab_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl or decl.startswith("typedef"):
+            decl = decl.split("{", 1)[-1].strip()
+        if not decl:
+            continue
+        fn = re.match(r".*\(\s*\*\s*(\w+)\s*\)", decl, flags=re.S)
+        if fn:
+            names.append(fn.group(1))
+            continue
+        for part in decl.split(","):
+            nm = re.findall(r"(\w+)\s*(\[\d+\])?\s*$", part.strip())
+            if nm:
+                names.append(nm[0][0])
+    assert names == [f[0] for f in Params._fields_]

@@ -54,7 +54,7 @@ def test_fitted_ach_and_risk_chain():
     S.close()
     t = [d["t"] for d in diags]
     cm = [d["co2_room_mean"] for d in diags]
-    ach = postproc.fitted_ach(diags)
+    ach = postproc.fitted_ach(diags, c_out=400.0)
     assert abs(ach - PP.ach_fit(t, cm)) < 1e-9 * abs(ach)
     assert ach > 0
     c0 = 100 / (sc.lx * sc.ly * sc.lz)

@@ -2,6 +2,7 @@
 import os
 
 import numpy as np
+import pytest
 
 from oracle import postproc as PP
 
@@ -54,6 +55,25 @@ def test_ach_fit_recovers_exponential():
     ach = 37.5
     c = 400 + 600 * np.exp(-ach / 3600 * t)
     assert abs(PP.ach_fit(t, c) - ach) < 1e-9
+
+
+@pytest.mark.parametrize("c0,ach,c1", [(600.0, 12.0, 550.0), (450.0, 36.9, 350.0), (-200.0, 4.5, 900.0)])
+def test_ach_fit3_recovers_free_asymptote(c0, ach, c1):
+    """The three-parameter fit C0 exp(-ACH t) + C1 of Section 3.3 recovers the
+    rate of a synthetic decay whose asymptote is not the 400 ppm outdoor
+    level (also below it, and a rising curve), over a record of about two
+    decay times, irregularly sampled."""
+    rng = np.random.default_rng(3)
+    t = np.sort(rng.uniform(0.0, 2.0 * 3600.0 / ach, 400))
+    c = c0 * np.exp(-ach / 3600.0 * t) + c1
+    assert abs(PP.ach_fit3(t, c) / ach - 1) < 1e-7
+
+
+def test_ach_fit_known_level_refuses_values_below_it():
+    t = np.linspace(0, 3600, 50)
+    c = 400 * np.exp(-t / 1800) + 300       # crosses 400 ppm
+    with pytest.raises(ValueError):
+        PP.ach_fit(t, c)
 
 
 def test_histogram_brute_force():

@@ -425,6 +425,35 @@ def test_step_diagnostics_definitions():
     assert dg["cfl_max"] == pytest.approx(0.02 * rate, rel=1e-14)
 
 
+def test_div_l2_definition_masked():
+    """div_l2 of the diagnostics is sqrt(sum (div u)^2 dV) of the projected
+    velocity.  With solids the projected field keeps a divergence at the
+    walls (the immersed-boundary iteration is not exact after n solves), so
+    the norm is O(1) here, not round-off; the central differences are written
+    out with np.roll in this test, independently of the oracle's operators.
+    The spacing makes dV far from 1 and the norm far from its square, so a
+    dropped dV or square root fails."""
+    shape = (6, 8, 10)
+    L = (0.7, 1.9, 0.45)
+    rng = np.random.default_rng(42)
+    beta = np.ones(shape, np.uint8)
+    beta[1:3, 2:6, 3:7] = 0
+    beta[:, 0, :] = 0
+    u0 = [5.0 * rng.standard_normal(shape) * beta for _ in range(3)]
+    O = make(shape, L, beta=beta, n_piter=2, dt_fixed=1e-3, nu=1e-3)
+    s = OracleState(u0[0].copy(), u0[1].copy(), u0[2].copy(), zeros(shape), zeros(shape))
+    s, dg = O.step(s)
+    dx, dy, dz = L[0] / shape[2], L[1] / shape[1], L[2] / shape[0]
+    div = ((np.roll(s.u, -1, axis=2) - np.roll(s.u, 1, axis=2)) / (2 * dx)
+           + (np.roll(s.v, -1, axis=1) - np.roll(s.v, 1, axis=1)) / (2 * dy)
+           + (np.roll(s.w, -1, axis=0) - np.roll(s.w, 1, axis=0)) / (2 * dz))
+    dv = dx * dy * dz
+    expected = np.sqrt(np.sum(div ** 2) * dv)
+    assert expected > 1e-2                     # a real divergence, not round-off
+    assert abs(dv - 1) > 0.9 and abs(expected - expected ** 2) > 0.1 * expected
+    assert dg["div_l2"] == pytest.approx(expected, rel=1e-13)
+
+
 def test_momentum_shear_mode_advected_by_uniform_flow():
     """u = (U, A cos(k x), 0): C_y = U D_x v and C_x = 0 exactly, the field is
     divergence-free, so v is advected and diffused with the exact complex RK4

@@ -1,6 +1,7 @@
 """Host-side post-processing of the package against the oracle and against
 synthetic records with known answers (no GPU)."""
 import numpy as np
+import pytest
 
 from oracle import postproc as PP
 from paper_2204_02107_amd import postproc
@@ -33,3 +34,28 @@ def test_obstacle_coefficients_of_synthetic_records():
     assert abs(c["C_L_rms"] - 0.5 / np.sqrt(2)) < 1e-3
     assert abs(c["St"] - 0.2) < 1e-4
     assert c["samples"] == t.size - t.size // 2
+
+
+@pytest.mark.parametrize("c0,ach,c1", [(600.0, 12.0, 550.0), (450.0, 36.9, 350.0), (30.0, 2.1, 1000.0)])
+def test_fitted_ach_three_parameters_matches_oracle(c0, ach, c1):
+    """The package's three-parameter ACH fit (golden-section search) against
+    the oracle's (scan + scipy bounded minimiser) and the exact rate, on
+    synthetic decays whose asymptote is not the outdoor level; with a little
+    noise both land on the same least-squares rate."""
+    rng = np.random.default_rng(8)
+    t = np.sort(rng.uniform(0.0, 1.5 * 3600.0 / ach, 300))
+    c = c0 * np.exp(-ach / 3600.0 * t) + c1
+    diags = [{"t": a, "co2_room_mean": b} for a, b in zip(t, c)]
+    assert abs(postproc.fitted_ach(diags) / ach - 1) < 1e-7
+    noisy = c + 0.01 * abs(c0) * rng.standard_normal(t.size)
+    nd = [{"t": a, "co2_room_mean": b} for a, b in zip(t, noisy)]
+    assert abs(postproc.fitted_ach(nd) / PP.ach_fit3(t, noisy) - 1) < 1e-6
+
+
+def test_fitted_ach_known_level():
+    t = np.linspace(0.0, 60.0, 100)
+    c = 400.0 + 600.0 * np.exp(-2.0 / 3600.0 * t)
+    diags = [{"t": a, "co2_room_mean": b} for a, b in zip(t, c)]
+    assert abs(postproc.fitted_ach(diags, c_out=400.0) - PP.ach_fit(t, c)) < 1e-9
+    with pytest.raises(ValueError):
+        postproc.fitted_ach([{"t": 0.0, "co2_room_mean": 399.0}, {"t": 1.0, "co2_room_mean": 398.0}], c_out=400.0)
