@@ -142,13 +142,17 @@ def check_pool(rc, pool=None):
 # calls these back (on the calling thread) for its workspace and releases the
 # blocks after synchronising the streams that used them.
 _TORCH_USERS = {}     # key -> (device index, stream handle)
+_TORCH_HELD = {}      # key -> {pointer: bytes requested} of the blocks not yet freed
 
 
 def _torch_alloc(nbytes, user):
     try:
         import torch
-        dev, stream = _TORCH_USERS[int(user or 0)]
-        return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=stream)
+        key = int(user or 0)
+        dev, stream = _TORCH_USERS[key]
+        ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=stream)
+        _TORCH_HELD.setdefault(key, {})[int(ptr)] = int(nbytes)
+        return ptr
     except Exception:
         return None
 
@@ -156,6 +160,7 @@ def _torch_alloc(nbytes, user):
 def _torch_free(ptr, user):
     try:
         import torch
+        _TORCH_HELD.get(int(user or 0), {}).pop(int(ptr), None)
         torch.cuda.caching_allocator_delete(int(ptr))
     except Exception:
         pass
@@ -185,5 +190,11 @@ class TorchAllocator:
     def triple(self):
         return TORCH_ALLOC, TORCH_FREE, self.user
 
+    def bytes_held(self) -> int:
+        """Bytes the library has requested through this allocator and not
+        freed yet (torch's own figure rounds each block up)."""
+        return sum(_TORCH_HELD.get(self.key, {}).values())
+
     def close(self):
         _TORCH_USERS.pop(self.key, None)
+        _TORCH_HELD.pop(self.key, None)
