@@ -150,6 +150,26 @@ int dnslab_read_diags(dnslab_ctx* ctx, int32_t n, dnslab_diag* out);
  * may alias. */
 int dnslab_poisson(dnslab_ctx* ctx, const void* rhs_dev, void* p_dev);
 
+/* Size of the static device scratch of dnslab_poisson_noalloc (64 MiB). */
+#define DNSLAB_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * dnslab_poisson without a context.  Grid, lengths, precision and stream come
+ * from params (which must pass the same checks as for dnslab_init; the other
+ * fields are ignored); rhs_dev and p_dev are as for dnslab_poisson and may
+ * alias.  The spectrum and the FFT tables (computed on the device each call)
+ * live in a static device array of DNSLAB_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends; the call
+ * allocates nothing and synchronises nothing.  A grid whose spectrum and
+ * tables exceed that size (the spectrum takes 16 * ceil16(nx/2+1) * ny * nz
+ * bytes in FP64, half in FP32: 256x128x192 fits in FP64, 256x256x128 does
+ * not) returns DNSLAB_EINVAL before anything is enqueued.  Every call on one GPU uses the
+ * same array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be ordered by the caller.  Errors are reported through
+ * dnslab_last_error(NULL). */
+int dnslab_poisson_noalloc(const dnslab_params* params, const void* rhs_dev, void* p_dev);
+
 /* The projection of Section 2.2 applied in place to the velocity u*, v*, w*
  * (device, field type): n_piter immersed-boundary iterations warm-started from
  * the bound pressure p (which is updated), then u = beta (u* - grad p).  In

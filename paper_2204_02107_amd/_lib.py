@@ -18,6 +18,7 @@ FP64, FP32_REFINE = 0, 1
 # Every symbol the header declares; the CPU tests check that the library exports them.
 EXPORTS = [
     "dnslab_workspace_bytes", "dnslab_init", "dnslab_step", "dnslab_read_diags", "dnslab_poisson",
+    "dnslab_poisson_noalloc",
     "dnslab_project", "dnslab_scalar_step", "dnslab_momentum_rhs", "dnslab_scalar_rhs",
     "dnslab_filter", "dnslab_set_time", "dnslab_destroy", "dnslab_last_error",
     "dnslab_profile_enable", "dnslab_profile_read", "dnslab_set_graph_steps", "dnslab_set_overlap", "dnslab_pool_set_graph",
@@ -86,6 +87,7 @@ def load():
         "dnslab_step": (c_int, [V, c_int32, P(Diag)]),
         "dnslab_read_diags": (c_int, [V, c_int32, P(Diag)]),
         "dnslab_poisson": (c_int, [V, V, V]),
+        "dnslab_poisson_noalloc": (c_int, [P(Params), V, V]),
         "dnslab_project": (c_int, [V, V, V, V]),
         "dnslab_scalar_step": (c_int, [V, c_double]),
         "dnslab_momentum_rhs": (c_int, [V, V, V, V, V, V, V]),

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -452,32 +453,40 @@ Forcing forcing_of(dnslab_ctx* x) {
     return f;
 }
 
+// The FFT description of a grid whose spectrum starts at spec, its twiddle
+// tables at w (W_m, W_ny, W_nz, then e^{-2 pi i k/nx} for k <= m) and its
+// symbol tables at s2 (x, y, z).
+template <typename T>
+FFTArgs<T> fft_args_of(const Layout& Lo, const Grid& g, void* spec, const void* w, const double* s2) {
+    FFTArgs<T> a;
+    a.g = g;
+    a.m = Lo.m;
+    a.sx = Lo.sx;
+    a.ps = Lo.yz ? g.ny * g.nz : 0;
+    a.spec = (C2<T>*)spec;
+    a.px = Lo.px;
+    a.py = Lo.py;
+    a.pz = Lo.pz;
+    a.wx = (const C2<T>*)w;
+    a.wy = a.wx + Lo.m;
+    a.wz = a.wy + g.ny;
+    a.tw = a.wz + g.nz;
+    a.sx2 = s2;
+    a.sy2 = s2 + Lo.m + 1;
+    a.sz2 = a.sy2 + g.ny;
+    a.inv_ntot = 1.0 / (double)g.n;
+    a.nl_x = Lo.nl_x;
+    a.ls_x = Lo.ls_x;
+    a.lg_tx_y = Lo.lg_tx_y;
+    a.lg_tx_z = Lo.lg_tx_z;
+    a.lg_ca = Lo.lg_ca;
+    a.lg_cb = Lo.lg_cb;
+    return a;
+}
+
 template <typename T>
 FFTArgs<T> fft_args(dnslab_ctx* x) {
-    FFTArgs<T> a;
-    a.g = x->g;
-    a.m = x->Lo.m;
-    a.sx = x->Lo.sx;
-    a.ps = x->Lo.yz ? x->g.ny * x->g.nz : 0;
-    a.spec = (C2<T>*)x->spec;
-    a.px = x->Lo.px;
-    a.py = x->Lo.py;
-    a.pz = x->Lo.pz;
-    a.wx = (const C2<T>*)x->wx;
-    a.wy = (const C2<T>*)x->wy;
-    a.wz = (const C2<T>*)x->wz;
-    a.tw = (const C2<T>*)x->tw;
-    a.sx2 = x->sx2;
-    a.sy2 = x->sy2;
-    a.sz2 = x->sz2;
-    a.inv_ntot = 1.0 / (double)x->g.n;
-    a.nl_x = x->Lo.nl_x;
-    a.ls_x = x->Lo.ls_x;
-    a.lg_tx_y = x->Lo.lg_tx_y;
-    a.lg_tx_z = x->Lo.lg_tx_z;
-    a.lg_ca = x->Lo.lg_ca;
-    a.lg_cb = x->Lo.lg_cb;
-    return a;
+    return fft_args_of<T>(x->Lo, x->g, x->spec, x->wx, x->sx2);
 }
 
 // One FFT solve of Lap p = r (central-difference symbol, null modes zero).
@@ -1025,6 +1034,88 @@ int filt1(dnslab_ctx* x, const void* f, void* out) {
 }
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// The allocation-free Poisson solve keeps its spectrum and tables in one
+// file-scope device array.  In host code `scratch` only stands in for the
+// symbol: its device address (one copy per GPU) is looked up once per device
+// with hipGetSymbolAddress, and that address is what the kernels receive.
+static __device__ __align__(256) unsigned char scratch[DNSLAB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`.
+int noalloc_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, DNSLAB_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(nullptr, DNSLAB_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, DNSLAB_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return DNSLAB_OK;
+}
+
+// Scratch layout of the allocation-free solve: the spectrum as a context
+// stores it, then the twiddle tables, then the symbol tables.
+struct NoallocLayout {
+    size_t off_w, off_s2, total;
+};
+
+NoallocLayout noalloc_layout(const Layout& Lo, const dnslab_params* P) {
+    const size_t csz = 2 * Lo.esz;
+    NoallocLayout N;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    take((size_t)Lo.sx * P->ny * P->nz * csz);
+    N.off_w = take((size_t)(2 * Lo.m + 1 + P->ny + P->nz) * csz);
+    N.off_s2 = take((size_t)(Lo.m + 1 + P->ny + P->nz) * sizeof(double));
+    N.total = off;
+    return N;
+}
+
+template <typename T>
+int poisson_noalloc(const dnslab_params* P, const T* r, T* pout) {
+    const Layout Lo = make_layout(P, 0);
+    const Grid g = make_grid(P);
+    const NoallocLayout N = noalloc_layout(Lo, P);
+    if (N.total > (size_t)DNSLAB_NOALLOC_SCRATCH_BYTES)
+        return fail(nullptr, DNSLAB_EINVAL,
+                    "grid " + std::to_string(P->nx) + "x" + std::to_string(P->ny) + "x" + std::to_string(P->nz) +
+                        " needs " + std::to_string(N.total) + " bytes of scratch; the allocation-free solve holds " +
+                        std::to_string((size_t)DNSLAB_NOALLOC_SCRATCH_BYTES));
+    void* base = nullptr;
+    if (int rc = noalloc_scratch(&base)) return rc;
+    char* b = (char*)base;
+    const FFTArgs<T> a = fft_args_of<T>(Lo, g, b, b + N.off_w, (const double*)(b + N.off_s2));
+    const hipStream_t s = (hipStream_t)P->stream;
+    hipError_t e = launch_fft_tables<T>((C2<T>*)(b + N.off_w), (double*)(b + N.off_s2), g, s);
+    if (e == hipSuccess) e = launch_fft_x_fwd<T>(a, r, s);
+    if (e == hipSuccess) {
+        if (Lo.yz) {
+            e = launch_fft_yz_solve<T>(a, s);
+        } else {
+            if (g.ny > 1) e = launch_fft_y<T>(a, false, s);
+            if (e == hipSuccess) e = launch_fft_z_solve<T>(a, s);
+            if (e == hipSuccess && g.ny > 1) e = launch_fft_y<T>(a, true, s);
+        }
+    }
+    if (e == hipSuccess) e = launch_fft_x_inv<T>(a, pout, s);
+    if (e != hipSuccess) return fail(nullptr, DNSLAB_EHIP, std::string("launch: ") + hipGetErrorString(e));
+    return DNSLAB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int dnslab_workspace_bytes(const dnslab_params* params, size_t* out_bytes) {
@@ -1178,6 +1269,19 @@ int dnslab_poisson(dnslab_ctx* x, const void* rhs, void* p) {
     if (!rhs || !p) return fail(x, DNSLAB_EINVAL, "NULL pointer");
     if (x->Lo.esz == 8) return poisson_solve<double>(x, (const double*)rhs, (double*)p);
     return poisson_solve<float>(x, (const float*)rhs, (float*)p);
+}
+
+int dnslab_poisson_noalloc(const dnslab_params* params, const void* rhs, void* p) {
+    try {
+        std::string why;
+        int rc = validate(params, why);
+        if (rc) return fail(nullptr, rc, why);
+        if (!rhs || !p) return fail(nullptr, DNSLAB_EINVAL, "NULL pointer");
+        if (params->precision == DNSLAB_FP64) return poisson_noalloc<double>(params, (const double*)rhs, (double*)p);
+        return poisson_noalloc<float>(params, (const float*)rhs, (float*)p);
+    } catch (...) {
+        return fail(nullptr, DNSLAB_ENOMEM, "host allocation failed");
+    }
 }
 
 int dnslab_project(dnslab_ctx* x, void* u, void* v, void* w) {

@@ -129,6 +129,13 @@ hipError_t launch_fft_yz_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec
 template <typename T>
 hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s, Recorder* rec = nullptr);
 
+// The twiddle tables (W_m^j, W_ny^j, W_nz^j, e^{-2 pi i k/nx} for k <= m, in
+// that order, contiguous at w) and the symbol tables (sin^2(2 pi j/N)/dx^2 for
+// x (j <= m), y, z, contiguous at s2) of grid g, computed on the device; the
+// same layout as the tables a context uploads.
+template <typename T>
+hipError_t launch_fft_tables(C2<T>* w, double* s2, const Grid& g, hipStream_t s);
+
 // Batched replay of one recorded FFT-kernel position (see launch_batched_stencil).
 hipError_t launch_batched_fft(int kind, const void* tab, const unsigned* starts, int ns, unsigned total_blocks,
                               dim3 block, size_t lds, hipStream_t s);

@@ -765,6 +765,43 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? YZ_THREADS : YZ_THREADS32) void k_
     fft_yz_body<T, Q>(a, blk_);
 }
 
+// Twiddle and symbol tables of one grid, computed on the device: entry i of
+// the twiddle block is W_n^j = e^{-2 pi i j / n} for (n, j) = (m, j < m),
+// (ny, j < ny), (nz, j < nz), (nx, j <= m) in turn; entry k of the symbol
+// block is sin^2(2 pi j / N) / dx^2 for (N, j) = (nx, j <= m), (ny, j < ny),
+// (nz, j < nz), exactly zero where 2j is a multiple of N (the null set of
+// Section 2.2's central-difference symbol).  One thread per entry.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_tables(C2<T>* __restrict__ w, double* __restrict__ s2, int nx, int ny,
+                                                    int nz, double dx, double dy, double dz) {
+    const int m = nx / 2;
+    const int nw = 2 * m + 1 + ny + nz, nsym = m + 1 + ny + nz;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) {
+        int n, j;
+        if (i < m) { n = m; j = i; }
+        else if (i < m + ny) { n = ny; j = i - m; }
+        else if (i < m + ny + nz) { n = nz; j = i - m - ny; }
+        else { n = nx; j = i - m - ny - nz; }
+        double sn, cs;
+        sincospi(2.0 * (double)j / (double)n, &sn, &cs);
+        w[i] = C2<T>{(T)cs, (T)(-sn)};
+    } else if (i < nw + nsym) {
+        const int k = i - nw;
+        int n, j;
+        double h;
+        if (k < m + 1) { n = nx; j = k; h = dx; }
+        else if (k < m + 1 + ny) { n = ny; j = k - m - 1; h = dy; }
+        else { n = nz; j = k - m - 1 - ny; h = dz; }
+        double v = 0.0;
+        if ((2LL * j) % n != 0) {
+            const double sn = sinpi(2.0 * (double)j / (double)n);
+            v = sn * sn / (h * h);
+        }
+        s2[k] = v;
+    }
+}
+
 inline int round64(int t) { return ((t + 63) / 64) * 64; }
 
 }  // namespace
@@ -905,6 +942,15 @@ hipError_t launch_fft_yz_solve(const FFTArgs<T>& a, hipStream_t s, Recorder* rec
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_fft_tables(C2<T>* w, double* s2, const Grid& g, hipStream_t s) {
+    const int m = g.nx / 2;
+    const int total = (2 * m + 1 + g.ny + g.nz) + (m + 1 + g.ny + g.nz);
+    hipLaunchKernelGGL((k_fft_tables<T>), dim3((total + 255) / 256), dim3(256), 0, s, w, s2, g.nx, g.ny, g.nz,
+                       g.d[0], g.d[1], g.d[2]);
+    return hipGetLastError();
+}
+
 namespace {
 template <typename T>
 hipError_t fft_batched_typed(int base, int mode, const void* tab, const unsigned* st, int ns, unsigned nb, dim3 blk,
@@ -953,7 +999,8 @@ hipError_t launch_batched_fft(int kind, const void* tab, const unsigned* st, int
     template hipError_t launch_fft_x_inv<T>(const FFTArgs<T>&, T*, hipStream_t, Recorder*);              \
     template hipError_t launch_fft_y<T>(const FFTArgs<T>&, bool, hipStream_t, Recorder*);                \
     template hipError_t launch_fft_z_solve<T>(const FFTArgs<T>&, hipStream_t, Recorder*);                \
-    template hipError_t launch_fft_yz_solve<T>(const FFTArgs<T>&, hipStream_t, Recorder*);
+    template hipError_t launch_fft_yz_solve<T>(const FFTArgs<T>&, hipStream_t, Recorder*);               \
+    template hipError_t launch_fft_tables<T>(C2<T>*, double*, const Grid&, hipStream_t);
 DNSLAB_INST(double)
 DNSLAB_INST(float)
 #undef DNSLAB_INST
