@@ -54,6 +54,10 @@ def kernel_bytes(sc, esz=8):
     return {
         # RK4 momentum: fields touched per stage 9, 15, 15, 9 (x esz) + mask byte
         "mom_stage": n * ((9 + 15 + 15 + 9) / 4 * esz + 1),
+        # two stages per pass: u^n in, acc and u2 out (9 fields); u2, u^n, acc in, u* out (12)
+        "mom_pair": n * ((9 + 12) / 2 * esz + 1),
+        # the same for the scalar: c^n, u, v, w in, acc and c2 out (6); c2, c^n, acc, u, v, w in, c* out (7)
+        "scalar_pair": n * ((6 + 7) / 2 * esz + 1),
         # RK4 scalar: 6, 8, 8, 6 fields + mask byte
         "scalar_stage": n * ((6 + 8 + 8 + 6) / 4 * esz + 1),
         "ib_rhs": nib * (4 + 1 + 3 * esz),             # list entry, saved r0, r, p centre
@@ -71,9 +75,10 @@ def kernel_bytes(sc, esz=8):
     }
 
 
-def step_bytes(sc, esz=8, per_stage=False, fused_yz=False):
+def step_bytes(sc, esz=8, per_stage=False, fused_yz=False, mom_pairs=False, sca_pairs=False):
     """Pass-model bytes of one whole step (launch counts of the step sequence;
-    fused_yz: the y/z passes of a solve run as one fused pass)."""
+    fused_yz: the y/z passes of a solve run as one fused pass; mom_pairs,
+    sca_pairs: the RK4 stages run two per pass)."""
     kb = kernel_bytes(sc, esz)
     it = sc.n_piter if (sc.beta == 0).any() else min(sc.n_piter, 1)
     y_passes = 2 if sc.ny > 1 else 0
@@ -83,8 +88,9 @@ def step_bytes(sc, esz=8, per_stage=False, fused_yz=False):
     projection = kb["div"] + it * (poisson + ib) + kb["correct"]
     if esz == 4 and it > 0:
         projection += kb["refine_res"] + poisson      # FP64 residual and one correction solve
-    total = (4 * kb["mom_stage"] + (4 if per_stage else 1) * projection
-             + 4 * kb["scalar_stage"] + (kb["filter"] + kb["filter_c"] if sc.filter else 0))
+    mom = 2 * kb["mom_pair"] if mom_pairs else 4 * kb["mom_stage"]
+    sca = 2 * kb["scalar_pair"] if sca_pairs else 4 * kb["scalar_stage"]
+    total = (mom + (4 if per_stage else 1) * projection + sca + (kb["filter"] + kb["filter_c"] if sc.filter else 0))
     return total
 
 
@@ -262,19 +268,23 @@ def serving_bench(n_req, n_steps, budget_gib, mean_gap=0.5, seed=7, log=None,
 CUBE_PAPER = {30: {"St": 0.2097, "C_D": 3.12}, 60: {"St": 0.2094, "C_D": 3.05}}
 
 
-def cube_bench(n_h, t_end, every=20, precision="fp64", chunk=512):
+def cube_bench(n_h, t_end, every=20, precision="fp64", chunk=512, cfl=0.3, per_stage=False):
     """Run the obstacle-in-channel case to t_end (units of h / U_b), sampling
-    the obstacle force every ``every`` steps on the device, and report the
-    step throughput with the drag coefficient and Strouhal number over the
-    second half of the run."""
+    the obstacle force every ``every`` steps at CFL 0.3 (proportionally more
+    steps at a smaller CFL, so that the samples stay equally spaced in time)
+    on the device, and report the step throughput with the drag coefficient
+    and Strouhal number over the second half of the run."""
     import torch
     import scenarios
     import paper_2204_02107_amd as m
     from paper_2204_02107_amd import postproc
-    sc = scenarios.cube_channel(n_h)
+    sc = scenarios.cube_channel(n_h, cfl=cfl)
+    # the forcing relaxation time stays that of CFL 0.3, so that only the time step changes
+    sc.tau_f = 2.0 * 0.3 * (sc.lx / sc.nx) / sc.meta["u_max"]
+    every = max(1, int(round(every * 0.3 / cfl)))
     h, u_b = sc.meta["h"], sc.meta["u_b"]
     prec = m.FP64 if precision == "fp64" else m.FP32_REFINE
-    S = m.Solver(sc, precision=prec)
+    S = m.Solver(sc, precision=prec, project_each_stage=per_stage)
     i0, i1, j0, j1, _, _ = sc.meta["obstacle_cells"]
     box = (i0 - 1, i1 + 1, j0 - 1, j1 + 1, 0, 1)
     buf = torch.zeros((chunk, 8), dtype=torch.float64, device=S.device)
@@ -302,7 +312,8 @@ def cube_bench(n_h, t_end, every=20, precision="fp64", chunk=512):
     rec = np.concatenate(recs)
     coef = postproc.obstacle_coefficients(rec, h, u_b, sc.lz)
     return {"workload": f"obstacle in channel, {n_h} cells per edge, {sc.nx}x{sc.ny}, Re_ob 84", "cells": sc.ncells,
-            "precision": precision, "steps": steps, "t_end_h_over_Ub": float(rec[-1, 6] * u_b / h),
+            "precision": precision, "cfl": cfl, "projection": "every RK4 stage" if per_stage else "once per step",
+            "steps": steps, "t_end_h_over_Ub": float(rec[-1, 6] * u_b / h),
             "wall_s": el, "Gcell_steps_s": sc.ncells * steps / el / 1e9, **coef,
             "paper_DNSLABIB": CUBE_PAPER.get(n_h)}
 
@@ -352,6 +363,10 @@ def kernel_key(sym):
     base, targs = m.group(1), (m.group(4) or "")
     if base == "mom_stage":
         return "mom_stage"
+    if base == "mom_pair":
+        return "mom_pair"
+    if base == "sca_pair":
+        return "scalar_pair"
     if base == "sca_stage":
         return "scalar_stage"
     if base in ("filter", "filter_lds"):
@@ -466,7 +481,8 @@ def measure(sc, prec, args, label):
     dom = max(per, key=lambda k: per[k]["ms_per_step"])
     print(f"[bench] {label} per-kernel: " + json.dumps({k: {kk: round(vv, 3) for kk, vv in v.items()}
                                                        for k, v in per.items()}), file=sys.stderr, flush=True)
-    sbytes = step_bytes(sc, esz, args.per_stage, fused_yz="fft_yz" in per)
+    sbytes = step_bytes(sc, esz, args.per_stage, fused_yz="fft_yz" in per, mom_pairs="mom_pair" in per,
+                        sca_pairs="scalar_pair" in per)
     rnd = lambda d: {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["GBs"], 1),
                          "frac": round(v["GBs"] / HBM_PEAK_GBS, 3), "launches_per_step": v["launches_per_step"]}
                      for k, v in d.items()}
@@ -514,6 +530,7 @@ def main():
     ap.add_argument("--cube", type=int, nargs="*", metavar="N_H",
                     help="only run the obstacle-in-channel validation at these resolutions (cells per obstacle edge)")
     ap.add_argument("--cube-t-end", type=float, default=300.0, help="simulated time in units of h / U_b")
+    ap.add_argument("--cube-cfl", type=float, default=0.3, help="maximum Courant number of the obstacle case")
     ap.add_argument("--consistency", type=int, metavar="STEPS",
                     help="only run the workload STEPS steps in FP64 and in the FP32 form and compare them")
     ap.add_argument("--copy-probe", action="store_true",
@@ -547,7 +564,8 @@ def main():
         return
     if args.cube is not None:
         for n_h in args.cube or [30]:
-            print(json.dumps(cube_bench(n_h, args.cube_t_end, precision=args.precision)), flush=True)
+            print(json.dumps(cube_bench(n_h, args.cube_t_end, precision=args.precision, cfl=args.cube_cfl,
+                                        per_stage=args.per_stage)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the step runs on a single MI355X and this build has "

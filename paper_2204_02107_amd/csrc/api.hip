@@ -29,10 +29,10 @@ constexpr int RING_CAP = 4096;
 constexpr int PROF_POOL = 32768;
 
 enum KernelId { K_NONE = -1, K_MOM = 0, K_SCA, K_FXF, K_FY, K_FZ, K_FXI, K_FILT, K_FILTC, K_CORR, K_DIV, K_IB,
-                K_ADV, K_DIAG, K_REF, K_PART, K_FYZ, K_COUNT };
+                K_ADV, K_DIAG, K_REF, K_PART, K_FYZ, K_MOMP, K_SCAP, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {"mom_stage", "scalar_stage", "fft_x_fwd", "fft_y", "fft_z", "fft_x_inv",
                                             "filter", "filter_c", "correct", "div", "ib_rhs", "advance", "diag",
-                                            "refine_res", "particles", "fft_yz"};
+                                            "refine_res", "particles", "fft_yz", "mom_pair", "scalar_pair"};
 
 bool is_2a3b(int n) {
     if (n < 1) return false;
@@ -103,6 +103,7 @@ struct Layout {
     StencilLaunch L;       // momentum and scalar stage kernels
     StencilLaunch L1;      // one-cell-per-thread kernels (correct, div, rate)
     StencilLaunch LF;      // filter
+    StencilLaunch LP;      // fused RK4 stage pairs
     int nparts;            // partial-result slots (max block count of the reducing kernels)
     int nfields;           // work fields: 13, plus 3 for the projected velocity when the filter is on
     // byte offsets inside the workspace
@@ -206,6 +207,15 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_COL_LDS_KB
 #define DNSLAB_COL_LDS_KB 32
 #endif
+#ifndef DNSLAB_PAIRS
+#define DNSLAB_PAIRS 1         // RK4 stages two at a time (fused stage pairs) where the tile divides the grid
+#endif
+#ifndef DNSLAB_PROWS
+#define DNSLAB_PROWS 8         // rows of the 64-wide tile of the stage-pair kernels
+#endif
+#ifndef DNSLAB_PKC_DIV
+#define DNSLAB_PKC_DIV 1024    // stage-pair z chunk: nz * tiles per plane / this, clamped to [8, 32]
+#endif
 
 // z chunk: enough blocks to fill the chip, each walking at least 4 planes.
 int stencil_kc(const Grid& g, int rows, int forced) {
@@ -287,6 +297,14 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     const int fkc_min = Lo.esz == 8 ? DNSLAB_FKC_MIN : DNSLAB_FKC_MIN32;
     Lo.LF = stencil_launch(g, DNSLAB_FROWS,
                            std::max(stencil_kc(g, DNSLAB_FROWS, DNSLAB_FKC), std::min(fkc_min, P->nz)), 1);
+    {
+        // the pair kernels read kc + 4 planes and evaluate their first stage on
+        // kc + 2 planes per chunk: longer chunks than the single-stage kernels
+        const StencilLaunch one = stencil_launch(g, DNSLAB_PROWS, g.nz, 1);
+        const long long cols = (long long)one.grid.x * one.grid.y;
+        const long long pkc = std::max(8LL, std::min(32LL, (long long)g.nz * cols / DNSLAB_PKC_DIV));
+        Lo.LP = stencil_launch(g, DNSLAB_PROWS, (int)std::min<long long>(pkc, g.nz), 1);
+    }
     Lo.nparts = std::max(std::max(Lo.L.nblocks, Lo.L1.nblocks), Lo.LF.nblocks);
     // workspace layout
     size_t off = 0;
@@ -769,17 +787,33 @@ int one_step(dnslab_ctx* x) {
         if (!r) r = project_correct<T>(x, sc, s, PartSoA{}, scr);
         return r;
     };
-    for (int a = 0; a < 3; ++a) { m.us[a] = U[a]; m.acc[a] = A[a]; m.out[a] = B[a]; m.un[a] = nullptr; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FIRST, m, L, x->cur, x->rec));
-    if (per_stage && (rc = project_stage(B, Cb))) return rc;
-    for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = U[a]; m.out[a] = Cb[a]; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_HALF, m, L, x->cur, x->rec));
-    if (per_stage && (rc = project_stage(Cb, B))) return rc;
-    for (int a = 0; a < 3; ++a) { m.us[a] = Cb[a]; m.out[a] = B[a]; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FULL, m, L, x->cur, x->rec));
-    if (per_stage && (rc = project_stage(B, Cb))) return rc;
-    for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = nullptr; m.out[a] = Cb[a]; }
-    LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_LAST, m, L, x->cur, x->rec));
+    if (!per_stage && DNSLAB_PAIRS && mom_pair_supported(x->g, x->Lo.LP)) {
+        // two stages per pass: u^n -> acc after stage 2 (A) and u2 (B); then
+        // u2, u^n and acc -> u* (Cb)
+        MomPairArgs<T> q = {};
+        q.flags = m.flags;
+        q.dtp = m.dtp;
+        q.frc = m.frc;
+        q.nu = m.nu;
+        for (int a = 0; a < 3; ++a) q.body[a] = m.body[a];
+        q.g = m.g;
+        for (int a = 0; a < 3; ++a) { q.vin[a] = U[a]; q.acc[a] = A[a]; q.out[a] = B[a]; }
+        LAUNCH(x, K_MOMP, launch_mom_pair<T>(0, q, x->Lo.LP, x->cur, x->rec));
+        for (int a = 0; a < 3; ++a) { q.vin[a] = B[a]; q.un[a] = U[a]; q.accin[a] = A[a]; q.acc[a] = nullptr; q.out[a] = Cb[a]; }
+        LAUNCH(x, K_MOMP, launch_mom_pair<T>(1, q, x->Lo.LP, x->cur, x->rec));
+    } else {
+        for (int a = 0; a < 3; ++a) { m.us[a] = U[a]; m.acc[a] = A[a]; m.out[a] = B[a]; m.un[a] = nullptr; }
+        LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FIRST, m, L, x->cur, x->rec));
+        if (per_stage && (rc = project_stage(B, Cb))) return rc;
+        for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = U[a]; m.out[a] = Cb[a]; }
+        LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_HALF, m, L, x->cur, x->rec));
+        if (per_stage && (rc = project_stage(Cb, B))) return rc;
+        for (int a = 0; a < 3; ++a) { m.us[a] = Cb[a]; m.out[a] = B[a]; }
+        LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_FULL, m, L, x->cur, x->rec));
+        if (per_stage && (rc = project_stage(B, Cb))) return rc;
+        for (int a = 0; a < 3; ++a) { m.us[a] = B[a]; m.un[a] = nullptr; m.out[a] = Cb[a]; }
+        LAUNCH(x, K_MOM, launch_mom_stage<T>(ST_LAST, m, L, x->cur, x->rec));
+    }
     // projection: u* in Cb -> projected velocity V
     const T* const us[3] = {Cb[0], Cb[1], Cb[2]};
     rc = project_div<T>(x, us);

@@ -134,6 +134,7 @@ __device__ __forceinline__ int batch_slot(const unsigned* __restrict__ starts, i
 // Kernel kinds of the step sequence (for recording and batched replay).
 enum KernelKind : int {
     KK_MOM = 1, KK_SCA, KK_FILT, KK_CORR, KK_DIV, KK_REFRES, KK_REFCORR, KK_ADVANCE, KK_DIAG,   // stencil.hip
+    KK_MOMPAIR, KK_SCAPAIR,
     KK_IB = 32, KK_FXF, KK_FXI, KK_COLS,                                              // fft.hip
 };
 __host__ __device__ constexpr int kind_code(int base, int mode, int fp32) { return (base << 8) | (mode << 1) | fp32; }

@@ -30,6 +30,30 @@ struct MomArgs {
     int kc;              // cells per thread along z
 };
 
+// Two RK4 stages in one pass (the stages need no pressure: the projection
+// comes once per step).  Pair 0: k1 = F(u^n), u1 = u^n + dt/2 k1 on the tile
+// and a one-cell ring around it, k2 = F(u1) on the tile; writes
+// acc = (u^n + dt/6 k1) + dt/3 k2 and u2 = u^n + dt/2 k2.  Pair 1: k3 = F(u2),
+// u3 = u^n + dt k3 on tile and ring, k4 = F(u3); writes
+// u* = (acc + dt/3 k3) + dt/6 k4.  Each value is computed with the same
+// expressions as by the single-stage kernels.
+template <typename T>
+struct MomPairArgs {
+    const T* vin[3];    // stage input: u^n (pair 0), u2 (pair 1), read with a radius-2 halo
+    const T* un[3];     // u^n (pair 1: on the tile and its ring)
+    const T* accin[3];  // acc after stage 2 (pair 1)
+    T* acc[3];          // pair 0: acc after stage 2
+    T* out[3];          // pair 0: u2; pair 1: u*
+    const uint8_t* flags;
+    const double* dtp;
+    double dt;
+    Forcing frc;
+    double nu;
+    double body[3];
+    Grid g;
+    int kc;
+};
+
 template <typename T>
 struct ScaArgs {
     const T* cs;      // stage input (read with neighbours)
@@ -121,6 +145,11 @@ StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x);
 // records the launch (for batched replay by the pool) without issuing it.
 template <typename T> hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s,
                                                   Recorder* rec = nullptr);
+// The pair kernels need the 64 x rows tile to divide the grid in x and y
+// (mom_pair_supported); otherwise the single-stage kernels run.
+bool mom_pair_supported(const Grid& g, const StencilLaunch& L);
+template <typename T> hipError_t launch_mom_pair(int pair, const MomPairArgs<T>& a, const StencilLaunch& L,
+                                                 hipStream_t s, Recorder* rec = nullptr);
 template <typename T> hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s,
                                                   Recorder* rec = nullptr);
 template <typename T> hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream_t s,

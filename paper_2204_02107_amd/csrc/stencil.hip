@@ -157,6 +157,46 @@ __device__ __forceinline__ HaloMap<HMAX> halo_map(int i0, int j0, const Grid& g,
 // with the skew-symmetric convection written per axis as
 //   1/2 [D_a(u_a u_i) + u_a D_a u_i] = [(u_a+ + u_a0) u_i+ - (u_a- + u_a0) u_i-] / (4 dx_a).
 // ---------------------------------------------------------------------------
+template <typename T>
+struct MomCoef {
+    T q4x, q4y, q4z, ix2, iy2, iz2, nu, b[3];
+};
+template <typename T>
+__device__ __forceinline__ MomCoef<T> mom_coef(const Grid& g, double nu, const double body[3]) {
+    MomCoef<T> c;
+    c.q4x = T(g.inv4d[0]); c.q4y = T(g.inv4d[1]); c.q4z = T(g.inv4d[2]);
+    c.ix2 = T(g.invd2[0]); c.iy2 = T(g.invd2[1]); c.iz2 = T(g.invd2[2]);
+    c.nu = T(nu);
+    c.b[0] = T(body[0]); c.b[1] = T(body[1]); c.b[2] = T(body[2]);
+    return c;
+}
+
+// k = F(u) at one cell from its value z0 and its six face neighbours (every
+// momentum kernel evaluates F through this one function).
+template <typename T>
+__device__ __forceinline__ void mom_rhs_cell(const MomCoef<T>& cf, const T z0[3], const T xm[3], const T xp[3],
+                                             const T ym[3], const T yp[3], const T zm[3], const T zp[3], uint8_t fl,
+                                             const Forcing& frc, unsigned idx, T kv[3]) {
+    const T ax_p = xp[0] + z0[0], ax_m = xm[0] + z0[0];
+    const T ay_p = yp[1] + z0[1], ay_m = ym[1] + z0[1];
+    const T az_p = zp[2] + z0[2], az_m = zm[2] + z0[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T C = (ax_p * xp[c] - ax_m * xm[c]) * cf.q4x + (ay_p * yp[c] - ay_m * ym[c]) * cf.q4y +
+                    (az_p * zp[c] - az_m * zm[c]) * cf.q4z;
+        const T L = (xp[c] - T(2) * z0[c] + xm[c]) * cf.ix2 + (yp[c] - T(2) * z0[c] + ym[c]) * cf.iy2 +
+                    (zp[c] - T(2) * z0[c] + zm[c]) * cf.iz2;
+        kv[c] = -C + cf.nu * L + cf.b[c];
+    }
+    if (fl & F_FORCED) {
+        const int e = forced_entry(frc, (long long)idx);
+        const T S = T(frc.S[e]) * T(frc.inv_tau);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) kv[c] += S * (T(frc.uset[3 * e + c]) - z0[c]);
+    }
+    if (!(fl & F_FLUID)) { kv[0] = T(0); kv[1] = T(0); kv[2] = T(0); }
+}
+
 template <typename T, int MODE, bool LDS>
 __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
@@ -165,10 +205,7 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T dt = (MODE == ST_RHS) ? T(0) : T(a.dtp ? *a.dtp : a.dt);
-    const T q4x = T(g.inv4d[0]), q4y = T(g.inv4d[1]), q4z = T(g.inv4d[2]);
-    const T ix2 = T(g.invd2[0]), iy2 = T(g.invd2[1]), iz2 = T(g.invd2[2]);
-    const T nu = T(a.nu);
-    const T bx = T(a.body[0]), by = T(a.body[1]), bz = T(a.body[2]);
+    const MomCoef<T> cf = mom_coef<T>(g, a.nu, a.body);
     const T* __restrict__ u0p = a.us[0];
     const T* __restrict__ u1p = a.us[1];
     const T* __restrict__ u2p = a.us[2];
@@ -261,25 +298,7 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
         const uint8_t fl = a.flags[idx];
 
         T kv[3];
-        const T ax_p = xp[0] + z0[0], ax_m = xm[0] + z0[0];
-        const T ay_p = yp[1] + z0[1], ay_m = ym[1] + z0[1];
-        const T az_p = zp[2] + z0[2], az_m = zm[2] + z0[2];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T C = (ax_p * xp[c] - ax_m * xm[c]) * q4x + (ay_p * yp[c] - ay_m * ym[c]) * q4y +
-                        (az_p * zp[c] - az_m * zm[c]) * q4z;
-            const T L = (xp[c] - T(2) * z0[c] + xm[c]) * ix2 + (yp[c] - T(2) * z0[c] + ym[c]) * iy2 +
-                        (zp[c] - T(2) * z0[c] + zm[c]) * iz2;
-            const T b = c == 0 ? bx : (c == 1 ? by : bz);
-            kv[c] = -C + nu * L + b;
-        }
-        if (fl & F_FORCED) {
-            const int e = forced_entry(a.frc, (long long)idx);
-            const T S = T(a.frc.S[e]) * T(a.frc.inv_tau);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) kv[c] += S * (T(a.frc.uset[3 * e + c]) - z0[c]);
-        }
-        if (!(fl & F_FLUID)) { kv[0] = T(0); kv[1] = T(0); kv[2] = T(0); }
+        mom_rhs_cell<T>(cf, z0, xm, xp, ym, yp, zm, zp, fl, a.frc, idx, kv);
 
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -316,6 +335,261 @@ __device__ __forceinline__ void mom_stage_body(const MomArgs<T>& a, const BlockI
                 zq[0] = u0p[ir_]; zq[1] = u1p[ir_]; zq[2] = u2p[ir_];
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two momentum RK4 stages in one pass (MomPairArgs).  A block owns a BX x BY
+// tile and marches along z.  At output plane K it has, in LDS, the stage input
+// v of plane K+1 on the tile with a radius-2 halo (and plane K+2 for the z
+// neighbours of the ring) and the intermediate stage value w = base + c dt F(v)
+// of plane K on the tile with a one-cell ring (no corners); it computes w of
+// plane K+1 on tile and ring, then the second stage at plane K on the tile:
+//   iteration K:  store v(K+2) -> V;  sync;  w(K+1) on tile + ring -> W;  sync;
+//                 F(w) at plane K -> outputs.
+// The ring cells (2 BX + 2 BY of them, one per thread from thread 0) keep their
+// own z neighbours of v.  Two iterations before the first output plane fill
+// the pipeline, so a chunk reads kc + 4 planes of v and evaluates the first
+// stage on kc + 2 planes.  Loads run one plane ahead of their use.
+// ---------------------------------------------------------------------------
+template <int HMAX>
+struct PairHalo {
+    unsigned src[HMAX];   // in-plane offsets of this thread's halo cells of v
+    int dst[HMAX];        // their positions in a V tile
+    int n;
+};
+// Halo of the V tile (row length BX + 4, origin 2): two rows above and below
+// the tile spanning x in [-1, BX], two columns left and right spanning the
+// tile's rows.  That covers every neighbour of the tile and its ring.
+template <int HMAX>
+__device__ __forceinline__ PairHalo<HMAX> pair_halo(int i0, int j0, const Grid& g, int BX, int BY, int tid,
+                                                    int nthr) {
+    PairHalo<HMAX> h;
+    const int WV = BX + 4;
+    const int rw = BX + 2, nrow = 4 * rw, n = nrow + 4 * BY;
+    h.n = 0;
+#pragma unroll
+    for (int q = 0; q < HMAX; ++q) {
+        const int r = tid + q * nthr;
+        h.src[q] = 0;
+        h.dst[q] = 0;
+        if (r < n) {
+            int lx, ly;
+            if (r < nrow) {
+                const int row = r / rw, c = r - row * rw;
+                ly = row < 2 ? row - 2 : BY + row - 2;
+                lx = c - 1;
+            } else {
+                const int q2 = r - nrow, row = q2 >> 2, c = q2 & 3;
+                ly = row;
+                lx = c < 2 ? c - 2 : BX + c - 2;
+            }
+            const int gi = wrap1(i0 + lx, g.nx), gj = wrap1(j0 + ly, g.ny);
+            h.src[q] = (unsigned)gj * g.nx + gi;
+            h.dst[q] = (ly + 2) * WV + lx + 2;
+            h.n = q + 1;
+        }
+    }
+    return h;
+}
+
+// Ring cell r of a BX x BY tile (r < 2 BX + 2 BY): the rows below and above
+// the tile, then the columns left and right of it.
+__device__ __forceinline__ void ring_cell(int r, int BX, int BY, int& lx, int& ly) {
+    if (r < BX) { lx = r; ly = -1; }
+    else if (r < 2 * BX) { lx = r - BX; ly = BY; }
+    else if (r < 2 * BX + BY) { lx = -1; ly = r - 2 * BX; }
+    else { lx = BX; ly = r - 2 * BX - BY; }
+}
+
+template <typename T, int PAIR>
+__device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const BlockIdx3& bi) {
+    const Grid& g = a.g;
+    const Col col = column(g, a.kc, bi);
+    const int k0 = col.k0, k1 = col.k1;
+    const unsigned nxy = (unsigned)g.nxy;
+    const int nz = g.nz;
+    const T dt = T(a.dtp ? *a.dtp : a.dt);
+    const MomCoef<T> cf = mom_coef<T>(g, a.nu, a.body);
+    extern __shared__ unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int BX = blockDim.x, BY = blockDim.y;
+    const int WV = BX + 4, tv = WV * (BY + 4);     // V tile: radius 2, per component
+    const int WW = BX + 2, tw = WW * (BY + 2);     // W tile: radius 1, per component
+    T* const Vb = lds;                              // 2 planes x 3 components
+    T* const Wb = lds + 6 * tv;                     // 2 planes x 3 components
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty, nthr = BX * BY;
+    const int i0 = col.i - tx, j0 = col.j - ty;
+    const unsigned cell = col.row + col.i;
+    const int cV = (ty + 2) * WV + tx + 2, cW = (ty + 1) * WW + tx + 1;
+    constexpr int HM = 2;
+    const PairHalo<HM> hm = pair_halo<HM>(i0, j0, g, BX, BY, tid, nthr);
+    // this thread's ring cell, if any
+    const int nring = 2 * (BX + BY);
+    const bool ring = tid < nring;
+    int rlx = 0, rly = 0;
+    if (ring) ring_cell(tid, BX, BY, rlx, rly);
+    const unsigned rcell = (unsigned)wrap1(j0 + rly, g.ny) * g.nx + (unsigned)wrap1(i0 + rlx, g.nx);
+    const int rV = (rly + 2) * WV + rlx + 2, rW = (rly + 1) * WW + rlx + 1;
+    auto plane = [&](int K) -> unsigned { return (unsigned)wrap(K, nz) * nxy; };
+
+    // pipeline state for the first iteration K = k0 - 2
+    T vz0[3], vz1[3], vz2[3], vzn[3], hv[3][HM];
+    T wz0[3] = {T(0), T(0), T(0)}, wz1[3] = {T(0), T(0), T(0)};
+    T accK[3] = {T(0), T(0), T(0)};             // pair 0: acc1 of plane K; pair 1: acc3 of plane K
+    T rvm[3] = {T(0), T(0), T(0)};              // ring: v of plane K
+    T un1[3] = {T(0), T(0), T(0)}, unn[3] = {T(0), T(0), T(0)};     // pair 1: u^n, planes K+1, K+2 (tile)
+    T run1[3] = {T(0), T(0), T(0)}, runn[3] = {T(0), T(0), T(0)};   // pair 1: u^n at the ring cell
+    T ac1[3] = {T(0), T(0), T(0)}, acn[3] = {T(0), T(0), T(0)};     // pair 1: acc after stage 2, planes K+1, K+2
+    uint8_t flK = 0, flK1, flKn = 0, rfl1 = 0, rfln = 0;
+    {
+        const unsigned pa = plane(k0 - 2), pb = plane(k0 - 1), pc = plane(k0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vz0[c] = a.vin[c][pa + cell];
+            vz1[c] = a.vin[c][pb + cell];
+            vz2[c] = a.vin[c][pc + cell];
+        }
+        flK1 = a.flags[pb + cell];
+        if (ring) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rvm[c] = a.vin[c][pa + rcell];
+            rfl1 = a.flags[pb + rcell];
+        }
+        if (PAIR == 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                un1[c] = a.un[c][pb + cell];
+                if (ring) run1[c] = a.un[c][pb + rcell];
+            }
+        }
+        // V tile of plane k0 - 1
+        T* Vp = Vb + ((k0 - 1) & 1) * 3 * tv;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Vp[c * tv + cV] = vz1[c];
+#pragma unroll
+            for (int h = 0; h < HM; ++h)
+                if (h < hm.n) Vp[c * tv + hm.dst[h]] = a.vin[c][pb + hm.src[h]];
+        }
+        // halo of plane k0, stored by the first iteration
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int h = 0; h < HM; ++h) hv[c][h] = h < hm.n ? a.vin[c][pc + hm.src[h]] : T(0);
+    }
+
+    for (int K = k0 - 2; K < k1; ++K) {
+        // 1. stage input of plane K + 2 into V
+        T* const Vq = Vb + ((K + 2) & 1) * 3 * tv;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Vq[c * tv + cV] = vz2[c];
+#pragma unroll
+            for (int h = 0; h < HM; ++h)
+                if (h < hm.n) Vq[c * tv + hm.dst[h]] = hv[c][h];
+        }
+        // 2. loads for the next iteration: v of plane K + 3, the rest of plane K + 2
+        const bool more = K + 1 < k1;
+        if (more) {
+            const unsigned p3 = plane(K + 3), p2 = plane(K + 2);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                vzn[c] = a.vin[c][p3 + cell];
+#pragma unroll
+                for (int h = 0; h < HM; ++h)
+                    if (h < hm.n) hv[c][h] = a.vin[c][p3 + hm.src[h]];
+            }
+            flKn = a.flags[p2 + cell];
+            if (ring) rfln = a.flags[p2 + rcell];
+            if (PAIR == 1) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    unn[c] = a.un[c][p2 + cell];
+                    if (ring) runn[c] = a.un[c][p2 + rcell];
+                    if (K + 2 >= k0 && K + 2 < k1) acn[c] = a.accin[c][p2 + cell];
+                }
+            }
+        }
+        __syncthreads();
+        // 3. first stage at plane K + 1: w on the tile and the ring
+        const T* const Vp = Vb + ((K + 1) & 1) * 3 * tv;
+        T* const Wp = Wb + ((K + 1) & 1) * 3 * tw;
+        const unsigned p1 = plane(K + 1);
+        T wz2[3], accn[3];
+        {
+            T xm[3], xp[3], ym[3], yp[3], kv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xm[c] = Vp[c * tv + cV - 1];
+                xp[c] = Vp[c * tv + cV + 1];
+                ym[c] = Vp[c * tv + cV - WV];
+                yp[c] = Vp[c * tv + cV + WV];
+            }
+            mom_rhs_cell<T>(cf, vz1, xm, xp, ym, yp, vz0, vz2, flK1, a.frc, p1 + cell, kv);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (PAIR == 0) {
+                    accn[c] = vz1[c] + (dt / T(6)) * kv[c];
+                    wz2[c] = vz1[c] + (dt / T(2)) * kv[c];
+                } else {
+                    accn[c] = ac1[c] + (dt / T(3)) * kv[c];
+                    wz2[c] = un1[c] + dt * kv[c];
+                }
+                Wp[c * tw + cW] = wz2[c];
+            }
+        }
+        if (ring) {
+            T c0[3], xm[3], xp[3], ym[3], yp[3], zp[3], kv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                c0[c] = Vp[c * tv + rV];
+                xm[c] = Vp[c * tv + rV - 1];
+                xp[c] = Vp[c * tv + rV + 1];
+                ym[c] = Vp[c * tv + rV - WV];
+                yp[c] = Vp[c * tv + rV + WV];
+                zp[c] = Vq[c * tv + rV];
+            }
+            mom_rhs_cell<T>(cf, c0, xm, xp, ym, yp, rvm, zp, rfl1, a.frc, p1 + rcell, kv);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Wp[c * tw + rW] = PAIR == 0 ? c0[c] + (dt / T(2)) * kv[c] : run1[c] + dt * kv[c];
+                rvm[c] = c0[c];
+            }
+        }
+        __syncthreads();
+        // 4. second stage at plane K
+        if (K >= k0) {
+            const T* const Wk = Wb + (K & 1) * 3 * tw;
+            T xm[3], xp[3], ym[3], yp[3], kv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xm[c] = Wk[c * tw + cW - 1];
+                xp[c] = Wk[c * tw + cW + 1];
+                ym[c] = Wk[c * tw + cW - WW];
+                yp[c] = Wk[c * tw + cW + WW];
+            }
+            const unsigned idx = plane(K) + cell;
+            mom_rhs_cell<T>(cf, wz1, xm, xp, ym, yp, wz0, wz2, flK, a.frc, idx, kv);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (PAIR == 0) {
+                    a.acc[c][idx] = accK[c] + (dt / T(3)) * kv[c];
+                    a.out[c][idx] = vz0[c] + (dt / T(2)) * kv[c];
+                } else {
+                    a.out[c][idx] = accK[c] + (dt / T(6)) * kv[c];
+                }
+            }
+        }
+        // 5. advance the windows
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vz0[c] = vz1[c]; vz1[c] = vz2[c]; vz2[c] = vzn[c];
+            wz0[c] = wz1[c]; wz1[c] = wz2[c];
+            accK[c] = accn[c];
+            if (PAIR == 1) { un1[c] = unn[c]; run1[c] = runn[c]; ac1[c] = acn[c]; }
+        }
+        flK = flK1; flK1 = flKn; rfl1 = rfln;
     }
 }
 
@@ -894,6 +1168,15 @@ __global__ __launch_bounds__(1024) void k_mom_stage_b(const BRec<MomArgs<T>>* __
     const MomArgs<T> a = tab[s_].a;
     mom_stage_body<T, MODE, LDS>(a, bi_);
 }
+template <typename T, int PAIR>
+__global__ __launch_bounds__(512) void k_mom_pair(const MomPairArgs<T> a) { mom_pair_body<T, PAIR>(a, hw_block()); }
+template <typename T, int PAIR>
+__global__ __launch_bounds__(512) void k_mom_pair_b(const BRec<MomPairArgs<T>>* __restrict__ tab,
+                                                    const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const MomPairArgs<T> a = tab[s_].a;
+    mom_pair_body<T, PAIR>(a, bi_);
+}
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) { sca_stage_body<T, MODE>(a, hw_block()); }
 template <typename T, int MODE>
@@ -1024,6 +1307,29 @@ hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& 
     }
     if (use_lds) launch_mom_modes<T, true>(mode, b, L, lds, s);
     else launch_mom_modes<T, false>(mode, b, L, 0, s);
+    return hipGetLastError();
+}
+
+bool mom_pair_supported(const Grid& g, const StencilLaunch& L) {
+    const int bx = (int)L.block.x, by = (int)L.block.y;
+    // at most two halo cells of V per thread (4 (BX + 2) + 4 BY of them) and
+    // one ring cell per thread (2 BX + 2 BY of them)
+    return bx == 64 && by * bx <= 512 && g.nx % bx == 0 && g.ny % by == 0 && 4 * (bx + 2) + 4 * by <= 2 * bx * by &&
+           2 * (bx + by) <= bx * by;
+}
+
+template <typename T>
+hipError_t launch_mom_pair(int pair, const MomPairArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
+    if (!mom_pair_supported(a.g, L) || (pair != 0 && pair != 1)) return hipErrorInvalidValue;
+    MomPairArgs<T> b = a;
+    b.kc = L.kc;
+    const size_t lds = (size_t)6 * ((L.block.x + 4) * (L.block.y + 4) + (L.block.x + 2) * (L.block.y + 2)) * sizeof(T);
+    if (rec) {
+        record_launch(rec, kind_code(KK_MOMPAIR, pair, sizeof(T) == 4), L.grid, L.block, lds, b);
+        return hipSuccess;
+    }
+    if (pair == 0) hipLaunchKernelGGL((k_mom_pair<T, 0>), L.grid, L.block, lds, s, b);
+    else hipLaunchKernelGGL((k_mom_pair<T, 1>), L.grid, L.block, lds, s, b);
     return hipGetLastError();
 }
 
@@ -1169,6 +1475,12 @@ hipError_t batched_typed(int base, int mode, const void* tab, const unsigned* st
             }
             break;
         }
+        case KK_MOMPAIR: {
+            auto t = (const BRec<MomPairArgs<T>>*)tab;
+            if (mode == 0) hipLaunchKernelGGL((k_mom_pair_b<T, 0>), grid, blk, lds, s, t, st, ns);
+            else hipLaunchKernelGGL((k_mom_pair_b<T, 1>), grid, blk, lds, s, t, st, ns);
+            break;
+        }
         case KK_SCA: {
             auto t = (const BRec<ScaArgs<T>>*)tab;
             switch (mode) {
@@ -1236,6 +1548,7 @@ hipError_t launch_set_rate(PartSoA part, int np, StepScalars* sc, hipStream_t s)
 
 #define DNSLAB_INST(T)                                                                                              \
     template hipError_t launch_mom_stage<T>(int, const MomArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*); \
+    template hipError_t launch_mom_pair<T>(int, const MomPairArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*); \
     template hipError_t launch_sca_stage<T>(int, const ScaArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*); \
     template hipError_t launch_filter<T>(const FiltArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);        \
     template hipError_t launch_correct<T>(const CorrArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);       \

@@ -25,6 +25,9 @@ def test_kernel_key_mapping():
     assert k("dnslab::(anonymous namespace)::k_refine_correct(dnslab::RefineCorrArgs)") == "correct"
     assert k("dnslab::(anonymous namespace)::k_refine_res(dnslab::RefineResArgs)") == "refine_res"
     assert k("dnslab::(anonymous namespace)::k_refine_res_ib(dnslab::RefineResArgs)") == "refine_res_ib"
+    assert k("void dnslab::(anonymous namespace)::k_mom_pair<double, 1>(dnslab::MomPairArgs<double>)") == "mom_pair"
+    assert k("void dnslab::(anonymous namespace)::k_mom_pair_b<float, 0>(dnslab::BRec<...> const*)") == "mom_pair"
+    assert k("void dnslab::(anonymous namespace)::k_sca_pair<double, 0>(dnslab::ScaPairArgs<double>)") == "scalar_pair"
     assert k("dnslab::(anonymous namespace)::k_advance(dnslab::AdvanceArgs)") is None
     assert k("__amd_rocclr_copyBuffer") is None
 
@@ -74,6 +77,10 @@ def test_step_byte_model():
     fused = bench.step_bytes(sc, 8, fused_yz=True) / n
     assert abs(per - fused - 4 * (2 * 2 * 8.25)) < 1e-9
     assert bench.step_bytes(sc, 8, per_stage=True) > 2 * bench.step_bytes(sc, 8)
+    # RK4 stages two per pass: momentum 9 + 12 instead of 48 field accesses
+    # (+ one mask byte per pass), scalar 6 + 7 instead of 28
+    pairs = bench.step_bytes(sc, 8, mom_pairs=True, sca_pairs=True) / n
+    assert abs(per - pairs - (4 * 97 - (21 * 8 + 2)) - (4 * 57 - (13 * 8 + 2))) < 1e-9
     assert bench.step_bytes(sc, 4) < 0.6 * bench.step_bytes(sc, 8)
 
 
