@@ -298,6 +298,17 @@ int dnslab_set_graph_steps(dnslab_ctx* ctx, int32_t k);
  * deferred scalar work first.  DNSLAB_EINVAL unless enable is 0 or 1. */
 int dnslab_set_overlap(dnslab_ctx* ctx, int32_t enable);
 
+/* RK4 stages two per pass (Section 2.1's stages carry no pressure, so a
+ * kernel can evaluate the first stage of a pair on its tile and a one-cell
+ * ring and the second on the tile, reading and writing the fields once per
+ * pair).  mode -1 (the default): by grid size (where each block's z chunk is
+ * long enough to pay for the pipeline's extra planes); 0: never (one kernel
+ * per stage); 1: wherever the 64 x 8 tile divides the grid (nx % 64 == 0,
+ * ny % 8 == 0).  The scalar's pairs also need the filter on.  Results agree
+ * to rounding (every value is computed with the same expressions).  Enqueues
+ * any deferred scalar work first.  DNSLAB_EINVAL unless mode is -1, 0 or 1. */
+int dnslab_set_stage_pairs(dnslab_ctx* ctx, int32_t mode);
+
 /* ------------------------------------------------------------------------
  * Serving pool: many scenarios of different grid sizes resident at once,
  * admitted against an HBM budget and advanced together.  Each step of the

@@ -240,6 +240,11 @@ class Solver:
         kernel alone (same results)."""
         self._check(self.lib.dnslab_set_overlap(self.ctx, int(bool(enable))))
 
+    def set_stage_pairs(self, mode: int):
+        """RK4 stages two per pass: -1 by grid size (the default), 0 never,
+        1 wherever the 64 x 8 tile divides the grid."""
+        self._check(self.lib.dnslab_set_stage_pairs(self.ctx, int(mode)))
+
     # -- kernel timing -------------------------------------------------------
     def profile(self, kernel: Optional[str]):
         self._check(self.lib.dnslab_profile_enable(self.ctx, kernel.encode() if kernel else None))

@@ -98,6 +98,7 @@ struct Layout {
     long long n;
     int m, sx;            // fft
     int nl_x, ls_x, lg_tx_y, lg_tx_z;
+    int xtw_lds;          // x passes stage their twiddle tables in LDS
     int yz, lg_ca, lg_cb;  // fused plane pass (plane-major spectrum) and its LDS chunks
     AxisPlan px, py, pz;
     StencilLaunch L;       // momentum and scalar stage kernels
@@ -183,6 +184,14 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_XPASS_THREADS
 #define DNSLAB_XPASS_THREADS 256
 #endif
+#ifndef DNSLAB_XPASS_TW_LDS_MAX_M
+// x passes stage their W_m and twist tables in LDS up to this half length m
+// and read them through the caches beyond: on 1024x512x256 (m = 512) the
+// tables took half of each block's LDS and reading them through the caches
+// took the passes from 552 / 712 to 406 / 496 us (FP64 forward / inverse);
+// on 256x128x96 (m = 128) staging them stays 5-7% faster
+#define DNSLAB_XPASS_TW_LDS_MAX_M 256
+#endif
 #ifndef DNSLAB_XPASS_LDS_KB
 #define DNSLAB_XPASS_LDS_KB 48
 #endif
@@ -207,8 +216,14 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_COL_LDS_KB
 #define DNSLAB_COL_LDS_KB 32
 #endif
+#ifndef DNSLAB_COL_FP32_WIDE
+#define DNSLAB_COL_FP32_WIDE 0    // measured slower on 1024x512x256 (y 272 -> 288 us, z 382 -> 436 us)
+#endif
 #ifndef DNSLAB_PAIRS
 #define DNSLAB_PAIRS 1         // RK4 stages two at a time (fused stage pairs) where the tile divides the grid
+#endif
+#ifndef DNSLAB_PAIR_MIN_KC
+#define DNSLAB_PAIR_MIN_KC 16  // shortest z chunk for the scalar pairs and the FP32 momentum pairs
 #endif
 #ifndef DNSLAB_PROWS
 #define DNSLAB_PROWS 8         // rows of the 64-wide tile of the stage-pair kernels
@@ -239,13 +254,15 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     Lo.py = make_axis_plan(P->ny);
     Lo.pz = make_axis_plan(P->nz);
     Lo.ls_x = ((Lo.m + 1) % 2 == 1) ? Lo.m + 1 : Lo.m + 2;
+    Lo.xtw_lds = Lo.m < DNSLAB_XPASS_TW_LDS_MAX_M ? 1 : 0;
     const long long nlines = (long long)P->ny * P->nz;
     {
         int nl = 1;
         // (the LDS bounds count FP64 complex values in both precisions: the FP32
         // form keeps the FP64 tile shapes, hence as many blocks)
         while (nl * 2 * Lo.px.tpl <= DNSLAB_XPASS_THREADS &&
-               ((size_t)nl * 2 * Lo.ls_x + 2 * Lo.m + 1) * 16 <= DNSLAB_XPASS_LDS_KB * 1024 && nl < nlines)
+               ((size_t)nl * 2 * Lo.ls_x + (Lo.xtw_lds ? 2 * Lo.m + 1 : 0)) * 16 <= DNSLAB_XPASS_LDS_KB * 1024 &&
+               nl < nlines)
             nl *= 2;
         Lo.nl_x = ilog2(nl);
     }
@@ -261,6 +278,17 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     // pass, whose tiles are read with the larger row stride, is not)
     if ((1 << Lo.lg_tx_y) <= 4) Lo.lg_tx_y = pick_tx(P->ny, Lo.py, 2 * DNSLAB_COL_LDS_KB * 1024);
     Lo.lg_tx_z = pick_tx(P->nz, Lo.pz, DNSLAB_COL_LDS_KB * 1024);
+    // FP32: twice the columns in the same LDS bytes, so that a tile's row
+    // segments span as many bytes as in FP64 (with half-length segments the
+    // L2 fetched whole lines twice: FETCH_SIZE twice the spectrum per pass)
+    if (Lo.esz == 4 && DNSLAB_COL_FP32_WIDE) {
+        auto widen = [&](int lg, int n, const AxisPlan& ap) {
+            const int cap = std::min(64, pow2_floor(2LL * (Lo.m + 1) - 1));
+            return (2 << lg) <= cap && (2LL << lg) * ap.tpl <= 1024 ? lg + 1 : lg;
+        };
+        Lo.lg_tx_y = widen(Lo.lg_tx_y, P->ny, Lo.py);
+        Lo.lg_tx_z = widen(Lo.lg_tx_z, P->nz, Lo.pz);
+    }
     // Fused plane pass: each of the nx/2 + 1 kx planes (ny * nz values) held
     // by one block in registers, its y and z lines transformed in LDS chunks.
     // It cuts two of the three column passes and their launches, but one
@@ -305,7 +333,7 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
         const long long pkc = std::max(8LL, std::min(32LL, (long long)g.nz * cols / DNSLAB_PKC_DIV));
         Lo.LP = stencil_launch(g, DNSLAB_PROWS, (int)std::min<long long>(pkc, g.nz), 1);
     }
-    Lo.nparts = std::max(std::max(Lo.L.nblocks, Lo.L1.nblocks), Lo.LF.nblocks);
+    Lo.nparts = std::max(std::max(std::max(Lo.L.nblocks, Lo.L1.nblocks), Lo.LF.nblocks), Lo.LP.nblocks);
     // workspace layout
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
@@ -385,6 +413,7 @@ struct dnslab_ctx {
     // step n; it runs on a second stream, overlapping the pressure solves of
     // step n + 1 (see one_step).
     bool overlap;          // defer the scalar work to aux (plain contexts; not when recording)
+    int pairs_mode = -1;   // RK4 stage pairs: -1 by grid size, 0 never, 1 wherever the tile divides the grid
     hipStream_t aux;       // created on first use
     hipEvent_t ev_fork, ev_join;
     bool tail_pending;     // scalar work of the last step taken not yet enqueued
@@ -493,6 +522,7 @@ FFTArgs<T> fft_args_of(const Layout& Lo, const Grid& g, void* spec, const void* 
     a.sy2 = s2 + Lo.m + 1;
     a.sz2 = a.sy2 + g.ny;
     a.inv_ntot = 1.0 / (double)g.n;
+    a.xtw_lds = Lo.xtw_lds;
     a.nl_x = Lo.nl_x;
     a.ls_x = Lo.ls_x;
     a.lg_tx_y = Lo.lg_tx_y;
@@ -611,6 +641,29 @@ int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
     return rc;
 }
 
+// RK4 stages two per pass where the pair kernels' tile divides the grid and
+// the grid gives each block a z chunk long enough for the pipeline's four
+// extra planes: measured, the momentum pairs gain on 256x128x96 in FP64
+// (8-plane chunks: 261 -> 224 us per step) but lose in FP32 (139 -> 152 us),
+// and the scalar pairs lose on it in both (152 -> 189, 104 -> 137 us), while
+// on 1024x512x256 (32-plane chunks) both gain (FP64 momentum 12.0 -> 6.6 ms,
+// scalar 7.6 -> 5.2 ms per step).
+// dnslab_set_stage_pairs overrides the choice (pairs_mode 0: never, 1:
+// wherever supported).
+bool mom_pairs(const dnslab_ctx* x) {
+    if (x->pairs_mode == 0 || !DNSLAB_PAIRS || !mom_pair_supported(x->g, x->Lo.LP)) return false;
+    return x->pairs_mode == 1 || x->Lo.esz == 8 || x->Lo.LP.kc >= DNSLAB_PAIR_MIN_KC;
+}
+// The scalar's second pair reads c^n at the cells around its tile, so it
+// cannot write c^n in place: the pairs run when the filter is on (the RK4
+// result then goes to a work field).
+bool sca_pairs(const dnslab_ctx* x) {
+    if (x->pairs_mode == 0 || !DNSLAB_PAIRS || x->P.filter == 0 || !mom_pair_supported(x->g, x->Lo.LP)) return false;
+    return x->pairs_mode == 1 || x->Lo.LP.kc >= DNSLAB_PAIR_MIN_KC;
+}
+// Partial-sum slots the scalar stages fill (divergence and, without the filter, CO2).
+int sca_nblocks(const dnslab_ctx* x) { return sca_pairs(x) ? x->Lo.LP.nblocks : x->Lo.L.nblocks; }
+
 template <typename T>
 int scalar_rk4(dnslab_ctx* x, const T* const uvel[3], const double* dtp, double dt, T* cout, PartSoA pdiv,
                PartSoA psca) {
@@ -628,6 +681,23 @@ int scalar_rk4(dnslab_ctx* x, const T* const uvel[3], const double* dtp, double 
     s.g = x->g;
     s.acc = CA;
     const StencilLaunch& L = x->Lo.L;
+    if (sca_pairs(x) && (const void*)cout != (const void*)C) {
+        // two stages per pass: c^n -> acc after stage 2 (CA) and c2 (CS1);
+        // then c2, c^n and acc -> c*
+        ScaPairArgs<T> q = {};
+        for (int a = 0; a < 3; ++a) q.u[a] = uvel[a];
+        q.flags = s.flags;
+        q.dtp = dtp;
+        q.dt = dt;
+        q.frc = s.frc;
+        q.alpha = s.alpha;
+        q.g = s.g;
+        q.cin = C; q.acc = CA; q.out = CS1; q.part = pdiv;
+        LAUNCH(x, K_SCAP, launch_sca_pair<T>(0, q, x->Lo.LP, x->cur, x->rec));
+        q.cin = CS1; q.cn = C; q.accin = CA; q.acc = nullptr; q.out = cout; q.part = psca;
+        LAUNCH(x, K_SCAP, launch_sca_pair<T>(1, q, x->Lo.LP, x->cur, x->rec));
+        return DNSLAB_OK;
+    }
     s.cs = C; s.out = CS1; s.part = pdiv;
     LAUNCH(x, K_SCA, launch_sca_stage<T>(ST_FIRST, s, L, x->cur, x->rec));
     s.cs = CS1; s.cn = C; s.out = CS2; s.part = PartSoA{};
@@ -685,8 +755,8 @@ int scalar_half(dnslab_ctx* x) {
     DiagArgs d;
     d.part = x->part;
     d.np_vel = filt ? x->Lo.LF.nblocks : x->Lo.L1.nblocks;
-    d.np_sca = filt ? x->Lo.LF.nblocks : x->Lo.L.nblocks;
-    d.np_div = x->Lo.L.nblocks;
+    d.np_sca = filt ? x->Lo.LF.nblocks : sca_nblocks(x);
+    d.np_div = sca_nblocks(x);
     d.sc = x->sc;
     d.ring = x->ring;
     d.ring_cap = RING_CAP;
@@ -787,7 +857,7 @@ int one_step(dnslab_ctx* x) {
         if (!r) r = project_correct<T>(x, sc, s, PartSoA{}, scr);
         return r;
     };
-    if (!per_stage && DNSLAB_PAIRS && mom_pair_supported(x->g, x->Lo.LP)) {
+    if (!per_stage && mom_pairs(x)) {
         // two stages per pass: u^n -> acc after stage 2 (A) and u2 (B); then
         // u2, u^n and acc -> u* (Cb)
         MomPairArgs<T> q = {};
@@ -1605,6 +1675,23 @@ int dnslab_set_overlap(dnslab_ctx* x, int32_t enable) {
         x->gexec = nullptr;
     }
     x->overlap = enable != 0;
+    return DNSLAB_OK;
+}
+
+int dnslab_set_stage_pairs(dnslab_ctx* x, int32_t mode) {
+    if (int rc = check_ctx(x)) return rc;
+    if (mode < -1 || mode > 1) return fail(x, DNSLAB_EINVAL, "mode must be -1, 0 or 1");
+    try {
+        int rc = x->Lo.esz == 8 ? settle<double>(x) : settle<float>(x);
+        if (rc) return rc;
+    } catch (...) {
+        return fail(x, DNSLAB_ENOMEM, "host allocation failed");
+    }
+    if (x->pairs_mode != mode && x->gexec) {
+        HIPCHK(x, hipGraphExecDestroy(x->gexec));   // captured with the other kernels
+        x->gexec = nullptr;
+    }
+    x->pairs_mode = mode;
     return DNSLAB_OK;
 }
 

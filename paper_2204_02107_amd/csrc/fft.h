@@ -37,6 +37,7 @@ struct FFTArgs {
     const double* sz2;
     double inv_ntot;
     // x pass
+    int xtw_lds;        // 1: the W_m and twist tables are staged in each block's LDS; 0: read through the caches
     int nl_x;           // lines per block (power of two)
     int ls_x;           // LDS line stride (odd, >= m + 1)
     // y / z passes

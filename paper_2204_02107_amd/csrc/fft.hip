@@ -405,10 +405,17 @@ __device__ __forceinline__ void fft_x_fwd_body(const FxfArgs<T>& A, unsigned blk
     const unsigned nx = a.g.nx;
     const LineSplit sp = line_split(m);
     const int tot = m << lg;
-    C2<T>* wl = s + (ls << lg);      // W_m table, then the real-transform twist
-    C2<T>* tl = wl + m;
-    for (int j = tid; j < m; j += nthr) wl[j] = a.wx[j];
-    for (int j = tid; j <= m; j += nthr) tl[j] = a.tw[j];
+    // the W_m table and the real-transform twist: staged in LDS, or read
+    // through the caches (long lines: LDS then holds only the lines)
+    const C2<T>* wl = a.wx;
+    const C2<T>* tl = a.tw;
+    if (a.xtw_lds) {
+        C2<T>* w = s + (ls << lg);
+        for (int j = tid; j < m; j += nthr) w[j] = a.wx[j];
+        for (int j = tid; j <= m; j += nthr) w[m + j] = a.tw[j];
+        wl = w;
+        tl = w + m;
+    }
     C2<T> buf[STAGE_MAX];
 #pragma unroll
     for (int q = 0; q < STAGE_MAX; ++q) {
@@ -460,10 +467,15 @@ __device__ __forceinline__ void fft_x_inv_body(const FxiArgs<T>& A, unsigned blk
     const int nlines = a.g.ny * a.g.nz;
     const unsigned nx = a.g.nx;
     const int m1 = m + 1;
-    C2<T>* wl = s + (ls << lg);
-    C2<T>* tl = wl + m;
-    for (int j = tid; j < m; j += nthr) wl[j] = a.wx[j];
-    for (int j = tid; j <= m; j += nthr) tl[j] = a.tw[j];
+    const C2<T>* wl = a.wx;
+    const C2<T>* tl = a.tw;
+    if (a.xtw_lds) {
+        C2<T>* w = s + (ls << lg);
+        for (int j = tid; j < m; j += nthr) w[j] = a.wx[j];
+        for (int j = tid; j <= m; j += nthr) w[m + j] = a.tw[j];
+        wl = w;
+        tl = w + m;
+    }
     {
         const int tot = m1 << lg;
         // element e -> (line l, kx k): kx fastest for the row-major spectrum,
@@ -856,7 +868,7 @@ hipError_t launch_fft_x_fwd(const FFTArgs<T>& a, const T* r, hipStream_t s, Reco
     const int nlines = a.g.ny * a.g.nz;
     dim3 grid((nlines + nl - 1) / nl);
     dim3 block(round64(std::min(1024, nl * a.px.tpl * DNSLAB_FFT_TPL_MUL)));
-    size_t lds = ((size_t)nl * a.ls_x + 2 * a.m + 1) * sizeof(C2<T>);
+    size_t lds = ((size_t)nl * a.ls_x + (a.xtw_lds ? 2 * a.m + 1 : 0)) * sizeof(C2<T>);
     FxfArgs<T> b;
     b.f = a;
     b.r = r;
@@ -874,7 +886,7 @@ hipError_t launch_fft_x_inv(const FFTArgs<T>& a, T* p, hipStream_t s, Recorder* 
     const int nlines = a.g.ny * a.g.nz;
     dim3 grid((nlines + nl - 1) / nl);
     dim3 block(round64(std::min(1024, nl * a.px.tpl * DNSLAB_FFT_TPL_MUL)));
-    size_t lds = ((size_t)nl * a.ls_x + 2 * a.m + 1) * sizeof(C2<T>);
+    size_t lds = ((size_t)nl * a.ls_x + (a.xtw_lds ? 2 * a.m + 1 : 0)) * sizeof(C2<T>);
     FxiArgs<T> b;
     b.f = a;
     b.p = p;

@@ -71,6 +71,30 @@ struct ScaArgs {
     PartSoA part;     // ST_FIRST: div^2 partials; ST_LAST: CO2 diagnostics partials (p NULL: none)
 };
 
+// Two scalar RK4 stages in one pass, as MomPairArgs for the momentum: pair 0
+// k1 = G(c^n) on tile and ring, c1 = c^n + dt/2 k1, k2 = G(c1); writes
+// acc = (c^n + dt/6 k1) + dt/3 k2 and c2 = c^n + dt/2 k2 (partials: div u
+// squared).  Pair 1: k3 = G(c2), c3 = c^n + dt k3 on tile and ring, k4 = G(c3);
+// writes c* = beta ((acc + dt/3 k3) + dt/6 k4) (partials: CO2 mass and room
+// sums).  The velocity is frozen.
+template <typename T>
+struct ScaPairArgs {
+    const T* cin;     // stage input: c^n (pair 0), c2 (pair 1), read with a radius-2 halo
+    const T* cn;      // c^n (pair 1: tile and ring)
+    const T* accin;   // acc after stage 2 (pair 1)
+    T* acc;           // pair 0: acc after stage 2
+    T* out;           // pair 0: c2; pair 1: c*
+    const T* u[3];
+    const uint8_t* flags;
+    const double* dtp;
+    double dt;
+    Forcing frc;
+    double alpha;
+    Grid g;
+    int kc;
+    PartSoA part;
+};
+
 template <typename T>
 struct FiltArgs {
     const T* in[3];
@@ -149,6 +173,8 @@ template <typename T> hipError_t launch_mom_stage(int mode, const MomArgs<T>& a,
 // (mom_pair_supported); otherwise the single-stage kernels run.
 bool mom_pair_supported(const Grid& g, const StencilLaunch& L);
 template <typename T> hipError_t launch_mom_pair(int pair, const MomPairArgs<T>& a, const StencilLaunch& L,
+                                                 hipStream_t s, Recorder* rec = nullptr);
+template <typename T> hipError_t launch_sca_pair(int pair, const ScaPairArgs<T>& a, const StencilLaunch& L,
                                                  hipStream_t s, Recorder* rec = nullptr);
 template <typename T> hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s,
                                                   Recorder* rec = nullptr);

@@ -598,6 +598,42 @@ __device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const Blo
 //                              + S (c_set - c)/tau_f ],
 // the masked diffusion conducting only across fluid-fluid faces.
 // ---------------------------------------------------------------------------
+template <typename T>
+struct ScaCoef {
+    T h2x, h2y, h2z, ix2, iy2, iz2, alpha;
+};
+template <typename T>
+__device__ __forceinline__ ScaCoef<T> sca_coef(const Grid& g, double alpha) {
+    ScaCoef<T> c;
+    c.h2x = T(g.inv2d[0]); c.h2y = T(g.inv2d[1]); c.h2z = T(g.inv2d[2]);
+    c.ix2 = T(g.invd2[0]); c.iy2 = T(g.invd2[1]); c.iz2 = T(g.invd2[2]);
+    c.alpha = T(alpha);
+    return c;
+}
+
+// G(c) at one cell from c at the cell and its six face neighbours, the
+// velocity component normal to each face pair at those neighbours, and the
+// flags (every scalar kernel evaluates G through this one function).
+template <typename T>
+__device__ __forceinline__ T sca_rhs_cell(const ScaCoef<T>& cf, T c0, T cxm, T cxp, T cym, T cyp, T cm, T cp,
+                                          T uxm, T uxp, T vym, T vyp, T wm, T wp, uint8_t f0, uint8_t fxm,
+                                          uint8_t fxp, uint8_t fym, uint8_t fyp, uint8_t fm, uint8_t fp,
+                                          const Forcing& frc, unsigned idx) {
+    T G = T(0);
+    if (f0 & F_FLUID) {
+        const T conv = (uxp * cxp - uxm * cxm) * cf.h2x + (vyp * cyp - vym * cym) * cf.h2y + (wp * cp - wm * cm) * cf.h2z;
+        const T lx = ((fxp & F_FLUID) ? cxp - c0 : T(0)) - ((fxm & F_FLUID) ? c0 - cxm : T(0));
+        const T ly = ((fyp & F_FLUID) ? cyp - c0 : T(0)) - ((fym & F_FLUID) ? c0 - cym : T(0));
+        const T lz = ((fp & F_FLUID) ? cp - c0 : T(0)) - ((fm & F_FLUID) ? c0 - cm : T(0));
+        G = -conv + cf.alpha * (lx * cf.ix2 + ly * cf.iy2 + lz * cf.iz2);
+        if (f0 & F_FORCED) {
+            const int e = forced_entry(frc, (long long)idx);
+            G += T(frc.S[e]) * T(frc.inv_tau) * (T(frc.cset[e]) - c0);
+        }
+    }
+    return G;
+}
+
 template <typename T, int MODE>
 __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
@@ -605,9 +641,7 @@ __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockI
     const int k0 = col.k0, k1 = col.k1;
     const unsigned nxy = (unsigned)g.nxy;
     const T dt = (MODE == ST_RHS) ? T(0) : T(a.dtp ? *a.dtp : a.dt);
-    const T h2x = T(g.inv2d[0]), h2y = T(g.inv2d[1]), h2z = T(g.inv2d[2]);
-    const T ix2 = T(g.invd2[0]), iy2 = T(g.invd2[1]), iz2 = T(g.invd2[2]);
-    const T alpha = T(a.alpha);
+    const ScaCoef<T> cf = sca_coef<T>(g, a.alpha);
     const T* __restrict__ cs = a.cs;
     const T* __restrict__ ux = a.u[0];
     const T* __restrict__ uy = a.u[1];
@@ -637,19 +671,8 @@ __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockI
             const T uxm = ux[ixm], uxp = ux[ixp], vym = uy[iym], vyp = uy[iyp];
             const uint8_t fxm = a.flags[ixm], fxp = a.flags[ixp], fym = a.flags[iym], fyp = a.flags[iyp];
 
-            T G = T(0);
-            if (f0 & F_FLUID) {
-                const T conv = (uxp * cxp - uxm * cxm) * h2x + (vyp * cyp - vym * cym) * h2y +
-                               (wp * cp - wm * cm) * h2z;
-                const T lx = ((fxp & F_FLUID) ? cxp - c0 : T(0)) - ((fxm & F_FLUID) ? c0 - cxm : T(0));
-                const T ly = ((fyp & F_FLUID) ? cyp - c0 : T(0)) - ((fym & F_FLUID) ? c0 - cym : T(0));
-                const T lz = ((fp & F_FLUID) ? cp - c0 : T(0)) - ((fm & F_FLUID) ? c0 - cm : T(0));
-                G = -conv + alpha * (lx * ix2 + ly * iy2 + lz * iz2);
-                if (f0 & F_FORCED) {
-                    const int e = forced_entry(a.frc, (long long)idx);
-                    G += T(a.frc.S[e]) * T(a.frc.inv_tau) * (T(a.frc.cset[e]) - c0);
-                }
-            }
+            const T G = sca_rhs_cell<T>(cf, c0, cxm, cxp, cym, cyp, cm, cp, uxm, uxp, vym, vyp, wm, wp, f0, fxm, fxp,
+                                        fym, fyp, fm, fp, a.frc, idx);
             if (MODE == ST_FIRST) {
                 a.acc[idx] = c0 + (dt / T(6)) * G;
                 a.out[idx] = c0 + (dt / T(2)) * G;
@@ -678,6 +701,225 @@ __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockI
     }
     if (MODE == ST_FIRST && a.part.p) block_reduce_partial<PM_DIV>(part, a.part, (int)bi.hw);
     if (MODE == ST_LAST && a.part.p) block_reduce_partial<PM_SCA>(part, a.part, (int)bi.hw);
+}
+
+// ---------------------------------------------------------------------------
+// Two scalar RK4 stages in one pass (ScaPairArgs), with the pipeline of
+// mom_pair_body.  The first stage at plane K+1 needs c with a radius-2 halo,
+// u and v at x and y neighbours and the flags with a radius-2 halo, so c, u,
+// v and the flags of planes K+1 and K+2 are staged in LDS; w is only needed at
+// z neighbours (the threads' own z windows, and the ring cells' own).  The
+// second stage at plane K needs u, v and the flags at the same neighbours the
+// first stage read one plane earlier: each thread keeps them from there.
+// ---------------------------------------------------------------------------
+template <typename T, int PAIR>
+__device__ __forceinline__ void sca_pair_body(const ScaPairArgs<T>& a, const BlockIdx3& bi) {
+    const Grid& g = a.g;
+    const Col col = column(g, a.kc, bi);
+    const int k0 = col.k0, k1 = col.k1;
+    const unsigned nxy = (unsigned)g.nxy;
+    const int nz = g.nz;
+    const T dt = T(a.dtp ? *a.dtp : a.dt);
+    const ScaCoef<T> cf = sca_coef<T>(g, a.alpha);
+    extern __shared__ unsigned char smem_raw[];
+    const int BX = blockDim.x, BY = blockDim.y;
+    const int WV = BX + 4, tv = WV * (BY + 4);
+    const int WW = BX + 2, tw = WW * (BY + 2);
+    T* const Cs = reinterpret_cast<T*>(smem_raw);   // c, 2 planes
+    T* const Us = Cs + 2 * tv;                        // u, 2 planes
+    T* const Vs = Us + 2 * tv;                        // v, 2 planes
+    T* const Ws = Vs + 2 * tv;                        // first-stage value c1, 2 planes (radius 1)
+    uint8_t* const Fs = reinterpret_cast<uint8_t*>(Ws + 2 * tw);   // flags, 2 planes
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty, nthr = BX * BY;
+    const int i0 = col.i - tx, j0 = col.j - ty;
+    const unsigned cell = col.row + col.i;
+    const int cV = (ty + 2) * WV + tx + 2, cW = (ty + 1) * WW + tx + 1;
+    constexpr int HM = 2;
+    const PairHalo<HM> hm = pair_halo<HM>(i0, j0, g, BX, BY, tid, nthr);
+    const int nring = 2 * (BX + BY);
+    const bool ring = tid < nring;
+    int rlx = 0, rly = 0;
+    if (ring) ring_cell(tid, BX, BY, rlx, rly);
+    const unsigned rcell = (unsigned)wrap1(j0 + rly, g.ny) * g.nx + (unsigned)wrap1(i0 + rlx, g.nx);
+    const int rV = (rly + 2) * WV + rlx + 2, rW = (rly + 1) * WW + rlx + 1;
+    auto plane = [&](int K) -> unsigned { return (unsigned)wrap(K, nz) * nxy; };
+    const T* __restrict__ ux = a.u[0];
+    const T* __restrict__ uy = a.u[1];
+    const T* __restrict__ uz = a.u[2];
+    Partial part = {0, 0, 0, 0, 0, 0};
+
+    // own z windows (planes K-1 .. K+3)
+    T cz0, cz1, cz2, czn = T(0);                       // c_in: K, K+1, K+2, next
+    T wzm = T(0), wz0, wz1, wz2, wzn = T(0);           // w: K-1 .. K+2, next
+    T uz2, vz2, uzn = T(0), vzn = T(0);                // u, v of plane K+2 (staged by this thread), next
+    uint8_t fzm = 0, fz0, fz1, fz2, fzn = 0;           // flags: K-1 .. K+2, next
+    T hc[HM], hu[HM], hv[HM];
+    uint8_t hf[HM];
+    T c1z0 = T(0), c1z1 = T(0);                       // first-stage value c1, planes K-1, K
+    T accK = T(0);                                     // pair 0: acc1 of plane K; pair 1: acc3 of plane K
+    // the first stage's x/y neighbours of u, v and flags at plane K (for the second stage)
+    T kuxm = T(0), kuxp = T(0), kvym = T(0), kvyp = T(0);
+    uint8_t kfxm = 0, kfxp = 0, kfym = 0, kfyp = 0;
+    // ring cell: c and flags of plane K, w of planes K .. K+2 and next
+    T rcK = T(0), rw0 = T(0), rw1 = T(0), rw2 = T(0), rwn = T(0);
+    uint8_t rfK = 0;
+    // pair 1: c^n (own and ring) and acc after stage 2, planes K+1 and K+2
+    T cn1 = T(0), cnn = T(0), rcn1 = T(0), rcnn = T(0), ac1 = T(0), acn = T(0);
+    {
+        const unsigned pa = plane(k0 - 2), pb = plane(k0 - 1), pc = plane(k0);
+        cz0 = a.cin[pa + cell]; cz1 = a.cin[pb + cell]; cz2 = a.cin[pc + cell];
+        wz0 = uz[pa + cell]; wz1 = uz[pb + cell]; wz2 = uz[pc + cell];
+        fz0 = a.flags[pa + cell]; fz1 = a.flags[pb + cell]; fz2 = a.flags[pc + cell];
+        uz2 = ux[pc + cell];
+        vz2 = uy[pc + cell];
+        if (ring) {
+            rcK = a.cin[pa + rcell];
+            rfK = a.flags[pa + rcell];
+            rw0 = uz[pa + rcell]; rw1 = uz[pb + rcell]; rw2 = uz[pc + rcell];
+        }
+        if (PAIR == 1) {
+            cn1 = a.cn[pb + cell];
+            if (ring) rcn1 = a.cn[pb + rcell];
+        }
+        // LDS planes of k0 - 1
+        const int b = (k0 - 1) & 1;
+        Cs[b * tv + cV] = cz1;
+        Us[b * tv + cV] = ux[pb + cell];
+        Vs[b * tv + cV] = uy[pb + cell];
+        Fs[b * tv + cV] = fz1;
+#pragma unroll
+        for (int h = 0; h < HM; ++h)
+            if (h < hm.n) {
+                Cs[b * tv + hm.dst[h]] = a.cin[pb + hm.src[h]];
+                Us[b * tv + hm.dst[h]] = ux[pb + hm.src[h]];
+                Vs[b * tv + hm.dst[h]] = uy[pb + hm.src[h]];
+                Fs[b * tv + hm.dst[h]] = a.flags[pb + hm.src[h]];
+            }
+        // halo of plane k0, staged by the first iteration
+#pragma unroll
+        for (int h = 0; h < HM; ++h) {
+            const bool on = h < hm.n;
+            hc[h] = on ? a.cin[pc + hm.src[h]] : T(0);
+            hu[h] = on ? ux[pc + hm.src[h]] : T(0);
+            hv[h] = on ? uy[pc + hm.src[h]] : T(0);
+            hf[h] = on ? a.flags[pc + hm.src[h]] : 0;
+        }
+    }
+
+    for (int K = k0 - 2; K < k1; ++K) {
+        // 1. plane K + 2 into LDS
+        const int bq = (K + 2) & 1, bp = (K + 1) & 1;
+        Cs[bq * tv + cV] = cz2;
+        Us[bq * tv + cV] = uz2;
+        Vs[bq * tv + cV] = vz2;
+        Fs[bq * tv + cV] = fz2;
+#pragma unroll
+        for (int h = 0; h < HM; ++h)
+            if (h < hm.n) {
+                Cs[bq * tv + hm.dst[h]] = hc[h];
+                Us[bq * tv + hm.dst[h]] = hu[h];
+                Vs[bq * tv + hm.dst[h]] = hv[h];
+                Fs[bq * tv + hm.dst[h]] = hf[h];
+            }
+        // 2. loads for the next iteration
+        if (K + 1 < k1) {
+            const unsigned p3 = plane(K + 3), p2 = plane(K + 2);
+            czn = a.cin[p3 + cell];
+            wzn = uz[p3 + cell];
+            uzn = ux[p3 + cell];
+            vzn = uy[p3 + cell];
+            fzn = a.flags[p3 + cell];
+#pragma unroll
+            for (int h = 0; h < HM; ++h)
+                if (h < hm.n) {
+                    hc[h] = a.cin[p3 + hm.src[h]];
+                    hu[h] = ux[p3 + hm.src[h]];
+                    hv[h] = uy[p3 + hm.src[h]];
+                    hf[h] = a.flags[p3 + hm.src[h]];
+                }
+            if (ring) rwn = uz[p3 + rcell];
+            if (PAIR == 1) {
+                cnn = a.cn[p2 + cell];
+                if (ring) rcnn = a.cn[p2 + rcell];
+                if (K + 2 >= k0 && K + 2 < k1) acn = a.accin[p2 + cell];
+            }
+        }
+        __syncthreads();
+        // 3. first stage at plane K + 1 on the tile and the ring
+        const unsigned p1 = plane(K + 1);
+        T* const Wp = Ws + bp * tw;
+        T c1z2, accn;
+        T suxm, suxp, svym, svyp;
+        uint8_t sfxm, sfxp, sfym, sfyp;
+        {
+            const T* C = Cs + bp * tv;
+            const T* U = Us + bp * tv;
+            const T* V = Vs + bp * tv;
+            const uint8_t* F = Fs + bp * tv;
+            suxm = U[cV - 1]; suxp = U[cV + 1]; svym = V[cV - WV]; svyp = V[cV + WV];
+            sfxm = F[cV - 1]; sfxp = F[cV + 1]; sfym = F[cV - WV]; sfyp = F[cV + WV];
+            const T G = sca_rhs_cell<T>(cf, cz1, C[cV - 1], C[cV + 1], C[cV - WV], C[cV + WV], cz0, cz2, suxm, suxp,
+                                        svym, svyp, wz0, wz2, fz1, sfxm, sfxp, sfym, sfyp, fz0, fz2, a.frc, p1 + cell);
+            if (PAIR == 0) {
+                accn = cz1 + (dt / T(6)) * G;
+                c1z2 = cz1 + (dt / T(2)) * G;
+            } else {
+                accn = ac1 + (dt / T(3)) * G;
+                c1z2 = cn1 + dt * G;
+            }
+            Wp[cW] = c1z2;
+            if (ring) {
+                const T* Cq = Cs + bq * tv;
+                const uint8_t* Fq = Fs + bq * tv;
+                const T rc0 = C[rV];
+                const uint8_t rf0 = F[rV];
+                const T Gr = sca_rhs_cell<T>(cf, rc0, C[rV - 1], C[rV + 1], C[rV - WV], C[rV + WV], rcK, Cq[rV],
+                                             U[rV - 1], U[rV + 1], V[rV - WV], V[rV + WV], rw0, rw2, rf0, F[rV - 1],
+                                             F[rV + 1], F[rV - WV], F[rV + WV], rfK, Fq[rV], a.frc, p1 + rcell);
+                Wp[rW] = PAIR == 0 ? rc0 + (dt / T(2)) * Gr : rcn1 + dt * Gr;
+                rcK = rc0;
+                rfK = rf0;
+            }
+        }
+        __syncthreads();
+        // 4. second stage at plane K on the tile
+        if (K >= k0) {
+            const T* Wk = Ws + (K & 1) * tw;
+            const unsigned idx = plane(K) + cell;
+            const T G = sca_rhs_cell<T>(cf, c1z1, Wk[cW - 1], Wk[cW + 1], Wk[cW - WW], Wk[cW + WW], c1z0, c1z2, kuxm,
+                                        kuxp, kvym, kvyp, wzm, wz1, fz0, kfxm, kfxp, kfym, kfyp, fzm, fz1, a.frc, idx);
+            if (PAIR == 0) {
+                a.acc[idx] = accK + (dt / T(3)) * G;
+                a.out[idx] = cz0 + (dt / T(2)) * G;
+                if (a.part.p) {
+                    const double dv = ((double)kuxp - (double)kuxm) * g.inv2d[0] +
+                                      ((double)kvyp - (double)kvym) * g.inv2d[1] + ((double)wz1 - (double)wzm) * g.inv2d[2];
+                    part.div2 += dv * dv;
+                }
+            } else {
+                const T cnew = (fz0 & F_FLUID) ? accK + (dt / T(6)) * G : T(0);
+                a.out[idx] = cnew;
+                if (a.part.p) {
+                    const double b = (fz0 & F_FLUID) ? 1.0 : 0.0;
+                    part.mass += b * (double)cnew;
+                    if (fz0 & F_ROOM) { part.room_num += b * (double)cnew; part.room_den += b; }
+                }
+            }
+        }
+        // 5. advance the windows
+        cz0 = cz1; cz1 = cz2; cz2 = czn;
+        wzm = wz0; wz0 = wz1; wz1 = wz2; wz2 = wzn;
+        uz2 = uzn; vz2 = vzn;
+        fzm = fz0; fz0 = fz1; fz1 = fz2; fz2 = fzn;
+        c1z0 = c1z1; c1z1 = c1z2;
+        accK = accn;
+        kuxm = suxm; kuxp = suxp; kvym = svym; kvyp = svyp;
+        kfxm = sfxm; kfxp = sfxp; kfym = sfym; kfyp = sfyp;
+        rw0 = rw1; rw1 = rw2; rw2 = rwn;
+        if (PAIR == 1) { cn1 = cnn; rcn1 = rcnn; ac1 = acn; }
+    }
+    if (PAIR == 0 && a.part.p) block_reduce_partial<PM_DIV>(part, a.part, (int)bi.hw);
+    if (PAIR == 1 && a.part.p) block_reduce_partial<PM_SCA>(part, a.part, (int)bi.hw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1177,6 +1419,15 @@ __global__ __launch_bounds__(512) void k_mom_pair_b(const BRec<MomPairArgs<T>>* 
     const MomPairArgs<T> a = tab[s_].a;
     mom_pair_body<T, PAIR>(a, bi_);
 }
+template <typename T, int PAIR>
+__global__ __launch_bounds__(512) void k_sca_pair(const ScaPairArgs<T> a) { sca_pair_body<T, PAIR>(a, hw_block()); }
+template <typename T, int PAIR>
+__global__ __launch_bounds__(512) void k_sca_pair_b(const BRec<ScaPairArgs<T>>* __restrict__ tab,
+                                                    const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const ScaPairArgs<T> a = tab[s_].a;
+    sca_pair_body<T, PAIR>(a, bi_);
+}
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) { sca_stage_body<T, MODE>(a, hw_block()); }
 template <typename T, int MODE>
@@ -1334,6 +1585,22 @@ hipError_t launch_mom_pair(int pair, const MomPairArgs<T>& a, const StencilLaunc
 }
 
 template <typename T>
+hipError_t launch_sca_pair(int pair, const ScaPairArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
+    if (!mom_pair_supported(a.g, L) || (pair != 0 && pair != 1)) return hipErrorInvalidValue;
+    ScaPairArgs<T> b = a;
+    b.kc = L.kc;
+    const size_t tv = (size_t)(L.block.x + 4) * (L.block.y + 4), tw = (size_t)(L.block.x + 2) * (L.block.y + 2);
+    const size_t lds = (6 * tv + 2 * tw) * sizeof(T) + 2 * tv;
+    if (rec) {
+        record_launch(rec, kind_code(KK_SCAPAIR, pair, sizeof(T) == 4), L.grid, L.block, lds, b);
+        return hipSuccess;
+    }
+    if (pair == 0) hipLaunchKernelGGL((k_sca_pair<T, 0>), L.grid, L.block, lds, s, b);
+    else hipLaunchKernelGGL((k_sca_pair<T, 1>), L.grid, L.block, lds, s, b);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_sca_stage(int mode, const ScaArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     ScaArgs<T> b = a;
     b.kc = L.kc;
@@ -1481,6 +1748,12 @@ hipError_t batched_typed(int base, int mode, const void* tab, const unsigned* st
             else hipLaunchKernelGGL((k_mom_pair_b<T, 1>), grid, blk, lds, s, t, st, ns);
             break;
         }
+        case KK_SCAPAIR: {
+            auto t = (const BRec<ScaPairArgs<T>>*)tab;
+            if (mode == 0) hipLaunchKernelGGL((k_sca_pair_b<T, 0>), grid, blk, lds, s, t, st, ns);
+            else hipLaunchKernelGGL((k_sca_pair_b<T, 1>), grid, blk, lds, s, t, st, ns);
+            break;
+        }
         case KK_SCA: {
             auto t = (const BRec<ScaArgs<T>>*)tab;
             switch (mode) {
@@ -1550,6 +1823,7 @@ hipError_t launch_set_rate(PartSoA part, int np, StepScalars* sc, hipStream_t s)
     template hipError_t launch_mom_stage<T>(int, const MomArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*); \
     template hipError_t launch_mom_pair<T>(int, const MomPairArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*); \
     template hipError_t launch_sca_stage<T>(int, const ScaArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*); \
+    template hipError_t launch_sca_pair<T>(int, const ScaPairArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*); \
     template hipError_t launch_filter<T>(const FiltArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);        \
     template hipError_t launch_correct<T>(const CorrArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);       \
     template hipError_t launch_div<T>(const DivArgs<T>&, const StencilLaunch&, hipStream_t, Recorder*);            \
