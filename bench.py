@@ -441,6 +441,8 @@ def measure(sc, prec, args, label):
     esz = 8 if prec == m.FP64 else 4
     dev = torch.device("cuda:0")
     S = m.Solver(sc, precision=prec, device=dev, project_each_stage=args.per_stage)
+    S.set_stage_pairs(args.stage_pairs)
+    S.set_fft_pipeline(args.fft_pipeline)
     print(f"[bench] {label}: workload {sc.name} cells={sc.ncells} warmup={args.warmup}", file=sys.stderr, flush=True)
     S.step(args.warmup, diag=False)
     torch.cuda.synchronize()
@@ -523,6 +525,10 @@ def main():
     ap.add_argument("--per-stage", action="store_true",
                     help="the per-stage projection variant (a projection after every RK4 stage)")
     ap.add_argument("--no-particles", action="store_true")
+    ap.add_argument("--stage-pairs", type=int, default=-1, choices=[-1, 0, 1],
+                    help="RK4 stages two per pass: -1 by grid size (default), 0 never, 1 wherever the tile divides the grid")
+    ap.add_argument("--fft-pipeline", type=int, default=-1, choices=[-1, 0, 1],
+                    help="pipelined FFT column passes: -1 by tile count (default), 0 never, 1 wherever they apply")
     ap.add_argument("--serving", default="config4", choices=["none", "short", "config4", "config4-all"],
                     help="serving stream: config4 = 64 requests x 2000 steps, pool FP32 form vs FIFO FP64; "
                          "config4-all adds the pool in FP64; short = 16 x 300")

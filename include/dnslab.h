@@ -309,6 +309,18 @@ int dnslab_set_overlap(dnslab_ctx* ctx, int32_t enable);
  * any deferred scalar work first.  DNSLAB_EINVAL unless mode is -1, 0 or 1. */
 int dnslab_set_stage_pairs(dnslab_ctx* ctx, int32_t mode);
 
+/* Column passes of the FFT solve (Section 2.2) with the next tile's load in
+ * flight while the current tile is transformed (each block walks several
+ * tiles, moving them into LDS with asynchronous loads).  mode -1 (the
+ * default): the library's choice (currently never: one tile per block
+ * measured faster on the grids tried); 0: never; 1: wherever the pass
+ * applies (row-major spectrum, plain launches, transform lengths 64 to 1024
+ * of the form 2^a 3^b with a compiled chain).  Same arithmetic either way:
+ * results are bitwise the same.
+ * Enqueues any deferred scalar work first.  DNSLAB_EINVAL unless mode is -1,
+ * 0 or 1. */
+int dnslab_set_fft_pipeline(dnslab_ctx* ctx, int32_t mode);
+
 /* ------------------------------------------------------------------------
  * Serving pool: many scenarios of different grid sizes resident at once,
  * admitted against an HBM budget and advanced together.  Each step of the

@@ -245,6 +245,11 @@ class Solver:
         1 wherever the 64 x 8 tile divides the grid."""
         self._check(self.lib.dnslab_set_stage_pairs(self.ctx, int(mode)))
 
+    def set_fft_pipeline(self, mode: int):
+        """Pipelined column passes of the FFT solve: -1 by tile count (the
+        default), 0 never, 1 wherever they apply."""
+        self._check(self.lib.dnslab_set_fft_pipeline(self.ctx, int(mode)))
+
     # -- kernel timing -------------------------------------------------------
     def profile(self, kernel: Optional[str]):
         self._check(self.lib.dnslab_profile_enable(self.ctx, kernel.encode() if kernel else None))

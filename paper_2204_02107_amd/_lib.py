@@ -21,7 +21,7 @@ EXPORTS = [
     "dnslab_poisson_noalloc",
     "dnslab_project", "dnslab_scalar_step", "dnslab_momentum_rhs", "dnslab_scalar_rhs",
     "dnslab_filter", "dnslab_set_time", "dnslab_destroy", "dnslab_last_error",
-    "dnslab_profile_enable", "dnslab_profile_read", "dnslab_set_graph_steps", "dnslab_set_overlap", "dnslab_set_stage_pairs", "dnslab_pool_set_graph",
+    "dnslab_profile_enable", "dnslab_profile_read", "dnslab_set_graph_steps", "dnslab_set_overlap", "dnslab_set_stage_pairs", "dnslab_set_fft_pipeline", "dnslab_pool_set_graph",
     "dnslab_particles_step", "dnslab_particles_sort", "dnslab_co2_histogram", "dnslab_accumulate", "dnslab_body_force",
     "dnslab_pool_create", "dnslab_pool_admit", "dnslab_pool_step", "dnslab_pool_query",
     "dnslab_pool_read_field", "dnslab_pool_release", "dnslab_pool_usage", "dnslab_pool_last_error",
@@ -101,6 +101,7 @@ def load():
         "dnslab_set_graph_steps": (c_int, [V, c_int32]),
         "dnslab_set_overlap": (c_int, [V, c_int32]),
         "dnslab_set_stage_pairs": (c_int, [V, c_int32]),
+        "dnslab_set_fft_pipeline": (c_int, [V, c_int32]),
         "dnslab_particles_step": (c_int, [V, c_int64, V, V, V, P(ParticleParams), c_double]),
         "dnslab_particles_sort": (c_int, [V, c_int64, V, V, V]),
         "dnslab_co2_histogram": (c_int, [V, c_int32, c_double, c_double, V]),

@@ -184,6 +184,14 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_XPASS_THREADS
 #define DNSLAB_XPASS_THREADS 256
 #endif
+#ifndef DNSLAB_COL_PIPE
+// Pipelined column passes (asynchronous LDS loads, several tiles per block)
+// by tile count when set; off by default: measured slower than one tile per
+// block on 1024x512x256 (y 433 -> 442, z 552 -> 594 us FP64) and on
+// 512x256x192 (z 107 -> 146 us), where the plain pass keeps 2-4 blocks per CU
+// against the pipeline's 1-2 (two tile buffers per block)
+#define DNSLAB_COL_PIPE 0
+#endif
 #ifndef DNSLAB_XPASS_TW_LDS_MAX_M
 // x passes stage their W_m and twist tables in LDS up to this half length m
 // and read them through the caches beyond: on 1024x512x256 (m = 512) the
@@ -414,6 +422,7 @@ struct dnslab_ctx {
     // step n + 1 (see one_step).
     bool overlap;          // defer the scalar work to aux (plain contexts; not when recording)
     int pairs_mode = -1;   // RK4 stage pairs: -1 by grid size, 0 never, 1 wherever the tile divides the grid
+    int fft_pipe_mode = -1;   // pipelined column passes: -1 by tile count, 0 never, 1 wherever they apply
     hipStream_t aux;       // created on first use
     hipEvent_t ev_fork, ev_join;
     bool tail_pending;     // scalar work of the last step taken not yet enqueued
@@ -523,6 +532,7 @@ FFTArgs<T> fft_args_of(const Layout& Lo, const Grid& g, void* spec, const void* 
     a.sz2 = a.sy2 + g.ny;
     a.inv_ntot = 1.0 / (double)g.n;
     a.xtw_lds = Lo.xtw_lds;
+    a.col_pipe = DNSLAB_COL_PIPE ? -1 : 0;
     a.nl_x = Lo.nl_x;
     a.ls_x = Lo.ls_x;
     a.lg_tx_y = Lo.lg_tx_y;
@@ -534,7 +544,9 @@ FFTArgs<T> fft_args_of(const Layout& Lo, const Grid& g, void* spec, const void* 
 
 template <typename T>
 FFTArgs<T> fft_args(dnslab_ctx* x) {
-    return fft_args_of<T>(x->Lo, x->g, x->spec, x->wx, x->sx2);
+    FFTArgs<T> a = fft_args_of<T>(x->Lo, x->g, x->spec, x->wx, x->sx2);
+    if (x->fft_pipe_mode != -1) a.col_pipe = x->fft_pipe_mode;
+    return a;
 }
 
 // One FFT solve of Lap p = r (central-difference symbol, null modes zero).
@@ -1692,6 +1704,23 @@ int dnslab_set_stage_pairs(dnslab_ctx* x, int32_t mode) {
         x->gexec = nullptr;
     }
     x->pairs_mode = mode;
+    return DNSLAB_OK;
+}
+
+int dnslab_set_fft_pipeline(dnslab_ctx* x, int32_t mode) {
+    if (int rc = check_ctx(x)) return rc;
+    if (mode < -1 || mode > 1) return fail(x, DNSLAB_EINVAL, "mode must be -1, 0 or 1");
+    try {
+        int rc = x->Lo.esz == 8 ? settle<double>(x) : settle<float>(x);
+        if (rc) return rc;
+    } catch (...) {
+        return fail(x, DNSLAB_ENOMEM, "host allocation failed");
+    }
+    if (x->fft_pipe_mode != mode && x->gexec) {
+        HIPCHK(x, hipGraphExecDestroy(x->gexec));   // captured with the other kernels
+        x->gexec = nullptr;
+    }
+    x->fft_pipe_mode = mode;
     return DNSLAB_OK;
 }
 

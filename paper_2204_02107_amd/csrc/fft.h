@@ -42,6 +42,7 @@ struct FFTArgs {
     int ls_x;           // LDS line stride (odd, >= m + 1)
     // y / z passes
     int lg_tx_y, lg_tx_z;
+    int col_pipe;       // pipelined column passes: -1 where each block gets two tiles or more, 0 never, 1 wherever they apply
     // fused plane pass: lines per LDS chunk of the y and the z transforms
     int lg_ca, lg_cb;
 };

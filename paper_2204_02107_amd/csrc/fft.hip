@@ -208,7 +208,17 @@ constexpr int cns(int n, int pass) {
 
 // One Stockham pass with the transform length, radix and span known at
 // compile time (the index arithmetic becomes shifts and constant multiplies).
-template <typename T, int R, int MAXB, bool INV, int N, int NS>
+// Barrier between LDS phases of one block.  The plain one (__syncthreads)
+// also waits for the wave's outstanding global memory operations; the LDS
+// one waits only for its LDS operations, so that asynchronous global -> LDS
+// loads of another buffer stay in flight across it.
+template <bool LB>
+__device__ __forceinline__ void phase_barrier() {
+    if (LB) asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else __syncthreads();
+}
+
+template <typename T, int R, int MAXB, bool INV, int N, int NS, bool LB = false>
 __device__ __forceinline__ void stockham_pass_c(C2<T>* s, const C2<T>* W, int es, int ls, int lg_nl, int tid,
                                                 int nthr) {
     constexpr int nbl = N / R;
@@ -226,7 +236,7 @@ __device__ __forceinline__ void stockham_pass_c(C2<T>* s, const C2<T>* W, int es
             for (int r = 0; r < R; ++r) v[q][r] = base[(j + r * nbl) * es];
         }
     }
-    __syncthreads();
+    phase_barrier<LB>();
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
         const int b = tid + q * nthr;
@@ -247,17 +257,17 @@ __device__ __forceinline__ void stockham_pass_c(C2<T>* s, const C2<T>* W, int es
             for (int r = 0; r < R; ++r) base[(d + r * NS) * es] = v[q][r];
         }
     }
-    __syncthreads();
+    phase_barrier<LB>();
 }
 
-template <typename T, bool INV, int N, int P>
+template <typename T, bool INV, int N, int P, bool LB = false>
 __device__ __forceinline__ void fft_chain(C2<T>* s, const C2<T>* W, int es, int ls, int lg_nl, int tid, int nthr) {
     constexpr CPlan pl = cplan(N);
     if constexpr (P < pl.np) {
         constexpr int R = pl.r[P];
         constexpr int MAXB = (pl.r[0] + R - 1) / R;
-        stockham_pass_c<T, R, MAXB, INV, N, cns(N, P)>(s, W, es, ls, lg_nl, tid, nthr);
-        fft_chain<T, INV, N, P + 1>(s, W, es, ls, lg_nl, tid, nthr);
+        stockham_pass_c<T, R, MAXB, INV, N, cns(N, P), LB>(s, W, es, ls, lg_nl, tid, nthr);
+        fft_chain<T, INV, N, P + 1, LB>(s, W, es, ls, lg_nl, tid, nthr);
     }
 }
 
@@ -547,6 +557,71 @@ __device__ __forceinline__ double recip(double x) {
 // per row); the Nyquist column kx = m, which would otherwise leave a nearly
 // empty tile in every plane, is handled by a few extra blocks that take TX
 // different planes of that column each.
+// One tile of a column pass: TX consecutive kx columns of one plane (the
+// main tiles), or TX planes of the Nyquist column kx = m.
+template <typename T>
+struct ColTile {
+    C2<T>* base;    // element (row, column c) at base[row * rs + c * cs]
+    size_t cs;
+    int ncol;       // columns present (<= TX)
+    int kx0, plane0;
+    bool nyq;
+};
+template <typename T, int MODE>
+__device__ __forceinline__ ColTile<T> col_tile(const FFTArgs<T>& a, int b) {
+    const bool zp = MODE == 2;
+    const int lg = zp ? a.lg_tx_z : a.lg_tx_y, tx = 1 << lg;
+    const int ny = a.g.ny, nz = a.g.nz, m = a.m;
+    const int nplane = zp ? ny : nz;
+    const size_t ps = zp ? (size_t)a.sx : (size_t)ny * a.sx;
+    const int ntile = (m + tx - 1) >> lg;
+    const int nmain = ntile * nplane;
+    ColTile<T> t;
+    if (b < nmain) {
+        const int tile = b % ntile;
+        t.plane0 = b / ntile;
+        t.kx0 = tile << lg;
+        t.base = a.spec + (size_t)t.plane0 * ps + t.kx0;
+        t.cs = 1;
+        t.ncol = min(tx, m - t.kx0);
+        t.nyq = false;
+    } else {
+        t.plane0 = (b - nmain) << lg;
+        t.kx0 = m;
+        t.base = a.spec + (size_t)t.plane0 * ps + m;
+        t.cs = ps;
+        t.ncol = min(tx, nplane - t.plane0);
+        t.nyq = true;
+    }
+    return t;
+}
+
+// The transforms of one staged tile in LDS (s, element (row, c) at
+// s[row * TX + c]): y forward or inverse, or z forward, divide, z inverse.
+template <typename T, int MODE>
+__device__ __forceinline__ void cols_transform(const FFTArgs<T>& a, const ColTile<T>& t, C2<T>* s, const C2<T>* wl,
+                                               int tid, int nthr) {
+    const int lg = MODE == 2 ? a.lg_tx_z : a.lg_tx_y, tx = 1 << lg;
+    if (MODE == 2) {
+        const int tot = a.g.nz << lg;
+        fft_lds<T, false>(s, a.pz, wl, tx, 1, lg, tid, nthr);
+        for (int e = tid; e < tot; e += nthr) {
+            const int kz = e >> lg, c = e & (tx - 1);
+            if (c < t.ncol) {
+                const int kx = t.nyq ? a.m : t.kx0 + c;
+                const int ky = t.nyq ? t.plane0 + c : t.plane0;
+                const double lam = (a.sz2[kz] + a.sy2[ky]) + a.sx2[kx];   // -lambda
+                const T f = lam == 0.0 ? T(0) : T(-a.inv_ntot * recip(lam));
+                s[e] = cscale(s[e], f);
+            }
+        }
+        __syncthreads();
+        fft_lds<T, true>(s, a.pz, wl, tx, 1, lg, tid, nthr);
+    } else {
+        fft_lds<T, MODE == 1>(s, a.py, wl, tx, 1, lg, tid, nthr);
+    }
+}
+
 template <typename T, int MODE>
 __device__ __forceinline__ void fft_cols_body(const FFTArgs<T>& a, unsigned blk) {
     extern __shared__ unsigned char smem_raw[];
@@ -554,34 +629,9 @@ __device__ __forceinline__ void fft_cols_body(const FFTArgs<T>& a, unsigned blk)
     const int tid = threadIdx.x, nthr = blockDim.x;
     const bool zp = MODE == 2;
     const int lg = zp ? a.lg_tx_z : a.lg_tx_y, tx = 1 << lg;
-    const int ny = a.g.ny, nz = a.g.nz, m = a.m;
-    const int nrow = zp ? nz : ny;                 // transform length
-    const int nplane = zp ? ny : nz;               // other spectral index
-    const size_t rs = zp ? (size_t)ny * a.sx : (size_t)a.sx;   // row (transform) stride
-    const size_t ps = zp ? (size_t)a.sx : (size_t)ny * a.sx;   // plane stride
-    const int ntile = (m + tx - 1) >> lg;
-    const int nmain = ntile * nplane;
-    const int b = (int)blk;
-    C2<T>* base;
-    size_t cs;
-    int ncol, kx0, plane0;
-    bool nyq;
-    if (b < nmain) {
-        const int tile = b % ntile;
-        plane0 = b / ntile;
-        kx0 = tile << lg;
-        base = a.spec + (size_t)plane0 * ps + kx0;
-        cs = 1;
-        ncol = min(tx, m - kx0);
-        nyq = false;
-    } else {
-        plane0 = (b - nmain) << lg;
-        kx0 = m;
-        base = a.spec + (size_t)plane0 * ps + m;
-        cs = ps;
-        ncol = min(tx, nplane - plane0);
-        nyq = true;
-    }
+    const int nrow = zp ? a.g.nz : a.g.ny;                 // transform length
+    const size_t rs = zp ? (size_t)a.g.ny * a.sx : (size_t)a.sx;   // row (transform) stride
+    const ColTile<T> t = col_tile<T, MODE>(a, (int)blk);
     const int tot = nrow << lg;
     C2<T>* wl = s + tot;               // W_nrow table
     {
@@ -595,7 +645,7 @@ __device__ __forceinline__ void fft_cols_body(const FFTArgs<T>& a, unsigned blk)
             const int e = tid + q * nthr;
             const int row = e >> lg, c = e & (tx - 1);
             buf[q] = C2<T>{T(0), T(0)};
-            if (e < tot && c < ncol) buf[q] = base[row * rs + c * cs];
+            if (e < tot && c < t.ncol) buf[q] = t.base[row * rs + c * t.cs];
         }
 #pragma unroll
         for (int q = 0; q < STAGE_MAX; ++q) {
@@ -604,40 +654,138 @@ __device__ __forceinline__ void fft_cols_body(const FFTArgs<T>& a, unsigned blk)
         }
     }
     __syncthreads();
-    if (MODE == 2) {
-        fft_lds<T, false>(s, a.pz, wl, tx, 1, lg, tid, nthr);
-        for (int e = tid; e < tot; e += nthr) {
-            const int kz = e >> lg, c = e & (tx - 1);
-            if (c < ncol) {
-                const int kx = nyq ? m : kx0 + c;
-                const int ky = nyq ? plane0 + c : plane0;
-                const double lam = (a.sz2[kz] + a.sy2[ky]) + a.sx2[kx];   // -lambda
-                const T f = lam == 0.0 ? T(0) : T(-a.inv_ntot * recip(lam));
-                s[e] = cscale(s[e], f);
-            }
-        }
-        __syncthreads();
-        fft_lds<T, true>(s, a.pz, wl, tx, 1, lg, tid, nthr);
-    } else {
-        fft_lds<T, MODE == 1>(s, a.py, wl, tx, 1, lg, tid, nthr);
-    }
+    cols_transform<T, MODE>(a, t, s, wl, tid, nthr);
 #pragma unroll
     for (int q = 0; q < STAGE_MAX; ++q) {
         const int e = tid + q * nthr;
         const int row = e >> lg, c = e & (tx - 1);
-        if (e < tot && c < ncol) base[row * rs + c * cs] = s[e];
+        if (e < tot && c < t.ncol) t.base[row * rs + c * t.cs] = s[e];
     }
 }
 
+// Column pass over many tiles per block, the next tile's load in flight
+// while the current one is transformed: each block walks tiles blockIdx.x,
+// + gridDim.x, ... with two LDS tile buffers.  The main tiles are moved
+// global -> LDS by the asynchronous LDS loads of gfx950 (16 bytes per lane:
+// one FP64 complex, or two adjacent FP32 complex values of a row), which hold
+// no registers; the top of each iteration waits for them (vmcnt) and
+// synchronises, then issues the next tile's loads before transforming this
+// one.  The few Nyquist tiles (strided columns) are loaded the plain way.
+// Requires the main tiles' row segments 16-byte aligned and, in FP32, an even
+// column count (m even); the launcher checks.
+template <typename T>
+__device__ __forceinline__ void lds_dma16(const void* g, C2<T>* lds_wave_base) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds_wave_base, 16, 0, 0);
+}
+template <typename T, int MODE>
+__device__ __forceinline__ void cols_fill(const FFTArgs<T>& a, const ColTile<T>& t, C2<T>* s, int tid, int nthr) {
+    const bool zp = MODE == 2;
+    const int lg = zp ? a.lg_tx_z : a.lg_tx_y, tx = 1 << lg;
+    const int nrow = zp ? a.g.nz : a.g.ny;
+    const size_t rs = zp ? (size_t)a.g.ny * a.sx : (size_t)a.sx;
+    const int tot = nrow << lg;
+    if (t.nyq) {
+        for (int e = tid; e < tot; e += nthr) {
+            const int row = e >> lg, c = e & (tx - 1);
+            s[e] = c < t.ncol ? t.base[row * rs + c * t.cs] : C2<T>{T(0), T(0)};
+        }
+        return;
+    }
+    constexpr int PER = 16 / (int)sizeof(C2<T>);     // complex values per lane and load (1 FP64, 2 FP32)
+    const int wbase = tid & ~63;
+    for (int e0 = wbase * PER; e0 < tot; e0 += nthr * PER) {
+        const int e = e0 + (tid - wbase) * PER;
+        const int row = e >> lg;
+        int c = e & (tx - 1);
+        if (c >= t.ncol) c = t.ncol - PER;            // a valid row segment; the column is never stored
+        const C2<T>* src = t.base + (size_t)row * rs + c;
+        if (e < tot) lds_dma16<T>(src, s + e0);
+    }
+}
+constexpr unsigned WAIT_VMCNT0 = 0x0F70;   // s_waitcnt vmcnt(0), expcnt and lgkmcnt left alone
 
-// Fused plane pass (plane-major spectrum): block kx holds the whole (ky, kz)
-// plane of that kx in registers, Q values per thread.  The block size is a
-// multiple of ny, so thread t keeps one y = t mod ny and the z values
-// t / ny + q * (nthr / ny).  The y transforms run on chunks of z lines
-// and the z transforms on chunks of y lines staged through LDS (line-
-// interleaved, padded row stride against bank conflicts); the spectral divide
-// happens between the forward and inverse z transforms of a chunk.  One read
-// and one write of the spectrum replace three passes.
+template <typename T, int MODE, int N>
+__device__ __forceinline__ void fft_cols_pipe_loop(const FFTArgs<T>& a, int ntiles, C2<T>* s0, const C2<T>* wl,
+                                                   const double* s2l, int tid, int nthr) {
+    const bool zp = MODE == 2;
+    const int lg = zp ? a.lg_tx_z : a.lg_tx_y, tx = 1 << lg;
+    const size_t rs = zp ? (size_t)a.g.ny * a.sx : (size_t)a.sx;
+    const int tot = N << lg;
+    int b = (int)blockIdx.x;
+    if (b < ntiles) cols_fill<T, MODE>(a, col_tile<T, MODE>(a, b), s0, tid, nthr);
+    for (int i = 0; b < ntiles; ++i, b += (int)gridDim.x) {
+        __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
+        __syncthreads();
+        C2<T>* s = s0 + (i & 1) * tot;
+        const int bn = b + (int)gridDim.x;
+        if (bn < ntiles) cols_fill<T, MODE>(a, col_tile<T, MODE>(a, bn), s0 + ((i + 1) & 1) * tot, tid, nthr);
+        const ColTile<T> t = col_tile<T, MODE>(a, b);
+        // (no global loads from here to the stores: the symbol tables are in
+        // LDS, so nothing waits for the next tile's loads)
+        if (MODE == 2) {
+            const double* sx2l = s2l;
+            const double* sy2l = s2l + a.m + 1;
+            const double* sz2l = sy2l + a.g.ny;
+            fft_chain<T, false, N, 0, true>(s, wl, tx, 1, lg, tid, nthr);
+            for (int e = tid; e < tot; e += nthr) {
+                const int kz = e >> lg, c = e & (tx - 1);
+                if (c < t.ncol) {
+                    const int kx = t.nyq ? a.m : t.kx0 + c;
+                    const int ky = t.nyq ? t.plane0 + c : t.plane0;
+                    const double lam = (sz2l[kz] + sy2l[ky]) + sx2l[kx];   // -lambda
+                    const T f = lam == 0.0 ? T(0) : T(-a.inv_ntot * recip(lam));
+                    s[e] = cscale(s[e], f);
+                }
+            }
+            phase_barrier<true>();
+            fft_chain<T, true, N, 0, true>(s, wl, tx, 1, lg, tid, nthr);
+        } else {
+            fft_chain<T, MODE == 1, N, 0, true>(s, wl, tx, 1, lg, tid, nthr);
+        }
+        for (int e = tid; e < tot; e += nthr) {
+            const int row = e >> lg, c = e & (tx - 1);
+            if (c < t.ncol) t.base[row * rs + c * t.cs] = s[e];
+        }
+    }
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void fft_cols_pipe_body(const FFTArgs<T>& a, int ntiles) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<T>* s0 = reinterpret_cast<C2<T>*>(smem_raw);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const bool zp = MODE == 2;
+    const int lg = zp ? a.lg_tx_z : a.lg_tx_y;
+    const int nrow = zp ? a.g.nz : a.g.ny;
+    C2<T>* wl = s0 + 2 * (nrow << lg);
+    {
+        const C2<T>* W = zp ? a.wz : a.wy;
+        for (int j = tid; j < nrow; j += nthr) wl[j] = W[j];
+    }
+    // z pass: the three symbol tables (x: m + 1, y: ny, z: nz values) in LDS too
+    double* s2l = reinterpret_cast<double*>(wl + nrow);
+    if (MODE == 2) {
+        const int nt = a.m + 1 + a.g.ny + a.g.nz;
+        for (int j = tid; j < nt; j += nthr) s2l[j] = a.sx2[j];     // the three tables are contiguous
+    }
+    // one loop per transform length (the launcher only picks these lengths)
+    switch (nrow) {
+        case 64: fft_cols_pipe_loop<T, MODE, 64>(a, ntiles, s0, wl, s2l, tid, nthr); break;
+        case 96: fft_cols_pipe_loop<T, MODE, 96>(a, ntiles, s0, wl, s2l, tid, nthr); break;
+        case 128: fft_cols_pipe_loop<T, MODE, 128>(a, ntiles, s0, wl, s2l, tid, nthr); break;
+        case 192: fft_cols_pipe_loop<T, MODE, 192>(a, ntiles, s0, wl, s2l, tid, nthr); break;
+        case 256: fft_cols_pipe_loop<T, MODE, 256>(a, ntiles, s0, wl, s2l, tid, nthr); break;
+        case 384: fft_cols_pipe_loop<T, MODE, 384>(a, ntiles, s0, wl, s2l, tid, nthr); break;
+        case 512: fft_cols_pipe_loop<T, MODE, 512>(a, ntiles, s0, wl, s2l, tid, nthr); break;
+        case 768: fft_cols_pipe_loop<T, MODE, 768>(a, ntiles, s0, wl, s2l, tid, nthr); break;
+        case 1024: fft_cols_pipe_loop<T, MODE, 1024>(a, ntiles, s0, wl, s2l, tid, nthr); break;
+        default: break;
+    }
+}
+__host__ __device__ constexpr bool pipe_length(int n) {
+    return n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512 || n == 768 || n == 1024;
+}
+
 template <typename T, int Q, bool INV>
 __device__ __forceinline__ void yz_y_phase(const FFTArgs<T>& a, C2<T> (&v)[Q], C2<T>* d, const C2<T>* wyl, int yt,
                                            int zt, int zs, int tid, int nthr) {
@@ -763,6 +911,11 @@ __global__ __launch_bounds__(1024) void k_fft_cols_b(const BRec<FFTArgs<T>>* __r
     DNSLAB_BATCH_BLOCK(st, ns)
     const FFTArgs<T>& a = tab[s_].a;   // read in place: a private copy of the plan would sit in scratch
     fft_cols_body<T, MODE>(a, blk_);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(512) void k_fft_cols_pipe(const FFTArgs<T> a, int ntiles) {
+    fft_cols_pipe_body<T, MODE>(a, ntiles);
 }
 
 template <typename T, int Q>
@@ -908,6 +1061,23 @@ static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s, Reco
     const AxisPlan& ap = zp ? a.pz : a.py;
     dim3 block(round64(std::min(1024, tx * ap.tpl * DNSLAB_FFT_TPL_MUL)));
     size_t lds = ((size_t)tx * nrow + nrow) * sizeof(C2<T>);
+    // the pipelined pass (plain launches): two tile buffers, each block
+    // walking at least two tiles
+    const size_t lds_pipe = ((size_t)2 * tx * nrow + nrow) * sizeof(C2<T>) +
+                            (mode == 2 ? (size_t)(a.m + 1 + a.g.ny + a.g.nz) * sizeof(double) : 0);
+    const int per = 16 / (int)sizeof(C2<T>);
+    const bool fits = a.ps == 0 && tx >= per && (sizeof(T) == 8 || a.m % 2 == 0) && lds_pipe <= 160 * 1024 &&
+                      (size_t)nrow * tx >= (size_t)block.x * per && block.x <= 512 && pipe_length(nrow);
+    if (!rec && fits && a.col_pipe != 0) {
+        const int bpc = (int)std::max<size_t>(1, (160 * 1024) / lds_pipe);
+        const int grid = std::min(nblocks, 256 * bpc);
+        if (a.col_pipe == 1 || nblocks >= 2 * grid) {
+            if (mode == 0) hipLaunchKernelGGL((k_fft_cols_pipe<T, 0>), dim3(grid), block, lds_pipe, s, a, nblocks);
+            else if (mode == 1) hipLaunchKernelGGL((k_fft_cols_pipe<T, 1>), dim3(grid), block, lds_pipe, s, a, nblocks);
+            else hipLaunchKernelGGL((k_fft_cols_pipe<T, 2>), dim3(grid), block, lds_pipe, s, a, nblocks);
+            return hipGetLastError();
+        }
+    }
     if (rec) {
         record_launch(rec, kind_code(KK_COLS, mode, sizeof(T) == 4), dim3(nblocks), block, lds, a);
         return hipSuccess;
