@@ -237,7 +237,8 @@ int dnslab_particles_step(dnslab_ctx* ctx, int64_t n, double* pos, double* vel, 
  * order is free; sorted particles gather their fluid velocities from
  * neighbouring cells, which the step kernel turns into coalesced reads.  On
  * the context's stream; allocates device scratch on first use and when n
- * grows (then synchronises the stream first).  0 <= n < 2^32, else
+ * grows (then synchronises the stream first).  The sort is a stable radix
+ * sort on the bits the cell count needs (8 per pass).  0 <= n <= 2^28, else
  * DNSLAB_EINVAL. */
 int dnslab_particles_sort(dnslab_ctx* ctx, int64_t n, double* pos, double* vel, double* diam);
 

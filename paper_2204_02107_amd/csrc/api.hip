@@ -1550,7 +1550,7 @@ int dnslab_particles_step(dnslab_ctx* x, int64_t n, double* pos, double* vel, co
 
 int dnslab_particles_sort(dnslab_ctx* x, int64_t n, double* pos, double* vel, double* diam) {
     if (int rc = check_ctx(x)) return rc;
-    if (n < 0 || n >= (1LL << 32)) return fail(x, DNSLAB_EINVAL, "bad particle count");
+    if (n < 0 || n > particle_sort_max()) return fail(x, DNSLAB_EINVAL, "bad particle count (0 <= n <= 2^28)");
     if (n > 0 && (!pos || !vel || !diam)) return fail(x, DNSLAB_EINVAL, "NULL pointer");
     if (n == 0) return DNSLAB_OK;
     size_t sort_bytes = 0;

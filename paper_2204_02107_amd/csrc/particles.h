@@ -38,11 +38,13 @@ struct ParticleSortScratch {
     unsigned* keys[2];     // n cell indices each
     unsigned* vals[2];     // n particle indices each
     double* tmp;           // n doubles
-    void* sort_tmp;        // radix-sort temporary storage
+    void* sort_tmp;        // radix-sort counts and scan totals
     size_t sort_bytes;
 };
-// Bytes of radix-sort temporary storage for n particles.
+// Bytes of radix-sort counts and scan totals for n particles.
 hipError_t particle_sort_bytes(long long n, size_t* bytes);
+// Largest n the sort handles (its scan has two levels).
+long long particle_sort_max();
 // Stable sort of the n particles (SoA pos, vel: 3 n doubles each; diam: n)
 // by the linear index of the containing cell; every array is permuted in place.
 hipError_t sort_particles(const Grid& g, long long n, double* pos, double* vel, double* diam,

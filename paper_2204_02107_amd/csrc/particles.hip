@@ -2,8 +2,6 @@
 // drag and gravity, advanced by implicit Euler in the bound velocity field.
 #include "particles.h"
 
-#include <rocprim/device/device_radix_sort.hpp>
-
 namespace dnslab {
 namespace {
 
@@ -105,7 +103,170 @@ __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ in, c
     if (q < n) out[q] = in[perm[q]];
 }
 
+// ---------------------------------------------------------------------------
+// Stable least-significant-digit radix sort of (key, value) pairs, 8-bit
+// digits.  One pass per digit: every block counts the digits of its chunk of
+// SORT_CHUNK consecutive keys (counts stored digit-major: digit d of block b
+// at d * nblocks + b), an exclusive scan of those counts gives each (digit,
+// block) its first output slot, and every block scatters its chunk in input
+// order, each key going after the keys of its digit that precede it (in
+// earlier blocks, earlier tiles of its own chunk, earlier waves of its tile,
+// earlier lanes of its wave).  Stable passes make the whole sort stable.
+// ---------------------------------------------------------------------------
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_CHUNK = SORT_THREADS * SORT_ITEMS;    // keys per block
+constexpr int SORT_RADIX = 256;
+constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;   // counts per scan block
+
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const unsigned* __restrict__ keys, long long n,
+                                                             int shift, unsigned* __restrict__ counts, int nblocks) {
+    __shared__ unsigned hist[SORT_RADIX];
+    const int t = threadIdx.x;
+    hist[t] = 0;
+    __syncthreads();
+    const long long c0 = (long long)blockIdx.x * SORT_CHUNK;
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        const long long q = c0 + (long long)it * SORT_THREADS + t;
+        if (q < n) atomicAdd(&hist[(keys[q] >> shift) & (SORT_RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    counts[(size_t)t * nblocks + blockIdx.x] = hist[t];
+}
+
+// Exclusive scan of len values in place, in blocks of SCAN_CHUNK; each block
+// writes its total to sums[blockIdx.x].
+__device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned* sh, unsigned& total) {
+    // Hillis-Steele over the block's threads in LDS
+    const int t = threadIdx.x, nt = blockDim.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        const unsigned add = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    total = sh[nt - 1];
+    const unsigned incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_blocks(unsigned* __restrict__ a, long long len,
+                                                              unsigned* __restrict__ sums) {
+    __shared__ unsigned sh[SCAN_THREADS];
+    const long long base = (long long)blockIdx.x * SCAN_CHUNK + (long long)threadIdx.x * SCAN_ITEMS;
+    unsigned v[SCAN_ITEMS], run = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = base + i < len ? a[base + i] : 0u;
+        run += v[i];
+    }
+    unsigned total;
+    unsigned pre = block_exclusive_scan(run, sh, total);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < len) a[base + i] = pre;
+        pre += v[i];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the block totals (at most SCAN_CHUNK of them) in one block.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(unsigned* __restrict__ sums, int nsums) {
+    __shared__ unsigned sh[SCAN_THREADS];
+    const int base = threadIdx.x * SCAN_ITEMS;
+    unsigned v[SCAN_ITEMS], run = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = base + i < nsums ? sums[base + i] : 0u;
+        run += v[i];
+    }
+    unsigned total;
+    unsigned pre = block_exclusive_scan(run, sh, total);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < nsums) sums[base + i] = pre;
+        pre += v[i];
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_add(unsigned* __restrict__ a, long long len,
+                                                           const unsigned* __restrict__ sums) {
+    const unsigned add = sums[blockIdx.x];
+    const long long base = (long long)blockIdx.x * SCAN_CHUNK + (long long)threadIdx.x * SCAN_ITEMS;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+        if (base + i < len) a[base + i] += add;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const unsigned* __restrict__ kin,
+                                                                const unsigned* __restrict__ vin, long long n,
+                                                                int shift, const unsigned* __restrict__ offsets,
+                                                                int nblocks, unsigned* __restrict__ kout,
+                                                                unsigned* __restrict__ vout) {
+    constexpr int NW = SORT_THREADS / 64;
+    __shared__ unsigned base[SORT_RADIX];          // next output slot of each digit for this block
+    __shared__ unsigned wcnt[NW][SORT_RADIX];      // keys of each digit in each wave of the tile
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    base[t] = offsets[(size_t)t * nblocks + blockIdx.x];
+    const long long c0 = (long long)blockIdx.x * SORT_CHUNK;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        const long long q = c0 + (long long)it * SORT_THREADS + t;
+        const bool valid = q < n;
+        unsigned key = 0, val = 0;
+        if (valid) { key = kin[q]; val = vin[q]; }
+        // digits 0..255; 256 marks an empty slot (it matches only other empty slots)
+        const unsigned d = valid ? (key >> shift) & (SORT_RADIX - 1) : (unsigned)SORT_RADIX;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) wcnt[w][t] = 0;
+        __syncthreads();
+        // lanes of this wave holding the same digit
+        unsigned long long peers = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
+            const unsigned long long m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const unsigned rank = (unsigned)__popcll(peers & lt);
+        if (valid && rank == 0) wcnt[wave][d] = (unsigned)__popcll(peers);
+        __syncthreads();
+        // keys of each digit in earlier waves of the tile
+        unsigned before = 0;
+        if (valid)
+            for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+        if (valid) {
+            const unsigned dst = base[d] + before + rank;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+        {
+            unsigned tot = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) tot += wcnt[w][t];
+            base[t] += tot;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
+
+long long particle_sort_max() { return (long long)SCAN_CHUNK * SCAN_CHUNK / SORT_RADIX * SORT_CHUNK; }
+
+hipError_t particle_sort_bytes(long long n, size_t* bytes) {
+    const long long nblocks = (n + SORT_CHUNK - 1) / SORT_CHUNK;
+    const long long len = nblocks * SORT_RADIX;
+    const long long nscan = (len + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    *bytes = (size_t)(len + nscan + 64) * sizeof(unsigned);
+    return hipSuccess;
+}
 
 template <typename T>
 hipError_t launch_particles(const ParticleArgs<T>& a, hipStream_t s) {
@@ -115,15 +276,10 @@ hipError_t launch_particles(const ParticleArgs<T>& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t particle_sort_bytes(long long n, size_t* bytes) {
-    *bytes = 0;
-    return rocprim::radix_sort_pairs(nullptr, *bytes, (const unsigned*)nullptr, (unsigned*)nullptr,
-                                     (const unsigned*)nullptr, (unsigned*)nullptr, (size_t)n);
-}
-
 hipError_t sort_particles(const Grid& g, long long n, double* pos, double* vel, double* diam,
                           const ParticleSortScratch& s, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (n > particle_sort_max()) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_particle_keys, dim3(nb), dim3(256), 0, st, pos, n, g, s.keys[0], s.vals[0]);
     hipError_t e = hipGetLastError();
@@ -131,13 +287,28 @@ hipError_t sort_particles(const Grid& g, long long n, double* pos, double* vel, 
     // cell indices are below nx ny nz < 2^31: sort on the bits that can be set
     unsigned end_bit = 1;
     while (end_bit < 32 && ((unsigned long long)1 << end_bit) < (unsigned long long)g.n) ++end_bit;
-    size_t bytes = s.sort_bytes;
-    e = rocprim::radix_sort_pairs(s.sort_tmp, bytes, s.keys[0], s.keys[1], s.vals[0], s.vals[1], (size_t)n, 0u,
-                                  end_bit, st);
-    if (e != hipSuccess) return e;
+    const int nblocks = (int)((n + SORT_CHUNK - 1) / SORT_CHUNK);
+    const long long len = (long long)nblocks * SORT_RADIX;
+    const int nscan = (int)((len + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    unsigned* counts = (unsigned*)s.sort_tmp;
+    unsigned* sums = counts + len;
+    int cur = 0;
+    for (unsigned shift = 0; shift < end_bit; shift += 8) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(nblocks), dim3(SORT_THREADS), 0, st, (const unsigned*)s.keys[cur], n,
+                           (int)shift, counts, nblocks);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(nscan), dim3(SCAN_THREADS), 0, st, counts, len, sums);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_THREADS), 0, st, sums, nscan);
+        hipLaunchKernelGGL(k_scan_add, dim3(nscan), dim3(SCAN_THREADS), 0, st, counts, len, (const unsigned*)sums);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nblocks), dim3(SORT_THREADS), 0, st, (const unsigned*)s.keys[cur],
+                           (const unsigned*)s.vals[cur], n, (int)shift, (const unsigned*)counts, nblocks,
+                           s.keys[cur ^ 1], s.vals[cur ^ 1]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+    }
     double* arrays[7] = {pos, pos + n, pos + 2 * n, vel, vel + n, vel + 2 * n, diam};
     for (double* a : arrays) {
-        hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, st, (const double*)a, (const unsigned*)s.vals[1], n,
+        hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, st, (const double*)a, (const unsigned*)s.vals[cur], n,
                            s.tmp);
         e = hipMemcpyAsync(a, s.tmp, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;

@@ -402,7 +402,22 @@ __device__ __forceinline__ void ring_cell(int r, int BX, int BY, int& lx, int& l
     else { lx = BX; ly = r - 2 * BX - BY; }
 }
 
-template <typename T, int PAIR>
+// Prefetch distance of the pair kernels' loads, in planes: each block keeps
+// the loads of the next D planes in flight.
+// Measured on 1024x512x256: two planes in flight take the FP64 momentum
+// pairs from 3337 to 3208 us; the FP64 scalar pairs lose 2% with them, and
+// in FP32 the extra registers cost a block per CU (momentum pairs 1677 ->
+// 1919 us), so those keep one plane.
+#ifndef DNSLAB_PAIR_DIST_MOM64
+#define DNSLAB_PAIR_DIST_MOM64 2
+#endif
+#ifndef DNSLAB_PAIR_DIST_OTHER
+#define DNSLAB_PAIR_DIST_OTHER 1
+#endif
+template <typename T, bool MOM>
+constexpr int pair_dist() { return (MOM && sizeof(T) == 8) ? DNSLAB_PAIR_DIST_MOM64 : DNSLAB_PAIR_DIST_OTHER; }
+
+template <typename T, int PAIR, int D>
 __device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
     const Col col = column(g, a.kc, bi);
@@ -433,50 +448,74 @@ __device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const Blo
     const int rV = (rly + 2) * WV + rlx + 2, rW = (rly + 1) * WW + rlx + 1;
     auto plane = [&](int K) -> unsigned { return (unsigned)wrap(K, nz) * nxy; };
 
-    // pipeline state for the first iteration K = k0 - 2
-    T vz0[3], vz1[3], vz2[3], vzn[3], hv[3][HM];
+    // Pipeline state at the start of iteration K (q[i] holds plane K + i
+    // unless noted; the last D - 1 entries of each queue are loads in flight):
+    //   vq: stage input of this thread's cell, planes K .. K+1+D (slot 2+D free)
+    //   hq: halo of V, planes K+2 .. K+1+D
+    //   fq: flags, planes K .. K+D (slot 1+D free)
+    //   rfq: ring cell flags, planes K+1 .. K+D (slot D free)
+    //   unq, runq, acq (pair 1): u^n (cell, ring cell) and acc after stage 2,
+    //   planes K+1 .. K+D (slot D free)
+    T vq[3 + D][3], hq[D][3][HM];
+    uint8_t fq[2 + D], rfq[1 + D];
+    T unq[1 + D][3], runq[1 + D][3], acq[1 + D][3];
     T wz0[3] = {T(0), T(0), T(0)}, wz1[3] = {T(0), T(0), T(0)};
     T accK[3] = {T(0), T(0), T(0)};             // pair 0: acc1 of plane K; pair 1: acc3 of plane K
     T rvm[3] = {T(0), T(0), T(0)};              // ring: v of plane K
-    T un1[3] = {T(0), T(0), T(0)}, unn[3] = {T(0), T(0), T(0)};     // pair 1: u^n, planes K+1, K+2 (tile)
-    T run1[3] = {T(0), T(0), T(0)}, runn[3] = {T(0), T(0), T(0)};   // pair 1: u^n at the ring cell
-    T ac1[3] = {T(0), T(0), T(0)}, acn[3] = {T(0), T(0), T(0)};     // pair 1: acc after stage 2, planes K+1, K+2
-    uint8_t flK = 0, flK1, flKn = 0, rfl1 = 0, rfln = 0;
+#pragma unroll
+    for (int i = 0; i < 1 + D; ++i) {
+        rfq[i] = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { unq[i][c] = T(0); runq[i][c] = T(0); acq[i][c] = T(0); }
+    }
+#pragma unroll
+    for (int i = 0; i < 2 + D; ++i) fq[i] = 0;
     {
-        const unsigned pa = plane(k0 - 2), pb = plane(k0 - 1), pc = plane(k0);
+        const int K = k0 - 2;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            vz0[c] = a.vin[c][pa + cell];
-            vz1[c] = a.vin[c][pb + cell];
-            vz2[c] = a.vin[c][pc + cell];
+        for (int i = 0; i < 2 + D; ++i) {
+            const unsigned pi = plane(K + i);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vq[i][c] = a.vin[c][pi + cell];
         }
-        flK1 = a.flags[pb + cell];
-        if (ring) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) rvm[c] = a.vin[c][pa + rcell];
-            rfl1 = a.flags[pb + rcell];
-        }
-        if (PAIR == 1) {
+        for (int i = 1; i < 1 + D; ++i) fq[i] = a.flags[plane(K + i) + cell];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                un1[c] = a.un[c][pb + cell];
-                if (ring) run1[c] = a.un[c][pb + rcell];
+        for (int i = 0; i < D; ++i) {
+            const unsigned pi = plane(K + 1 + i);
+            if (ring) rfq[i] = a.flags[pi + rcell];
+            if (PAIR == 1) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    unq[i][c] = a.un[c][pi + cell];
+                    if (ring) runq[i][c] = a.un[c][pi + rcell];
+                    if (K + 1 + i >= k0 && K + 1 + i < k1) acq[i][c] = a.accin[c][pi + cell];
+                }
             }
         }
+        if (ring) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rvm[c] = a.vin[c][plane(K) + rcell];
+        }
         // V tile of plane k0 - 1
-        T* Vp = Vb + ((k0 - 1) & 1) * 3 * tv;
+        const unsigned pb = plane(K + 1);
+        T* Vp = Vb + ((K + 1) & 1) * 3 * tv;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Vp[c * tv + cV] = vz1[c];
+            Vp[c * tv + cV] = vq[1][c];
 #pragma unroll
             for (int h = 0; h < HM; ++h)
                 if (h < hm.n) Vp[c * tv + hm.dst[h]] = a.vin[c][pb + hm.src[h]];
         }
-        // halo of plane k0, stored by the first iteration
+        // halos of planes k0 .. k0 + D - 1
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < D; ++i) {
+            const unsigned pi = plane(K + 2 + i);
 #pragma unroll
-            for (int h = 0; h < HM; ++h) hv[c][h] = h < hm.n ? a.vin[c][pc + hm.src[h]] : T(0);
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int h = 0; h < HM; ++h) hq[i][c][h] = h < hm.n ? a.vin[c][pi + hm.src[h]] : T(0);
+        }
     }
 
     for (int K = k0 - 2; K < k1; ++K) {
@@ -484,30 +523,35 @@ __device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const Blo
         T* const Vq = Vb + ((K + 2) & 1) * 3 * tv;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Vq[c * tv + cV] = vz2[c];
+            Vq[c * tv + cV] = vq[2][c];
 #pragma unroll
             for (int h = 0; h < HM; ++h)
-                if (h < hm.n) Vq[c * tv + hm.dst[h]] = hv[c][h];
+                if (h < hm.n) Vq[c * tv + hm.dst[h]] = hq[0][c][h];
         }
-        // 2. loads for the next iteration: v of plane K + 3, the rest of plane K + 2
-        const bool more = K + 1 < k1;
-        if (more) {
-            const unsigned p3 = plane(K + 3), p2 = plane(K + 2);
+#pragma unroll
+        for (int i = 0; i + 1 < D; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int h = 0; h < HM; ++h) hq[i][c][h] = hq[i + 1][c][h];
+        // 2. loads D planes ahead: v and halo of plane K + 2 + D, the rest of plane K + 1 + D
+        if (K + D < k1) {
+            const unsigned pv = plane(K + 2 + D), pr = plane(K + 1 + D);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                vzn[c] = a.vin[c][p3 + cell];
+                vq[2 + D][c] = a.vin[c][pv + cell];
 #pragma unroll
                 for (int h = 0; h < HM; ++h)
-                    if (h < hm.n) hv[c][h] = a.vin[c][p3 + hm.src[h]];
+                    if (h < hm.n) hq[D - 1][c][h] = a.vin[c][pv + hm.src[h]];
             }
-            flKn = a.flags[p2 + cell];
-            if (ring) rfln = a.flags[p2 + rcell];
+            fq[1 + D] = a.flags[pr + cell];
+            if (ring) rfq[D] = a.flags[pr + rcell];
             if (PAIR == 1) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    unn[c] = a.un[c][p2 + cell];
-                    if (ring) runn[c] = a.un[c][p2 + rcell];
-                    if (K + 2 >= k0 && K + 2 < k1) acn[c] = a.accin[c][p2 + cell];
+                    unq[D][c] = a.un[c][pr + cell];
+                    if (ring) runq[D][c] = a.un[c][pr + rcell];
+                    if (K + 1 + D >= k0 && K + 1 + D < k1) acq[D][c] = a.accin[c][pr + cell];
                 }
             }
         }
@@ -526,15 +570,15 @@ __device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const Blo
                 ym[c] = Vp[c * tv + cV - WV];
                 yp[c] = Vp[c * tv + cV + WV];
             }
-            mom_rhs_cell<T>(cf, vz1, xm, xp, ym, yp, vz0, vz2, flK1, a.frc, p1 + cell, kv);
+            mom_rhs_cell<T>(cf, vq[1], xm, xp, ym, yp, vq[0], vq[2], fq[1], a.frc, p1 + cell, kv);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (PAIR == 0) {
-                    accn[c] = vz1[c] + (dt / T(6)) * kv[c];
-                    wz2[c] = vz1[c] + (dt / T(2)) * kv[c];
+                    accn[c] = vq[1][c] + (dt / T(6)) * kv[c];
+                    wz2[c] = vq[1][c] + (dt / T(2)) * kv[c];
                 } else {
-                    accn[c] = ac1[c] + (dt / T(3)) * kv[c];
-                    wz2[c] = un1[c] + dt * kv[c];
+                    accn[c] = acq[0][c] + (dt / T(3)) * kv[c];
+                    wz2[c] = unq[0][c] + dt * kv[c];
                 }
                 Wp[c * tw + cW] = wz2[c];
             }
@@ -550,10 +594,10 @@ __device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const Blo
                 yp[c] = Vp[c * tv + rV + WV];
                 zp[c] = Vq[c * tv + rV];
             }
-            mom_rhs_cell<T>(cf, c0, xm, xp, ym, yp, rvm, zp, rfl1, a.frc, p1 + rcell, kv);
+            mom_rhs_cell<T>(cf, c0, xm, xp, ym, yp, rvm, zp, rfq[0], a.frc, p1 + rcell, kv);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                Wp[c * tw + rW] = PAIR == 0 ? c0[c] + (dt / T(2)) * kv[c] : run1[c] + dt * kv[c];
+                Wp[c * tw + rW] = PAIR == 0 ? c0[c] + (dt / T(2)) * kv[c] : runq[0][c] + dt * kv[c];
                 rvm[c] = c0[c];
             }
         }
@@ -570,26 +614,37 @@ __device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const Blo
                 yp[c] = Wk[c * tw + cW + WW];
             }
             const unsigned idx = plane(K) + cell;
-            mom_rhs_cell<T>(cf, wz1, xm, xp, ym, yp, wz0, wz2, flK, a.frc, idx, kv);
+            mom_rhs_cell<T>(cf, wz1, xm, xp, ym, yp, wz0, wz2, fq[0], a.frc, idx, kv);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (PAIR == 0) {
                     a.acc[c][idx] = accK[c] + (dt / T(3)) * kv[c];
-                    a.out[c][idx] = vz0[c] + (dt / T(2)) * kv[c];
+                    a.out[c][idx] = vq[0][c] + (dt / T(2)) * kv[c];
                 } else {
                     a.out[c][idx] = accK[c] + (dt / T(6)) * kv[c];
                 }
             }
         }
-        // 5. advance the windows
+        // 5. advance the queues
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            vz0[c] = vz1[c]; vz1[c] = vz2[c]; vz2[c] = vzn[c];
+#pragma unroll
+            for (int i = 0; i < 2 + D; ++i) vq[i][c] = vq[i + 1][c];
             wz0[c] = wz1[c]; wz1[c] = wz2[c];
             accK[c] = accn[c];
-            if (PAIR == 1) { un1[c] = unn[c]; run1[c] = runn[c]; ac1[c] = acn[c]; }
+            if (PAIR == 1) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    unq[i][c] = unq[i + 1][c];
+                    runq[i][c] = runq[i + 1][c];
+                    acq[i][c] = acq[i + 1][c];
+                }
+            }
         }
-        flK = flK1; flK1 = flKn; rfl1 = rfln;
+#pragma unroll
+        for (int i = 0; i < 1 + D; ++i) fq[i] = fq[i + 1];
+#pragma unroll
+        for (int i = 0; i < D; ++i) rfq[i] = rfq[i + 1];
     }
 }
 
@@ -712,7 +767,7 @@ __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockI
 // second stage at plane K needs u, v and the flags at the same neighbours the
 // first stage read one plane earlier: each thread keeps them from there.
 // ---------------------------------------------------------------------------
-template <typename T, int PAIR>
+template <typename T, int PAIR, int D>
 __device__ __forceinline__ void sca_pair_body(const ScaPairArgs<T>& a, const BlockIdx3& bi) {
     const Grid& g = a.g;
     const Col col = column(g, a.kc, bi);
@@ -748,45 +803,79 @@ __device__ __forceinline__ void sca_pair_body(const ScaPairArgs<T>& a, const Blo
     const T* __restrict__ uz = a.u[2];
     Partial part = {0, 0, 0, 0, 0, 0};
 
-    // own z windows (planes K-1 .. K+3)
-    T cz0, cz1, cz2, czn = T(0);                       // c_in: K, K+1, K+2, next
-    T wzm = T(0), wz0, wz1, wz2, wzn = T(0);           // w: K-1 .. K+2, next
-    T uz2, vz2, uzn = T(0), vzn = T(0);                // u, v of plane K+2 (staged by this thread), next
-    uint8_t fzm = 0, fz0, fz1, fz2, fzn = 0;           // flags: K-1 .. K+2, next
-    T hc[HM], hu[HM], hv[HM];
-    uint8_t hf[HM];
+    // Queues at the start of iteration K (the last entries are loads in
+    // flight, D planes ahead of their use):
+    //   cq: c_in, planes K .. K+1+D (slot 2+D free)
+    //   wq, fq: w and flags, planes K-1 .. K+1+D (slot 3+D free)
+    //   uq, vq, halo queues: planes K+2 .. K+1+D (staged into LDS in turn)
+    //   rwq: the ring cell's w, planes K .. K+1+D (slot 2+D free)
+    //   cnq, rcnq, acq (pair 1): c^n (cell, ring cell), acc after stage 2,
+    //   planes K+1 .. K+D (slot D free)
+    T cq[3 + D], wq[4 + D], uq[D], vq[D], hc[D][HM], hu[D][HM], hv[D][HM];
+    uint8_t fq[4 + D], hf[D][HM];
+    T rwq[3 + D];
+    T cnq[1 + D], rcnq[1 + D], acq[1 + D];
     T c1z0 = T(0), c1z1 = T(0);                       // first-stage value c1, planes K-1, K
     T accK = T(0);                                     // pair 0: acc1 of plane K; pair 1: acc3 of plane K
     // the first stage's x/y neighbours of u, v and flags at plane K (for the second stage)
     T kuxm = T(0), kuxp = T(0), kvym = T(0), kvyp = T(0);
     uint8_t kfxm = 0, kfxp = 0, kfym = 0, kfyp = 0;
-    // ring cell: c and flags of plane K, w of planes K .. K+2 and next
-    T rcK = T(0), rw0 = T(0), rw1 = T(0), rw2 = T(0), rwn = T(0);
-    uint8_t rfK = 0;
-    // pair 1: c^n (own and ring) and acc after stage 2, planes K+1 and K+2
-    T cn1 = T(0), cnn = T(0), rcn1 = T(0), rcnn = T(0), ac1 = T(0), acn = T(0);
+    T rcK = T(0);                                      // ring cell: c of plane K
+    uint8_t rfK = 0;                                   // ring cell: flags of plane K
+#pragma unroll
+    for (int i = 0; i < 4 + D; ++i) { wq[i] = T(0); fq[i] = 0; }
+#pragma unroll
+    for (int i = 0; i < 3 + D; ++i) { cq[i] = T(0); rwq[i] = T(0); }
+#pragma unroll
+    for (int i = 0; i < 1 + D; ++i) { cnq[i] = T(0); rcnq[i] = T(0); acq[i] = T(0); }
     {
-        const unsigned pa = plane(k0 - 2), pb = plane(k0 - 1), pc = plane(k0);
-        cz0 = a.cin[pa + cell]; cz1 = a.cin[pb + cell]; cz2 = a.cin[pc + cell];
-        wz0 = uz[pa + cell]; wz1 = uz[pb + cell]; wz2 = uz[pc + cell];
-        fz0 = a.flags[pa + cell]; fz1 = a.flags[pb + cell]; fz2 = a.flags[pc + cell];
-        uz2 = ux[pc + cell];
-        vz2 = uy[pc + cell];
+        const int K = k0 - 2;
+#pragma unroll
+        for (int i = 0; i < 2 + D; ++i) {
+            const unsigned pi = plane(K + i);
+            cq[i] = a.cin[pi + cell];
+            if (ring) rwq[i] = uz[pi + rcell];
+        }
+#pragma unroll
+        for (int i = 1; i < 3 + D; ++i) {
+            const unsigned pi = plane(K - 1 + i);
+            wq[i] = uz[pi + cell];
+            fq[i] = a.flags[pi + cell];
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const unsigned pi = plane(K + 2 + i);
+            uq[i] = ux[pi + cell];
+            vq[i] = uy[pi + cell];
+#pragma unroll
+            for (int h = 0; h < HM; ++h) {
+                const bool on = h < hm.n;
+                hc[i][h] = on ? a.cin[pi + hm.src[h]] : T(0);
+                hu[i][h] = on ? ux[pi + hm.src[h]] : T(0);
+                hv[i][h] = on ? uy[pi + hm.src[h]] : T(0);
+                hf[i][h] = on ? a.flags[pi + hm.src[h]] : 0;
+            }
+        }
         if (ring) {
-            rcK = a.cin[pa + rcell];
-            rfK = a.flags[pa + rcell];
-            rw0 = uz[pa + rcell]; rw1 = uz[pb + rcell]; rw2 = uz[pc + rcell];
+            rcK = a.cin[plane(K) + rcell];
+            rfK = a.flags[plane(K) + rcell];
         }
         if (PAIR == 1) {
-            cn1 = a.cn[pb + cell];
-            if (ring) rcn1 = a.cn[pb + rcell];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const unsigned pi = plane(K + 1 + i);
+                cnq[i] = a.cn[pi + cell];
+                if (ring) rcnq[i] = a.cn[pi + rcell];
+                if (K + 1 + i >= k0 && K + 1 + i < k1) acq[i] = a.accin[pi + cell];
+            }
         }
         // LDS planes of k0 - 1
-        const int b = (k0 - 1) & 1;
-        Cs[b * tv + cV] = cz1;
+        const unsigned pb = plane(K + 1);
+        const int b = (K + 1) & 1;
+        Cs[b * tv + cV] = cq[1];
         Us[b * tv + cV] = ux[pb + cell];
         Vs[b * tv + cV] = uy[pb + cell];
-        Fs[b * tv + cV] = fz1;
+        Fs[b * tv + cV] = fq[2];
 #pragma unroll
         for (int h = 0; h < HM; ++h)
             if (h < hm.n) {
@@ -795,53 +884,53 @@ __device__ __forceinline__ void sca_pair_body(const ScaPairArgs<T>& a, const Blo
                 Vs[b * tv + hm.dst[h]] = uy[pb + hm.src[h]];
                 Fs[b * tv + hm.dst[h]] = a.flags[pb + hm.src[h]];
             }
-        // halo of plane k0, staged by the first iteration
-#pragma unroll
-        for (int h = 0; h < HM; ++h) {
-            const bool on = h < hm.n;
-            hc[h] = on ? a.cin[pc + hm.src[h]] : T(0);
-            hu[h] = on ? ux[pc + hm.src[h]] : T(0);
-            hv[h] = on ? uy[pc + hm.src[h]] : T(0);
-            hf[h] = on ? a.flags[pc + hm.src[h]] : 0;
-        }
     }
 
     for (int K = k0 - 2; K < k1; ++K) {
         // 1. plane K + 2 into LDS
         const int bq = (K + 2) & 1, bp = (K + 1) & 1;
-        Cs[bq * tv + cV] = cz2;
-        Us[bq * tv + cV] = uz2;
-        Vs[bq * tv + cV] = vz2;
-        Fs[bq * tv + cV] = fz2;
+        Cs[bq * tv + cV] = cq[2];
+        Us[bq * tv + cV] = uq[0];
+        Vs[bq * tv + cV] = vq[0];
+        Fs[bq * tv + cV] = fq[3];
 #pragma unroll
         for (int h = 0; h < HM; ++h)
             if (h < hm.n) {
-                Cs[bq * tv + hm.dst[h]] = hc[h];
-                Us[bq * tv + hm.dst[h]] = hu[h];
-                Vs[bq * tv + hm.dst[h]] = hv[h];
-                Fs[bq * tv + hm.dst[h]] = hf[h];
+                Cs[bq * tv + hm.dst[h]] = hc[0][h];
+                Us[bq * tv + hm.dst[h]] = hu[0][h];
+                Vs[bq * tv + hm.dst[h]] = hv[0][h];
+                Fs[bq * tv + hm.dst[h]] = hf[0][h];
             }
-        // 2. loads for the next iteration
-        if (K + 1 < k1) {
-            const unsigned p3 = plane(K + 3), p2 = plane(K + 2);
-            czn = a.cin[p3 + cell];
-            wzn = uz[p3 + cell];
-            uzn = ux[p3 + cell];
-            vzn = uy[p3 + cell];
-            fzn = a.flags[p3 + cell];
+#pragma unroll
+        for (int i = 0; i + 1 < D; ++i) {
+            uq[i] = uq[i + 1];
+            vq[i] = vq[i + 1];
+#pragma unroll
+            for (int h = 0; h < HM; ++h) {
+                hc[i][h] = hc[i + 1][h]; hu[i][h] = hu[i + 1][h]; hv[i][h] = hv[i + 1][h]; hf[i][h] = hf[i + 1][h];
+            }
+        }
+        // 2. loads D planes ahead
+        if (K + D < k1) {
+            const unsigned pv = plane(K + 2 + D), pr = plane(K + 1 + D);
+            cq[2 + D] = a.cin[pv + cell];
+            wq[3 + D] = uz[pv + cell];
+            fq[3 + D] = a.flags[pv + cell];
+            uq[D - 1] = ux[pv + cell];
+            vq[D - 1] = uy[pv + cell];
 #pragma unroll
             for (int h = 0; h < HM; ++h)
                 if (h < hm.n) {
-                    hc[h] = a.cin[p3 + hm.src[h]];
-                    hu[h] = ux[p3 + hm.src[h]];
-                    hv[h] = uy[p3 + hm.src[h]];
-                    hf[h] = a.flags[p3 + hm.src[h]];
+                    hc[D - 1][h] = a.cin[pv + hm.src[h]];
+                    hu[D - 1][h] = ux[pv + hm.src[h]];
+                    hv[D - 1][h] = uy[pv + hm.src[h]];
+                    hf[D - 1][h] = a.flags[pv + hm.src[h]];
                 }
-            if (ring) rwn = uz[p3 + rcell];
+            if (ring) rwq[2 + D] = uz[pv + rcell];
             if (PAIR == 1) {
-                cnn = a.cn[p2 + cell];
-                if (ring) rcnn = a.cn[p2 + rcell];
-                if (K + 2 >= k0 && K + 2 < k1) acn = a.accin[p2 + cell];
+                cnq[D] = a.cn[pr + cell];
+                if (ring) rcnq[D] = a.cn[pr + rcell];
+                if (K + 1 + D >= k0 && K + 1 + D < k1) acq[D] = a.accin[pr + cell];
             }
         }
         __syncthreads();
@@ -858,14 +947,15 @@ __device__ __forceinline__ void sca_pair_body(const ScaPairArgs<T>& a, const Blo
             const uint8_t* F = Fs + bp * tv;
             suxm = U[cV - 1]; suxp = U[cV + 1]; svym = V[cV - WV]; svyp = V[cV + WV];
             sfxm = F[cV - 1]; sfxp = F[cV + 1]; sfym = F[cV - WV]; sfyp = F[cV + WV];
-            const T G = sca_rhs_cell<T>(cf, cz1, C[cV - 1], C[cV + 1], C[cV - WV], C[cV + WV], cz0, cz2, suxm, suxp,
-                                        svym, svyp, wz0, wz2, fz1, sfxm, sfxp, sfym, sfyp, fz0, fz2, a.frc, p1 + cell);
+            const T G = sca_rhs_cell<T>(cf, cq[1], C[cV - 1], C[cV + 1], C[cV - WV], C[cV + WV], cq[0], cq[2], suxm,
+                                        suxp, svym, svyp, wq[1], wq[3], fq[2], sfxm, sfxp, sfym, sfyp, fq[1], fq[3],
+                                        a.frc, p1 + cell);
             if (PAIR == 0) {
-                accn = cz1 + (dt / T(6)) * G;
-                c1z2 = cz1 + (dt / T(2)) * G;
+                accn = cq[1] + (dt / T(6)) * G;
+                c1z2 = cq[1] + (dt / T(2)) * G;
             } else {
-                accn = ac1 + (dt / T(3)) * G;
-                c1z2 = cn1 + dt * G;
+                accn = acq[0] + (dt / T(3)) * G;
+                c1z2 = cnq[0] + dt * G;
             }
             Wp[cW] = c1z2;
             if (ring) {
@@ -874,9 +964,10 @@ __device__ __forceinline__ void sca_pair_body(const ScaPairArgs<T>& a, const Blo
                 const T rc0 = C[rV];
                 const uint8_t rf0 = F[rV];
                 const T Gr = sca_rhs_cell<T>(cf, rc0, C[rV - 1], C[rV + 1], C[rV - WV], C[rV + WV], rcK, Cq[rV],
-                                             U[rV - 1], U[rV + 1], V[rV - WV], V[rV + WV], rw0, rw2, rf0, F[rV - 1],
-                                             F[rV + 1], F[rV - WV], F[rV + WV], rfK, Fq[rV], a.frc, p1 + rcell);
-                Wp[rW] = PAIR == 0 ? rc0 + (dt / T(2)) * Gr : rcn1 + dt * Gr;
+                                             U[rV - 1], U[rV + 1], V[rV - WV], V[rV + WV], rwq[0], rwq[2], rf0,
+                                             F[rV - 1], F[rV + 1], F[rV - WV], F[rV + WV], rfK, Fq[rV], a.frc,
+                                             p1 + rcell);
+                Wp[rW] = PAIR == 0 ? rc0 + (dt / T(2)) * Gr : rcnq[0] + dt * Gr;
                 rcK = rc0;
                 rfK = rf0;
             }
@@ -887,36 +978,40 @@ __device__ __forceinline__ void sca_pair_body(const ScaPairArgs<T>& a, const Blo
             const T* Wk = Ws + (K & 1) * tw;
             const unsigned idx = plane(K) + cell;
             const T G = sca_rhs_cell<T>(cf, c1z1, Wk[cW - 1], Wk[cW + 1], Wk[cW - WW], Wk[cW + WW], c1z0, c1z2, kuxm,
-                                        kuxp, kvym, kvyp, wzm, wz1, fz0, kfxm, kfxp, kfym, kfyp, fzm, fz1, a.frc, idx);
+                                        kuxp, kvym, kvyp, wq[0], wq[2], fq[1], kfxm, kfxp, kfym, kfyp, fq[0], fq[2],
+                                        a.frc, idx);
             if (PAIR == 0) {
                 a.acc[idx] = accK + (dt / T(3)) * G;
-                a.out[idx] = cz0 + (dt / T(2)) * G;
+                a.out[idx] = cq[0] + (dt / T(2)) * G;
                 if (a.part.p) {
                     const double dv = ((double)kuxp - (double)kuxm) * g.inv2d[0] +
-                                      ((double)kvyp - (double)kvym) * g.inv2d[1] + ((double)wz1 - (double)wzm) * g.inv2d[2];
+                                      ((double)kvyp - (double)kvym) * g.inv2d[1] +
+                                      ((double)wq[2] - (double)wq[0]) * g.inv2d[2];
                     part.div2 += dv * dv;
                 }
             } else {
-                const T cnew = (fz0 & F_FLUID) ? accK + (dt / T(6)) * G : T(0);
+                const T cnew = (fq[1] & F_FLUID) ? accK + (dt / T(6)) * G : T(0);
                 a.out[idx] = cnew;
                 if (a.part.p) {
-                    const double b = (fz0 & F_FLUID) ? 1.0 : 0.0;
+                    const double b = (fq[1] & F_FLUID) ? 1.0 : 0.0;
                     part.mass += b * (double)cnew;
-                    if (fz0 & F_ROOM) { part.room_num += b * (double)cnew; part.room_den += b; }
+                    if (fq[1] & F_ROOM) { part.room_num += b * (double)cnew; part.room_den += b; }
                 }
             }
         }
-        // 5. advance the windows
-        cz0 = cz1; cz1 = cz2; cz2 = czn;
-        wzm = wz0; wz0 = wz1; wz1 = wz2; wz2 = wzn;
-        uz2 = uzn; vz2 = vzn;
-        fzm = fz0; fz0 = fz1; fz1 = fz2; fz2 = fzn;
+        // 5. advance the queues
+#pragma unroll
+        for (int i = 0; i < 2 + D; ++i) { cq[i] = cq[i + 1]; rwq[i] = rwq[i + 1]; }
+#pragma unroll
+        for (int i = 0; i < 3 + D; ++i) { wq[i] = wq[i + 1]; fq[i] = fq[i + 1]; }
+        if (PAIR == 1) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) { cnq[i] = cnq[i + 1]; rcnq[i] = rcnq[i + 1]; acq[i] = acq[i + 1]; }
+        }
         c1z0 = c1z1; c1z1 = c1z2;
         accK = accn;
         kuxm = suxm; kuxp = suxp; kvym = svym; kvyp = svyp;
         kfxm = sfxm; kfxp = sfxp; kfym = sfym; kfyp = sfyp;
-        rw0 = rw1; rw1 = rw2; rw2 = rwn;
-        if (PAIR == 1) { cn1 = cnn; rcn1 = rcnn; ac1 = acn; }
     }
     if (PAIR == 0 && a.part.p) block_reduce_partial<PM_DIV>(part, a.part, (int)bi.hw);
     if (PAIR == 1 && a.part.p) block_reduce_partial<PM_SCA>(part, a.part, (int)bi.hw);
@@ -1411,22 +1506,26 @@ __global__ __launch_bounds__(1024) void k_mom_stage_b(const BRec<MomArgs<T>>* __
     mom_stage_body<T, MODE, LDS>(a, bi_);
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) void k_mom_pair(const MomPairArgs<T> a) { mom_pair_body<T, PAIR>(a, hw_block()); }
+__global__ __launch_bounds__(512) void k_mom_pair(const MomPairArgs<T> a) {
+    mom_pair_body<T, PAIR, pair_dist<T, true>()>(a, hw_block());
+}
 template <typename T, int PAIR>
 __global__ __launch_bounds__(512) void k_mom_pair_b(const BRec<MomPairArgs<T>>* __restrict__ tab,
                                                     const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const MomPairArgs<T> a = tab[s_].a;
-    mom_pair_body<T, PAIR>(a, bi_);
+    mom_pair_body<T, PAIR, pair_dist<T, true>()>(a, bi_);
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) void k_sca_pair(const ScaPairArgs<T> a) { sca_pair_body<T, PAIR>(a, hw_block()); }
+__global__ __launch_bounds__(512) void k_sca_pair(const ScaPairArgs<T> a) {
+    sca_pair_body<T, PAIR, pair_dist<T, false>()>(a, hw_block());
+}
 template <typename T, int PAIR>
 __global__ __launch_bounds__(512) void k_sca_pair_b(const BRec<ScaPairArgs<T>>* __restrict__ tab,
                                                     const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const ScaPairArgs<T> a = tab[s_].a;
-    sca_pair_body<T, PAIR>(a, bi_);
+    sca_pair_body<T, PAIR, pair_dist<T, false>()>(a, bi_);
 }
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) { sca_stage_body<T, MODE>(a, hw_block()); }

@@ -150,3 +150,50 @@ def test_particles_sort_is_the_stable_cell_order():
         S.particles_sort(a, b, c)
         assert np.array_equal(a.cpu().numpy(), pos[:, :k])
     S.close()
+
+
+def test_particles_sort_ties_and_four_digit_passes():
+    """The radix sort's stability under heavy ties (70001 particles in five
+    cells plus a scattered tail, so chunks, tiles and waves all hold equal
+    keys) and its fourth 8-bit pass (a 512 x 256 x 192 grid: 25 key bits)."""
+    torch, m, sc, S, box, pos, vel, diam, t = setup(n=1000, seed=11)
+    announce("particles sort: ties; 25-bit keys")
+    d = sc.spacing
+    rng = np.random.default_rng(12)
+
+    def keys(p):
+        idx = [np.floor(p[a] / d[a]).astype(np.int64) % n_ax for a, n_ax in enumerate((sc.nx, sc.ny, sc.nz))]
+        return idx[0] + sc.nx * (idx[1] + sc.ny * idx[2])
+
+    n = 70_001
+    cells = rng.integers(0, 8, (5, 3))
+    pick = rng.integers(0, 5, n)
+    p = np.stack([(cells[pick, a] + rng.uniform(0.1, 0.9, n)) * d[a] for a in range(3)])
+    p[:, ::97] = np.stack([rng.uniform(0, box[a], p[:, ::97].shape[1]) for a in range(3)])
+    v, dm = rng.standard_normal((3, n)), rng.uniform(1e-6, 1e-4, n)
+    tp, tv, td = t(p), t(v), t(dm)
+    S.particles_sort(tp, tv, td)
+    o = np.argsort(keys(p), kind="stable")
+    assert np.array_equal(tp.cpu().numpy(), p[:, o])
+    assert np.array_equal(tv.cpu().numpy(), v[:, o])
+    assert np.array_equal(td.cpu().numpy(), dm[o])
+    S.close()
+    # 25-bit cell indices: four passes
+    big = scenarios.room(512, 256, 192, dx=10.0 / 512, n_boxes=2, seed=3)
+    S2 = m.Solver(big)
+    bbox = (big.lx, big.ly, big.lz)
+    n2 = 200_003
+    p2 = np.stack([rng.uniform(0, bbox[a], n2) for a in range(3)])
+    p2[:, :5000] = p2[:, :1][:, [0] * 5000]          # a block of identical keys at the front
+    v2, d2 = rng.standard_normal((3, n2)), rng.uniform(1e-6, 1e-4, n2)
+    tp2, tv2, td2 = t(p2), t(v2), t(d2)
+    S2.particles_sort(tp2, tv2, td2)
+    bd = big.spacing
+    idx = [np.floor(p2[a] / bd[a]).astype(np.int64) % n_ax for a, n_ax in enumerate((big.nx, big.ny, big.nz))]
+    k2 = idx[0] + big.nx * (idx[1] + big.ny * idx[2])
+    assert k2.max() >= 1 << 24
+    o2 = np.argsort(k2, kind="stable")
+    assert np.array_equal(tp2.cpu().numpy(), p2[:, o2])
+    assert np.array_equal(td2.cpu().numpy(), d2[o2])
+    S2.close()
+    torch.cuda.empty_cache()
