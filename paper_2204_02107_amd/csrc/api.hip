@@ -216,7 +216,10 @@ Grid make_grid(const dnslab_params* P) {
 #define DNSLAB_YZ_MAX_PLANE32 16384   // the same for the FP32 form (1024-thread blocks)
 #endif
 #ifndef DNSLAB_FORK_EARLY_CELLS
-#define DNSLAB_FORK_EARLY_CELLS (1LL << 23)   // from this grid size the scalar half forks before the momentum stages
+#define DNSLAB_FORK_EARLY_CELLS (1LL << 62)   // FP64: from this grid size the scalar half forks before the momentum stages
+#endif
+#ifndef DNSLAB_FORK_EARLY_CELLS32
+#define DNSLAB_FORK_EARLY_CELLS32 (1LL << 23)   // the same for the FP32 form
 #endif
 #ifndef DNSLAB_OVERLAP
 #define DNSLAB_OVERLAP 1       // run the scalar half of a step on a second stream
@@ -850,11 +853,14 @@ int one_step(dnslab_ctx* x) {
     // overlaps the pressure solves only, whose passes leave the memory system
     // idle between their load and store phases (best when the solves are
     // long against the scalar half: the 256x128x96 room loses 7% forking
-    // earlier); on large grids the solves run closer to the bandwidth and the
-    // scalar half outlasts them, stalling the correction that waits for it,
-    // so it forks before the momentum stages (512x256x192: +3% in FP64 and
-    // FP32; 1024x512x256: +0.5% / +1.3%).
-    if (defer && x->g.n >= DNSLAB_FORK_EARLY_CELLS) {
+    // earlier).  In FP64 that holds at every size once the stages run two
+    // per pass (forking late: 512x256x192 +2.8%, 1024x512x256 +3.4%).  In
+    // the FP32 form the solves run closer to the bandwidth and the scalar
+    // half outlasts them on large grids, stalling the correction that waits
+    // for it, so there it forks before the momentum stages (512x256x192
+    // +2.9%, 1024x512x256 +0.5%).
+    const long long fork_early = sizeof(T) == 8 ? DNSLAB_FORK_EARLY_CELLS : DNSLAB_FORK_EARLY_CELLS32;
+    if (defer && x->g.n >= fork_early) {
         rc = flush_scalar_half<T>(x);
         if (rc) return rc;
         forked = true;
