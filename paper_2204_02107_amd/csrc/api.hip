@@ -236,9 +236,6 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_PAIR_MIN_KC
 #define DNSLAB_PAIR_MIN_KC 16  // shortest z chunk for the scalar pairs and the FP32 momentum pairs
 #endif
-#ifndef DNSLAB_PROWS
-#define DNSLAB_PROWS 8         // rows of the 64-wide tile of the stage-pair kernels
-#endif
 #ifndef DNSLAB_PKC_DIV
 #define DNSLAB_PKC_DIV 1024    // stage-pair z chunk: nz * tiles per plane / this, clamped to [8, 32]
 #endif

@@ -169,8 +169,13 @@ StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x);
 // records the launch (for batched replay by the pool) without issuing it.
 template <typename T> hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s,
                                                   Recorder* rec = nullptr);
-// The pair kernels need the 64 x rows tile to divide the grid in x and y
-// (mom_pair_supported); otherwise the single-stage kernels run.
+// Rows of the 64-wide tile of the stage-pair kernels (a compile-time tile
+// shape: the kernels' LDS offsets are immediates).
+#ifndef DNSLAB_PROWS
+#define DNSLAB_PROWS 8
+#endif
+// The pair kernels need the 64 x DNSLAB_PROWS tile to divide the grid in x
+// and y (mom_pair_supported); otherwise the single-stage kernels run.
 bool mom_pair_supported(const Grid& g, const StencilLaunch& L);
 template <typename T> hipError_t launch_mom_pair(int pair, const MomPairArgs<T>& a, const StencilLaunch& L,
                                                  hipStream_t s, Recorder* rec = nullptr);

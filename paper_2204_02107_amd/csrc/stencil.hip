@@ -11,6 +11,8 @@
 #include "stencil.h"
 
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 namespace dnslab {
 
@@ -403,248 +405,336 @@ __device__ __forceinline__ void ring_cell(int r, int BX, int BY, int& lx, int& l
 }
 
 // Prefetch distance of the pair kernels' loads, in planes: each block keeps
-// the loads of the next D planes in flight.
-// Measured on 1024x512x256: two planes in flight take the FP64 momentum
-// pairs from 3337 to 3208 us; the FP64 scalar pairs lose 2% with them, and
-// in FP32 the extra registers cost a block per CU (momentum pairs 1677 ->
-// 1919 us), so those keep one plane.
+// the loads of the next D planes in flight.  With the register rings one
+// plane suffices (two push the FP64 momentum pair past 256 registers).
 #ifndef DNSLAB_PAIR_DIST_MOM64
-#define DNSLAB_PAIR_DIST_MOM64 2
+#define DNSLAB_PAIR_DIST_MOM64 1
 #endif
 #ifndef DNSLAB_PAIR_DIST_OTHER
 #define DNSLAB_PAIR_DIST_OTHER 1
 #endif
+// Waves per SIMD the FP32 pair kernels are compiled for (0: the compiler's
+// choice).  Four keep them within 128 registers, two 512-thread blocks per
+// CU (measured on 1024x512x256: momentum pairs 1747 -> 1621 us, scalar
+// pairs 1318 -> 1243 us, against one block per CU at 133-151 registers).
+#ifndef DNSLAB_PAIR_WAVES32
+#define DNSLAB_PAIR_WAVES32 4
+#endif
 template <typename T, bool MOM>
 constexpr int pair_dist() { return (MOM && sizeof(T) == 8) ? DNSLAB_PAIR_DIST_MOM64 : DNSLAB_PAIR_DIST_OTHER; }
 
-template <typename T, int PAIR, int D>
+// Register rings of the pair kernels.  A value belonging to z plane x of the
+// march (x counted from the chunk's first iteration) sits in slot x % U of
+// its ring, and the z loop is unrolled U times (pair_phases), so every slot
+// index is a compile-time constant: values stay in the register they were
+// loaded into.  Shifting a queue instead (q[i] = q[i+1]) costs a move per
+// value and plane, and a move of a register whose load is still in flight
+// makes the wave wait for that load, which defeats the prefetch.
+template <int... Is, typename F>
+__device__ __forceinline__ bool pair_phases(std::integer_sequence<int, Is...>, F&& f) {
+    return (f(std::integral_constant<int, Is>{}) && ...);
+}
+// Loads and stores of the pair kernels as raw buffer accesses: the array's
+// resource (base address) and the plane's byte offset are wave-uniform
+// (scalar registers), the in-plane byte offset is the lane's (one vector
+// register, fixed for the whole march), and the address is formed by the
+// memory unit: no per-lane 64-bit address arithmetic, and nothing the
+// compiler can hoist into one 64-bit pointer per array and lane.  The
+// resource does no range clipping (every offset is inside its array).
+typedef unsigned u32x2_t __attribute__((__vector_size__(2 * sizeof(unsigned))));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_res(const void* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
+}
+template <typename T> struct BufIO;
+template <> struct BufIO<double> {
+    static __device__ __forceinline__ double ld(const void* p, unsigned v, unsigned s) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(buf_res(p), v, s, 0));
+    }
+    static __device__ __forceinline__ void st(void* p, unsigned v, unsigned s, double x) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), buf_res(p), v, s, 0);
+    }
+};
+template <> struct BufIO<float> {
+    static __device__ __forceinline__ float ld(const void* p, unsigned v, unsigned s) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(buf_res(p), v, s, 0));
+    }
+    static __device__ __forceinline__ void st(void* p, unsigned v, unsigned s, float x) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), buf_res(p), v, s, 0);
+    }
+};
+template <> struct BufIO<uint8_t> {
+    static __device__ __forceinline__ uint8_t ld(const void* p, unsigned v, unsigned s) {
+        return __builtin_amdgcn_raw_buffer_load_b8(buf_res(p), v, s, 0);
+    }
+};
+// element at byte offset voff of the plane at byte offset soff
+template <typename T>
+__device__ __forceinline__ T bld(const T* p, unsigned voff, unsigned soff) { return BufIO<T>::ld(p, voff, soff); }
+template <typename T>
+__device__ __forceinline__ void bst(T* p, unsigned voff, unsigned soff, T x) { BufIO<T>::st(p, voff, soff, x); }
+// A per-lane value the compiler must take as redefined at this point.  The
+// pair kernels pass their LDS indices through it once per plane: otherwise
+// the address of every LDS access of the unrolled march (a different
+// constant offset per plane of the buffer cycle) is hoisted out of the loop
+// and held in a register of its own for the whole kernel.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+// Offsets of planes K + s (s = 0, 1, 1 + D, 2 + D, wrapped periodically),
+// advanced by one plane per iteration without a division.
+template <int D>
+struct PlaneOffsets {
+    unsigned p0, p1, pd1, pd2;
+    unsigned nxy, ntot;
+    __device__ __forceinline__ PlaneOffsets(int K, int nz, unsigned nxy_) : nxy(nxy_), ntot((unsigned)nz * nxy_) {
+        p0 = (unsigned)wrap(K, nz) * nxy;
+        p1 = (unsigned)wrap(K + 1, nz) * nxy;
+        pd1 = (unsigned)wrap(K + 1 + D, nz) * nxy;
+        pd2 = (unsigned)wrap(K + 2 + D, nz) * nxy;
+    }
+    __device__ __forceinline__ static unsigned step(unsigned p, unsigned nxy, unsigned ntot) {
+        p += nxy;
+        return p == ntot ? 0u : p;
+    }
+    __device__ __forceinline__ void advance() {
+        p0 = step(p0, nxy, ntot);
+        p1 = step(p1, nxy, ntot);
+        pd1 = step(pd1, nxy, ntot);
+        pd2 = step(pd2, nxy, ntot);
+    }
+};
+
+template <typename T, int PAIR, int D, int BY>
 __device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const BlockIdx3& bi) {
+    constexpr int BX = 64;
+    constexpr int U = (4 + D) & ~1;                   // ring slots: even (LDS buffer parity), >= 3 + D
+    constexpr int WV = BX + 4, TV = WV * (BY + 4);    // V tile: radius 2, per component
+    constexpr int WW = BX + 2, TW = WW * (BY + 2);    // W tile: radius 1, per component
+    constexpr int NRING = 2 * (BX + BY);
+    constexpr int HM = (4 * (BX + 2) + 4 * BY + BX * BY - 1) / (BX * BY);   // halo cells per thread
+    constexpr unsigned E = sizeof(T);
     const Grid& g = a.g;
     const Col col = column(g, a.kc, bi);
     const int k0 = col.k0, k1 = col.k1;
-    const unsigned nxy = (unsigned)g.nxy;
-    const int nz = g.nz;
     const T dt = T(a.dtp ? *a.dtp : a.dt);
     const MomCoef<T> cf = mom_coef<T>(g, a.nu, a.body);
     extern __shared__ unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
-    const int BX = blockDim.x, BY = blockDim.y;
-    const int WV = BX + 4, tv = WV * (BY + 4);     // V tile: radius 2, per component
-    const int WW = BX + 2, tw = WW * (BY + 2);     // W tile: radius 1, per component
-    T* const Vb = lds;                              // 2 planes x 3 components
-    T* const Wb = lds + 6 * tv;                     // 2 planes x 3 components
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty, nthr = BX * BY;
+    T* const Vb = reinterpret_cast<T*>(smem_raw);    // [2 planes][3 components][TV]
+    T* const Wb = Vb + 6 * TV;                       // [2 planes][3 components][TW]
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty;
     const int i0 = col.i - tx, j0 = col.j - ty;
     const unsigned cell = col.row + col.i;
-    const int cV = (ty + 2) * WV + tx + 2, cW = (ty + 1) * WW + tx + 1;
-    constexpr int HM = 2;
-    const PairHalo<HM> hm = pair_halo<HM>(i0, j0, g, BX, BY, tid, nthr);
+    const unsigned cb = cell * E;
+    const int cV0 = (ty + 2) * WV + tx + 2, cW0 = (ty + 1) * WW + tx + 1;
+    const PairHalo<HM> hm = pair_halo<HM>(i0, j0, g, BX, BY, tid, BX * BY);
+    unsigned hb[HM];
+#pragma unroll
+    for (int h = 0; h < HM; ++h) hb[h] = hm.src[h] * E;
     // this thread's ring cell, if any
-    const int nring = 2 * (BX + BY);
-    const bool ring = tid < nring;
+    const bool ring = tid < NRING;
     int rlx = 0, rly = 0;
     if (ring) ring_cell(tid, BX, BY, rlx, rly);
     const unsigned rcell = (unsigned)wrap1(j0 + rly, g.ny) * g.nx + (unsigned)wrap1(i0 + rlx, g.nx);
-    const int rV = (rly + 2) * WV + rlx + 2, rW = (rly + 1) * WW + rlx + 1;
-    auto plane = [&](int K) -> unsigned { return (unsigned)wrap(K, nz) * nxy; };
+    const unsigned rcb = rcell * E;
+    const int rV0 = (rly + 2) * WV + rlx + 2, rW0 = (rly + 1) * WW + rlx + 1;
 
-    // Pipeline state at the start of iteration K (q[i] holds plane K + i
-    // unless noted; the last D - 1 entries of each queue are loads in flight):
-    //   vq: stage input of this thread's cell, planes K .. K+1+D (slot 2+D free)
-    //   hq: halo of V, planes K+2 .. K+1+D
-    //   fq: flags, planes K .. K+D (slot 1+D free)
-    //   rfq: ring cell flags, planes K+1 .. K+D (slot D free)
-    //   unq, runq, acq (pair 1): u^n (cell, ring cell) and acc after stage 2,
-    //   planes K+1 .. K+D (slot D free)
-    T vq[3 + D][3], hq[D][3][HM];
-    uint8_t fq[2 + D], rfq[1 + D];
-    T unq[1 + D][3], runq[1 + D][3], acq[1 + D][3];
-    T wz0[3] = {T(0), T(0), T(0)}, wz1[3] = {T(0), T(0), T(0)};
-    T accK[3] = {T(0), T(0), T(0)};             // pair 0: acc1 of plane K; pair 1: acc3 of plane K
-    T rvm[3] = {T(0), T(0), T(0)};              // ring: v of plane K
+    // Rings, by plane of the march:
+    //   vq: stage input of this thread's cell (planes K .. K+2+D live in iteration K)
+    //   hq: V halo (planes K+2 .. K+2+D, staged into LDS at K+2)
+    //   fq: flags of the cell; rfq: flags of the ring cell
+    //   unq, runq, acq (pair 1): u^n of cell and ring cell, acc after stage 2
+    //   wz: first-stage value of the cell; ac: its running accumulator
+    //   rv: the ring cell's stage input (its z- neighbour one plane later)
+    T vq[U][3], hq[U][3][HM], unq[U][3], runq[U][3], acq[U][3], wz[U][3], ac[U][3], rv[U][3];
+    uint8_t fq[U], rfq[U];
 #pragma unroll
-    for (int i = 0; i < 1 + D; ++i) {
-        rfq[i] = 0;
+    for (int s = 0; s < U; ++s) {
+        fq[s] = 0;
+        rfq[s] = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) { unq[i][c] = T(0); runq[i][c] = T(0); acq[i][c] = T(0); }
+        for (int c = 0; c < 3; ++c) {
+            vq[s][c] = T(0); unq[s][c] = T(0); runq[s][c] = T(0); acq[s][c] = T(0);
+            wz[s][c] = T(0); ac[s][c] = T(0); rv[s][c] = T(0);
+#pragma unroll
+            for (int h = 0; h < HM; ++h) hq[s][c][h] = T(0);
+        }
     }
-#pragma unroll
-    for (int i = 0; i < 2 + D; ++i) fq[i] = 0;
+    PlaneOffsets<D> po(k0 - 2, g.nz, (unsigned)g.nxy);
     {
+        // iteration 0 is plane K = k0 - 2
         const int K = k0 - 2;
 #pragma unroll
         for (int i = 0; i < 2 + D; ++i) {
-            const unsigned pi = plane(K + i);
+            const unsigned pi = (unsigned)wrap(K + i, g.nz) * g.nxy;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) vq[i][c] = a.vin[c][pi + cell];
+            for (int c = 0; c < 3; ++c) vq[i][c] = bld(a.vin[c], cb, pi * E);
         }
 #pragma unroll
-        for (int i = 1; i < 1 + D; ++i) fq[i] = a.flags[plane(K + i) + cell];
+        for (int i = 1; i < 1 + D; ++i) fq[i] = a.flags[(unsigned)wrap(K + i, g.nz) * g.nxy + cell];
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const unsigned pi = plane(K + 1 + i);
+        for (int i = 1; i < 1 + D; ++i) {
+            const unsigned pi = (unsigned)wrap(K + i, g.nz) * g.nxy;
             if (ring) rfq[i] = a.flags[pi + rcell];
             if (PAIR == 1) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    unq[i][c] = a.un[c][pi + cell];
-                    if (ring) runq[i][c] = a.un[c][pi + rcell];
-                    if (K + 1 + i >= k0 && K + 1 + i < k1) acq[i][c] = a.accin[c][pi + cell];
+                    unq[i][c] = bld(a.un[c], cb, pi * E);
+                    if (ring) runq[i][c] = bld(a.un[c], rcb, pi * E);
+                    if (K + i >= k0 && K + i < k1) acq[i][c] = bld(a.accin[c], cb, pi * E);
                 }
             }
         }
         if (ring) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) rvm[c] = a.vin[c][plane(K) + rcell];
+            for (int c = 0; c < 3; ++c) rv[0][c] = bld(a.vin[c], rcb, po.p0 * E);
         }
-        // V tile of plane k0 - 1
-        const unsigned pb = plane(K + 1);
-        T* Vp = Vb + ((K + 1) & 1) * 3 * tv;
+        // V tile of plane k0 - 1 (buffer 1)
+        T* Vp = Vb + 3 * TV;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Vp[c * tv + cV] = vq[1][c];
+            Vp[c * TV + cV0] = vq[1][c];
 #pragma unroll
             for (int h = 0; h < HM; ++h)
-                if (h < hm.n) Vp[c * tv + hm.dst[h]] = a.vin[c][pb + hm.src[h]];
+                if (h < hm.n) Vp[c * TV + hm.dst[h]] = bld(a.vin[c], hb[h], po.p1 * E);
         }
         // halos of planes k0 .. k0 + D - 1
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const unsigned pi = plane(K + 2 + i);
+        for (int i = 2; i < 2 + D; ++i) {
+            const unsigned pi = (unsigned)wrap(K + i, g.nz) * g.nxy;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int h = 0; h < HM; ++h) hq[i][c][h] = h < hm.n ? a.vin[c][pi + hm.src[h]] : T(0);
+                for (int h = 0; h < HM; ++h) hq[i][c][h] = h < hm.n ? bld(a.vin[c], hb[h], pi * E) : T(0);
         }
     }
 
-    for (int K = k0 - 2; K < k1; ++K) {
-        // 1. stage input of plane K + 2 into V
-        T* const Vq = Vb + ((K + 2) & 1) * 3 * tv;
+    const int nit = k1 - k0 + 2;
+    int r = 0;   // iteration: K = k0 - 2 + r
+    auto iter = [&](auto phase) __attribute__((always_inline)) -> bool {
+        constexpr int P = decltype(phase)::value;
+        constexpr int S0 = P % U, S1 = (P + 1) % U, S2 = (P + 2) % U, SM = (P + U - 1) % U;
+        constexpr int SD1 = (P + 1 + D) % U, SD2 = (P + 2 + D) % U;
+        if (r >= nit) return false;
+        const int K = k0 - 2 + r;
+        const int cV = opaque(cV0), cW = opaque(cW0), rV = opaque(rV0), rW = opaque(rW0);
+        int hd[HM];
+#pragma unroll
+        for (int h = 0; h < HM; ++h) hd[h] = opaque(hm.dst[h]);
+        // 1. stage input of plane K + 2 into V (buffer parity of K + 2)
+        T* const Vq = Vb + (P & 1) * 3 * TV;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Vq[c * tv + cV] = vq[2][c];
+            Vq[c * TV + cV] = vq[S2][c];
 #pragma unroll
             for (int h = 0; h < HM; ++h)
-                if (h < hm.n) Vq[c * tv + hm.dst[h]] = hq[0][c][h];
+                if (h < hm.n) Vq[c * TV + hd[h]] = hq[S2][c][h];
         }
+        // 2. loads D planes ahead: v and halo of plane K + 2 + D, the rest of plane K + 1 + D.
+        // Every slot written here is written on all paths (zero where no load
+        // is due), so that the value it held U planes earlier is dead.
 #pragma unroll
-        for (int i = 0; i + 1 < D; ++i)
+        for (int c = 0; c < 3; ++c) {
+            vq[SD2][c] = T(0); unq[SD1][c] = T(0); runq[SD1][c] = T(0); acq[SD1][c] = T(0);
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int h = 0; h < HM; ++h) hq[i][c][h] = hq[i + 1][c][h];
-        // 2. loads D planes ahead: v and halo of plane K + 2 + D, the rest of plane K + 1 + D
+            for (int h = 0; h < HM; ++h) hq[SD2][c][h] = T(0);
+        }
+        fq[SD1] = 0;
+        rfq[SD1] = 0;
         if (K + D < k1) {
-            const unsigned pv = plane(K + 2 + D), pr = plane(K + 1 + D);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                vq[2 + D][c] = a.vin[c][pv + cell];
+                const unsigned sv = po.pd2 * E;
+                vq[SD2][c] = bld(a.vin[c], cb, sv);
 #pragma unroll
                 for (int h = 0; h < HM; ++h)
-                    if (h < hm.n) hq[D - 1][c][h] = a.vin[c][pv + hm.src[h]];
+                    if (h < hm.n) hq[SD2][c][h] = bld(a.vin[c], hb[h], sv);
             }
-            fq[1 + D] = a.flags[pr + cell];
-            if (ring) rfq[D] = a.flags[pr + rcell];
+            fq[SD1] = bld(a.flags, cell, po.pd1);
+            if (ring) rfq[SD1] = bld(a.flags, rcell, po.pd1);
             if (PAIR == 1) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    unq[D][c] = a.un[c][pr + cell];
-                    if (ring) runq[D][c] = a.un[c][pr + rcell];
-                    if (K + 1 + D >= k0 && K + 1 + D < k1) acq[D][c] = a.accin[c][pr + cell];
+                    unq[SD1][c] = bld(a.un[c], cb, po.pd1 * E);
+                    if (ring) runq[SD1][c] = bld(a.un[c], rcb, po.pd1 * E);
+                    if (K + 1 + D >= k0 && K + 1 + D < k1) acq[SD1][c] = bld(a.accin[c], cb, po.pd1 * E);
                 }
             }
         }
         __syncthreads();
         // 3. first stage at plane K + 1: w on the tile and the ring
-        const T* const Vp = Vb + ((K + 1) & 1) * 3 * tv;
-        T* const Wp = Wb + ((K + 1) & 1) * 3 * tw;
-        const unsigned p1 = plane(K + 1);
-        T wz2[3], accn[3];
+        const T* const Vp = Vb + ((P + 1) & 1) * 3 * TV;
+        T* const Wp = Wb + ((P + 1) & 1) * 3 * TW;
         {
             T xm[3], xp[3], ym[3], yp[3], kv[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                xm[c] = Vp[c * tv + cV - 1];
-                xp[c] = Vp[c * tv + cV + 1];
-                ym[c] = Vp[c * tv + cV - WV];
-                yp[c] = Vp[c * tv + cV + WV];
+                xm[c] = Vp[c * TV + cV - 1];
+                xp[c] = Vp[c * TV + cV + 1];
+                ym[c] = Vp[c * TV + cV - WV];
+                yp[c] = Vp[c * TV + cV + WV];
             }
-            mom_rhs_cell<T>(cf, vq[1], xm, xp, ym, yp, vq[0], vq[2], fq[1], a.frc, p1 + cell, kv);
+            mom_rhs_cell<T>(cf, vq[S1], xm, xp, ym, yp, vq[S0], vq[S2], fq[S1], a.frc, po.p1 + cell, kv);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (PAIR == 0) {
-                    accn[c] = vq[1][c] + (dt / T(6)) * kv[c];
-                    wz2[c] = vq[1][c] + (dt / T(2)) * kv[c];
+                    ac[S1][c] = vq[S1][c] + (dt / T(6)) * kv[c];
+                    wz[S1][c] = vq[S1][c] + (dt / T(2)) * kv[c];
                 } else {
-                    accn[c] = acq[0][c] + (dt / T(3)) * kv[c];
-                    wz2[c] = unq[0][c] + dt * kv[c];
+                    ac[S1][c] = acq[S1][c] + (dt / T(3)) * kv[c];
+                    wz[S1][c] = unq[S1][c] + dt * kv[c];
                 }
-                Wp[c * tw + cW] = wz2[c];
+                Wp[c * TW + cW] = wz[S1][c];
             }
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rv[S1][c] = T(0);
         if (ring) {
             T c0[3], xm[3], xp[3], ym[3], yp[3], zp[3], kv[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                c0[c] = Vp[c * tv + rV];
-                xm[c] = Vp[c * tv + rV - 1];
-                xp[c] = Vp[c * tv + rV + 1];
-                ym[c] = Vp[c * tv + rV - WV];
-                yp[c] = Vp[c * tv + rV + WV];
-                zp[c] = Vq[c * tv + rV];
+                c0[c] = Vp[c * TV + rV];
+                xm[c] = Vp[c * TV + rV - 1];
+                xp[c] = Vp[c * TV + rV + 1];
+                ym[c] = Vp[c * TV + rV - WV];
+                yp[c] = Vp[c * TV + rV + WV];
+                zp[c] = Vq[c * TV + rV];
             }
-            mom_rhs_cell<T>(cf, c0, xm, xp, ym, yp, rvm, zp, rfq[0], a.frc, p1 + rcell, kv);
+            mom_rhs_cell<T>(cf, c0, xm, xp, ym, yp, rv[S0], zp, rfq[S1], a.frc, po.p1 + rcell, kv);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                Wp[c * tw + rW] = PAIR == 0 ? c0[c] + (dt / T(2)) * kv[c] : runq[0][c] + dt * kv[c];
-                rvm[c] = c0[c];
+                Wp[c * TW + rW] = PAIR == 0 ? c0[c] + (dt / T(2)) * kv[c] : runq[S1][c] + dt * kv[c];
+                rv[S1][c] = c0[c];
             }
         }
         __syncthreads();
         // 4. second stage at plane K
-        if (K >= k0) {
-            const T* const Wk = Wb + (K & 1) * 3 * tw;
+        if (r >= 2) {
+            const T* const Wk = Wb + (P & 1) * 3 * TW;
             T xm[3], xp[3], ym[3], yp[3], kv[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                xm[c] = Wk[c * tw + cW - 1];
-                xp[c] = Wk[c * tw + cW + 1];
-                ym[c] = Wk[c * tw + cW - WW];
-                yp[c] = Wk[c * tw + cW + WW];
+                xm[c] = Wk[c * TW + cW - 1];
+                xp[c] = Wk[c * TW + cW + 1];
+                ym[c] = Wk[c * TW + cW - WW];
+                yp[c] = Wk[c * TW + cW + WW];
             }
-            const unsigned idx = plane(K) + cell;
-            mom_rhs_cell<T>(cf, wz1, xm, xp, ym, yp, wz0, wz2, fq[0], a.frc, idx, kv);
+            mom_rhs_cell<T>(cf, wz[S0], xm, xp, ym, yp, wz[SM], wz[S1], fq[S0], a.frc, po.p0 + cell, kv);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (PAIR == 0) {
-                    a.acc[c][idx] = accK[c] + (dt / T(3)) * kv[c];
-                    a.out[c][idx] = vq[0][c] + (dt / T(2)) * kv[c];
+                    bst(a.acc[c], cb, po.p0 * E, ac[S0][c] + (dt / T(3)) * kv[c]);
+                    bst(a.out[c], cb, po.p0 * E, vq[S0][c] + (dt / T(2)) * kv[c]);
                 } else {
-                    a.out[c][idx] = accK[c] + (dt / T(6)) * kv[c];
+                    bst(a.out[c], cb, po.p0 * E, ac[S0][c] + (dt / T(6)) * kv[c]);
                 }
             }
         }
-        // 5. advance the queues
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-#pragma unroll
-            for (int i = 0; i < 2 + D; ++i) vq[i][c] = vq[i + 1][c];
-            wz0[c] = wz1[c]; wz1[c] = wz2[c];
-            accK[c] = accn[c];
-            if (PAIR == 1) {
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    unq[i][c] = unq[i + 1][c];
-                    runq[i][c] = runq[i + 1][c];
-                    acq[i][c] = acq[i + 1][c];
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 1 + D; ++i) fq[i] = fq[i + 1];
-#pragma unroll
-        for (int i = 0; i < D; ++i) rfq[i] = rfq[i + 1];
+        po.advance();
+        ++r;
+        return true;
+    };
+    while (pair_phases(std::make_integer_sequence<int, U>{}, iter)) {
     }
 }
 
@@ -767,251 +857,248 @@ __device__ __forceinline__ void sca_stage_body(const ScaArgs<T>& a, const BlockI
 // second stage at plane K needs u, v and the flags at the same neighbours the
 // first stage read one plane earlier: each thread keeps them from there.
 // ---------------------------------------------------------------------------
-template <typename T, int PAIR, int D>
+template <typename T, int PAIR, int D, int BY>
 __device__ __forceinline__ void sca_pair_body(const ScaPairArgs<T>& a, const BlockIdx3& bi) {
+    constexpr int BX = 64;
+    constexpr int U = (5 + D) & ~1;                   // ring slots: even (LDS buffer parity), >= 4 + D
+    constexpr int WV = BX + 4, TV = WV * (BY + 4);
+    constexpr int WW = BX + 2, TW = WW * (BY + 2);
+    constexpr int NRING = 2 * (BX + BY);
+    constexpr int HM = (4 * (BX + 2) + 4 * BY + BX * BY - 1) / (BX * BY);
+    constexpr unsigned E = sizeof(T);
     const Grid& g = a.g;
     const Col col = column(g, a.kc, bi);
     const int k0 = col.k0, k1 = col.k1;
-    const unsigned nxy = (unsigned)g.nxy;
-    const int nz = g.nz;
     const T dt = T(a.dtp ? *a.dtp : a.dt);
     const ScaCoef<T> cf = sca_coef<T>(g, a.alpha);
     extern __shared__ unsigned char smem_raw[];
-    const int BX = blockDim.x, BY = blockDim.y;
-    const int WV = BX + 4, tv = WV * (BY + 4);
-    const int WW = BX + 2, tw = WW * (BY + 2);
     T* const Cs = reinterpret_cast<T*>(smem_raw);   // c, 2 planes
-    T* const Us = Cs + 2 * tv;                        // u, 2 planes
-    T* const Vs = Us + 2 * tv;                        // v, 2 planes
-    T* const Ws = Vs + 2 * tv;                        // first-stage value c1, 2 planes (radius 1)
-    uint8_t* const Fs = reinterpret_cast<uint8_t*>(Ws + 2 * tw);   // flags, 2 planes
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty, nthr = BX * BY;
+    T* const Us = Cs + 2 * TV;                        // u, 2 planes
+    T* const Vs = Us + 2 * TV;                        // v, 2 planes
+    T* const Ws = Vs + 2 * TV;                        // first-stage value c1, 2 planes (radius 1)
+    uint8_t* const Fs = reinterpret_cast<uint8_t*>(Ws + 2 * TW);   // flags, 2 planes
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty;
     const int i0 = col.i - tx, j0 = col.j - ty;
     const unsigned cell = col.row + col.i;
-    const int cV = (ty + 2) * WV + tx + 2, cW = (ty + 1) * WW + tx + 1;
-    constexpr int HM = 2;
-    const PairHalo<HM> hm = pair_halo<HM>(i0, j0, g, BX, BY, tid, nthr);
-    const int nring = 2 * (BX + BY);
-    const bool ring = tid < nring;
+    const unsigned cb = cell * E;
+    const int cV0 = (ty + 2) * WV + tx + 2, cW0 = (ty + 1) * WW + tx + 1;
+    const PairHalo<HM> hm = pair_halo<HM>(i0, j0, g, BX, BY, tid, BX * BY);
+    unsigned hb[HM];
+#pragma unroll
+    for (int h = 0; h < HM; ++h) hb[h] = hm.src[h] * E;
+    const bool ring = tid < NRING;
     int rlx = 0, rly = 0;
     if (ring) ring_cell(tid, BX, BY, rlx, rly);
     const unsigned rcell = (unsigned)wrap1(j0 + rly, g.ny) * g.nx + (unsigned)wrap1(i0 + rlx, g.nx);
-    const int rV = (rly + 2) * WV + rlx + 2, rW = (rly + 1) * WW + rlx + 1;
-    auto plane = [&](int K) -> unsigned { return (unsigned)wrap(K, nz) * nxy; };
+    const unsigned rcb = rcell * E;
+    const int rV0 = (rly + 2) * WV + rlx + 2, rW0 = (rly + 1) * WW + rlx + 1;
+    Partial part = {0, 0, 0, 0, 0, 0};
+
+    // Rings, by plane of the march (iteration K):
+    //   cq: c_in of the cell (planes K .. K+2+D); wq, fq: w and flags of the
+    //   cell (planes K-1 .. K+2+D); uq, vq and the halo rings: planes
+    //   K+2 .. K+2+D, staged into LDS at K+2; rwq: the ring cell's w;
+    //   cnq, rcnq, acq (pair 1): c^n of cell and ring cell, acc after stage 2;
+    //   c1: first-stage value of the cell; ac: its accumulator;
+    //   sx, sf: u, v and flags at the cell's x/y neighbours, read by the first
+    //   stage of plane K+1 and used again by the second stage there;
+    //   rc, rf: the ring cell's c and flags.
+    T cq[U], wq[U], uq[U], vq[U], hc[U][HM], hu[U][HM], hv[U][HM], rwq[U];
+    T cnq[U], rcnq[U], acq[U], c1[U], ac[U], sx[U][4], rc[U];
+    uint8_t fq[U], hf[U][HM], sf[U][4], rf[U];
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+        cq[s] = T(0); wq[s] = T(0); uq[s] = T(0); vq[s] = T(0); rwq[s] = T(0);
+        cnq[s] = T(0); rcnq[s] = T(0); acq[s] = T(0); c1[s] = T(0); ac[s] = T(0); rc[s] = T(0);
+        fq[s] = 0; rf[s] = 0;
+#pragma unroll
+        for (int h = 0; h < HM; ++h) { hc[s][h] = T(0); hu[s][h] = T(0); hv[s][h] = T(0); hf[s][h] = 0; }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { sx[s][q] = T(0); sf[s][q] = 0; }
+    }
     const T* __restrict__ ux = a.u[0];
     const T* __restrict__ uy = a.u[1];
     const T* __restrict__ uz = a.u[2];
-    Partial part = {0, 0, 0, 0, 0, 0};
-
-    // Queues at the start of iteration K (the last entries are loads in
-    // flight, D planes ahead of their use):
-    //   cq: c_in, planes K .. K+1+D (slot 2+D free)
-    //   wq, fq: w and flags, planes K-1 .. K+1+D (slot 3+D free)
-    //   uq, vq, halo queues: planes K+2 .. K+1+D (staged into LDS in turn)
-    //   rwq: the ring cell's w, planes K .. K+1+D (slot 2+D free)
-    //   cnq, rcnq, acq (pair 1): c^n (cell, ring cell), acc after stage 2,
-    //   planes K+1 .. K+D (slot D free)
-    T cq[3 + D], wq[4 + D], uq[D], vq[D], hc[D][HM], hu[D][HM], hv[D][HM];
-    uint8_t fq[4 + D], hf[D][HM];
-    T rwq[3 + D];
-    T cnq[1 + D], rcnq[1 + D], acq[1 + D];
-    T c1z0 = T(0), c1z1 = T(0);                       // first-stage value c1, planes K-1, K
-    T accK = T(0);                                     // pair 0: acc1 of plane K; pair 1: acc3 of plane K
-    // the first stage's x/y neighbours of u, v and flags at plane K (for the second stage)
-    T kuxm = T(0), kuxp = T(0), kvym = T(0), kvyp = T(0);
-    uint8_t kfxm = 0, kfxp = 0, kfym = 0, kfyp = 0;
-    T rcK = T(0);                                      // ring cell: c of plane K
-    uint8_t rfK = 0;                                   // ring cell: flags of plane K
-#pragma unroll
-    for (int i = 0; i < 4 + D; ++i) { wq[i] = T(0); fq[i] = 0; }
-#pragma unroll
-    for (int i = 0; i < 3 + D; ++i) { cq[i] = T(0); rwq[i] = T(0); }
-#pragma unroll
-    for (int i = 0; i < 1 + D; ++i) { cnq[i] = T(0); rcnq[i] = T(0); acq[i] = T(0); }
+    PlaneOffsets<D> po(k0 - 2, g.nz, (unsigned)g.nxy);
     {
         const int K = k0 - 2;
+        auto pl = [&](int k) -> unsigned { return (unsigned)wrap(k, g.nz) * g.nxy; };
 #pragma unroll
         for (int i = 0; i < 2 + D; ++i) {
-            const unsigned pi = plane(K + i);
-            cq[i] = a.cin[pi + cell];
-            if (ring) rwq[i] = uz[pi + rcell];
-        }
-#pragma unroll
-        for (int i = 1; i < 3 + D; ++i) {
-            const unsigned pi = plane(K - 1 + i);
-            wq[i] = uz[pi + cell];
+            const unsigned pi = pl(K + i);
+            cq[i] = bld(a.cin, cb, pi * E);
+            wq[i] = bld(uz, cb, pi * E);
             fq[i] = a.flags[pi + cell];
+            if (ring) rwq[i] = bld(uz, rcb, pi * E);
         }
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const unsigned pi = plane(K + 2 + i);
-            uq[i] = ux[pi + cell];
-            vq[i] = uy[pi + cell];
+        for (int i = 2; i < 2 + D; ++i) {
+            const unsigned pi = pl(K + i);
+            uq[i] = bld(ux, cb, pi * E);
+            vq[i] = bld(uy, cb, pi * E);
 #pragma unroll
             for (int h = 0; h < HM; ++h) {
                 const bool on = h < hm.n;
-                hc[i][h] = on ? a.cin[pi + hm.src[h]] : T(0);
-                hu[i][h] = on ? ux[pi + hm.src[h]] : T(0);
-                hv[i][h] = on ? uy[pi + hm.src[h]] : T(0);
+                hc[i][h] = on ? bld(a.cin, hb[h], pi * E) : T(0);
+                hu[i][h] = on ? bld(ux, hb[h], pi * E) : T(0);
+                hv[i][h] = on ? bld(uy, hb[h], pi * E) : T(0);
                 hf[i][h] = on ? a.flags[pi + hm.src[h]] : 0;
             }
         }
         if (ring) {
-            rcK = a.cin[plane(K) + rcell];
-            rfK = a.flags[plane(K) + rcell];
+            rc[0] = bld(a.cin, rcb, po.p0 * E);
+            rf[0] = a.flags[po.p0 + rcell];
         }
         if (PAIR == 1) {
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                const unsigned pi = plane(K + 1 + i);
-                cnq[i] = a.cn[pi + cell];
-                if (ring) rcnq[i] = a.cn[pi + rcell];
-                if (K + 1 + i >= k0 && K + 1 + i < k1) acq[i] = a.accin[pi + cell];
+            for (int i = 1; i < 1 + D; ++i) {
+                const unsigned pi = pl(K + i);
+                cnq[i] = bld(a.cn, cb, pi * E);
+                if (ring) rcnq[i] = bld(a.cn, rcb, pi * E);
+                if (K + i >= k0 && K + i < k1) acq[i] = bld(a.accin, cb, pi * E);
             }
         }
-        // LDS planes of k0 - 1
-        const unsigned pb = plane(K + 1);
-        const int b = (K + 1) & 1;
-        Cs[b * tv + cV] = cq[1];
-        Us[b * tv + cV] = ux[pb + cell];
-        Vs[b * tv + cV] = uy[pb + cell];
-        Fs[b * tv + cV] = fq[2];
+        // LDS planes of k0 - 1 (buffer 1)
+        const unsigned pb = po.p1;
+        Cs[TV + cV0] = cq[1];
+        Us[TV + cV0] = bld(ux, cb, pb * E);
+        Vs[TV + cV0] = bld(uy, cb, pb * E);
+        Fs[TV + cV0] = fq[1];
 #pragma unroll
         for (int h = 0; h < HM; ++h)
             if (h < hm.n) {
-                Cs[b * tv + hm.dst[h]] = a.cin[pb + hm.src[h]];
-                Us[b * tv + hm.dst[h]] = ux[pb + hm.src[h]];
-                Vs[b * tv + hm.dst[h]] = uy[pb + hm.src[h]];
-                Fs[b * tv + hm.dst[h]] = a.flags[pb + hm.src[h]];
+                Cs[TV + hm.dst[h]] = bld(a.cin, hb[h], pb * E);
+                Us[TV + hm.dst[h]] = bld(ux, hb[h], pb * E);
+                Vs[TV + hm.dst[h]] = bld(uy, hb[h], pb * E);
+                Fs[TV + hm.dst[h]] = a.flags[pb + hm.src[h]];
             }
     }
 
-    for (int K = k0 - 2; K < k1; ++K) {
+    const int nit = k1 - k0 + 2;
+    int r = 0;   // iteration: K = k0 - 2 + r
+    auto iter = [&](auto phase) __attribute__((always_inline)) -> bool {
+        constexpr int P = decltype(phase)::value;
+        constexpr int S0 = P % U, S1 = (P + 1) % U, S2 = (P + 2) % U, SM = (P + U - 1) % U;
+        constexpr int SD1 = (P + 1 + D) % U, SD2 = (P + 2 + D) % U;
+        constexpr int bq = P & 1, bp = (P + 1) & 1;   // LDS buffers of planes K + 2 and K + 1
+        if (r >= nit) return false;
+        const int K = k0 - 2 + r;
+        const int cV = opaque(cV0), cW = opaque(cW0), rV = opaque(rV0), rW = opaque(rW0);
+        int hd[HM];
+#pragma unroll
+        for (int h = 0; h < HM; ++h) hd[h] = opaque(hm.dst[h]);
         // 1. plane K + 2 into LDS
-        const int bq = (K + 2) & 1, bp = (K + 1) & 1;
-        Cs[bq * tv + cV] = cq[2];
-        Us[bq * tv + cV] = uq[0];
-        Vs[bq * tv + cV] = vq[0];
-        Fs[bq * tv + cV] = fq[3];
+        Cs[bq * TV + cV] = cq[S2];
+        Us[bq * TV + cV] = uq[S2];
+        Vs[bq * TV + cV] = vq[S2];
+        Fs[bq * TV + cV] = fq[S2];
 #pragma unroll
         for (int h = 0; h < HM; ++h)
             if (h < hm.n) {
-                Cs[bq * tv + hm.dst[h]] = hc[0][h];
-                Us[bq * tv + hm.dst[h]] = hu[0][h];
-                Vs[bq * tv + hm.dst[h]] = hv[0][h];
-                Fs[bq * tv + hm.dst[h]] = hf[0][h];
+                Cs[bq * TV + hd[h]] = hc[S2][h];
+                Us[bq * TV + hd[h]] = hu[S2][h];
+                Vs[bq * TV + hd[h]] = hv[S2][h];
+                Fs[bq * TV + hd[h]] = hf[S2][h];
             }
+        // 2. loads D planes ahead (every slot written on all paths, as in
+        // mom_pair_body)
+        cq[SD2] = T(0); wq[SD2] = T(0); uq[SD2] = T(0); vq[SD2] = T(0); rwq[SD2] = T(0);
+        cnq[SD1] = T(0); rcnq[SD1] = T(0); acq[SD1] = T(0);
+        fq[SD2] = 0;
 #pragma unroll
-        for (int i = 0; i + 1 < D; ++i) {
-            uq[i] = uq[i + 1];
-            vq[i] = vq[i + 1];
-#pragma unroll
-            for (int h = 0; h < HM; ++h) {
-                hc[i][h] = hc[i + 1][h]; hu[i][h] = hu[i + 1][h]; hv[i][h] = hv[i + 1][h]; hf[i][h] = hf[i + 1][h];
-            }
-        }
-        // 2. loads D planes ahead
+        for (int h = 0; h < HM; ++h) { hc[SD2][h] = T(0); hu[SD2][h] = T(0); hv[SD2][h] = T(0); hf[SD2][h] = 0; }
         if (K + D < k1) {
-            const unsigned pv = plane(K + 2 + D), pr = plane(K + 1 + D);
-            cq[2 + D] = a.cin[pv + cell];
-            wq[3 + D] = uz[pv + cell];
-            fq[3 + D] = a.flags[pv + cell];
-            uq[D - 1] = ux[pv + cell];
-            vq[D - 1] = uy[pv + cell];
+            const unsigned pv = po.pd2, pr = po.pd1;
+            cq[SD2] = bld(a.cin, cb, pv * E);
+            wq[SD2] = bld(uz, cb, pv * E);
+            fq[SD2] = bld(a.flags, cell, pv);
+            uq[SD2] = bld(ux, cb, pv * E);
+            vq[SD2] = bld(uy, cb, pv * E);
 #pragma unroll
             for (int h = 0; h < HM; ++h)
                 if (h < hm.n) {
-                    hc[D - 1][h] = a.cin[pv + hm.src[h]];
-                    hu[D - 1][h] = ux[pv + hm.src[h]];
-                    hv[D - 1][h] = uy[pv + hm.src[h]];
-                    hf[D - 1][h] = a.flags[pv + hm.src[h]];
+                    hc[SD2][h] = bld(a.cin, hb[h], pv * E);
+                    hu[SD2][h] = bld(ux, hb[h], pv * E);
+                    hv[SD2][h] = bld(uy, hb[h], pv * E);
+                    hf[SD2][h] = bld(a.flags, hm.src[h], pv);
                 }
-            if (ring) rwq[2 + D] = uz[pv + rcell];
+            if (ring) rwq[SD2] = bld(uz, rcb, pv * E);
             if (PAIR == 1) {
-                cnq[D] = a.cn[pr + cell];
-                if (ring) rcnq[D] = a.cn[pr + rcell];
-                if (K + 1 + D >= k0 && K + 1 + D < k1) acq[D] = a.accin[pr + cell];
+                cnq[SD1] = bld(a.cn, cb, pr * E);
+                if (ring) rcnq[SD1] = bld(a.cn, rcb, pr * E);
+                if (K + 1 + D >= k0 && K + 1 + D < k1) acq[SD1] = bld(a.accin, cb, pr * E);
             }
         }
         __syncthreads();
         // 3. first stage at plane K + 1 on the tile and the ring
-        const unsigned p1 = plane(K + 1);
-        T* const Wp = Ws + bp * tw;
-        T c1z2, accn;
-        T suxm, suxp, svym, svyp;
-        uint8_t sfxm, sfxp, sfym, sfyp;
+        T* const Wp = Ws + bp * TW;
         {
-            const T* C = Cs + bp * tv;
-            const T* U = Us + bp * tv;
-            const T* V = Vs + bp * tv;
-            const uint8_t* F = Fs + bp * tv;
-            suxm = U[cV - 1]; suxp = U[cV + 1]; svym = V[cV - WV]; svyp = V[cV + WV];
-            sfxm = F[cV - 1]; sfxp = F[cV + 1]; sfym = F[cV - WV]; sfyp = F[cV + WV];
-            const T G = sca_rhs_cell<T>(cf, cq[1], C[cV - 1], C[cV + 1], C[cV - WV], C[cV + WV], cq[0], cq[2], suxm,
-                                        suxp, svym, svyp, wq[1], wq[3], fq[2], sfxm, sfxp, sfym, sfyp, fq[1], fq[3],
-                                        a.frc, p1 + cell);
+            const T* C = Cs + bp * TV;
+            const T* Uu = Us + bp * TV;
+            const T* V = Vs + bp * TV;
+            const uint8_t* F = Fs + bp * TV;
+            sx[S1][0] = Uu[cV - 1]; sx[S1][1] = Uu[cV + 1]; sx[S1][2] = V[cV - WV]; sx[S1][3] = V[cV + WV];
+            sf[S1][0] = F[cV - 1]; sf[S1][1] = F[cV + 1]; sf[S1][2] = F[cV - WV]; sf[S1][3] = F[cV + WV];
+            const T G = sca_rhs_cell<T>(cf, cq[S1], C[cV - 1], C[cV + 1], C[cV - WV], C[cV + WV], cq[S0], cq[S2],
+                                        sx[S1][0], sx[S1][1], sx[S1][2], sx[S1][3], wq[S0], wq[S2], fq[S1],
+                                        sf[S1][0], sf[S1][1], sf[S1][2], sf[S1][3], fq[S0], fq[S2], a.frc,
+                                        po.p1 + cell);
             if (PAIR == 0) {
-                accn = cq[1] + (dt / T(6)) * G;
-                c1z2 = cq[1] + (dt / T(2)) * G;
+                ac[S1] = cq[S1] + (dt / T(6)) * G;
+                c1[S1] = cq[S1] + (dt / T(2)) * G;
             } else {
-                accn = acq[0] + (dt / T(3)) * G;
-                c1z2 = cnq[0] + dt * G;
+                ac[S1] = acq[S1] + (dt / T(3)) * G;
+                c1[S1] = cnq[S1] + dt * G;
             }
-            Wp[cW] = c1z2;
+            Wp[cW] = c1[S1];
+            rc[S1] = T(0);
+            rf[S1] = 0;
             if (ring) {
-                const T* Cq = Cs + bq * tv;
-                const uint8_t* Fq = Fs + bq * tv;
+                const T* Cq = Cs + bq * TV;
+                const uint8_t* Fq = Fs + bq * TV;
                 const T rc0 = C[rV];
                 const uint8_t rf0 = F[rV];
-                const T Gr = sca_rhs_cell<T>(cf, rc0, C[rV - 1], C[rV + 1], C[rV - WV], C[rV + WV], rcK, Cq[rV],
-                                             U[rV - 1], U[rV + 1], V[rV - WV], V[rV + WV], rwq[0], rwq[2], rf0,
-                                             F[rV - 1], F[rV + 1], F[rV - WV], F[rV + WV], rfK, Fq[rV], a.frc,
-                                             p1 + rcell);
-                Wp[rW] = PAIR == 0 ? rc0 + (dt / T(2)) * Gr : rcnq[0] + dt * Gr;
-                rcK = rc0;
-                rfK = rf0;
+                const T Gr = sca_rhs_cell<T>(cf, rc0, C[rV - 1], C[rV + 1], C[rV - WV], C[rV + WV], rc[S0], Cq[rV],
+                                             Uu[rV - 1], Uu[rV + 1], V[rV - WV], V[rV + WV], rwq[S0], rwq[S2], rf0,
+                                             F[rV - 1], F[rV + 1], F[rV - WV], F[rV + WV], rf[S0], Fq[rV], a.frc,
+                                             po.p1 + rcell);
+                Wp[rW] = PAIR == 0 ? rc0 + (dt / T(2)) * Gr : rcnq[S1] + dt * Gr;
+                rc[S1] = rc0;
+                rf[S1] = rf0;
             }
         }
         __syncthreads();
         // 4. second stage at plane K on the tile
-        if (K >= k0) {
-            const T* Wk = Ws + (K & 1) * tw;
-            const unsigned idx = plane(K) + cell;
-            const T G = sca_rhs_cell<T>(cf, c1z1, Wk[cW - 1], Wk[cW + 1], Wk[cW - WW], Wk[cW + WW], c1z0, c1z2, kuxm,
-                                        kuxp, kvym, kvyp, wq[0], wq[2], fq[1], kfxm, kfxp, kfym, kfyp, fq[0], fq[2],
-                                        a.frc, idx);
+        if (r >= 2) {
+            const T* Wk = Ws + bq * TW;
+            const T G = sca_rhs_cell<T>(cf, c1[S0], Wk[cW - 1], Wk[cW + 1], Wk[cW - WW], Wk[cW + WW], c1[SM], c1[S1],
+                                        sx[S0][0], sx[S0][1], sx[S0][2], sx[S0][3], wq[SM], wq[S1], fq[S0],
+                                        sf[S0][0], sf[S0][1], sf[S0][2], sf[S0][3], fq[SM], fq[S1], a.frc,
+                                        po.p0 + cell);
             if (PAIR == 0) {
-                a.acc[idx] = accK + (dt / T(3)) * G;
-                a.out[idx] = cq[0] + (dt / T(2)) * G;
+                bst(a.acc, cb, po.p0 * E, ac[S0] + (dt / T(3)) * G);
+                bst(a.out, cb, po.p0 * E, cq[S0] + (dt / T(2)) * G);
                 if (a.part.p) {
-                    const double dv = ((double)kuxp - (double)kuxm) * g.inv2d[0] +
-                                      ((double)kvyp - (double)kvym) * g.inv2d[1] +
-                                      ((double)wq[2] - (double)wq[0]) * g.inv2d[2];
+                    const double dv = ((double)sx[S0][1] - (double)sx[S0][0]) * g.inv2d[0] +
+                                      ((double)sx[S0][3] - (double)sx[S0][2]) * g.inv2d[1] +
+                                      ((double)wq[S1] - (double)wq[SM]) * g.inv2d[2];
                     part.div2 += dv * dv;
                 }
             } else {
-                const T cnew = (fq[1] & F_FLUID) ? accK + (dt / T(6)) * G : T(0);
-                a.out[idx] = cnew;
+                const T cnew = (fq[S0] & F_FLUID) ? ac[S0] + (dt / T(6)) * G : T(0);
+                bst(a.out, cb, po.p0 * E, cnew);
                 if (a.part.p) {
-                    const double b = (fq[1] & F_FLUID) ? 1.0 : 0.0;
+                    const double b = (fq[S0] & F_FLUID) ? 1.0 : 0.0;
                     part.mass += b * (double)cnew;
-                    if (fq[1] & F_ROOM) { part.room_num += b * (double)cnew; part.room_den += b; }
+                    if (fq[S0] & F_ROOM) { part.room_num += b * (double)cnew; part.room_den += b; }
                 }
             }
         }
-        // 5. advance the queues
-#pragma unroll
-        for (int i = 0; i < 2 + D; ++i) { cq[i] = cq[i + 1]; rwq[i] = rwq[i + 1]; }
-#pragma unroll
-        for (int i = 0; i < 3 + D; ++i) { wq[i] = wq[i + 1]; fq[i] = fq[i + 1]; }
-        if (PAIR == 1) {
-#pragma unroll
-            for (int i = 0; i < D; ++i) { cnq[i] = cnq[i + 1]; rcnq[i] = rcnq[i + 1]; acq[i] = acq[i + 1]; }
-        }
-        c1z0 = c1z1; c1z1 = c1z2;
-        accK = accn;
-        kuxm = suxm; kuxp = suxp; kvym = svym; kvyp = svyp;
-        kfxm = sfxm; kfxp = sfxp; kfym = sfym; kfyp = sfyp;
+        po.advance();
+        ++r;
+        return true;
+    };
+    while (pair_phases(std::make_integer_sequence<int, U>{}, iter)) {
     }
     if (PAIR == 0 && a.part.p) block_reduce_partial<PM_DIV>(part, a.part, (int)bi.hw);
     if (PAIR == 1 && a.part.p) block_reduce_partial<PM_SCA>(part, a.part, (int)bi.hw);
@@ -1506,26 +1593,26 @@ __global__ __launch_bounds__(1024) void k_mom_stage_b(const BRec<MomArgs<T>>* __
     mom_stage_body<T, MODE, LDS>(a, bi_);
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) void k_mom_pair(const MomPairArgs<T> a) {
-    mom_pair_body<T, PAIR, pair_dist<T, true>()>(a, hw_block());
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_mom_pair(const MomPairArgs<T> a) {
+    mom_pair_body<T, PAIR, pair_dist<T, true>(), DNSLAB_PROWS>(a, hw_block());
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) void k_mom_pair_b(const BRec<MomPairArgs<T>>* __restrict__ tab,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_mom_pair_b(const BRec<MomPairArgs<T>>* __restrict__ tab,
                                                     const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const MomPairArgs<T> a = tab[s_].a;
-    mom_pair_body<T, PAIR, pair_dist<T, true>()>(a, bi_);
+    mom_pair_body<T, PAIR, pair_dist<T, true>(), DNSLAB_PROWS>(a, bi_);
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) void k_sca_pair(const ScaPairArgs<T> a) {
-    sca_pair_body<T, PAIR, pair_dist<T, false>()>(a, hw_block());
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_sca_pair(const ScaPairArgs<T> a) {
+    sca_pair_body<T, PAIR, pair_dist<T, false>(), DNSLAB_PROWS>(a, hw_block());
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) void k_sca_pair_b(const BRec<ScaPairArgs<T>>* __restrict__ tab,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_sca_pair_b(const BRec<ScaPairArgs<T>>* __restrict__ tab,
                                                     const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const ScaPairArgs<T> a = tab[s_].a;
-    sca_pair_body<T, PAIR, pair_dist<T, false>()>(a, bi_);
+    sca_pair_body<T, PAIR, pair_dist<T, false>(), DNSLAB_PROWS>(a, bi_);
 }
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) { sca_stage_body<T, MODE>(a, hw_block()); }
@@ -1664,7 +1751,7 @@ bool mom_pair_supported(const Grid& g, const StencilLaunch& L) {
     const int bx = (int)L.block.x, by = (int)L.block.y;
     // at most two halo cells of V per thread (4 (BX + 2) + 4 BY of them) and
     // one ring cell per thread (2 BX + 2 BY of them)
-    return bx == 64 && by * bx <= 512 && g.nx % bx == 0 && g.ny % by == 0 && 4 * (bx + 2) + 4 * by <= 2 * bx * by &&
+    return bx == 64 && by == DNSLAB_PROWS && g.nx % bx == 0 && g.ny % by == 0 && 4 * (bx + 2) + 4 * by <= 2 * bx * by &&
            2 * (bx + by) <= bx * by;
 }
 
