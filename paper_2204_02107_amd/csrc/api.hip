@@ -167,9 +167,6 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_KC
 #define DNSLAB_KC 0            // z cells per thread (0: from the grid size)
 #endif
-#ifndef DNSLAB_FROWS
-#define DNSLAB_FROWS 8         // block height of the radius-3 filter
-#endif
 #ifndef DNSLAB_FKC
 #define DNSLAB_FKC 0
 #endif

@@ -169,6 +169,11 @@ StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x);
 // records the launch (for batched replay by the pool) without issuing it.
 template <typename T> hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s,
                                                   Recorder* rec = nullptr);
+// Block height of the radius-3 filter (64 x DNSLAB_FROWS tiles; the
+// register-ring filter is compiled for this height).
+#ifndef DNSLAB_FROWS
+#define DNSLAB_FROWS 8
+#endif
 // Rows of the 64-wide tile of the stage-pair kernels (a compile-time tile
 // shape: the kernels' LDS offsets are immediates).
 #ifndef DNSLAB_PROWS

@@ -27,10 +27,14 @@ namespace {
 #ifndef DNSLAB_FILTER_LDS
 #define DNSLAB_FILTER_LDS 1
 #endif
+#ifndef DNSLAB_FILTER_RING
+#define DNSLAB_FILTER_RING 1
+#endif
 #ifndef DNSLAB_STENCIL_LDS
 #define DNSLAB_STENCIL_LDS 1
 #endif
 constexpr int FILT_LDS = 16;   // filter kind mode bit: LDS-tiled variant
+constexpr int FILT_RING = 32;  // filter kind mode bit: LDS-tiled variant with register rings
 constexpr int STAGE_LDS = 8;   // RK4 stage kind mode bit: LDS-tiled variant
 
 constexpr double INV_PI6 = 1.0 / (3.14159265358979323846 * 3.14159265358979323846 *
@@ -630,34 +634,34 @@ __device__ __forceinline__ void mom_pair_body(const MomPairArgs<T>& a, const Blo
             for (int h = 0; h < HM; ++h)
                 if (h < hm.n) Vq[c * TV + hd[h]] = hq[S2][c][h];
         }
-        // 2. loads D planes ahead: v and halo of plane K + 2 + D, the rest of plane K + 1 + D.
-        // Every slot written here is written on all paths (zero where no load
-        // is due), so that the value it held U planes earlier is dead.
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            vq[SD2][c] = T(0); unq[SD1][c] = T(0); runq[SD1][c] = T(0); acq[SD1][c] = T(0);
-#pragma unroll
-            for (int h = 0; h < HM; ++h) hq[SD2][c][h] = T(0);
-        }
-        fq[SD1] = 0;
-        rfq[SD1] = 0;
-        if (K + D < k1) {
+        // 2. loads D planes ahead: v and halo of plane K + 2 + D, the rest of
+        // plane K + 1 + D.  Past the chunk's last plane the loads still run,
+        // from plane K (valid memory, never used): a slot written on every
+        // path leaves its value of U planes earlier dead, and no branch or
+        // select on the loaded values is needed.
+        {
+            const bool more = K + D < k1;
+            const unsigned sv = (more ? po.pd2 : po.p0) * E, sr = (more ? po.pd1 : po.p0) * E;
+            const unsigned fr = more ? po.pd1 : po.p0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const unsigned sv = po.pd2 * E;
                 vq[SD2][c] = bld(a.vin[c], cb, sv);
 #pragma unroll
-                for (int h = 0; h < HM; ++h)
+                for (int h = 0; h < HM; ++h) {
+                    hq[SD2][c][h] = T(0);
                     if (h < hm.n) hq[SD2][c][h] = bld(a.vin[c], hb[h], sv);
+                }
             }
-            fq[SD1] = bld(a.flags, cell, po.pd1);
-            if (ring) rfq[SD1] = bld(a.flags, rcell, po.pd1);
+            fq[SD1] = bld(a.flags, cell, fr);
+            rfq[SD1] = 0;
+            if (ring) rfq[SD1] = bld(a.flags, rcell, fr);
             if (PAIR == 1) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    unq[SD1][c] = bld(a.un[c], cb, po.pd1 * E);
-                    if (ring) runq[SD1][c] = bld(a.un[c], rcb, po.pd1 * E);
-                    if (K + 1 + D >= k0 && K + 1 + D < k1) acq[SD1][c] = bld(a.accin[c], cb, po.pd1 * E);
+                    unq[SD1][c] = bld(a.un[c], cb, sr);
+                    runq[SD1][c] = T(0);
+                    if (ring) runq[SD1][c] = bld(a.un[c], rcb, sr);
+                    acq[SD1][c] = bld(a.accin[c], cb, sr);
                 }
             }
         }
@@ -1000,33 +1004,33 @@ __device__ __forceinline__ void sca_pair_body(const ScaPairArgs<T>& a, const Blo
                 Vs[bq * TV + hd[h]] = hv[S2][h];
                 Fs[bq * TV + hd[h]] = hf[S2][h];
             }
-        // 2. loads D planes ahead (every slot written on all paths, as in
+        // 2. loads D planes ahead (past the chunk's end from plane K, as in
         // mom_pair_body)
-        cq[SD2] = T(0); wq[SD2] = T(0); uq[SD2] = T(0); vq[SD2] = T(0); rwq[SD2] = T(0);
-        cnq[SD1] = T(0); rcnq[SD1] = T(0); acq[SD1] = T(0);
-        fq[SD2] = 0;
-#pragma unroll
-        for (int h = 0; h < HM; ++h) { hc[SD2][h] = T(0); hu[SD2][h] = T(0); hv[SD2][h] = T(0); hf[SD2][h] = 0; }
-        if (K + D < k1) {
-            const unsigned pv = po.pd2, pr = po.pd1;
+        {
+            const bool more = K + D < k1;
+            const unsigned pv = more ? po.pd2 : po.p0, pr = more ? po.pd1 : po.p0;
             cq[SD2] = bld(a.cin, cb, pv * E);
             wq[SD2] = bld(uz, cb, pv * E);
             fq[SD2] = bld(a.flags, cell, pv);
             uq[SD2] = bld(ux, cb, pv * E);
             vq[SD2] = bld(uy, cb, pv * E);
 #pragma unroll
-            for (int h = 0; h < HM; ++h)
+            for (int h = 0; h < HM; ++h) {
+                hc[SD2][h] = T(0); hu[SD2][h] = T(0); hv[SD2][h] = T(0); hf[SD2][h] = 0;
                 if (h < hm.n) {
                     hc[SD2][h] = bld(a.cin, hb[h], pv * E);
                     hu[SD2][h] = bld(ux, hb[h], pv * E);
                     hv[SD2][h] = bld(uy, hb[h], pv * E);
                     hf[SD2][h] = bld(a.flags, hm.src[h], pv);
                 }
+            }
+            rwq[SD2] = T(0);
             if (ring) rwq[SD2] = bld(uz, rcb, pv * E);
             if (PAIR == 1) {
                 cnq[SD1] = bld(a.cn, cb, pr * E);
+                rcnq[SD1] = T(0);
                 if (ring) rcnq[SD1] = bld(a.cn, rcb, pr * E);
-                if (K + 1 + D >= k0 && K + 1 + D < k1) acq[SD1] = bld(a.accin, cb, pr * E);
+                acq[SD1] = bld(a.accin, cb, pr * E);
             }
         }
         __syncthreads();
@@ -1272,6 +1276,135 @@ __device__ __forceinline__ void filter_lds_body(const FiltArgs<T>& a, const Bloc
                 if (fl & F_ROOM) { part.room_num += b * c; part.room_den += b; }
             }
         }
+    }
+    if (a.part.p) block_reduce_partial<NF == 3 ? PM_VEL : PM_SCA>(part, a.part, (int)bi.hw);
+}
+
+// The LDS filter with the pair kernels' register rings (filter_lds_body's
+// arithmetic, in the same order): the z window of each field, the flags and
+// the x/y halo live in rings indexed by the march position, over a z loop
+// unrolled U times, and every access is a raw buffer access with a scalar
+// plane offset.  The tile is 64 x BY (compile time), so LDS offsets are
+// immediates.
+template <typename T, int NF, int BY>
+__device__ __forceinline__ void filter_ring_body(const FiltArgs<T>& a, const BlockIdx3& bi) {
+    constexpr int BX = 64, W = BX + 6, H = BY + 6, TSZ = W * H;
+    constexpr int U = 8;                                   // window (7 planes) and its prefetch
+    constexpr int HM = (6 * (BX + BY) + BX * BY - 1) / (BX * BY);
+    constexpr unsigned E = sizeof(T);
+    extern __shared__ unsigned char smem_raw[];
+    T* const lds = reinterpret_cast<T*>(smem_raw);        // [2 planes][NF][TSZ]
+    const Grid& g = a.g;
+    const Col col = column(g, a.kc, bi);
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty;
+    const int i0 = col.i - tx, j0 = col.j - ty;
+    const unsigned cell = col.row + col.i, cb = cell * E;
+    const T c6 = T(INV_PI6);
+    Partial part = {0, 0, 0, 0, 0, 0};
+    const int dir = col.dir, k0 = col.k0, k1 = col.k1;
+    const int ks = dir > 0 ? k0 : k1 - 1;
+    const int n = k1 - k0;
+    const HaloMap<HM> hm = halo_map<3, HM>(i0, j0, g, BX, 6, BY, tid, BX * BY);
+    unsigned hb[HM];
+#pragma unroll
+    for (int h = 0; h < HM; ++h) hb[h] = hm.src[h] * E;
+    const int cc0 = (ty + 3) * W + tx + 3;
+    const unsigned nxy = (unsigned)g.nxy, ntot = (unsigned)g.nz * nxy;
+    auto pl = [&](int m) -> unsigned { return (unsigned)wrap(ks + m * dir, g.nz) * nxy; };
+    auto step = [&](unsigned p) -> unsigned {
+        return dir > 0 ? (p + nxy == ntot ? 0u : p + nxy) : (p == 0 ? ntot - nxy : p - nxy);
+    };
+    // rings by march position m (plane ks + m dir): win (the z window and
+    // its prefetch, positions r-3 .. r+4 at iteration r), fq (flags), hv
+    // (x/y halo, positions r and r+1)
+    T win[NF][U], hv[NF][2][HM];
+    uint8_t fq[U];
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+        fq[s] = 0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) win[f][s] = T(0);
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int m = -3; m <= 4; ++m) win[f][(m + U) % U] = bld(a.in[f], cb, pl(m) * E);
+#pragma unroll
+        for (int h = 0; h < HM; ++h) {
+            hv[f][0][h] = bld(a.in[f], hb[h], pl(0) * E);   // (lanes without a halo cell read cell 0)
+            hv[f][1][h] = T(0);
+        }
+    }
+    fq[0] = bld(a.flags, cell, pl(0));
+    unsigned p0 = pl(0), p1 = pl(1), p5 = pl(5);   // planes of positions r, r + 1, r + 5
+    int r = 0;
+    auto iter = [&](auto phase) __attribute__((always_inline)) -> bool {
+        constexpr int P = decltype(phase)::value;
+        constexpr int B = P & 1;
+        if (r >= n) return false;
+        const int cc = opaque(cc0);
+        int hd[HM];
+#pragma unroll
+        for (int h = 0; h < HM; ++h) hd[h] = opaque(hm.dst[h]);
+        T* const tb = lds + B * NF * TSZ;
+        // stage this plane: interior from the window, halo from the prefetch
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            tb[f * TSZ + cc] = win[f][P % U];
+#pragma unroll
+            for (int h = 0; h < HM; ++h)
+                if (h < hm.n) tb[f * TSZ + hd[h]] = hv[f][B][h];
+        }
+        // the next plane's halo and flags; on the chunk's last plane the
+        // loads still run, from this plane (valid memory, never used), so that
+        // no branch, and no select that the compiler could fold into the
+        // flag tests (which would wait for the load at once), is needed
+        const bool more = r + 1 < n;
+        const unsigned q1 = more ? p1 : p0, q5 = more ? p5 : p0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int h = 0; h < HM; ++h) hv[f][B ^ 1][h] = bld(a.in[f], hb[h], q1 * E);
+        fq[(P + 1) % U] = bld(a.flags, cell, q1);
+        __syncthreads();
+        const uint8_t fl = fq[P % U];
+        T res[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const T f0 = win[f][P % U];
+            const T* rowp = tb + f * TSZ + cc - 3;        // rowp[m] = x offset m - 3
+            const T* colp = tb + f * TSZ + cc - 3 * W;    // colp[m W] = y offset m - 3
+            const T dx6 = (rowp[0] + rowp[6]) - T(6) * (rowp[1] + rowp[5]) +
+                          T(15) * (rowp[2] + rowp[4]) - T(20) * f0;
+            const T dy6 = (colp[0] + colp[6 * W]) - T(6) * (colp[W] + colp[5 * W]) +
+                          T(15) * (colp[2 * W] + colp[4 * W]) - T(20) * f0;
+            const T dz6 = (win[f][(P + U - 3) % U] + win[f][(P + 3) % U]) -
+                          T(6) * (win[f][(P + U - 2) % U] + win[f][(P + 2) % U]) +
+                          T(15) * (win[f][(P + U - 1) % U] + win[f][(P + 1) % U]) - T(20) * f0;
+            res[f] = (fl & F_FLUID) ? f0 + c6 * (dx6 + dy6 + dz6) : T(0);
+            bst(a.out[f], cb, p0 * E, res[f]);
+            // the window's next plane (position r + 5, into the slot of r - 3)
+            win[f][(P + 5) % U] = bld(a.in[f], cb, q5 * E);
+        }
+        if (a.part.p) {
+            const double b = (fl & F_FLUID) ? 1.0 : 0.0;
+            if (NF == 3) {
+                const double u = (double)res[0], v = (double)res[1], w = (double)res[2];
+                part.ke += b * (u * u + v * v + w * w);
+                part.rate = fmax(part.rate, courant_rate(u, v, w, g));
+            } else {
+                const double c = (double)res[0];
+                part.mass += b * c;
+                if (fl & F_ROOM) { part.room_num += b * c; part.room_den += b; }
+            }
+        }
+        p0 = step(p0);
+        p1 = step(p1);
+        p5 = step(p5);
+        ++r;
+        return true;
+    };
+    while (pair_phases(std::make_integer_sequence<int, U>{}, iter)) {
     }
     if (a.part.p) block_reduce_partial<NF == 3 ? PM_VEL : PM_SCA>(part, a.part, (int)bi.hw);
 }
@@ -1641,6 +1774,17 @@ __global__ __launch_bounds__(1024) void k_filter_lds_b(const BRec<FiltArgs<T>>* 
     const FiltArgs<T> a = tab[s_].a;
     filter_lds_body<T, NF>(a, bi_);
 }
+template <typename T, int NF>
+__global__ __launch_bounds__(512) void k_filter_ring(const FiltArgs<T> a) {
+    filter_ring_body<T, NF, DNSLAB_FROWS>(a, hw_block());
+}
+template <typename T, int NF>
+__global__ __launch_bounds__(512) void k_filter_ring_b(const BRec<FiltArgs<T>>* __restrict__ tab,
+                                                       const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const FiltArgs<T> a = tab[s_].a;
+    filter_ring_body<T, NF, DNSLAB_FROWS>(a, bi_);
+}
 template <typename T>
 __global__ __launch_bounds__(1024) void k_correct(const CorrArgs<T> a) { correct_body<T>(a, hw_block()); }
 template <typename T>
@@ -1808,16 +1952,21 @@ template <typename T>
 hipError_t launch_filter(const FiltArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     FiltArgs<T> b = a;
     b.kc = L.kc;
-    // the LDS-tiled variant when the tile divides the grid in x and y
+    // the LDS-tiled variant when the tile divides the grid in x and y; its
+    // register-ring form for the 64 x DNSLAB_FROWS tile
     const bool use_lds = DNSLAB_FILTER_LDS && tile_divides(a.g, L, 3);
+    const bool use_ring = use_lds && DNSLAB_FILTER_RING && L.block.x == 64 && L.block.y == DNSLAB_FROWS;
     const int nf = a.nf == 3 ? 3 : 1;
     const size_t lds = use_lds ? (size_t)2 * nf * (L.block.x + 6) * (L.block.y + 6) * sizeof(T) : 0;
     if (rec) {
-        record_launch(rec, kind_code(KK_FILT, (a.nf == 3 ? 3 : 1) | (use_lds ? FILT_LDS : 0), sizeof(T) == 4), L.grid,
-                      L.block, lds, b);
+        record_launch(rec, kind_code(KK_FILT, (a.nf == 3 ? 3 : 1) | (use_lds ? FILT_LDS : 0) | (use_ring ? FILT_RING : 0),
+                                     sizeof(T) == 4), L.grid, L.block, lds, b);
         return hipSuccess;
     }
-    if (use_lds) {
+    if (use_ring) {
+        if (a.nf == 3) hipLaunchKernelGGL((k_filter_ring<T, 3>), L.grid, L.block, lds, s, b);
+        else hipLaunchKernelGGL((k_filter_ring<T, 1>), L.grid, L.block, lds, s, b);
+    } else if (use_lds) {
         if (a.nf == 3) hipLaunchKernelGGL((k_filter_lds<T, 3>), L.grid, L.block, lds, s, b);
         else hipLaunchKernelGGL((k_filter_lds<T, 1>), L.grid, L.block, lds, s, b);
     } else {
@@ -1954,7 +2103,10 @@ hipError_t batched_typed(int base, int mode, const void* tab, const unsigned* st
         case KK_FILT: {
             auto t = (const BRec<FiltArgs<T>>*)tab;
             const bool three = (mode & 7) == 3;
-            if (mode & FILT_LDS) {
+            if (mode & FILT_RING) {
+                if (three) hipLaunchKernelGGL((k_filter_ring_b<T, 3>), grid, blk, lds, s, t, st, ns);
+                else hipLaunchKernelGGL((k_filter_ring_b<T, 1>), grid, blk, lds, s, t, st, ns);
+            } else if (mode & FILT_LDS) {
                 if (three) hipLaunchKernelGGL((k_filter_lds_b<T, 3>), grid, blk, lds, s, t, st, ns);
                 else hipLaunchKernelGGL((k_filter_lds_b<T, 1>), grid, blk, lds, s, t, st, ns);
             } else {
