@@ -102,7 +102,8 @@ struct Layout {
     int yz, lg_ca, lg_cb;  // fused plane pass (plane-major spectrum) and its LDS chunks
     AxisPlan px, py, pz;
     StencilLaunch L;       // momentum and scalar stage kernels
-    StencilLaunch L1;      // one-cell-per-thread kernels (correct, div, rate)
+    StencilLaunch L1;      // one-cell-per-thread kernels (div, refinement residual, rate)
+    StencilLaunch LC;      // the velocity correction (64 x DNSLAB_FROWS tiles: its register-ring form)
     StencilLaunch LF;      // filter
     StencilLaunch LP;      // fused RK4 stage pairs
     int nparts;            // partial-result slots (max block count of the reducing kernels)
@@ -170,11 +171,16 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_FKC
 #define DNSLAB_FKC 0
 #endif
+// Least z cells per thread of the filter (and of the correction, divergence
+// and refinement residual, which share its launch): the radius-3 filter
+// re-reads 6 halo planes per chunk.  24 in both forms since the filter runs
+// as a register-ring march (512x256x192: filter 345 -> 305 us FP64,
+// 191 -> 172 us FP32; 1024x512x256 already has 32).
 #ifndef DNSLAB_FKC_MIN
-#define DNSLAB_FKC_MIN 12       // least z cells per thread of the filter (FP64)
+#define DNSLAB_FKC_MIN 24
 #endif
 #ifndef DNSLAB_FKC_MIN32
-#define DNSLAB_FKC_MIN32 8      // the same for the FP32 form (half the bytes per cell: more, shorter chunks)
+#define DNSLAB_FKC_MIN32 24
 #endif
 // FFT passes: x lines per block grow while the block stays within these
 // threads and LDS bytes; y/z column tiles within this much LDS.
@@ -338,6 +344,7 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
         const long long pkc = std::max(8LL, std::min(32LL, (long long)g.nz * cols / DNSLAB_PKC_DIV));
         Lo.LP = stencil_launch(g, DNSLAB_PROWS, (int)std::min<long long>(pkc, g.nz), 1);
     }
+    Lo.LC = Lo.LF;
     Lo.nparts = std::max(std::max(std::max(Lo.L.nblocks, Lo.L1.nblocks), Lo.LF.nblocks), Lo.LP.nblocks);
     // workspace layout
     size_t off = 0;
@@ -628,7 +635,7 @@ int project_correct(dnslab_ctx* x, const T* const us[3], T* const out[3], PartSo
             rc2.flags = x->flags;
             rc2.g = x->g;
             rc2.part = part;
-            LAUNCH(x, K_CORR, launch_refine_correct(rc2, x->Lo.L1, x->cur, x->rec));
+            LAUNCH(x, K_CORR, launch_refine_correct(rc2, x->Lo.LC, x->cur, x->rec));
             return DNSLAB_OK;
         }
     }
@@ -638,7 +645,7 @@ int project_correct(dnslab_ctx* x, const T* const us[3], T* const out[3], PartSo
     ca.flags = x->flags;
     ca.g = x->g;
     ca.part = part;
-    LAUNCH(x, K_CORR, launch_correct<T>(ca, x->Lo.L1, x->cur, x->rec));
+    LAUNCH(x, K_CORR, launch_correct<T>(ca, x->Lo.LC, x->cur, x->rec));
     return DNSLAB_OK;
 }
 
@@ -763,7 +770,7 @@ int scalar_half(dnslab_ctx* x) {
     }
     DiagArgs d;
     d.part = x->part;
-    d.np_vel = filt ? x->Lo.LF.nblocks : x->Lo.L1.nblocks;
+    d.np_vel = filt ? x->Lo.LF.nblocks : x->Lo.LC.nblocks;
     d.np_sca = filt ? x->Lo.LF.nblocks : sca_nblocks(x);
     d.np_div = sca_nblocks(x);
     d.sc = x->sc;
@@ -919,7 +926,7 @@ int one_step(dnslab_ctx* x) {
     }
     AdvanceArgs av;
     av.part = x->part;
-    av.np = filt ? x->Lo.LF.nblocks : x->Lo.L1.nblocks;
+    av.np = filt ? x->Lo.LF.nblocks : x->Lo.LC.nblocks;
     av.sc = x->sc;
     LAUNCH(x, K_ADV, launch_advance(av, x->cur, x->rec));
     if (defer) {

@@ -30,6 +30,17 @@ namespace {
 #ifndef DNSLAB_FILTER_RING
 #define DNSLAB_FILTER_RING 1
 #endif
+#ifndef DNSLAB_CORRECT_RING
+#define DNSLAB_CORRECT_RING 1
+#endif
+// Prefetch distance, in planes, of the register-ring correction (little
+// arithmetic per plane to cover the loads).  Register-ring forms of the
+// divergence and of the refinement residual (one cell per thread, 1024-thread
+// blocks, no LDS) were measured and dropped: 882 -> 901 us and 809 -> 878 us
+// on 1024x512x256.
+#ifndef DNSLAB_RING_DIST
+#define DNSLAB_RING_DIST 3
+#endif
 #ifndef DNSLAB_STENCIL_LDS
 #define DNSLAB_STENCIL_LDS 1
 #endif
@@ -1449,6 +1460,138 @@ __device__ __forceinline__ void correct_body(const CorrArgs<T>& a, const BlockId
     if (a.part.p) block_reduce_partial<PM_VEL>(part, a.part, (int)bi.hw);
 }
 
+// Velocity correction (correct_body, or refine_correct_body when REFINE: the
+// pressure is p4 + dp in FP64 and is written back) as a register-ring march
+// over 64 x BY tiles: the pressure of each plane is staged in LDS with its
+// one-cell x/y halo, its z neighbours come from a ring, the next plane's
+// u*, flags and halo and the pressure two planes ahead are in flight while a
+// plane is corrected, and every access is a raw buffer access with a scalar
+// plane offset.  Same arithmetic as the plain kernels.
+template <typename T, bool REFINE>
+struct CorrRingIO;
+template <typename T>
+struct CorrRingIO<T, false> {
+    using Q = T;
+    const T* p;
+    __device__ __forceinline__ Q q(unsigned voff, unsigned plane) const { return bld(p, voff * sizeof(T), plane * sizeof(T)); }
+};
+template <typename T>
+struct CorrRingIO<T, true> {
+    using Q = double;
+    const float* p4;
+    const float* dp;
+    __device__ __forceinline__ Q q(unsigned voff, unsigned plane) const {
+        return (double)bld(p4, voff * 4u, plane * 4u) + (double)bld(dp, voff * 4u, plane * 4u);
+    }
+};
+template <typename T, bool REFINE, int BY, int D>
+__device__ __forceinline__ void correct_ring_body(const T* const us[3], T* const out[3], const CorrRingIO<T, REFINE> io,
+                                                  float* pout, const uint8_t* flags, const Grid& g, int kc,
+                                                  const PartSoA& pa, const BlockIdx3& bi) {
+    using Q = typename CorrRingIO<T, REFINE>::Q;
+    constexpr int BX = 64, W = BX + 2, TS = W * (BY + 2);
+    constexpr int U = (D + 4) & ~1;                     // even, >= D + 3
+    constexpr int HM = (2 * (BX + BY) + BX * BY - 1) / (BX * BY);
+    constexpr unsigned E = sizeof(T);
+    extern __shared__ unsigned char smem_raw[];
+    Q* const lds = reinterpret_cast<Q*>(smem_raw);     // [2 planes][TS]
+    const Col col = column(g, kc, bi);
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + BX * ty;
+    const int i0 = col.i - tx, j0 = col.j - ty;
+    const unsigned cell = col.row + col.i, cb = cell * E;
+    const int k0 = col.k0, k1 = col.k1, n = k1 - k0;
+    const HaloMap<HM> hm = halo_map<1, HM>(i0, j0, g, BX, 6, BY, tid, BX * BY);
+    const int cc0 = (ty + 1) * W + tx + 1;
+    const unsigned nxy = (unsigned)g.nxy, ntot = (unsigned)g.nz * nxy;
+    auto pl = [&](int k) -> unsigned { return (unsigned)wrap(k, g.nz) * nxy; };
+    auto step = [&](unsigned p) -> unsigned { return p + nxy == ntot ? 0u : p + nxy; };
+    Partial part = {0, 0, 0, 0, 0, 0};
+    // rings by plane position m (plane k0 + m): pz (pressure at the cell,
+    // positions r-1 .. r+1+D), uq and fq (u* and flags, r .. r+D), hv (the
+    // pressure halo, r .. r+D); loads run D planes ahead
+    Q pz[U], hv[U][HM];
+    T uq[U][3];
+    uint8_t fq[U];
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+        pz[s] = Q(0);
+        fq[s] = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uq[s][c] = T(0);
+#pragma unroll
+        for (int h = 0; h < HM; ++h) hv[s][h] = Q(0);
+    }
+#pragma unroll
+    for (int m = -1; m <= D; ++m) pz[(m + U) % U] = io.q(cell, pl(k0 + m));
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+        const unsigned pm = pl(k0 + m);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uq[m][c] = bld(us[c], cb, pm * E);
+        fq[m] = bld(flags, cell, pm);
+#pragma unroll
+        for (int h = 0; h < HM; ++h) hv[m][h] = io.q(hm.src[h], pm);   // (lanes without a halo cell read cell 0)
+    }
+    unsigned p0 = pl(k0), pd = pl(k0 + D), pd1 = pl(k0 + D + 1);
+    int r = 0;
+    auto iter = [&](auto phase) __attribute__((always_inline)) -> bool {
+        constexpr int P = decltype(phase)::value;
+        constexpr int B = P & 1;
+        if (r >= n) return false;
+        const int cc = opaque(cc0);
+        int hd[HM];
+#pragma unroll
+        for (int h = 0; h < HM; ++h) hd[h] = opaque(hm.dst[h]);
+        Q* const tb = lds + B * TS;
+        tb[cc] = pz[P % U];
+#pragma unroll
+        for (int h = 0; h < HM; ++h)
+            if (h < hm.n) tb[hd[h]] = hv[P % U][h];
+        // u*, flags and halo of plane r + D, the pressure of plane r + 1 + D
+        // (past the chunk's end from this plane: valid memory, never used)
+        const bool more = r + D < n;
+        const unsigned q1 = more ? pd : p0, q2 = more ? pd1 : p0;
+#pragma unroll
+        for (int h = 0; h < HM; ++h) hv[(P + D) % U][h] = io.q(hm.src[h], q1);
+        pz[(P + 1 + D) % U] = io.q(cell, q2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uq[(P + D) % U][c] = bld(us[c], cb, q1 * E);
+        fq[(P + D) % U] = bld(flags, cell, q1);
+        __syncthreads();
+        const bool fluid = fq[P % U] & F_FLUID;
+        const Q gx = (tb[cc + 1] - tb[cc - 1]) * Q(g.inv2d[0]);
+        const Q gy = (tb[cc + W] - tb[cc - W]) * Q(g.inv2d[1]);
+        const Q gz = (pz[(P + 1) % U] - pz[(P + U - 1) % U]) * Q(g.inv2d[2]);
+        T o[3];
+        if (REFINE) {
+            const double u = uq[P % U][0], v = uq[P % U][1], w = uq[P % U][2];
+            o[0] = fluid ? (T)(u - gx) : T(0);
+            o[1] = fluid ? (T)(v - gy) : T(0);
+            o[2] = fluid ? (T)(w - gz) : T(0);
+            bst(pout, cell * 4u, p0 * 4u, (float)pz[P % U]);
+        } else {
+            o[0] = fluid ? uq[P % U][0] - (T)gx : T(0);
+            o[1] = fluid ? uq[P % U][1] - (T)gy : T(0);
+            o[2] = fluid ? uq[P % U][2] - (T)gz : T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bst(out[c], cb, p0 * E, o[c]);
+        if (pa.p) {
+            const double ud = (double)o[0], vd = (double)o[1], wd = (double)o[2];
+            part.ke += fluid ? ud * ud + vd * vd + wd * wd : 0.0;
+            part.rate = fmax(part.rate, courant_rate(ud, vd, wd, g));
+        }
+        p0 = step(p0);
+        pd = step(pd);
+        pd1 = step(pd1);
+        ++r;
+        return true;
+    };
+    while (pair_phases(std::make_integer_sequence<int, U>{}, iter)) {
+    }
+    if (pa.p) block_reduce_partial<PM_VEL>(part, pa, (int)bi.hw);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 residual of the last FP32 pressure solve (iterative refinement):
 // res = div u* + div((1-beta) grad p3) - div grad p4, all in FP64.  The
@@ -1817,6 +1960,36 @@ __global__ __launch_bounds__(256) void k_refine_res_ib_b(const BRec<RefineResArg
     const RefineResArgs a = tab[s_].a;
     refine_res_ib_body(a, blockIdx.x - st[s_]);
 }
+template <typename T>
+__device__ __forceinline__ void correct_ring(const CorrArgs<T>& a, const BlockIdx3& bi) {
+    CorrRingIO<T, false> io;
+    io.p = a.p;
+    correct_ring_body<T, false, DNSLAB_FROWS, DNSLAB_RING_DIST>(a.us, a.out, io, nullptr, a.flags, a.g, a.kc, a.part, bi);
+}
+__device__ __forceinline__ void refine_correct_ring(const RefineCorrArgs& a, const BlockIdx3& bi) {
+    CorrRingIO<float, true> io;
+    io.p4 = a.p4;
+    io.dp = a.dp;
+    correct_ring_body<float, true, DNSLAB_FROWS, DNSLAB_RING_DIST>(a.us, a.out, io, a.p, a.flags, a.g, a.kc, a.part, bi);
+}
+template <typename T>
+__global__ __launch_bounds__(512) void k_correct_ring(const CorrArgs<T> a) { correct_ring<T>(a, hw_block()); }
+template <typename T>
+__global__ __launch_bounds__(512) void k_correct_ring_b(const BRec<CorrArgs<T>>* __restrict__ tab,
+                                                        const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const CorrArgs<T> a = tab[s_].a;
+    correct_ring<T>(a, bi_);
+}
+__global__ __launch_bounds__(512) void k_refine_correct_ring(const RefineCorrArgs a) {
+    refine_correct_ring(a, hw_block());
+}
+__global__ __launch_bounds__(512) void k_refine_correct_ring_b(const BRec<RefineCorrArgs>* __restrict__ tab,
+                                                               const unsigned* __restrict__ st, int ns) {
+    DNSLAB_BATCH_COORD(tab, st, ns)
+    const RefineCorrArgs a = tab[s_].a;
+    refine_correct_ring(a, bi_);
+}
 __global__ __launch_bounds__(1024) void k_refine_correct(const RefineCorrArgs a) {
     refine_correct_body(a, hw_block());
 }
@@ -1857,6 +2030,12 @@ StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x) {
     return L;
 }
 
+
+// The register-ring correction: 64 x DNSLAB_FROWS tiles dividing the grid.
+inline bool correct_ring_fits(const Grid& g, const StencilLaunch& L) {
+    return DNSLAB_CORRECT_RING && L.block.x == 64 && L.block.y == DNSLAB_FROWS && g.nx % 64 == 0 &&
+           g.ny % DNSLAB_FROWS == 0;
+}
 
 // LDS variants of the z-marching kernels need the block's tile inside the grid.
 // radius: the halo width; every thread loads at most two halo cells per field.
@@ -1980,11 +2159,14 @@ template <typename T>
 hipError_t launch_correct(const CorrArgs<T>& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     CorrArgs<T> b = a;
     b.kc = L.kc;
+    const bool ring = correct_ring_fits(a.g, L);
+    const size_t lds = ring ? (size_t)2 * (L.block.x + 2) * (L.block.y + 2) * sizeof(T) : 0;
     if (rec) {
-        record_launch(rec, kind_code(KK_CORR, 0, sizeof(T) == 4), L.grid, L.block, 0, b);
+        record_launch(rec, kind_code(KK_CORR, ring ? 1 : 0, sizeof(T) == 4), L.grid, L.block, lds, b);
         return hipSuccess;
     }
-    hipLaunchKernelGGL((k_correct<T>), L.grid, L.block, 0, s, b);
+    if (ring) hipLaunchKernelGGL((k_correct_ring<T>), L.grid, L.block, lds, s, b);
+    else hipLaunchKernelGGL((k_correct<T>), L.grid, L.block, 0, s, b);
     return hipGetLastError();
 }
 
@@ -2024,11 +2206,14 @@ hipError_t launch_refine_res(const RefineResArgs& a, const StencilLaunch& L, hip
 hipError_t launch_refine_correct(const RefineCorrArgs& a, const StencilLaunch& L, hipStream_t s, Recorder* rec) {
     RefineCorrArgs b = a;
     b.kc = L.kc;
+    const bool ring = correct_ring_fits(a.g, L);
+    const size_t lds = ring ? (size_t)2 * (L.block.x + 2) * (L.block.y + 2) * sizeof(double) : 0;
     if (rec) {
-        record_launch(rec, kind_code(KK_REFCORR, 0, 1), L.grid, L.block, 0, b);
+        record_launch(rec, kind_code(KK_REFCORR, ring ? 1 : 0, 1), L.grid, L.block, lds, b);
         return hipSuccess;
     }
-    hipLaunchKernelGGL(k_refine_correct, L.grid, L.block, 0, s, b);
+    if (ring) hipLaunchKernelGGL(k_refine_correct_ring, L.grid, L.block, lds, s, b);
+    else hipLaunchKernelGGL(k_refine_correct, L.grid, L.block, 0, s, b);
     return hipGetLastError();
 }
 
@@ -2116,7 +2301,10 @@ hipError_t batched_typed(int base, int mode, const void* tab, const unsigned* st
             break;
         }
         case KK_CORR:
-            hipLaunchKernelGGL((k_correct_b<T>), grid, blk, 0, s, (const BRec<CorrArgs<T>>*)tab, st, ns);
+            if (mode == 1)
+                hipLaunchKernelGGL((k_correct_ring_b<T>), grid, blk, lds, s, (const BRec<CorrArgs<T>>*)tab, st, ns);
+            else
+                hipLaunchKernelGGL((k_correct_b<T>), grid, blk, 0, s, (const BRec<CorrArgs<T>>*)tab, st, ns);
             break;
         case KK_DIV:
             hipLaunchKernelGGL((k_div_b<T>), grid, blk, 0, s, (const BRec<DivArgs<T>>*)tab, st, ns);
@@ -2137,7 +2325,10 @@ hipError_t launch_batched_stencil(int kind, const void* tab, const unsigned* st,
         return hipGetLastError();
     }
     if (base == KK_REFCORR) {
-        hipLaunchKernelGGL(k_refine_correct_b, dim3(nb), blk, 0, s, (const BRec<RefineCorrArgs>*)tab, st, ns);
+        if (mode == 1)
+            hipLaunchKernelGGL(k_refine_correct_ring_b, dim3(nb), blk, lds, s, (const BRec<RefineCorrArgs>*)tab, st, ns);
+        else
+            hipLaunchKernelGGL(k_refine_correct_b, dim3(nb), blk, 0, s, (const BRec<RefineCorrArgs>*)tab, st, ns);
         return hipGetLastError();
     }
     if (base == KK_ADVANCE) {
