@@ -171,8 +171,11 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_FKC
 #define DNSLAB_FKC 0
 #endif
-// Least z cells per thread of the filter (and of the correction, divergence
-// and refinement residual, which share its launch): the radius-3 filter
+#ifndef DNSLAB_XLS_MOD
+#define DNSLAB_XLS_MOD 2       // x-pass LDS line stride modulo 16 (make_layout)
+#endif
+// Least z cells per thread of the filter (and of the velocity correction,
+// which shares its launch): the radius-3 filter
 // re-reads 6 halo planes per chunk.  24 in both forms since the filter runs
 // as a register-ring march (512x256x192: filter 345 -> 305 us FP64,
 // 191 -> 172 us FP32; 1024x512x256 already has 32).
@@ -264,7 +267,17 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     Lo.px = make_axis_plan(Lo.m);
     Lo.py = make_axis_plan(P->ny);
     Lo.pz = make_axis_plan(P->nz);
+    // x-pass line stride in LDS (complex values): the least stride >= m + 1
+    // congruent to DNSLAB_XLS_MOD modulo 16 (-1: the least odd one).  The
+    // Stockham passes give consecutive lanes consecutive lines, so the stride
+    // sets which banks a wave's lanes hit; 2 (mod 16) measured best on
+    // 1024x512x256 (x inverse 503 -> 491 us FP64, 331 -> 300 us FP32; 8 was
+    // slower than odd)
     Lo.ls_x = ((Lo.m + 1) % 2 == 1) ? Lo.m + 1 : Lo.m + 2;
+    if (DNSLAB_XLS_MOD >= 0) {
+        Lo.ls_x = Lo.m + 1;
+        while (Lo.ls_x % 16 != DNSLAB_XLS_MOD) ++Lo.ls_x;
+    }
     Lo.xtw_lds = Lo.m < DNSLAB_XPASS_TW_LDS_MAX_M ? 1 : 0;
     const long long nlines = (long long)P->ny * P->nz;
     {

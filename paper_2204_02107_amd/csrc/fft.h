@@ -39,7 +39,7 @@ struct FFTArgs {
     // x pass
     int xtw_lds;        // 1: the W_m and twist tables are staged in each block's LDS; 0: read through the caches
     int nl_x;           // lines per block (power of two)
-    int ls_x;           // LDS line stride (odd, >= m + 1)
+    int ls_x;           // LDS line stride (complex values, >= m + 1)
     // y / z passes
     int lg_tx_y, lg_tx_z;
     int col_pipe;       // pipelined column passes: -1 where each block gets two tiles or more, 0 never, 1 wherever they apply

@@ -1060,6 +1060,9 @@ static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s, Reco
     const int nblocks = ntile * nplane + (nplane + tx - 1) / tx;
     const AxisPlan& ap = zp ? a.pz : a.py;
     dim3 block(round64(std::min(1024, tx * ap.tpl * DNSLAB_FFT_TPL_MUL)));
+    // every first-pass butterfly needs a thread (longer lines than the block
+    // can cover are refused rather than transformed in part)
+    if ((long long)block.x < (long long)tx * ap.tpl) return hipErrorInvalidValue;
     size_t lds = ((size_t)tx * nrow + nrow) * sizeof(C2<T>);
     // the pipelined pass (plain launches): two tile buffers, each block
     // walking at least two tiles
