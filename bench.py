@@ -369,13 +369,13 @@ def kernel_key(sym):
         return "scalar_pair"
     if base == "sca_stage":
         return "scalar_stage"
-    if base in ("filter", "filter_lds"):
+    if base in ("filter", "filter_lds", "filter_ring"):
         return "filter" if targs.endswith("3") else "filter_c"
     if base == "fft_cols":
         return "fft_z" if targs.endswith("2") else "fft_y"
     if base == "fft_yz":
         return "fft_yz"
-    if base in ("correct", "refine_correct"):
+    if base in ("correct", "refine_correct", "correct_ring", "refine_correct_ring"):
         return "correct"
     if base in ("div", "fft_x_fwd", "fft_x_inv", "ib_rhs", "refine_res", "refine_res_ib"):
         return base

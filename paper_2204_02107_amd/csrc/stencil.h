@@ -169,10 +169,13 @@ StencilLaunch stencil_launch(const Grid& g, int rows, int kc, int cells_x);
 // records the launch (for batched replay by the pool) without issuing it.
 template <typename T> hipError_t launch_mom_stage(int mode, const MomArgs<T>& a, const StencilLaunch& L, hipStream_t s,
                                                   Recorder* rec = nullptr);
-// Block height of the radius-3 filter (64 x DNSLAB_FROWS tiles; the
-// register-ring filter is compiled for this height).
+// Block height of the radius-3 filter and of the velocity correction
+// (64 x DNSLAB_FROWS tiles; their register-ring forms are compiled for this
+// height).  16 rows cut the filter's x/y halo from 0.91 to 0.5 of the tile:
+// on 1024x512x256 the FP64 filter went from 1792 to 1637 us and the
+// correction from 1619 to 1532 us against 64 x 8.
 #ifndef DNSLAB_FROWS
-#define DNSLAB_FROWS 8
+#define DNSLAB_FROWS 16
 #endif
 // Rows of the 64-wide tile of the stage-pair kernels (a compile-time tile
 // shape: the kernels' LDS offsets are immediates).

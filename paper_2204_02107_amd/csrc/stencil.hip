@@ -1918,11 +1918,11 @@ __global__ __launch_bounds__(1024) void k_filter_lds_b(const BRec<FiltArgs<T>>* 
     filter_lds_body<T, NF>(a, bi_);
 }
 template <typename T, int NF>
-__global__ __launch_bounds__(512) void k_filter_ring(const FiltArgs<T> a) {
+__global__ __launch_bounds__(64 * DNSLAB_FROWS) void k_filter_ring(const FiltArgs<T> a) {
     filter_ring_body<T, NF, DNSLAB_FROWS>(a, hw_block());
 }
 template <typename T, int NF>
-__global__ __launch_bounds__(512) void k_filter_ring_b(const BRec<FiltArgs<T>>* __restrict__ tab,
+__global__ __launch_bounds__(64 * DNSLAB_FROWS) void k_filter_ring_b(const BRec<FiltArgs<T>>* __restrict__ tab,
                                                        const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const FiltArgs<T> a = tab[s_].a;
@@ -1973,18 +1973,18 @@ __device__ __forceinline__ void refine_correct_ring(const RefineCorrArgs& a, con
     correct_ring_body<float, true, DNSLAB_FROWS, DNSLAB_RING_DIST>(a.us, a.out, io, a.p, a.flags, a.g, a.kc, a.part, bi);
 }
 template <typename T>
-__global__ __launch_bounds__(512) void k_correct_ring(const CorrArgs<T> a) { correct_ring<T>(a, hw_block()); }
+__global__ __launch_bounds__(64 * DNSLAB_FROWS) void k_correct_ring(const CorrArgs<T> a) { correct_ring<T>(a, hw_block()); }
 template <typename T>
-__global__ __launch_bounds__(512) void k_correct_ring_b(const BRec<CorrArgs<T>>* __restrict__ tab,
+__global__ __launch_bounds__(64 * DNSLAB_FROWS) void k_correct_ring_b(const BRec<CorrArgs<T>>* __restrict__ tab,
                                                         const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const CorrArgs<T> a = tab[s_].a;
     correct_ring<T>(a, bi_);
 }
-__global__ __launch_bounds__(512) void k_refine_correct_ring(const RefineCorrArgs a) {
+__global__ __launch_bounds__(64 * DNSLAB_FROWS) void k_refine_correct_ring(const RefineCorrArgs a) {
     refine_correct_ring(a, hw_block());
 }
-__global__ __launch_bounds__(512) void k_refine_correct_ring_b(const BRec<RefineCorrArgs>* __restrict__ tab,
+__global__ __launch_bounds__(64 * DNSLAB_FROWS) void k_refine_correct_ring_b(const BRec<RefineCorrArgs>* __restrict__ tab,
                                                                const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const RefineCorrArgs a = tab[s_].a;

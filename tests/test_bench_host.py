@@ -28,6 +28,10 @@ def test_kernel_key_mapping():
     assert k("void dnslab::(anonymous namespace)::k_mom_pair<double, 1>(dnslab::MomPairArgs<double>)") == "mom_pair"
     assert k("void dnslab::(anonymous namespace)::k_mom_pair_b<float, 0>(dnslab::BRec<...> const*)") == "mom_pair"
     assert k("void dnslab::(anonymous namespace)::k_sca_pair<double, 0>(dnslab::ScaPairArgs<double>)") == "scalar_pair"
+    assert k("void dnslab::(anonymous namespace)::k_filter_ring<double, 3>(dnslab::FiltArgs<double>)") == "filter"
+    assert k("void dnslab::(anonymous namespace)::k_filter_ring_b<float, 1>(dnslab::BRec<...> const*)") == "filter_c"
+    assert k("void dnslab::(anonymous namespace)::k_correct_ring<double>(dnslab::CorrArgs<double>)") == "correct"
+    assert k("dnslab::(anonymous namespace)::k_refine_correct_ring(dnslab::RefineCorrArgs)") == "correct"
     assert k("dnslab::(anonymous namespace)::k_advance(dnslab::AdvanceArgs)") is None
     assert k("__amd_rocclr_copyBuffer") is None
 
