@@ -185,6 +185,17 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_FKC_MIN32
 #define DNSLAB_FKC_MIN32 24
 #endif
+// below this many blocks of 64 x DNSLAB_FROWS tiles, the filter and the
+// correction take 64 x 8 tiles with the shorter chunks below
+#ifndef DNSLAB_RING_MIN_BLOCKS
+#define DNSLAB_RING_MIN_BLOCKS 1024
+#endif
+#ifndef DNSLAB_FKC_MIN_SMALL
+#define DNSLAB_FKC_MIN_SMALL 12
+#endif
+#ifndef DNSLAB_FKC_MIN_SMALL32
+#define DNSLAB_FKC_MIN_SMALL32 8
+#endif
 // FFT passes: x lines per block grow while the block stays within these
 // threads and LDS bytes; y/z column tiles within this much LDS.
 #ifndef DNSLAB_XPASS_THREADS
@@ -345,10 +356,21 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     }
     Lo.L = stencil_launch(g, DNSLAB_ROWS, stencil_kc(g, DNSLAB_ROWS, DNSLAB_KC), 1);
     Lo.L1 = Lo.L;
-    // the radius-3 filter re-reads 6 halo planes per z chunk: longer chunks
+    // Filter and correction: 64 x DNSLAB_FROWS tiles with long z chunks (the
+    // radius-3 filter re-reads 6 halo planes per chunk), their register-ring
+    // forms, where that still gives DNSLAB_RING_MIN_BLOCKS blocks; on smaller
+    // grids 64 x 8 tiles with shorter chunks, the LDS filter and the
+    // one-cell-per-thread correction, which keep many more blocks (on
+    // 192x96x64 the large tiles made the filter 28 -> 53 us and the
+    // correction 12 -> 32 us: 24 blocks for 256 CUs).
     const int fkc_min = Lo.esz == 8 ? DNSLAB_FKC_MIN : DNSLAB_FKC_MIN32;
     Lo.LF = stencil_launch(g, DNSLAB_FROWS,
                            std::max(stencil_kc(g, DNSLAB_FROWS, DNSLAB_FKC), std::min(fkc_min, P->nz)), 1);
+    const bool ring_geometry = Lo.LF.nblocks >= DNSLAB_RING_MIN_BLOCKS;
+    if (!ring_geometry) {
+        const int small_min = Lo.esz == 8 ? DNSLAB_FKC_MIN_SMALL : DNSLAB_FKC_MIN_SMALL32;
+        Lo.LF = stencil_launch(g, 8, std::max(stencil_kc(g, 8, DNSLAB_FKC), std::min(small_min, P->nz)), 1);
+    }
     {
         // the pair kernels read kc + 4 planes and evaluate their first stage on
         // kc + 2 planes per chunk: longer chunks than the single-stage kernels
@@ -357,7 +379,7 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
         const long long pkc = std::max(8LL, std::min(32LL, (long long)g.nz * cols / DNSLAB_PKC_DIV));
         Lo.LP = stencil_launch(g, DNSLAB_PROWS, (int)std::min<long long>(pkc, g.nz), 1);
     }
-    Lo.LC = Lo.LF;
+    Lo.LC = ring_geometry ? Lo.LF : Lo.L1;
     Lo.nparts = std::max(std::max(std::max(Lo.L.nblocks, Lo.L1.nblocks), Lo.LF.nblocks), Lo.LP.nblocks);
     // workspace layout
     size_t off = 0;

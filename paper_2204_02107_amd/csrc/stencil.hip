@@ -421,12 +421,23 @@ __device__ __forceinline__ void ring_cell(int r, int BX, int BY, int& lx, int& l
 
 // Prefetch distance of the pair kernels' loads, in planes: each block keeps
 // the loads of the next D planes in flight.  With the register rings one
-// plane suffices (two push the FP64 momentum pair past 256 registers).
+// plane suffices for the momentum pairs (two push the FP64 pair 1 past 256
+// registers, and gain nothing for pair 0 or in FP32); the FP64 scalar pairs
+// gain 3% from two.
 #ifndef DNSLAB_PAIR_DIST_MOM64
 #define DNSLAB_PAIR_DIST_MOM64 1
 #endif
+#ifndef DNSLAB_PAIR_DIST_MOM64_P0
+#define DNSLAB_PAIR_DIST_MOM64_P0 DNSLAB_PAIR_DIST_MOM64   // FP64 momentum pair 0 (fewer registers than pair 1)
+#endif
+#ifndef DNSLAB_PAIR_DIST_SCA64
+#define DNSLAB_PAIR_DIST_SCA64 2   // FP64 scalar pairs: 2038 -> 1976 us on 1024x512x256 (201 / 235 registers)
+#endif
 #ifndef DNSLAB_PAIR_DIST_OTHER
 #define DNSLAB_PAIR_DIST_OTHER 1
+#endif
+#ifndef DNSLAB_PAIR_DIST_MOM32_P0
+#define DNSLAB_PAIR_DIST_MOM32_P0 DNSLAB_PAIR_DIST_OTHER   // FP32 momentum pair 0
 #endif
 // Waves per SIMD the FP32 pair kernels are compiled for (0: the compiler's
 // choice).  Four keep them within 128 registers, two 512-thread blocks per
@@ -435,8 +446,11 @@ __device__ __forceinline__ void ring_cell(int r, int BX, int BY, int& lx, int& l
 #ifndef DNSLAB_PAIR_WAVES32
 #define DNSLAB_PAIR_WAVES32 4
 #endif
-template <typename T, bool MOM>
-constexpr int pair_dist() { return (MOM && sizeof(T) == 8) ? DNSLAB_PAIR_DIST_MOM64 : DNSLAB_PAIR_DIST_OTHER; }
+template <typename T, bool MOM, int PAIR>
+constexpr int pair_dist() {
+    return sizeof(T) != 8 ? ((MOM && PAIR == 0) ? DNSLAB_PAIR_DIST_MOM32_P0 : DNSLAB_PAIR_DIST_OTHER)
+                          : (MOM ? (PAIR == 0 ? DNSLAB_PAIR_DIST_MOM64_P0 : DNSLAB_PAIR_DIST_MOM64) : DNSLAB_PAIR_DIST_SCA64);
+}
 
 // Register rings of the pair kernels.  A value belonging to z plane x of the
 // march (x counted from the chunk's first iteration) sits in slot x % U of
@@ -1870,25 +1884,25 @@ __global__ __launch_bounds__(1024) void k_mom_stage_b(const BRec<MomArgs<T>>* __
 }
 template <typename T, int PAIR>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_mom_pair(const MomPairArgs<T> a) {
-    mom_pair_body<T, PAIR, pair_dist<T, true>(), DNSLAB_PROWS>(a, hw_block());
+    mom_pair_body<T, PAIR, pair_dist<T, true, PAIR>(), DNSLAB_PROWS>(a, hw_block());
 }
 template <typename T, int PAIR>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_mom_pair_b(const BRec<MomPairArgs<T>>* __restrict__ tab,
                                                     const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const MomPairArgs<T> a = tab[s_].a;
-    mom_pair_body<T, PAIR, pair_dist<T, true>(), DNSLAB_PROWS>(a, bi_);
+    mom_pair_body<T, PAIR, pair_dist<T, true, PAIR>(), DNSLAB_PROWS>(a, bi_);
 }
 template <typename T, int PAIR>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_sca_pair(const ScaPairArgs<T> a) {
-    sca_pair_body<T, PAIR, pair_dist<T, false>(), DNSLAB_PROWS>(a, hw_block());
+    sca_pair_body<T, PAIR, pair_dist<T, false, PAIR>(), DNSLAB_PROWS>(a, hw_block());
 }
 template <typename T, int PAIR>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_sca_pair_b(const BRec<ScaPairArgs<T>>* __restrict__ tab,
                                                     const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const ScaPairArgs<T> a = tab[s_].a;
-    sca_pair_body<T, PAIR, pair_dist<T, false>(), DNSLAB_PROWS>(a, bi_);
+    sca_pair_body<T, PAIR, pair_dist<T, false, PAIR>(), DNSLAB_PROWS>(a, bi_);
 }
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_sca_stage(const ScaArgs<T> a) { sca_stage_body<T, MODE>(a, hw_block()); }
