@@ -250,6 +250,9 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_PAIRS
 #define DNSLAB_PAIRS 1         // RK4 stages two at a time (fused stage pairs) where the tile divides the grid
 #endif
+#ifndef DNSLAB_PAIR_MIN_BLOCKS64
+#define DNSLAB_PAIR_MIN_BLOCKS64 256   // FP64 momentum pairs from this many blocks on (mom_pairs)
+#endif
 #ifndef DNSLAB_PAIR_MIN_KC
 #define DNSLAB_PAIR_MIN_KC 16  // shortest z chunk for the scalar pairs and the FP32 momentum pairs
 #endif
@@ -701,9 +704,15 @@ int project(dnslab_ctx* x, const T* const us[3], T* const out[3]) {
 // scalar 7.6 -> 5.2 ms per step).
 // dnslab_set_stage_pairs overrides the choice (pairs_mode 0: never, 1:
 // wherever supported).
+// FP64 momentum pairs on short z chunks pay only with a block per CU or more:
+// with 8-plane chunks 64^3 (64 blocks) ran 1.11 Gcell-steps/s with single
+// stages against 1.01 with pairs, 128x64x64 (128 blocks) 1.95 against 1.83,
+// 192x96x64 (288) 3.00 either way, the 256x128x96 room (768) 3.80 against
+// 3.95.
 bool mom_pairs(const dnslab_ctx* x) {
     if (x->pairs_mode == 0 || !DNSLAB_PAIRS || !mom_pair_supported(x->g, x->Lo.LP)) return false;
-    return x->pairs_mode == 1 || x->Lo.esz == 8 || x->Lo.LP.kc >= DNSLAB_PAIR_MIN_KC;
+    return x->pairs_mode == 1 || (x->Lo.esz == 8 && x->Lo.LP.nblocks >= DNSLAB_PAIR_MIN_BLOCKS64) ||
+           x->Lo.LP.kc >= DNSLAB_PAIR_MIN_KC;
 }
 // The scalar's second pair reads c^n at the cells around its tile, so it
 // cannot write c^n in place: the pairs run when the filter is on (the RK4

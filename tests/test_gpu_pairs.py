@@ -1,8 +1,8 @@
 """RK4 stages two per pass (momentum and scalar stage pairs) against the FP64
 oracle and against one kernel per stage, forced on small rooms through
-dnslab_set_stage_pairs (by default they run only where each block's z chunk
-is long, i.e. on the 25M- and 134M-cell grids, which the full-size tests
-cover).  Ragged z chunks: nz = 36 and 54 are not multiples of the pair
+dnslab_set_stage_pairs (by default the FP64 momentum pairs run where a launch
+has a block per CU or more, the others where each block's z chunk is long:
+the 3.1M-, 25M- and 134M-cell grids of the full-size tests).  Ragged z chunks: nz = 36 and 54 are not multiples of the pair
 kernels' chunk length.
 
 Tolerances: FP64 whole steps 1e-10 against the oracle (the stated bar); the
