@@ -20,6 +20,9 @@
 
 #include <algorithm>
 
+#ifndef DNSLAB_COL_XCD
+#define DNSLAB_COL_XCD 1       // column passes: XCD-aware tile order (xcd_tile)
+#endif
 #ifndef DNSLAB_FFT_TPL_MUL
 #define DNSLAB_FFT_TPL_MUL 1   // threads per line = MUL * n / rad[0] (extra threads only stage memory)
 #endif
@@ -903,8 +906,21 @@ __global__ __launch_bounds__(1024) void k_fft_x_inv_b(const BRec<FxiArgs<T>>* __
     const FxiArgs<T>& a = tab[s_].a;
     fft_x_inv_body<T>(a, blk_);
 }
+// XCD-aware tile order for the column passes: workgroups are dealt to the 8
+// XCDs round-robin by hardware id, so consecutive ids (neighbouring kx tiles
+// of one plane, which share the 128-byte lines their row segments fall in)
+// would land in different L2s and each fetch the whole line.  The hardware id
+// is remapped so that each XCD owns a contiguous range of tiles.
+__device__ __forceinline__ unsigned xcd_tile(unsigned hw, unsigned nb) {
+    if (!DNSLAB_COL_XCD) return hw;
+    const unsigned x = hw & 7u, q = hw >> 3;
+    const unsigned per = nb >> 3, rem = nb & 7u;
+    return x * per + min(x, rem) + q;
+}
 template <typename T, int MODE>
-__global__ __launch_bounds__(1024) void k_fft_cols(const FFTArgs<T> a) { fft_cols_body<T, MODE>(a, blockIdx.x); }
+__global__ __launch_bounds__(1024) void k_fft_cols(const FFTArgs<T> a) {
+    fft_cols_body<T, MODE>(a, xcd_tile(blockIdx.x, gridDim.x));
+}
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_fft_cols_b(const BRec<FFTArgs<T>>* __restrict__ tab,
                                                      const unsigned* __restrict__ st, int ns) {

@@ -452,24 +452,25 @@ constexpr int pair_dist() {
                           : (MOM ? (PAIR == 0 ? DNSLAB_PAIR_DIST_MOM64_P0 : DNSLAB_PAIR_DIST_MOM64) : DNSLAB_PAIR_DIST_SCA64);
 }
 
-// Register rings of the pair kernels.  A value belonging to z plane x of the
-// march (x counted from the chunk's first iteration) sits in slot x % U of
-// its ring, and the z loop is unrolled U times (pair_phases), so every slot
-// index is a compile-time constant: values stay in the register they were
-// loaded into.  Shifting a queue instead (q[i] = q[i+1]) costs a move per
-// value and plane, and a move of a register whose load is still in flight
-// makes the wave wait for that load, which defeats the prefetch.
+// Register rings of the z-marching kernels (stage pairs, filter,
+// correction).  A value belonging to z plane x of the march (x counted from
+// the chunk's first iteration) sits in slot x % U of its ring, and the z loop
+// is unrolled U times (pair_phases), so every slot index is a compile-time
+// constant: values stay in the register they were loaded into.  Shifting a
+// queue instead (q[i] = q[i+1]) costs a move per value and plane, and a move
+// of a register whose load is still in flight makes the wave wait for that
+// load, which defeats the prefetch.
 template <int... Is, typename F>
 __device__ __forceinline__ bool pair_phases(std::integer_sequence<int, Is...>, F&& f) {
     return (f(std::integral_constant<int, Is>{}) && ...);
 }
-// Loads and stores of the pair kernels as raw buffer accesses: the array's
-// resource (base address) and the plane's byte offset are wave-uniform
-// (scalar registers), the in-plane byte offset is the lane's (one vector
-// register, fixed for the whole march), and the address is formed by the
-// memory unit: no per-lane 64-bit address arithmetic, and nothing the
-// compiler can hoist into one 64-bit pointer per array and lane.  The
-// resource does no range clipping (every offset is inside its array).
+// Loads and stores of the register-ring kernels as raw buffer accesses: the
+// array's resource (base address) and the plane's byte offset are
+// wave-uniform (scalar registers), the in-plane byte offset is the lane's
+// (one vector register, fixed for the whole march), and the address is
+// formed by the memory unit: no per-lane 64-bit address arithmetic, and
+// nothing the compiler can hoist into one 64-bit pointer per array and lane.
+// The resource does no range clipping (every offset is inside its array).
 typedef unsigned u32x2_t __attribute__((__vector_size__(2 * sizeof(unsigned))));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_res(const void* p) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
@@ -502,7 +503,8 @@ __device__ __forceinline__ T bld(const T* p, unsigned voff, unsigned soff) { ret
 template <typename T>
 __device__ __forceinline__ void bst(T* p, unsigned voff, unsigned soff, T x) { BufIO<T>::st(p, voff, soff, x); }
 // A per-lane value the compiler must take as redefined at this point.  The
-// pair kernels pass their LDS indices through it once per plane: otherwise
+// register-ring kernels (stage pairs, filter, correction) pass their LDS
+// indices through it once per plane: otherwise
 // the address of every LDS access of the unrolled march (a different
 // constant offset per plane of the buffer cycle) is hoisted out of the loop
 // and held in a register of its own for the whole kernel.
