@@ -103,6 +103,16 @@ struct BlockIdx3 {
     unsigned gx, gy, gz;  // the scenario's grid dimensions
 };
 
+// XCD-aware order for one-dimensional grids: workgroups are dealt to the 8
+// XCDs round-robin by hardware id, so consecutive ids would land in
+// different L2s; the remap gives each XCD a contiguous range of logical
+// blocks (a permutation of [0, nb)).
+__device__ __forceinline__ unsigned xcd_block(unsigned hw, unsigned nb) {
+    const unsigned x = hw & 7u, q = hw >> 3;
+    const unsigned per = nb >> 3, rem = nb & 7u;
+    return x * per + min(x, rem) + q;
+}
+
 __device__ __forceinline__ BlockIdx3 hw_block() {
     BlockIdx3 b;
     b.gx = gridDim.x;

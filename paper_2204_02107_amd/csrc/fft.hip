@@ -912,10 +912,7 @@ __global__ __launch_bounds__(1024) void k_fft_x_inv_b(const BRec<FxiArgs<T>>* __
 // would land in different L2s and each fetch the whole line.  The hardware id
 // is remapped so that each XCD owns a contiguous range of tiles.
 __device__ __forceinline__ unsigned xcd_tile(unsigned hw, unsigned nb) {
-    if (!DNSLAB_COL_XCD) return hw;
-    const unsigned x = hw & 7u, q = hw >> 3;
-    const unsigned per = nb >> 3, rem = nb & 7u;
-    return x * per + min(x, rem) + q;
+    return DNSLAB_COL_XCD ? xcd_block(hw, nb) : hw;
 }
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_fft_cols(const FFTArgs<T> a) {
