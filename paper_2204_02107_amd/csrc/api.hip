@@ -190,6 +190,14 @@ Grid make_grid(const dnslab_params* P) {
 #ifndef DNSLAB_RING_MIN_BLOCKS
 #define DNSLAB_RING_MIN_BLOCKS 1024
 #endif
+// Longer filter chunks where the 64 x DNSLAB_FROWS tiles still give this
+// many blocks.
+#ifndef DNSLAB_FKC_LONG
+#define DNSLAB_FKC_LONG 64
+#endif
+#ifndef DNSLAB_FKC_LONG_BLOCKS
+#define DNSLAB_FKC_LONG_BLOCKS 2048
+#endif
 #ifndef DNSLAB_FKC_MIN_SMALL
 #define DNSLAB_FKC_MIN_SMALL 12
 #endif
@@ -257,7 +265,25 @@ Grid make_grid(const dnslab_params* P) {
 #define DNSLAB_PAIR_MIN_KC 16  // shortest z chunk for the scalar pairs and the FP32 momentum pairs
 #endif
 #ifndef DNSLAB_PKC_DIV
-#define DNSLAB_PKC_DIV 1024    // stage-pair z chunk: nz * tiles per plane / this, clamped to [8, 32]
+#define DNSLAB_PKC_DIV 1024    // stage-pair z chunk: nz * tiles per plane / this, clamped to [8, DNSLAB_PKC_MAX]
+#endif
+#ifndef DNSLAB_PKC_MAX
+#define DNSLAB_PKC_MAX 32
+#endif
+// Longer stage-pair chunks where they still give this many blocks (the pair
+// kernels re-read 4 halo planes and recompute 2 planes of the first stage per
+// chunk).
+#ifndef DNSLAB_PKC_LONG
+#define DNSLAB_PKC_LONG 128
+#endif
+#ifndef DNSLAB_PKC_LONG_BLOCKS
+#define DNSLAB_PKC_LONG_BLOCKS 2048
+#endif
+#ifndef DNSLAB_PKC_LONG32
+#define DNSLAB_PKC_LONG32 64
+#endif
+#ifndef DNSLAB_PKC_LONG_BLOCKS32
+#define DNSLAB_PKC_LONG_BLOCKS32 4096
 #endif
 
 // z chunk: enough blocks to fill the chip, each walking at least 4 planes.
@@ -370,6 +396,10 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
     Lo.LF = stencil_launch(g, DNSLAB_FROWS,
                            std::max(stencil_kc(g, DNSLAB_FROWS, DNSLAB_FKC), std::min(fkc_min, P->nz)), 1);
     const bool ring_geometry = Lo.LF.nblocks >= DNSLAB_RING_MIN_BLOCKS;
+    if (ring_geometry && Lo.LF.kc < DNSLAB_FKC_LONG) {
+        const StencilLaunch lf = stencil_launch(g, DNSLAB_FROWS, std::min(DNSLAB_FKC_LONG, P->nz), 1);
+        if (lf.nblocks >= DNSLAB_FKC_LONG_BLOCKS) Lo.LF = lf;
+    }
     if (!ring_geometry) {
         const int small_min = Lo.esz == 8 ? DNSLAB_FKC_MIN_SMALL : DNSLAB_FKC_MIN_SMALL32;
         Lo.LF = stencil_launch(g, 8, std::max(stencil_kc(g, 8, DNSLAB_FKC), std::min(small_min, P->nz)), 1);
@@ -379,8 +409,14 @@ Layout make_layout(const dnslab_params* P, int n_forced) {
         // kc + 2 planes per chunk: longer chunks than the single-stage kernels
         const StencilLaunch one = stencil_launch(g, DNSLAB_PROWS, g.nz, 1);
         const long long cols = (long long)one.grid.x * one.grid.y;
-        const long long pkc = std::max(8LL, std::min(32LL, (long long)g.nz * cols / DNSLAB_PKC_DIV));
+        const long long pkc = std::max(8LL, std::min((long long)DNSLAB_PKC_MAX, (long long)g.nz * cols / DNSLAB_PKC_DIV));
         Lo.LP = stencil_launch(g, DNSLAB_PROWS, (int)std::min<long long>(pkc, g.nz), 1);
+        const int long_kc = Lo.esz == 8 ? DNSLAB_PKC_LONG : DNSLAB_PKC_LONG32;
+        const int long_blocks = Lo.esz == 8 ? DNSLAB_PKC_LONG_BLOCKS : DNSLAB_PKC_LONG_BLOCKS32;
+        if (Lo.LP.kc < long_kc) {
+            const StencilLaunch lp = stencil_launch(g, DNSLAB_PROWS, std::min(long_kc, g.nz), 1);
+            if (lp.nblocks >= long_blocks) Lo.LP = lp;
+        }
     }
     Lo.LC = ring_geometry ? Lo.LF : Lo.L1;
     Lo.nparts = std::max(std::max(std::max(Lo.L.nblocks, Lo.L1.nblocks), Lo.LF.nblocks), Lo.LP.nblocks);
