@@ -446,10 +446,29 @@ __device__ __forceinline__ void ring_cell(int r, int BX, int BY, int& lx, int& l
 #ifndef DNSLAB_PAIR_WAVES32
 #define DNSLAB_PAIR_WAVES32 4
 #endif
+#ifndef DNSLAB_PAIR_WAVES32_MOM1
+#define DNSLAB_PAIR_WAVES32_MOM1 DNSLAB_PAIR_WAVES32
+#endif
+// The FP32 scalar pair 1 needs 138 registers: held to 128 it spilled 19 per
+// lane.  Unconstrained (one block per CU) it is 3% slower alone, but the
+// FP32 step on 1024x512x256, where it runs beside the momentum pair 1 on the
+// second stream, went from 8.10 to 8.24 Gcell-steps/s.
+#ifndef DNSLAB_PAIR_WAVES32_SCA1
+#define DNSLAB_PAIR_WAVES32_SCA1 0
+#endif
+#ifndef DNSLAB_PAIR_DIST_SCA32
+#define DNSLAB_PAIR_DIST_SCA32 DNSLAB_PAIR_DIST_OTHER
+#endif
 template <typename T, bool MOM, int PAIR>
 constexpr int pair_dist() {
-    return sizeof(T) != 8 ? ((MOM && PAIR == 0) ? DNSLAB_PAIR_DIST_MOM32_P0 : DNSLAB_PAIR_DIST_OTHER)
+    return sizeof(T) != 8 ? (MOM ? (PAIR == 0 ? DNSLAB_PAIR_DIST_MOM32_P0 : DNSLAB_PAIR_DIST_OTHER) : DNSLAB_PAIR_DIST_SCA32)
                           : (MOM ? (PAIR == 0 ? DNSLAB_PAIR_DIST_MOM64_P0 : DNSLAB_PAIR_DIST_MOM64) : DNSLAB_PAIR_DIST_SCA64);
+}
+template <typename T, bool MOM, int PAIR>
+constexpr int pair_waves() {
+    constexpr int w = sizeof(T) != 4 ? 0
+                      : (PAIR == 1 ? (MOM ? DNSLAB_PAIR_WAVES32_MOM1 : DNSLAB_PAIR_WAVES32_SCA1) : DNSLAB_PAIR_WAVES32);
+    return w > 0 ? w : 1;
 }
 
 // Register rings of the z-marching kernels (stage pairs, filter,
@@ -1885,22 +1904,22 @@ __global__ __launch_bounds__(1024) void k_mom_stage_b(const BRec<MomArgs<T>>* __
     mom_stage_body<T, MODE, LDS>(a, bi_);
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_mom_pair(const MomPairArgs<T> a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(pair_waves<T, true, PAIR>()))) void k_mom_pair(const MomPairArgs<T> a) {
     mom_pair_body<T, PAIR, pair_dist<T, true, PAIR>(), DNSLAB_PROWS>(a, hw_block());
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_mom_pair_b(const BRec<MomPairArgs<T>>* __restrict__ tab,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(pair_waves<T, true, PAIR>()))) void k_mom_pair_b(const BRec<MomPairArgs<T>>* __restrict__ tab,
                                                     const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const MomPairArgs<T> a = tab[s_].a;
     mom_pair_body<T, PAIR, pair_dist<T, true, PAIR>(), DNSLAB_PROWS>(a, bi_);
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_sca_pair(const ScaPairArgs<T> a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(pair_waves<T, false, PAIR>()))) void k_sca_pair(const ScaPairArgs<T> a) {
     sca_pair_body<T, PAIR, pair_dist<T, false, PAIR>(), DNSLAB_PROWS>(a, hw_block());
 }
 template <typename T, int PAIR>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && DNSLAB_PAIR_WAVES32 ? DNSLAB_PAIR_WAVES32 : 1))) void k_sca_pair_b(const BRec<ScaPairArgs<T>>* __restrict__ tab,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(pair_waves<T, false, PAIR>()))) void k_sca_pair_b(const BRec<ScaPairArgs<T>>* __restrict__ tab,
                                                     const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_COORD(tab, st, ns)
     const ScaPairArgs<T> a = tab[s_].a;
