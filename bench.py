@@ -372,7 +372,8 @@ def kernel_key(sym):
     if base in ("filter", "filter_lds", "filter_ring"):
         return "filter" if targs.endswith("3") else "filter_c"
     if base == "fft_cols":
-        return "fft_z" if targs.endswith("2") else "fft_y"
+        parts = [x.strip() for x in targs.split(",")]
+        return "fft_z" if len(parts) > 1 and parts[1] == "2" else "fft_y"
     if base == "fft_yz":
         return "fft_yz"
     if base in ("correct", "refine_correct", "correct_ring", "refine_correct_ring"):

@@ -20,6 +20,9 @@
 
 #include <algorithm>
 
+#ifndef DNSLAB_COL_DIRECT
+#define DNSLAB_COL_DIRECT 1    // column passes: last radix pass stores to the spectrum
+#endif
 #ifndef DNSLAB_COL_XCD
 #define DNSLAB_COL_XCD 1       // column passes: XCD-aware tile order (xcd_tile)
 #endif
@@ -221,9 +224,15 @@ __device__ __forceinline__ void phase_barrier() {
     else __syncthreads();
 }
 
-template <typename T, int R, int MAXB, bool INV, int N, int NS, bool LB = false>
+// Epilogue of a pass: out value for line (column) c, row i.
+struct NoEpi {
+    template <typename V>
+    __device__ __forceinline__ V operator()(int, int, V v) const { return v; }
+};
+
+template <typename T, int R, int MAXB, bool INV, int N, int NS, bool LB = false, class Epi = NoEpi>
 __device__ __forceinline__ void stockham_pass_c(C2<T>* s, const C2<T>* W, int es, int ls, int lg_nl, int tid,
-                                                int nthr) {
+                                                int nthr, Epi epi = Epi()) {
     constexpr int nbl = N / R;
     constexpr int step = N / (NS * R);
     const int nb = nbl << lg_nl;
@@ -257,10 +266,51 @@ __device__ __forceinline__ void stockham_pass_c(C2<T>* s, const C2<T>* W, int es
             C2<T>* base = s + (b & mask) * ls;
             const int d = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) base[(d + r * NS) * es] = v[q][r];
+            for (int r = 0; r < R; ++r) base[(d + r * NS) * es] = epi(b & mask, d + r * NS, v[q][r]);
         }
     }
     phase_barrier<LB>();
+}
+
+// The last pass of a chain with its outputs handed to out(line, row, value)
+// instead of written back in place: no LDS writes, hence no barrier.
+template <typename T, int R, int MAXB, bool INV, int N, int NS, class Out>
+__device__ __forceinline__ void stockham_pass_out(const C2<T>* s, const C2<T>* W, int es, int ls, int lg_nl, int tid,
+                                                  int nthr, Out out) {
+    constexpr int nbl = N / R;
+    constexpr int step = N / (NS * R);
+    const int nb = nbl << lg_nl;
+    const int mask = (1 << lg_nl) - 1;
+    C2<T> v[MAXB][R];
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int b = tid + q * nthr;
+        if (b < nb) {
+            const int j = b >> lg_nl;
+            const C2<T>* base = s + (b & mask) * ls;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = base[(j + r * nbl) * es];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int b = tid + q * nthr;
+        if (b < nb) {
+            const int j = b >> lg_nl;
+            const int k = j % NS;
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const C2<T> w = W[r * k * step];
+                    v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
+                }
+            }
+            DFT<T, R, INV>::run(v[q]);
+            const int d = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) out(b & mask, d + r * NS, v[q][r]);
+        }
+    }
 }
 
 template <typename T, bool INV, int N, int P, bool LB = false>
@@ -271,6 +321,25 @@ __device__ __forceinline__ void fft_chain(C2<T>* s, const C2<T>* W, int es, int 
         constexpr int MAXB = (pl.r[0] + R - 1) / R;
         stockham_pass_c<T, R, MAXB, INV, N, cns(N, P), LB>(s, W, es, ls, lg_nl, tid, nthr);
         fft_chain<T, INV, N, P + 1, LB>(s, W, es, ls, lg_nl, tid, nthr);
+    }
+}
+
+// The chain of compile-time passes with a different last pass: OUT, its
+// outputs go to f(line, row, value) (no LDS writes); otherwise written back in
+// place through the epilogue f.
+template <typename T, bool INV, int N, int P, bool OUT, bool LB = false, class F>
+__device__ __forceinline__ void fft_chain_last(C2<T>* s, const C2<T>* W, int es, int ls, int lg_nl, int tid, int nthr,
+                                               F f) {
+    constexpr CPlan pl = cplan(N);
+    constexpr int R = pl.r[P];
+    constexpr int MAXB = (pl.r[0] + R - 1) / R;
+    if constexpr (P + 1 < pl.np) {
+        stockham_pass_c<T, R, MAXB, INV, N, cns(N, P), LB>(s, W, es, ls, lg_nl, tid, nthr);
+        fft_chain_last<T, INV, N, P + 1, OUT, LB>(s, W, es, ls, lg_nl, tid, nthr, f);
+    } else if constexpr (OUT) {
+        stockham_pass_out<T, R, MAXB, INV, N, cns(N, P)>(s, W, es, ls, lg_nl, tid, nthr, f);
+    } else {
+        stockham_pass_c<T, R, MAXB, INV, N, cns(N, P), LB>(s, W, es, ls, lg_nl, tid, nthr, f);
     }
 }
 
@@ -638,7 +707,79 @@ __device__ __forceinline__ void cols_transform(const FFTArgs<T>& a, const ColTil
     }
 }
 
+// The transforms of a staged tile with the last radix pass storing straight
+// to the spectrum (each row's TX columns are consecutive lanes, so a wave's
+// stores fill whole row segments); the z pass's divide is the epilogue of its
+// forward transform's last pass.  Every value gets the same operations as in
+// cols_transform and the store loop.
+template <typename T, int MODE, int N>
+__device__ __forceinline__ void cols_direct(const FFTArgs<T>& a, const ColTile<T>& t, C2<T>* s, const C2<T>* wl,
+                                            int tid, int nthr, size_t rs) {
+    const int lg = MODE == 2 ? a.lg_tx_z : a.lg_tx_y, tx = 1 << lg;
+    // (the functors capture plain values: a reference to the kernel's
+    // argument block would put a copy of it on the stack)
+    C2<T>* const base = t.base;
+    const size_t cs = t.cs;
+    const int ncol = t.ncol;
+    auto store = [=](int c, int row, const C2<T>& v) {
+        if (c < ncol) base[row * rs + c * cs] = v;
+    };
+    if constexpr (MODE == 2) {
+        const double *sx2 = a.sx2, *sy2 = a.sy2, *sz2 = a.sz2;
+        const double inv_ntot = a.inv_ntot;
+        const int m = a.m, kx0 = t.kx0, plane0 = t.plane0;
+        const bool nyq = t.nyq;
+        auto divide = [=](int c, int kz, C2<T> v) -> C2<T> {
+            if (c < ncol) {
+                const int kx = nyq ? m : kx0 + c;
+                const int ky = nyq ? plane0 + c : plane0;
+                const double lam = (sz2[kz] + sy2[ky]) + sx2[kx];   // -lambda
+                const T f = lam == 0.0 ? T(0) : T(-inv_ntot * recip(lam));
+                v = cscale(v, f);
+            }
+            return v;
+        };
+        fft_chain_last<T, false, N, 0, false>(s, wl, tx, 1, lg, tid, nthr, divide);
+        fft_chain_last<T, true, N, 0, true>(s, wl, tx, 1, lg, tid, nthr, store);
+    } else {
+        fft_chain_last<T, MODE == 1, N, 0, true>(s, wl, tx, 1, lg, tid, nthr, store);
+    }
+}
+// Which column passes store from their last radix pass (the launcher and the
+// batched kernels decide alike, so that both give the same results).  All of
+// them: on 1024x512x256 the FP32 y pass went from 259 to 214 us, the z solve
+// from 372 to 343 us (FP32) and from 549 to 509 us (FP64), the FP64 y pass
+// unchanged; 512x256x192 FP64 y 72 -> 68 us, z 108 -> 91 us.
 template <typename T, int MODE>
+__host__ __device__ constexpr bool col_direct_mode() {
+    return DNSLAB_COL_DIRECT != 0;
+}
+// The lengths with a compile-time chain (pipe_length);
+// the kernel that calls this is launched for those only.
+template <typename T, int MODE>
+__device__ __forceinline__ bool cols_direct_any(int n, const FFTArgs<T>& a, const ColTile<T>& t, C2<T>* s,
+                                                const C2<T>* wl, int tid, int nthr, size_t rs) {
+    switch (n) {
+        case 64: cols_direct<T, MODE, 64>(a, t, s, wl, tid, nthr, rs); return true;
+        case 96: cols_direct<T, MODE, 96>(a, t, s, wl, tid, nthr, rs); return true;
+        case 128: cols_direct<T, MODE, 128>(a, t, s, wl, tid, nthr, rs); return true;
+        case 192: cols_direct<T, MODE, 192>(a, t, s, wl, tid, nthr, rs); return true;
+        case 256: cols_direct<T, MODE, 256>(a, t, s, wl, tid, nthr, rs); return true;
+        case 384: cols_direct<T, MODE, 384>(a, t, s, wl, tid, nthr, rs); return true;
+        case 512: cols_direct<T, MODE, 512>(a, t, s, wl, tid, nthr, rs); return true;
+        case 768: cols_direct<T, MODE, 768>(a, t, s, wl, tid, nthr, rs); return true;
+        case 1024: cols_direct<T, MODE, 1024>(a, t, s, wl, tid, nthr, rs); return true;
+        default: return false;
+    }
+}
+
+// DIRECT 1: the transform length has a compile-time chain and the last radix
+// pass stores to the spectrum (a kernel of its own for the plain launches: the
+// out-of-line runtime transforms beside it would put the argument block, which
+// the plain kernels take by value, on the stack); 2: decided per tile (the
+// batched kernels, whose scenarios differ in length and whose arguments are
+// read in place); 0: transform in place, then store.
+template <typename T, int MODE, int DIRECT = 0>
 __device__ __forceinline__ void fft_cols_body(const FFTArgs<T>& a, unsigned blk) {
     extern __shared__ unsigned char smem_raw[];
     C2<T>* s = reinterpret_cast<C2<T>*>(smem_raw);
@@ -670,6 +811,13 @@ __device__ __forceinline__ void fft_cols_body(const FFTArgs<T>& a, unsigned blk)
         }
     }
     __syncthreads();
+    if constexpr (DIRECT == 1) {
+        cols_direct_any<T, MODE>(nrow, a, t, s, wl, tid, nthr, rs);
+        return;
+    }
+    if constexpr (DIRECT == 2 && col_direct_mode<T, MODE>()) {
+        if (cols_direct_any<T, MODE>(nrow, a, t, s, wl, tid, nthr, rs)) return;
+    }
     cols_transform<T, MODE>(a, t, s, wl, tid, nthr);
 #pragma unroll
     for (int q = 0; q < STAGE_MAX; ++q) {
@@ -737,30 +885,37 @@ __device__ __forceinline__ void fft_cols_pipe_loop(const FFTArgs<T>& a, int ntil
         if (bn < ntiles) cols_fill<T, MODE>(a, col_tile<T, MODE>(a, bn), s0 + ((i + 1) & 1) * tot, tid, nthr);
         const ColTile<T> t = col_tile<T, MODE>(a, b);
         // (no global loads from here to the stores: the symbol tables are in
-        // LDS, so nothing waits for the next tile's loads)
-        if (MODE == 2) {
+        // LDS, so nothing waits for the next tile's loads).  The transforms
+        // are those of cols_direct, the last radix pass storing to the
+        // spectrum; the next iteration's barrier precedes the refill of this
+        // buffer.
+        C2<T>* const base = t.base;
+        const size_t cs = t.cs;
+        const int ncol = t.ncol;
+        auto store = [=](int c, int row, const C2<T>& v) {
+            if (c < ncol) base[row * rs + c * cs] = v;
+        };
+        if constexpr (MODE == 2) {
             const double* sx2l = s2l;
             const double* sy2l = s2l + a.m + 1;
             const double* sz2l = sy2l + a.g.ny;
-            fft_chain<T, false, N, 0, true>(s, wl, tx, 1, lg, tid, nthr);
-            for (int e = tid; e < tot; e += nthr) {
-                const int kz = e >> lg, c = e & (tx - 1);
-                if (c < t.ncol) {
-                    const int kx = t.nyq ? a.m : t.kx0 + c;
-                    const int ky = t.nyq ? t.plane0 + c : t.plane0;
+            const double inv_ntot = a.inv_ntot;
+            const int m = a.m, kx0 = t.kx0, plane0 = t.plane0;
+            const bool nyq = t.nyq;
+            auto divide = [=](int c, int kz, C2<T> v) -> C2<T> {
+                if (c < ncol) {
+                    const int kx = nyq ? m : kx0 + c;
+                    const int ky = nyq ? plane0 + c : plane0;
                     const double lam = (sz2l[kz] + sy2l[ky]) + sx2l[kx];   // -lambda
-                    const T f = lam == 0.0 ? T(0) : T(-a.inv_ntot * recip(lam));
-                    s[e] = cscale(s[e], f);
+                    const T f = lam == 0.0 ? T(0) : T(-inv_ntot * recip(lam));
+                    v = cscale(v, f);
                 }
-            }
-            phase_barrier<true>();
-            fft_chain<T, true, N, 0, true>(s, wl, tx, 1, lg, tid, nthr);
+                return v;
+            };
+            fft_chain_last<T, false, N, 0, false, true>(s, wl, tx, 1, lg, tid, nthr, divide);
+            fft_chain_last<T, true, N, 0, true, true>(s, wl, tx, 1, lg, tid, nthr, store);
         } else {
-            fft_chain<T, MODE == 1, N, 0, true>(s, wl, tx, 1, lg, tid, nthr);
-        }
-        for (int e = tid; e < tot; e += nthr) {
-            const int row = e >> lg, c = e & (tx - 1);
-            if (c < t.ncol) t.base[row * rs + c * t.cs] = s[e];
+            fft_chain_last<T, MODE == 1, N, 0, true, true>(s, wl, tx, 1, lg, tid, nthr, store);
         }
     }
 }
@@ -927,16 +1082,16 @@ __global__ __launch_bounds__(1024) void k_fft_x_inv_b(const BRec<FxiArgs<T>>* __
 __device__ __forceinline__ unsigned xcd_tile(unsigned hw, unsigned nb) {
     return DNSLAB_COL_XCD ? xcd_block(hw, nb) : hw;
 }
-template <typename T, int MODE>
+template <typename T, int MODE, int DIRECT>
 __global__ __launch_bounds__(1024) void k_fft_cols(const FFTArgs<T> a) {
-    fft_cols_body<T, MODE>(a, xcd_tile(blockIdx.x, gridDim.x));
+    fft_cols_body<T, MODE, DIRECT>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void k_fft_cols_b(const BRec<FFTArgs<T>>* __restrict__ tab,
                                                      const unsigned* __restrict__ st, int ns) {
     DNSLAB_BATCH_BLOCK(st, ns)
     const FFTArgs<T>& a = tab[s_].a;   // read in place: a private copy of the plan would sit in scratch
-    fft_cols_body<T, MODE>(a, blk_);
+    fft_cols_body<T, MODE, 2>(a, blk_);
 }
 
 template <typename T, int MODE>
@@ -1111,9 +1266,18 @@ static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s, Reco
         record_launch(rec, kind_code(KK_COLS, mode, sizeof(T) == 4), dim3(nblocks), block, lds, a);
         return hipSuccess;
     }
-    if (mode == 0) hipLaunchKernelGGL((k_fft_cols<T, 0>), dim3(nblocks), block, lds, s, a);
-    else if (mode == 1) hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3(nblocks), block, lds, s, a);
-    else hipLaunchKernelGGL((k_fft_cols<T, 2>), dim3(nblocks), block, lds, s, a);
+    const bool direct = pipe_length(nrow) && (mode == 0   ? col_direct_mode<T, 0>()
+                                              : mode == 1 ? col_direct_mode<T, 1>()
+                                                          : col_direct_mode<T, 2>());
+    if (direct) {
+        if (mode == 0) hipLaunchKernelGGL((k_fft_cols<T, 0, 1>), dim3(nblocks), block, lds, s, a);
+        else if (mode == 1) hipLaunchKernelGGL((k_fft_cols<T, 1, 1>), dim3(nblocks), block, lds, s, a);
+        else hipLaunchKernelGGL((k_fft_cols<T, 2, 1>), dim3(nblocks), block, lds, s, a);
+    } else {
+        if (mode == 0) hipLaunchKernelGGL((k_fft_cols<T, 0, 0>), dim3(nblocks), block, lds, s, a);
+        else if (mode == 1) hipLaunchKernelGGL((k_fft_cols<T, 1, 0>), dim3(nblocks), block, lds, s, a);
+        else hipLaunchKernelGGL((k_fft_cols<T, 2, 0>), dim3(nblocks), block, lds, s, a);
+    }
     return hipGetLastError();
 }
 

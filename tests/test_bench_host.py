@@ -19,6 +19,9 @@ def test_kernel_key_mapping():
     assert k("void dnslab::(anonymous namespace)::k_filter<double, 1>(dnslab::FiltArgs<double>)") == "filter_c"
     assert k("void dnslab::(anonymous namespace)::k_fft_cols<double, 2>(dnslab::FFTArgs<double>)") == "fft_z"
     assert k("void dnslab::(anonymous namespace)::k_fft_cols<float, 1>(dnslab::FFTArgs<float>)") == "fft_y"
+    assert k("void dnslab::(anonymous namespace)::k_fft_cols<double, 2, 1>(dnslab::FFTArgs<double>)") == "fft_z"
+    assert k("void dnslab::(anonymous namespace)::k_fft_cols<float, 0, 0>(dnslab::FFTArgs<float>)") == "fft_y"
+    assert k("void dnslab::(anonymous namespace)::k_fft_cols<double, 1, 2>(dnslab::FFTArgs<double>)") == "fft_y"
     assert k("void dnslab::(anonymous namespace)::k_fft_yz<double>(dnslab::FFTArgs<double>)") == "fft_yz"
     assert k("void dnslab::(anonymous namespace)::k_fft_yz<double, 8>(dnslab::FFTArgs<double>)") == "fft_yz"
     assert k("void dnslab::(anonymous namespace)::k_fft_yz_b<float, 16>(dnslab::BRec<...> const*)") == "fft_yz"
