@@ -241,7 +241,10 @@ Grid make_grid(const dnslab_params* P) {
 #define DNSLAB_YZ_MAX_PLANE32 16384   // the same for the FP32 form (1024-thread blocks)
 #endif
 #ifndef DNSLAB_FORK_EARLY_CELLS
-#define DNSLAB_FORK_EARLY_CELLS (1LL << 62)   // FP64: from this grid size the scalar half forks before the momentum stages
+#define DNSLAB_FORK_EARLY_CELLS (1LL << 23)   // FP64: from this grid size the scalar half forks before the momentum stages
+#endif
+#ifndef DNSLAB_SERIAL_CELLS64
+#define DNSLAB_SERIAL_CELLS64 (1LL << 26)     // FP64: from this grid size a step runs on one stream
 #endif
 #ifndef DNSLAB_FORK_EARLY_CELLS32
 #define DNSLAB_FORK_EARLY_CELLS32 (1LL << 23)   // the same for the FP32 form
@@ -907,7 +910,8 @@ template <typename T>
 int one_step(dnslab_ctx* x) {
     int rc = ensure_rate<T>(x);
     if (rc) return rc;
-    const bool defer = x->overlap && !x->rec;
+    // (FP64 on the largest grids: one stream, see below)
+    const bool defer = x->overlap && !x->rec && !(sizeof(T) == 8 && x->g.n >= DNSLAB_SERIAL_CELLS64);
     if (defer) {
         rc = ensure_aux(x);
         if (rc) return rc;
@@ -934,12 +938,15 @@ int one_step(dnslab_ctx* x) {
     // overlaps the pressure solves only, whose passes leave the memory system
     // idle between their load and store phases (best when the solves are
     // long against the scalar half: the 256x128x96 room loses 7% forking
-    // earlier).  In FP64 that holds at every size once the stages run two
-    // per pass (forking late: 512x256x192 +2.8%, 1024x512x256 +3.4%).  In
-    // the FP32 form the solves run closer to the bandwidth and the scalar
-    // half outlasts them on large grids, stalling the correction that waits
-    // for it, so there it forks before the momentum stages (512x256x192
-    // +2.9%, 1024x512x256 +0.5%).
+    // earlier).  On large grids the solves run closer to the bandwidth and
+    // the scalar half outlasts them, stalling the correction that waits for
+    // it, so there it forks before the momentum stages (FP32 512x256x192
+    // +2.9%, 1024x512x256 +0.5%; FP64 512x256x192 5.53 -> 5.66
+    // Gcell-steps/s).  On 1024x512x256 in FP64, where every kernel fills
+    // the GPU many times over, one stream is faster still (5.84 forking
+    // late, 5.69 early, 5.93 on one stream); in the FP32 form, whose scalar
+    // pair leaves room on the CUs for the momentum pair beside it, two
+    // streams stay faster (8.61 against 8.50).
     const long long fork_early = sizeof(T) == 8 ? DNSLAB_FORK_EARLY_CELLS : DNSLAB_FORK_EARLY_CELLS32;
     if (defer && x->g.n >= fork_early) {
         rc = flush_scalar_half<T>(x);
