@@ -10,8 +10,9 @@ parity tests applies (1e-11 in FP64, 1e-5 in FP32).  The shapes (nz, ny, nx)
 cover ragged kx tiles (nx/2 not a multiple of the tile width), the Nyquist
 column tiles, both precisions, an odd nx/2 (FP64 only: the FP32 pipeline
 loads two columns per lane and needs nx/2 even), lengths of mixed radix,
-and a 128 x 128 plane that the FP32 form gives to the fused plane pass
-(the switch then changes nothing).
+a 128 x 128 plane that the FP32 form gives to the fused plane pass
+(the switch then changes nothing), and the longest compile-time transform
+lengths (z 384 and 768, y 1024).
 """
 import numpy as np
 import pytest
@@ -24,7 +25,8 @@ pytestmark = pytest.mark.gpu
 
 # (ky, kz) planes above 16384 values, so that the column passes (not the
 # fused plane pass) run in both precisions
-SHAPES = [(128, 192, 32), (192, 128, 48), (256, 96, 36), (96, 256, 54), (256, 128, 24), (128, 128, 64)]
+SHAPES = [(128, 192, 32), (192, 128, 48), (256, 96, 36), (96, 256, 54), (256, 128, 24), (128, 128, 64),
+          (768, 64, 32), (64, 1024, 16), (384, 96, 24)]
 
 
 def case(shape, seed):
