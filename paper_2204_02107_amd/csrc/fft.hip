@@ -20,8 +20,13 @@
 
 #include <algorithm>
 
+// Column passes: the last radix pass stores to the spectrum (plain and
+// batched kernels alike, so that both give the same results).  On
+// 1024x512x256 the FP32 y pass went from 259 to 214 us, the z solve from 372
+// to 343 us (FP32) and from 549 to 509 us (FP64), the FP64 y pass unchanged;
+// 512x256x192 FP64 y 72 -> 68 us, z 108 -> 91 us.
 #ifndef DNSLAB_COL_DIRECT
-#define DNSLAB_COL_DIRECT 1    // column passes: last radix pass stores to the spectrum
+#define DNSLAB_COL_DIRECT 1
 #endif
 #ifndef DNSLAB_COL_XCD
 #define DNSLAB_COL_XCD 1       // column passes: XCD-aware tile order (xcd_tile)
@@ -745,17 +750,8 @@ __device__ __forceinline__ void cols_direct(const FFTArgs<T>& a, const ColTile<T
         fft_chain_last<T, MODE == 1, N, 0, true>(s, wl, tx, 1, lg, tid, nthr, store);
     }
 }
-// Which column passes store from their last radix pass (the launcher and the
-// batched kernels decide alike, so that both give the same results).  All of
-// them: on 1024x512x256 the FP32 y pass went from 259 to 214 us, the z solve
-// from 372 to 343 us (FP32) and from 549 to 509 us (FP64), the FP64 y pass
-// unchanged; 512x256x192 FP64 y 72 -> 68 us, z 108 -> 91 us.
-template <typename T, int MODE>
-__host__ __device__ constexpr bool col_direct_mode() {
-    return DNSLAB_COL_DIRECT != 0;
-}
-// The lengths with a compile-time chain (pipe_length);
-// the kernel that calls this is launched for those only.
+// cols_direct for the lengths with a compile-time chain (the ones pipe_length
+// lists); false for any other length, with nothing done.
 template <typename T, int MODE>
 __device__ __forceinline__ bool cols_direct_any(int n, const FFTArgs<T>& a, const ColTile<T>& t, C2<T>* s,
                                                 const C2<T>* wl, int tid, int nthr, size_t rs) {
@@ -815,7 +811,7 @@ __device__ __forceinline__ void fft_cols_body(const FFTArgs<T>& a, unsigned blk)
         cols_direct_any<T, MODE>(nrow, a, t, s, wl, tid, nthr, rs);
         return;
     }
-    if constexpr (DIRECT == 2 && col_direct_mode<T, MODE>()) {
+    if constexpr (DIRECT == 2 && DNSLAB_COL_DIRECT != 0) {
         if (cols_direct_any<T, MODE>(nrow, a, t, s, wl, tid, nthr, rs)) return;
     }
     cols_transform<T, MODE>(a, t, s, wl, tid, nthr);
@@ -1266,9 +1262,7 @@ static hipError_t launch_cols(const FFTArgs<T>& a, int mode, hipStream_t s, Reco
         record_launch(rec, kind_code(KK_COLS, mode, sizeof(T) == 4), dim3(nblocks), block, lds, a);
         return hipSuccess;
     }
-    const bool direct = pipe_length(nrow) && (mode == 0   ? col_direct_mode<T, 0>()
-                                              : mode == 1 ? col_direct_mode<T, 1>()
-                                                          : col_direct_mode<T, 2>());
+    const bool direct = DNSLAB_COL_DIRECT && pipe_length(nrow);
     if (direct) {
         if (mode == 0) hipLaunchKernelGGL((k_fft_cols<T, 0, 1>), dim3(nblocks), block, lds, s, a);
         else if (mode == 1) hipLaunchKernelGGL((k_fft_cols<T, 1, 1>), dim3(nblocks), block, lds, s, a);
