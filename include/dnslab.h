@@ -293,10 +293,12 @@ int dnslab_set_graph_steps(dnslab_ctx* ctx, int32_t k);
 
 /* enable = 1 (the default): the scalar half of a step (scalar RK4, its filter
  * and the diagnostics record) runs on a second stream of the context beside
- * the next step's velocity work, as the data dependences allow.  0: every
- * launch of a step runs in order on the context's stream (for timing
- * kernels alone).  Results are bitwise the same either way.  Enqueues any
- * deferred scalar work first.  DNSLAB_EINVAL unless enable is 0 or 1. */
+ * the next step's velocity work, as the data dependences allow, except for
+ * FP64 grids of 2^26 cells or more, whose steps stay on one stream (there
+ * that is faster).  0: every launch of a step runs in order on the context's
+ * stream (for timing kernels alone).  Results are bitwise the same either
+ * way.  Enqueues any deferred scalar work first.  DNSLAB_EINVAL unless enable
+ * is 0 or 1. */
 int dnslab_set_overlap(dnslab_ctx* ctx, int32_t enable);
 
 /* RK4 stages two per pass (Section 2.1's stages carry no pressure, so a
